@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the GPU EMST / HDBSCAN* path on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload emst_1m]
+                [--no-cpu-baseline]
+
+A step is one complete solve (tree build, [core distances,] every
+filtered-Kruskal round, output sort and write) of one synthetic workload whose
+points are already resident in HBM.  Prints ONE JSON line on stdout; progress
+goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "points/s end-to-end + BCCP evals/s (% FP64 peak); batched/served vs plain, p50/p99"
+FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64, an FMA counted as two flops
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
+
+WORKLOADS = {
+    "emst_1m": dict(desc="EMST, 1,000,000 points i.i.d. uniform in [0,1000)^3, seed 1", n=1_000_000, d=3,
+                    min_pts=0),
+    "hdbscan_2m": dict(desc="HDBSCAN*, minPts=10, 2,000,000 points in 5-D: 95% from 64 Gaussians "
+                            "(centres uniform in [0,1e4)^5, sigma log-uniform [0.5,20]) + 5% uniform noise, seed 2",
+                       n=2_000_000, d=5, min_pts=10),
+    "emst_small": dict(desc="EMST, 2,000 points i.i.d. uniform in [0,1)^2, seed 0", n=2000, d=2, min_pts=0),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gen(name):
+    from paper_2104_01126_amd import workloads as W
+    return {"emst_1m": W.emst_1m, "hdbscan_2m": W.hdbscan_2m, "emst_small": W.emst_small}[name]()
+
+
+def solve(G, x, min_pts):
+    if min_pts:
+        return G.hdbscan(x, min_pts)
+    return G.emst(x)
+
+
+def unit_model(fam, st, d):
+    """Algorithmic work of one kernel family over a solve: (amount, unit,
+    bound).  Bytes are the data the method itself must move, flops the
+    arithmetic it must do; neither counts re-reads or bookkeeping."""
+    if fam == "bccp":
+        # large-pair BCCP: (3d-1) flops per distance (d sub, d mul, d-1 add)
+        return st.big_evals * (3 * d - 1), "TFLOP/s", "alu"
+    if fam == "expand":
+        # per examined node pair: its 16-byte record and the two nodes' box
+        # (2d doubles), radius, range and component (8+8+4 bytes) each
+        return st.pair_visits * (16 + 2 * (16 * d + 20)), "GB/s", "hbm"
+    if fam == "sort":
+        # per element and 8-bit pass: 12 bytes read, 12 bytes written
+        return st.sort_elems * 24, "GB/s", "hbm"
+    if fam == "kruskal":
+        # per committed edge and Boruvka step: rank and two endpoint positions
+        # read, two root lookups (4 bytes each) and the rank compare
+        return st.committed_edges * 24, "GB/s", "hbm"
+    return None, None, None
+
+
+def cpu_baseline(name, pts, min_pts, target_s=15.0):
+    import oracle
+    oracle.build(force=False)
+    n = len(pts)
+    m0 = min(n, 12000)
+    t = time.perf_counter()
+    if min_pts:
+        oracle.hdbscan(pts[:m0], min_pts)
+    else:
+        oracle.emst(pts[:m0])
+    t0 = time.perf_counter() - t
+    m = min(n, max(m0, int(m0 * math.sqrt(target_s / max(t0, 1e-3)))))
+    log(f"cpu baseline: calibration {m0} pts in {t0:.2f}s, sample {m} pts")
+    t = time.perf_counter()
+    if min_pts:
+        oracle.hdbscan(pts[:m], min_pts)
+    else:
+        oracle.emst(pts[:m])
+    dt = time.perf_counter() - t
+    what = "HDBSCAN* (brute-force core distances + dense Prim)" if min_pts else "EMST (dense Prim)"
+    return {"value": m / dt, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {m} of the {n} workload points, {what}, O(m^2), {dt:.1f} s",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="emst_1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the library has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2104_01126_amd import geomst as G
+
+    wl = WORKLOADS[a.workload]
+    log(f"workload {a.workload}: generating")
+    pts = gen(a.workload)
+    n, d = pts.shape
+    mp = wl["min_pts"]
+    G.load()
+    x = torch.from_numpy(pts).to("cuda:0")
+    torch.cuda.synchronize()
+    for i in range(a.warmup):
+        solve(G, x, mp)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{a.warmup}: {G.stats().ms_total:.2f} ms")
+    G.set_option("kernel_timing", 1)
+    kms = np.zeros(16)
+    agg = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        solve(G, x, mp)
+        st = G.stats()
+        kms += np.array(st.kernel_ms)
+        if agg is None:
+            agg = {k: 0 for k in ("pair_visits", "bccp_evals", "big_evals", "sort_elems", "committed_edges",
+                                  "bccp_pairs", "rounds")}
+        for k in agg:
+            agg[k] += getattr(st, k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    G.set_option("kernel_timing", 0)
+    ms_step = dt * 1000.0 / a.steps
+    value = n * a.steps / dt
+    log(f"timed {a.steps} steps: {ms_step:.2f} ms/step, {value / 1e6:.2f} Mpoints/s")
+
+    class S:
+        pass
+    s = S()
+    for k, v in agg.items():
+        setattr(s, k, v)
+    fams = G.KERNEL_FAMILIES
+    per_fam = {fams[i]: round(kms[i] / a.steps, 4) for i in range(len(fams))}
+    log("device ms per step by kernel family:", per_fam)
+    evals_per_s = agg["bccp_evals"] / dt
+    big_ms = kms[fams.index("bccp")]
+    bccp_tflops = (agg["big_evals"] * (3 * d - 1) / (big_ms / 1000.0) / 1e12) if big_ms > 0 else 0.0
+    # dominant kernel family and its roofline
+    order = sorted(range(len(fams)), key=lambda i: -kms[i])
+    roof = None
+    for i in order:
+        amount, unit, bound = unit_model(fams[i], s, d)
+        if amount is None or kms[i] <= 0:
+            continue
+        secs = kms[i] / 1000.0
+        if unit == "TFLOP/s":
+            ach, peak = amount / secs / 1e12, FP64_PEAK_TFLOPS
+        else:
+            ach, peak = amount / secs / 1e9, HBM_PEAK_GBS
+        roof = {"kernel": fams[i], "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+                "frac": round(ach / peak, 5), "traffic": None,
+                "device_ms_per_step": round(kms[i] / a.steps, 4),
+                "share_of_device_time": round(kms[i] / max(kms.sum(), 1e-9), 4)}
+        break
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": n, "d": d, "min_pts": mp or None, "parallelism": "single GPU"},
+        "bccp_evals_per_s": round(evals_per_s, 1),
+        "bccp_large_pair_tflops": round(bccp_tflops, 4),
+        "bccp_large_pair_frac_fp64_peak": round(bccp_tflops / FP64_PEAK_TFLOPS, 5),
+        "roofline": roof,
+        "kernel_ms_per_step": per_fam,
+        "counts_per_step": {k: v // a.steps for k, v in agg.items()},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(a.workload, pts, mp)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,149 @@
+/*
+ * geomst — exact Euclidean minimum spanning trees and HDBSCAN* mutual
+ * reachability MSTs on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Wang, Yu, Gu, Shun, "Fast Parallel Algorithms for Euclidean Minimum
+ * Spanning Tree and Hierarchical Spatial Clustering" (SIGMOD 2021):
+ * a well-separated pair decomposition over a k-d tree (Sec. 3.1.1, Alg. 1),
+ * bichromatic closest pairs of the separated node pairs (Sec. 2.3), and a
+ * filtered Kruskal that takes the pairs in rounds of growing weight
+ * thresholds and materialises only the pairs a round needs (Sec. 3.1.2-3.1.3,
+ * Alg. 2-3).  HDBSCAN* uses core distances from k-NN queries and the
+ * "geometrically separated or mutually unreachable" separation of Sec. 3.2.2.
+ *
+ * Result definition (Sec. 2.1, "Problem Definitions"):
+ *   EMST      the minimum spanning tree of the complete graph on the points
+ *             with Euclidean edge weights.
+ *   HDBSCAN*  cd(p) = distance from p to its minPts-nearest neighbour
+ *             counting p itself; the MST of the complete graph weighted by
+ *             d_m(p,q) = max{cd(p), cd(q), d(p,q)}.
+ * Arithmetic: d(p,q)^2 is summed over the dimensions in order in IEEE
+ * binary64 without fused multiply-add.  Edges are totally ordered by
+ * K = (w^2, d^2, min id, max id) (w = d for EMST, w = d_m for HDBSCAN*), which
+ * makes the tree unique; the library returns exactly that tree.
+ *
+ * Conventions for every call:
+ *   - points are row-major float64 [n][d], 1 <= d <= 7, 1 <= n <= 2^26;
+ *   - edges[k] = {min id, max id} (0-based row indices), int64 [n-1][2],
+ *     sorted ascending by K; weights[k] = correctly rounded sqrt(w^2);
+ *   - the caller owns every buffer; the library keeps no pointer after a
+ *     call returns and allocates its own device scratch (kept per device and
+ *     reused across calls);
+ *   - calls on one device are serialised internally (thread-safe);
+ *   - return 0 on success or a negative GEOMST_E* code; on error the outputs
+ *     are unspecified and geomst_last_error() describes the failure.
+ */
+#ifndef GEOMST_H
+#define GEOMST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GEOMST_OK 0
+#define GEOMST_EINVAL (-1)   /* bad size, dimension, minPts or NULL pointer */
+#define GEOMST_EDOM (-2)     /* a coordinate is not finite or |x| > 2^500 */
+#define GEOMST_ENOMEM (-3)   /* device or host allocation failed */
+#define GEOMST_EDEVICE (-4)  /* a HIP runtime call failed */
+#define GEOMST_EINTERNAL (-8)/* an internal consistency check failed */
+
+/*
+ * Euclidean MST of host-resident points (Sec. 2.1, EMST).
+ *   points   [n][d] float64, host memory, read only
+ *   edges    [n-1][2] int64 out (host), sorted by K
+ *   weights  [n-1] float64 out (host), may be NULL
+ * n = 1 succeeds with no edges.  Uses device 0's default scratch and an
+ * internal stream; the copies to and from the device are included.
+ */
+int geomst_emst(const double* points, int64_t n, int32_t d, int64_t* edges, double* weights);
+
+/*
+ * HDBSCAN* core distances and mutual reachability MST of host-resident points
+ * (Sec. 2.1, HDBSCAN*; Sec. 3.2.2).
+ *   min_pts    1 <= min_pts <= min(n, 64)
+ *   core_dist  [n] float64 out (host), cd of each input row; may be NULL
+ *   edges      [n-1][2] int64 out (host), sorted by K = (w^2, d^2, min, max)
+ *   weights    [n-1] float64 out (host), mutual reachability distances; may be NULL
+ */
+int geomst_hdbscan(const double* points, int64_t n, int32_t d, int32_t min_pts, double* core_dist,
+                   int64_t* edges, double* weights);
+
+/*
+ * Device-pointer variants: every pointer is device memory on the current
+ * HIP device (all may come from torch tensors); work is queued on `stream`
+ * (a hipStream_t, NULL = the legacy default stream) and the call returns
+ * after the results are complete on that stream.  Optional outputs may be
+ * NULL:
+ *   d_weights_sq     [n-1] w^2 exactly as ordered;
+ *   d_core_dist_sq   [n]   cd^2.
+ */
+int geomst_emst_dev(const double* d_points, int64_t n, int32_t d, int64_t* d_edges, double* d_weights,
+                    double* d_weights_sq, void* stream);
+int geomst_hdbscan_dev(const double* d_points, int64_t n, int32_t d, int32_t min_pts, double* d_core_dist,
+                       double* d_core_dist_sq, int64_t* d_edges, double* d_weights, double* d_weights_sq,
+                       void* stream);
+
+/* Kernel families timed by the "kernel_timing" option (index into
+ * geomst_stats_t.kernel_ms / kernel_launches). */
+enum {
+    GEOMST_K_TREE = 0,     /* bounding box, Morton codes, permute, radix tree, node bounds */
+    GEOMST_K_SORT = 1,     /* radix-sort passes (Morton keys and edge keys) */
+    GEOMST_K_CORE = 2,     /* k-NN core distances */
+    GEOMST_K_SPLIT = 3,    /* frontier and pool splits */
+    GEOMST_K_EXPAND = 4,   /* pair expansion (FindPair) with inline small BCCPs */
+    GEOMST_K_BCCP = 5,     /* large-pair BCCP tiles and their combine */
+    GEOMST_K_KRUSKAL = 6,  /* Boruvka pick / hook / reset */
+    GEOMST_K_REFRESH = 7,  /* union-find compression and node components */
+    GEOMST_K_OUTPUT = 8,   /* output writes */
+    GEOMST_K_COUNT = 9
+};
+
+/* Counters and timings of the last solve made by the calling thread. */
+typedef struct {
+    int64_t n;
+    int32_t d;
+    int32_t min_pts;          /* 0 for EMST */
+    int64_t rounds;           /* filtered-Kruskal rounds (weight thresholds) */
+    int64_t pair_visits;      /* node pairs examined by the decomposition */
+    int64_t bccp_pairs;       /* separated pairs whose BCCP was computed */
+    int64_t bccp_evals;       /* point-pair distance evaluations inside BCCPs */
+    int64_t big_pairs;        /* of which solved by the large-pair kernel */
+    int64_t committed_edges;  /* edges handed to the Kruskal steps */
+    int64_t max_frontier;     /* most node pairs waiting between rounds */
+    double ms_total;          /* wall time of the call */
+    double ms_tree;           /* bounding box, Morton sort, tree, bounds */
+    double ms_core;           /* core distances (HDBSCAN*) */
+    double ms_rounds;         /* all rounds */
+    double ms_final;          /* output sort and write */
+    int64_t big_evals;        /* distance evaluations in the large-pair kernel */
+    int64_t sort_elems;       /* elements x 8-bit passes moved by the radix sorts */
+    double kernel_ms[16];     /* device time per kernel family (kernel_timing on) */
+    int64_t kernel_launches[16];
+} geomst_stats_t;
+
+int geomst_get_stats(geomst_stats_t* out);
+
+/*
+ * Tuning knobs (they never change the result):
+ *   "beta_growth"    factor applied to the weight threshold between rounds
+ *                    (default 2: the threshold doubles each round), must be > 1.
+ *   "kernel_timing"  1 = bracket every kernel family launch with HIP events on
+ *                    the solve's stream and report device times in
+ *                    geomst_stats_t.kernel_ms; 0 = off (default).
+ * Returns GEOMST_EINVAL for an unknown name or a bad value.
+ */
+int geomst_set_option(const char* name, double value);
+
+/* Thread-local description of the last error (empty string if none). */
+const char* geomst_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int geomst_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEOMST_H */

@@ -1,0 +1,32 @@
+// Internal interface between the geomst orchestration and its generic
+// primitives (scan, radix sort) which live in their own translation unit.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace geomst {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+// Scratch bytes needed by the scans / sorts below for `count` elements.
+size_t scan_temp_bytes(size_t count);
+size_t radix_temp_bytes(size_t count);
+
+void scan_exclusive_u32(const u32* in, u32* out, size_t count, void* temp, hipStream_t s);
+void scan_inclusive_u32(const u32* in, u32* out, size_t count, void* temp, hipStream_t s);
+
+// Stable LSD sort of (key, val) pairs on key bits [0, bits).  Ping-pongs
+// between (key, val) and (key2, val2); returns 1 when the sorted result ends
+// in (key2, val2) and 0 when it ends in (key, val).
+int radix_sort_pairs(u64* key, u32* val, u64* key2, u32* val2, size_t count, int bits, void* temp,
+                     hipStream_t s);
+
+// One stable LSD pass group: reorders the permutation idx by bits [0, bits)
+// of w[idx[i]].  Ping-pongs between idx and idx2; returns 1 when the result
+// ends in idx2.
+int radix_sort_index(const u64* w, u32* idx, u32* idx2, size_t count, int bits, void* temp,
+                     hipStream_t s);
+
+}  // namespace geomst

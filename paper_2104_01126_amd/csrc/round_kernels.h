@@ -1,0 +1,827 @@
+// One round of the filtered Kruskal over the well-separated pair
+// decomposition (paper Sec. 3.1.2-3.1.3, Alg. 1-3, and Sec. 3.2.2):
+//
+//   * node pairs whose weight lower bound is at most beta are expanded as in
+//     FindPair: a well-separated pair yields its bichromatic closest pair
+//     (BCCP, or BCCP* under mutual reachability); otherwise the node with the
+//     larger bounding sphere is split;
+//   * pairs whose points are already in one component are dropped (the
+//     union-find filter);
+//   * pairs whose lower bound exceeds beta wait in a frontier for a later
+//     round, BCCP edges heavier than beta wait in a pool;
+//   * the edges of weight at most beta are merged into the spanning forest
+//     in key order (Kruskal's rule, done as Boruvka steps on the key ranks).
+//
+// Every bound used to schedule or prune is computed with the same operation
+// order as the distances it bounds, so it never crosses a computed distance:
+// rounding is monotone, hence fl(lo_B - hi_A) <= fl(|b - a|) per dimension and
+// the sums keep the order.
+#pragma once
+#include "common.h"
+#include "tree_kernels.h"
+
+namespace geomst {
+
+enum CounterSlot {
+    C_QN = 0,  // next expansion queue
+    C_Q,       // queue produced by the frontier split
+    C_F,       // frontier out
+    C_C,       // committed edges
+    C_P,       // pool out
+    C_BIG,     // pairs for the large-pair BCCP kernel
+    C_OUT,     // spanning-tree edges found so far
+    C_ALIVE,   // Boruvka: edges still undecided after this step
+    C_ERR,     // device-side error flags
+    C_NUM
+};
+enum CounterSlot64 { C64_EVALS = 0, C64_VISITS, C64_BCCP, C64_BIGEVALS, C64_NUM };
+enum MinSlot { M_F = 0, M_P, M_NUM };
+
+struct Counters {
+    u32 c[16];
+    unsigned long long c64[4];
+    u64 m[4];  // bit patterns of non-negative doubles (all ones = none)
+};
+
+struct PairRec {
+    u32 a, b;
+    double lb2;  // lower bound of the pair's edge weights (squared)
+};
+
+struct EdgeList {
+    double* w2;
+    double* e2;
+    u64* ids;  // (lo << 32) | hi, caller row indices
+    u64* pos;  // (sorted position i << 32) | sorted position j of the two ends
+};
+
+struct RoundArgs {
+    Counters* cnt;
+    double beta2;
+    const u32* uf;  // sorted position -> component root (fully compressed)
+    PairRec* fout;
+    u32 cap_f;
+    PairRec* q;
+    u32 cap_q;
+    uint2* big;
+    u32 cap_big;
+    EdgeList c;
+    u32 cap_c;
+    EdgeList pout;
+    u32 cap_p;
+};
+
+constexpr int kTinyEvals = 16;   // pairs with at most this many point pairs are solved inline
+constexpr int kStackDepth = 16;  // per-lane DFS stack in LDS
+constexpr int kMaxSteps = 64;    // pairs one lane expands before spilling its stack
+
+// ------------------------------------------------------------ bounds
+template <int D>
+__device__ __forceinline__ double box_lb2(const double* A, const double* B) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double g = fmax(fmax(B[k] - A[D + k], A[k] - B[D + k]), 0.0);
+        s = s + g * g;
+    }
+    return s;
+}
+
+template <int D>
+__device__ __forceinline__ double box_diag2(const double* A) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double t = A[D + k] - A[k];
+        s = s + t * t;
+    }
+    return s;
+}
+
+template <int D>
+__device__ __forceinline__ double pair_wlb2(const TreeView& t, int hdb, u32 a, u32 b) {
+    double l = box_lb2<D>(t.box + (size_t)a * 2 * D, t.box + (size_t)b * 2 * D);
+    if (hdb) l = fmax(l, fmax(t.cdb[a].x, t.cdb[b].x));
+    return l;
+}
+
+__device__ __forceinline__ bool connected(const TreeView& t, u32 a, u32 b) {
+    int ca = t.comp[a];
+    return ca >= 0 && ca == t.comp[b];
+}
+
+// Well-separation test.  Geometric (Sec. 2.3, s = 2, in the form of
+// Sec. 3.2.2): the gap between the bounding spheres is at least the larger
+// sphere diameter.  For HDBSCAN* also mutual unreachability (Sec. 3.2.2):
+// max(gap, cdmin A, cdmin B) >= max(diam A, diam B, cdmax A, cdmax B).
+// Both are taken together with a strict guard on computed values (largest
+// intra-node distance bound below the inter-node bound) which makes the
+// BCCP edge of each pair contain the tree's edge exactly; a pair of two
+// single points is always separated.
+template <int D>
+__device__ __forceinline__ bool well_separated(const TreeView& t, int hdb, u32 a, u32 b, int ca, int cb) {
+    if (ca == 1 && cb == 1) return true;
+    const double* A = t.box + (size_t)a * 2 * D;
+    const double* B = t.box + (size_t)b * 2 * D;
+    double L = box_lb2<D>(A, B);
+    double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
+    double ra = t.rad[a], rb = t.rad[b];
+    double c2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double x = 0.5 * (A[k] + A[D + k]) - 0.5 * (B[k] + B[D + k]);
+        c2 = c2 + x * x;
+    }
+    double need = ra + rb + 2.0 * fmax(ra, rb);
+    bool geo = (fmax(dA, dB) < L) && (c2 >= need * need);
+    if (geo || !hdb) return geo;
+    double2 ka = t.cdb[a], kb = t.cdb[b];
+    double gap = fmax(sqrt(c2) - ra - rb, 0.0);
+    double lhs_s = fmax(fmax(4.0 * ra * ra, 4.0 * rb * rb), fmax(ka.y, kb.y));
+    double rhs_s = fmax(gap * gap, fmax(ka.x, kb.x));
+    double lhs = fmax(fmax(dA, dB), fmax(ka.y, kb.y));
+    double rhs = fmax(L, fmax(ka.x, kb.x));
+    return (rhs_s >= lhs_s) && (lhs < rhs);
+}
+
+// ------------------------------------------------------------ edges
+struct EdgeOut {
+    EKey k;
+    u32 i, j;  // sorted positions
+};
+
+template <int D>
+__device__ __forceinline__ EdgeOut point_edge(const TreeView& t, int hdb, u32 i, u32 j) {
+    EdgeOut o;
+    double e2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double x = t.X[(size_t)i * D + k] - t.X[(size_t)j * D + k];
+        e2 = e2 + x * x;
+    }
+    double w2 = e2;
+    if (hdb) w2 = fmax(fmax(t.cd2[i], t.cd2[j]), e2);
+    u32 oi = t.orig[i], oj = t.orig[j];
+    o.k.w2 = w2;
+    o.k.e2 = e2;
+    o.k.lo = oi < oj ? oi : oj;
+    o.k.hi = oi < oj ? oj : oi;
+    o.i = i;
+    o.j = j;
+    return o;
+}
+
+__device__ __forceinline__ void put_edge(EdgeList L, u32 s, const EdgeOut& e) {
+    L.w2[s] = e.k.w2;
+    L.e2[s] = e.k.e2;
+    L.ids[s] = ((u64)e.k.lo << 32) | e.k.hi;
+    L.pos[s] = ((u64)e.i << 32) | e.j;
+}
+
+__device__ __forceinline__ void put_edge_raw(EdgeList L, u32 s, double w2, double e2, u64 ids, u64 pos) {
+    L.w2[s] = w2;
+    L.e2[s] = e2;
+    L.ids[s] = ids;
+    L.pos[s] = pos;
+}
+
+__device__ __forceinline__ void flag_overflow(Counters* cnt) { atomicOr(&cnt->c[C_ERR], 1u); }
+
+// ------------------------------------------------------------ frontier
+// Initial frontier: the two children of every internal node (Alg. 1, Wspd).
+template <int D>
+__global__ void k_init_frontier(TreeView t, int hdb, PairRec* f) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= t.n - 1) return;
+    int2 c = t.kids[i];
+    PairRec p;
+    p.a = (u32)c.x;
+    p.b = (u32)c.y;
+    p.lb2 = pair_wlb2<D>(t, hdb, p.a, p.b);
+    f[i] = p;
+}
+
+// Smallest positive lower bound over a pair list (the first beta).
+__global__ void k_min_positive_lb(const PairRec* f, u32 nf, Counters* cnt) {
+    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v = __longlong_as_double(0x7ff0000000000000ll);
+    if (i < nf && f[i].lb2 > 0.0) v = f[i].lb2;
+    v = wave_min_f64(v);
+    if (lane_id() == 0 && v < __longlong_as_double(0x7ff0000000000000ll)) atomic_min_pos_f64(&cnt->m[M_F], v);
+}
+
+// Frontier split: drop connected pairs, queue the due ones, keep the rest.
+__global__ void __launch_bounds__(256) k_split_frontier(TreeView t, RoundArgs r, const PairRec* fin, u32 nfin) {
+    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool have = i < nfin;
+    PairRec p;
+    p.a = p.b = 0;
+    p.lb2 = 0.0;
+    if (have) p = fin[i];
+    bool keep = have && !connected(t, p.a, p.b);
+    bool due = keep && p.lb2 <= r.beta2;
+    bool wait = keep && !due;
+    u32 s = wave_append(&r.cnt->c[C_Q], due);
+    if (due) {
+        if (s < r.cap_q) r.q[s] = p;
+        else flag_overflow(r.cnt);
+    }
+    s = wave_append(&r.cnt->c[C_F], wait);
+    if (wait) {
+        if (s < r.cap_f) r.fout[s] = p;
+        else flag_overflow(r.cnt);
+    }
+    double m = wait ? p.lb2 : __longlong_as_double(0x7ff0000000000000ll);
+    m = wave_min_f64(m);
+    if (lane_id() == 0 && m < __longlong_as_double(0x7ff0000000000000ll)) atomic_min_pos_f64(&r.cnt->m[M_F], m);
+}
+
+// ------------------------------------------------------------ expansion
+// One lane per queued pair; each lane walks the pair's FindPair recursion
+// depth-first with a small stack in LDS, solving tiny separated pairs inline
+// and emitting larger ones to the large-pair list.  After kMaxSteps pairs, or
+// when the stack is full, remaining work is spilled to the next queue.
+template <int D>
+__global__ void __launch_bounds__(256) k_expand(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 nq) {
+    __shared__ u64 stk[kStackDepth][256];
+    const int tid = threadIdx.x;
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    u32 gi = blockIdx.x * blockDim.x + tid;
+    int sp = 0;
+    if (gi < nq) {
+        PairRec p = qin[gi];
+        stk[0][tid] = ((u64)p.a << 32) | p.b;
+        sp = 1;
+    }
+    double minf = inf, minp = inf;
+    unsigned long long visits = 0, evals = 0, solved = 0;
+    for (int step = 0; step < kMaxSteps; ++step) {
+        bool have = sp > 0;
+        if (!__any(have)) break;
+        u32 a = 0, b = 0;
+        if (have) {
+            --sp;
+            u64 pr = stk[sp][tid];
+            a = (u32)(pr >> 32);
+            b = (u32)pr;
+        }
+        bool to_c = false, to_p = false, to_big = false;
+        EdgeOut e;
+        u32 ch[2] = {0, 0}, oth = 0;
+        bool ch_front[2] = {false, false}, ch_spill[2] = {false, false};
+        double ch_lb[2] = {0.0, 0.0};
+        if (have) {
+            ++visits;
+            int2 ra = t.rng[a], rb = t.rng[b];
+            if (well_separated<D>(t, hdb, a, b, ra.y, rb.y)) {
+                u64 work = (u64)ra.y * (u64)rb.y;
+                if (work <= (u64)kTinyEvals) {
+                    e = point_edge<D>(t, hdb, (u32)ra.x, (u32)rb.x);
+                    for (int i = ra.x; i < ra.x + ra.y; ++i)
+                        for (int j = rb.x; j < rb.x + rb.y; ++j) {
+                            EdgeOut c = point_edge<D>(t, hdb, (u32)i, (u32)j);
+                            if (key_less(c.k, e.k)) e = c;
+                        }
+                    evals += work;
+                    ++solved;
+                    to_c = e.k.w2 <= r.beta2;
+                    to_p = !to_c;
+                    if (to_p) minp = fmin(minp, e.k.w2);
+                } else {
+                    to_big = true;
+                }
+            } else {
+                // split the node with the larger bounding sphere (Alg. 1, FindPair)
+                bool split_a = (rb.y == 1) || (ra.y > 1 && (t.rad[a] > t.rad[b] ||
+                                                            (t.rad[a] == t.rad[b] && ra.y >= rb.y)));
+                u32 x = split_a ? a : b;
+                oth = split_a ? b : a;
+                int2 kk = t.kids[x];
+                ch[0] = (u32)kk.x;
+                ch[1] = (u32)kk.y;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    if (connected(t, ch[c], oth)) continue;
+                    double lb = pair_wlb2<D>(t, hdb, ch[c], oth);
+                    ch_lb[c] = lb;
+                    if (lb > r.beta2) {
+                        ch_front[c] = true;
+                        minf = fmin(minf, lb);
+                    } else if (sp < kStackDepth) {
+                        stk[sp][tid] = ((u64)ch[c] << 32) | oth;
+                        ++sp;
+                    } else {
+                        ch_spill[c] = true;
+                    }
+                }
+            }
+        }
+        // appends (all lanes of the wave take part)
+        u32 s = wave_append(&r.cnt->c[C_C], to_c);
+        if (to_c) {
+            if (s < r.cap_c) put_edge(r.c, s, e);
+            else flag_overflow(r.cnt);
+        }
+        s = wave_append(&r.cnt->c[C_P], to_p);
+        if (to_p) {
+            if (s < r.cap_p) put_edge(r.pout, s, e);
+            else flag_overflow(r.cnt);
+        }
+        s = wave_append(&r.cnt->c[C_BIG], to_big);
+        if (to_big) {
+            if (s < r.cap_big) r.big[s] = make_uint2(a, b);
+            else flag_overflow(r.cnt);
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            s = wave_append(&r.cnt->c[C_F], ch_front[c]);
+            if (ch_front[c]) {
+                if (s < r.cap_f) {
+                    PairRec p;
+                    p.a = ch[c];
+                    p.b = oth;
+                    p.lb2 = ch_lb[c];
+                    r.fout[s] = p;
+                } else {
+                    flag_overflow(r.cnt);
+                }
+            }
+            s = wave_append(&r.cnt->c[C_QN], ch_spill[c]);
+            if (ch_spill[c]) {
+                if (s < r.cap_q) {
+                    PairRec p;
+                    p.a = ch[c];
+                    p.b = oth;
+                    p.lb2 = ch_lb[c];
+                    r.q[s] = p;
+                } else {
+                    flag_overflow(r.cnt);
+                }
+            }
+        }
+    }
+    // spill what is left on the stacks
+    for (int i = 0; i < kStackDepth; ++i) {
+        bool sp_i = i < sp;
+        if (!__any(sp_i)) break;
+        u32 s = wave_append(&r.cnt->c[C_QN], sp_i);
+        if (sp_i) {
+            if (s < r.cap_q) {
+                u64 pr = stk[i][tid];
+                PairRec p;
+                p.a = (u32)(pr >> 32);
+                p.b = (u32)pr;
+                p.lb2 = 0.0;  // already known to be due
+                r.q[s] = p;
+            } else {
+                flag_overflow(r.cnt);
+            }
+        }
+    }
+    minf = wave_min_f64(minf);
+    minp = wave_min_f64(minp);
+    for (int o = 32; o > 0; o >>= 1) {
+        visits += __shfl_xor(visits, o);
+        evals += __shfl_xor(evals, o);
+        solved += __shfl_xor(solved, o);
+    }
+    if (lane_id() == 0) {
+        if (minf < inf) atomic_min_pos_f64(&r.cnt->m[M_F], minf);
+        if (minp < inf) atomic_min_pos_f64(&r.cnt->m[M_P], minp);
+        atomicAdd(&r.cnt->c64[C64_VISITS], visits);
+        atomicAdd(&r.cnt->c64[C64_EVALS], evals);
+        atomicAdd(&r.cnt->c64[C64_BCCP], solved);
+    }
+}
+
+// ------------------------------------------------------------ large pairs
+// A large separated pair is cut into tasks of up to kBigA points of the
+// larger node (two per lane) by up to kBigB points of the other; one wave per
+// task.  B points are staged in LDS 64 at a time and broadcast to all lanes;
+// the inner loop keeps only the running minimum weight per lane, and the
+// exact key (w2, e2, ids) is resolved afterwards by rescanning the few lanes
+// that hold the minimum.  Per-task partial keys are then combined per pair.
+constexpr int kBigA = 128;
+constexpr int kBigB = 2048;
+
+struct PartKey {
+    double w2, e2;
+    u64 ids, pos;
+};
+
+__device__ __forceinline__ void big_orient(const TreeView& t, uint2 pr, int2& ra, int2& rb) {
+    ra = t.rng[pr.x];
+    rb = t.rng[pr.y];
+    if (rb.y > ra.y) {
+        int2 x = ra;
+        ra = rb;
+        rb = x;
+    }
+}
+
+__global__ void k_big_ntasks(TreeView t, const uint2* big, u32 nbig, u32* ntask) {
+    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nbig) return;
+    int2 ra, rb;
+    big_orient(t, big[i], ra, rb);
+    ntask[i] = (u32)(((ra.y + kBigA - 1) / kBigA) * ((rb.y + kBigB - 1) / kBigB));
+}
+
+template <int D, int HDB>
+__global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u32 nbig, const u32* toff,
+                                                  PartKey* part, Counters* cnt) {
+    __shared__ double sb[64 * D];
+    __shared__ double scd[64];
+    const int lane = lane_id();
+    const u32 task = blockIdx.x;
+    // pair owning this task: last i with toff[i] <= task
+    u32 lo = 0, hi = nbig - 1;
+    while (lo < hi) {
+        u32 mid = (lo + hi + 1) >> 1;
+        if (toff[mid] <= task) lo = mid;
+        else hi = mid - 1;
+    }
+    int2 ra, rb;
+    big_orient(t, big[lo], ra, rb);
+    u32 local = task - toff[lo];
+    int nbt = (rb.y + kBigB - 1) / kBigB;
+    int ta = (int)(local / (u32)nbt), tb = (int)(local % (u32)nbt);
+    int aend = ra.x + ra.y;
+    int a0 = ra.x + ta * kBigA + lane, a1 = a0 + 64;
+    bool v0 = a0 < aend, v1 = a1 < aend;
+    int a0c = v0 ? a0 : ra.x, a1c = v1 ? a1 : ra.x;
+    double p0[D], p1[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        p0[k] = t.X[(size_t)a0c * D + k];
+        p1[k] = t.X[(size_t)a1c * D + k];
+    }
+    double c0 = HDB ? t.cd2[a0c] : 0.0, c1 = HDB ? t.cd2[a1c] : 0.0;
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    double m0 = inf, m1 = inf;
+    int jb0 = rb.x + tb * kBigB;
+    int jb1 = min(jb0 + kBigB, rb.x + rb.y);
+    for (int js = jb0; js < jb1; js += 64) {
+        int cntb = min(64, jb1 - js);
+        if (lane < cntb) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) sb[lane * D + k] = t.X[(size_t)(js + lane) * D + k];
+            if (HDB) scd[lane] = t.cd2[js + lane];
+        }
+        __syncthreads();
+        for (int j = 0; j < cntb; ++j) {
+            double q[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) q[k] = sb[j * D + k];
+            double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                double x0 = p0[k] - q[k];
+                double x1 = p1[k] - q[k];
+                d0 = d0 + x0 * x0;
+                d1 = d1 + x1 * x1;
+            }
+            if (HDB) {
+                double cb = scd[j];
+                d0 = fmax(fmax(c0, cb), d0);
+                d1 = fmax(fmax(c1, cb), d1);
+            }
+            m0 = fmin(m0, d0);
+            m1 = fmin(m1, d1);
+        }
+        __syncthreads();
+    }
+    double m = fmin(v0 ? m0 : inf, v1 ? m1 : inf);
+    double M = wave_min_f64(m);
+    // exact key among the entries that reach the minimum weight
+    EdgeOut best;
+    best.k = key_none();
+    best.i = best.j = kNone;
+    for (int r = 0; r < 2; ++r) {
+        bool mine = r == 0 ? (v0 && m0 == M) : (v1 && m1 == M);
+        if (!mine) continue;
+        u32 ai = (u32)(r == 0 ? a0 : a1);
+        for (int j = jb0; j < jb1; ++j) {
+            EdgeOut c = point_edge<D>(t, HDB, ai, (u32)j);
+            if (c.k.w2 == M && key_less(c.k, best.k)) best = c;
+        }
+    }
+    // wave minimum of the exact keys (carrying the positions)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        EdgeOut w;
+        w.k.w2 = __shfl_xor(best.k.w2, o);
+        w.k.e2 = __shfl_xor(best.k.e2, o);
+        w.k.lo = __shfl_xor(best.k.lo, o);
+        w.k.hi = __shfl_xor(best.k.hi, o);
+        w.i = __shfl_xor(best.i, o);
+        w.j = __shfl_xor(best.j, o);
+        if (key_less(w.k, best.k)) best = w;
+    }
+    if (lane == 0) {
+        PartKey pk;
+        pk.w2 = best.k.w2;
+        pk.e2 = best.k.e2;
+        pk.ids = ((u64)best.k.lo << 32) | best.k.hi;
+        pk.pos = ((u64)best.i << 32) | best.j;
+        part[task] = pk;
+        int na = min(kBigA, aend - (ra.x + ta * kBigA));
+        unsigned long long ev = (unsigned long long)na * (unsigned long long)(jb1 - jb0);
+        atomicAdd(&cnt->c64[C64_EVALS], ev);
+        atomicAdd(&cnt->c64[C64_BIGEVALS], ev);
+    }
+}
+
+__global__ void k_big_combine(RoundArgs r, u32 nbig, const u32* toff, const u32* ntask, const PartKey* part) {
+    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool have = i < nbig;
+    PartKey b;
+    b.w2 = __longlong_as_double(0x7ff0000000000000ll);
+    b.e2 = b.w2;
+    b.ids = ~0ull;
+    b.pos = 0;
+    if (have) {
+        u32 o = toff[i], c = ntask[i];
+        b = part[o];
+        for (u32 k = 1; k < c; ++k) {
+            PartKey x = part[o + k];
+            bool less = (x.w2 != b.w2) ? (x.w2 < b.w2) : (x.e2 != b.e2) ? (x.e2 < b.e2) : (x.ids < b.ids);
+            if (less) b = x;
+        }
+    }
+    bool to_c = have && b.w2 <= r.beta2;
+    bool to_p = have && !to_c;
+    u32 s = wave_append(&r.cnt->c[C_C], to_c);
+    if (to_c) {
+        if (s < r.cap_c) put_edge_raw(r.c, s, b.w2, b.e2, b.ids, b.pos);
+        else flag_overflow(r.cnt);
+    }
+    s = wave_append(&r.cnt->c[C_P], to_p);
+    if (to_p) {
+        if (s < r.cap_p) put_edge_raw(r.pout, s, b.w2, b.e2, b.ids, b.pos);
+        else flag_overflow(r.cnt);
+    }
+    double m = to_p ? b.w2 : __longlong_as_double(0x7ff0000000000000ll);
+    m = wave_min_f64(m);
+    if (lane_id() == 0 && m < __longlong_as_double(0x7ff0000000000000ll)) atomic_min_pos_f64(&r.cnt->m[M_P], m);
+}
+
+// ------------------------------------------------------------ pool split
+// Deferred BCCP edges: drop the ones whose ends are now connected, commit
+// those within the new beta, keep the rest.
+__global__ void __launch_bounds__(256) k_split_pool(RoundArgs r, EdgeList pin, u32 npin) {
+    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool have = i < npin;
+    double w2 = 0.0, e2 = 0.0;
+    u64 ids = 0, pos = 0;
+    bool keep = false;
+    if (have) {
+        pos = pin.pos[i];
+        keep = r.uf[(u32)(pos >> 32)] != r.uf[(u32)pos];
+        if (keep) {
+            w2 = pin.w2[i];
+            e2 = pin.e2[i];
+            ids = pin.ids[i];
+        }
+    }
+    bool to_c = keep && w2 <= r.beta2;
+    bool to_p = keep && !to_c;
+    u32 s = wave_append(&r.cnt->c[C_C], to_c);
+    if (to_c) {
+        if (s < r.cap_c) put_edge_raw(r.c, s, w2, e2, ids, pos);
+        else flag_overflow(r.cnt);
+    }
+    s = wave_append(&r.cnt->c[C_P], to_p);
+    if (to_p) {
+        if (s < r.cap_p) put_edge_raw(r.pout, s, w2, e2, ids, pos);
+        else flag_overflow(r.cnt);
+    }
+    double m = to_p ? w2 : __longlong_as_double(0x7ff0000000000000ll);
+    m = wave_min_f64(m);
+    if (lane_id() == 0 && m < __longlong_as_double(0x7ff0000000000000ll)) atomic_min_pos_f64(&r.cnt->m[M_P], m);
+}
+
+// ------------------------------------------------------------ Kruskal
+// Sort keys: ids packed tight as (lo << B) | hi, then e2 and w2 bit patterns
+// (non-negative doubles order like their bits).
+__global__ void k_sortkeys(const EdgeList L, u32 m, int B, u64* kid, u64* ke2, u64* kw2, u32* perm) {
+    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    u64 ids = L.ids[i];
+    kid[i] = ((ids >> 32) << B) | (ids & 0xffffffffull);
+    if (ke2) ke2[i] = dbits(L.e2[i]);
+    kw2[i] = dbits(L.w2[i]);
+    perm[i] = i;
+}
+
+__global__ void k_iota(u32* a, u32 m) {
+    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) a[i] = i;
+}
+
+constexpr int kFindCap = 1 << 22;  // bound on union-find walks (never reached by a forest)
+
+__device__ __forceinline__ u32 uf_find(u32* parent, u32 x, Counters* cnt) {
+    // path halving; every write points a vertex at one of its ancestors
+    for (int it = 0; it < kFindCap; ++it) {
+        u32 p = parent[x];
+        if (p == x) return x;
+        u32 g = parent[p];
+        if (g != p) parent[x] = g;
+        x = g;
+    }
+    atomicOr(&cnt->c[C_ERR], 8u);
+    return x;
+}
+
+// Boruvka step on the committed edges in key-rank order: every component
+// picks its lightest incident edge (atomic minimum of the rank); all picked
+// edges are tree edges by the cut property; components hook along them.
+__global__ void k_bor_pick(const u32* alive, const u32* nalive_p, const u32* perm, const EdgeList L, u32* parent,
+                           u32* best, u32* ru, u32* rv, Counters* cnt) {
+    u32 s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= *nalive_p) return;
+    u32 rank = alive[s];
+    u64 pos = L.pos[perm[rank]];
+    u32 a = uf_find(parent, (u32)(pos >> 32), cnt);
+    u32 b = uf_find(parent, (u32)pos, cnt);
+    if (a == b) {
+        ru[s] = kNone;
+        return;
+    }
+    ru[s] = a;
+    rv[s] = b;
+    atomicMin(&best[a], rank);
+    atomicMin(&best[b], rank);
+}
+
+__global__ void k_bor_hook(const u32* alive, const u32* nalive_p, const u32* perm, const EdgeList L, u32* parent,
+                           const u32* best, const u32* ru, const u32* rv, u32* alive_next, u32* nalive_next,
+                           EdgeList out, u32 cap_out, Counters* cnt) {
+    u32 s = blockIdx.x * blockDim.x + threadIdx.x;
+    u32 na = *nalive_p;
+    bool have = s < na;
+    u32 a = have ? ru[s] : kNone;
+    bool live = have && a != kNone;
+    bool sel = false, keep = false;
+    u32 rank = 0, e = 0;
+    if (live) {
+        u32 b = rv[s];
+        rank = alive[s];
+        bool pa = best[a] == rank, pb = best[b] == rank;
+        sel = pa || pb;
+        keep = !sel;
+        if (sel) {
+            e = perm[rank];
+            if (pa && pb) {
+                u32 hi = a > b ? a : b, lo = a > b ? b : a;
+                parent[hi] = lo;
+            } else if (pa) {
+                parent[a] = b;
+            } else {
+                parent[b] = a;
+            }
+        }
+    }
+    u32 o = wave_append(&cnt->c[C_OUT], sel);
+    if (sel) {
+        if (o < cap_out) put_edge_raw(out, o, L.w2[e], L.e2[e], L.ids[e], L.pos[e]);
+        else flag_overflow(cnt);
+    }
+    u32 k = wave_append(nalive_next, keep);
+    if (keep) alive_next[k] = rank;
+}
+
+__global__ void k_bor_reset(const u32* nalive_p, const u32* ru, const u32* rv, u32* best) {
+    u32 s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= *nalive_p) return;
+    u32 a = ru[s];
+    if (a == kNone) return;
+    best[a] = kNone;
+    best[rv[s]] = kNone;
+}
+
+__global__ void k_set_u32(u32* p, u32 v) { *p = v; }
+
+// Full path compression: afterwards parent[v] is v's component root.
+__global__ void k_uf_compress(u32* parent, int n, Counters* cnt) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    u32 r = (u32)v;
+    int it = 0;
+    while (parent[r] != r && it < kFindCap) {
+        r = parent[r];
+        ++it;
+    }
+    if (it == kFindCap) atomicOr(&cnt->c[C_ERR], 8u);
+    parent[v] = r;
+}
+
+// Component of each node: the root shared by all its points, else -1.
+__global__ void k_boundaries(const u32* uf, int n, u32* bnd) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    bnd[p] = (p > 0 && uf[p] != uf[p - 1]) ? 1u : 0u;
+}
+
+__global__ void k_node_comp(const int2* rng, const u32* uf, const u32* incl, int nn, int* comp) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nn) return;
+    int2 r = rng[v];
+    int last = r.x + r.y - 1;
+    comp[v] = (incl[last] == incl[r.x]) ? (int)uf[r.x] : -1;
+}
+
+// ------------------------------------------------------------ output
+// Correctly rounded square root.  The library result y is checked against
+// the exact condition lo^2 < x < hi^2, where lo and hi are the midpoints
+// between y and its neighbouring binary64 values (a binary64 square root is
+// never exactly halfway), using 128-bit integer arithmetic on the
+// significands, and moved by one unit in the last place until it holds.
+//
+// Sign of (M * 2^e)^2 - x for an integer M < 2^56 and a normal x > 0.
+__device__ __forceinline__ int cmp_sq(u64 M, int e, double x) {
+    int ex;
+    double fx = frexp(x, &ex);
+    u64 X = (u64)ldexp(fx, 53);  // x = X * 2^(ex-53)
+    unsigned __int128 S = (unsigned __int128)M * (unsigned __int128)M;  // value S * 2^(2e)
+    int sh = (ex - 53) - 2 * e;  // compare S with X * 2^sh
+    if (sh >= 0) {
+        if (sh > 70) return -1;  // X * 2^sh >= 2^123 > S
+        unsigned __int128 R = (unsigned __int128)X << sh;
+        return S > R ? 1 : (S < R ? -1 : 0);
+    }
+    int s2 = -sh;
+    if (s2 >= 120) return -1;  // S * 2^-s2 < 1 <= X
+    unsigned __int128 S2 = S >> s2;
+    unsigned __int128 lost = S - (S2 << s2);
+    unsigned __int128 R = (unsigned __int128)X;
+    if (S2 > R) return 1;
+    if (S2 < R) return -1;
+    return lost ? 1 : 0;
+}
+
+__device__ double sqrt_rn(double x) {
+    if (!(x > 0.0)) return x == 0.0 ? 0.0 : x;
+    // subnormal inputs: scale by 2^108 (exact), root scales by 2^54
+    double scale = 1.0;
+    if (x < 2.2250738585072014e-308) {
+        x = ldexp(x, 108);
+        scale = ldexp(1.0, -54);
+    }
+    double y = sqrt(x);
+    for (int it = 0; it < 4; ++it) {
+        int ey;
+        double fy = frexp(y, &ey);
+        u64 Y = (u64)ldexp(fy, 53);  // y = Y * 2^(ey-53), Y in [2^52, 2^53)
+        // upper midpoint (2Y+1) * 2^(ey-54)
+        if (cmp_sq(2 * Y + 1, ey - 54, x) < 0) {
+            y = nextafter(y, __longlong_as_double(0x7ff0000000000000ll));
+            continue;
+        }
+        // lower midpoint: (4Y-1) * 2^(ey-55) when y is a power of two, else (2Y-1) * 2^(ey-54)
+        bool pow2 = Y == (1ull << 52);
+        int c = pow2 ? cmp_sq(4 * Y - 1, ey - 55, x) : cmp_sq(2 * Y - 1, ey - 54, x);
+        if (c > 0) {
+            y = nextafter(y, 0.0);
+            continue;
+        }
+        break;
+    }
+    return y * scale;
+}
+
+__global__ void k_write_edges(const EdgeList L, const u32* perm, u32 m, long long* edges, double* w, double* w2) {
+    u32 k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    u32 e = perm[k];
+    u64 ids = L.ids[e];
+    edges[2 * (size_t)k] = (long long)(ids >> 32);
+    edges[2 * (size_t)k + 1] = (long long)(ids & 0xffffffffull);
+    double x = L.w2[e];
+    if (w) w[k] = sqrt_rn(x);
+    if (w2) w2[k] = x;
+}
+
+__global__ void k_write_cd(const double* cd2s, const u32* orig, int n, double* cd, double* cd2) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    u32 o = orig[p];
+    double x = cd2s[p];
+    if (cd) cd[o] = sqrt_rn(x);
+    if (cd2) cd2[o] = x;
+}
+
+// Input check: non-finite coordinates or |x| > 2^500 (keeps every squared
+// distance finite).
+__global__ void k_check_input(const double* P, size_t m, Counters* cnt) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    for (; i < m; i += (size_t)gridDim.x * blockDim.x) {
+        double x = P[i];
+        bad |= !(fabs(x) <= 3.273390607896142e150);  // 2^500; false for NaN
+    }
+    if (__any(bad) && lane_id() == 0) atomicOr(&cnt->c[C_ERR], 2u);
+}
+
+}  // namespace geomst

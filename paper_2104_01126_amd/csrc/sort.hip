@@ -1,0 +1,252 @@
+// Generic device primitives: prefix sums and stable LSD radix sorts (gfx950).
+//
+// The radix sort is the classic three-step pass (per-tile digit histograms,
+// an exclusive scan of the digit-major histogram table, a stable scatter).
+// Stability inside a tile comes from processing the tile in (iteration,
+// wave, lane) order, which is the element order, and ranking equal digits
+// inside a wave with ballots.
+#include <hip/hip_runtime.h>
+#include "internal.h"
+#include "common.h"
+
+namespace geomst {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 8;
+constexpr int kTile = kThreads * kItems;  // 2048 elements per block
+constexpr int kWaves = kThreads / kWave;
+
+inline size_t cdiv(size_t a, size_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- scan
+__device__ __forceinline__ u32 wave_incl_scan(u32 v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        u32 t = __shfl_up(v, o);
+        if (lane_id() >= o) v += t;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread; returns the block total.
+__device__ __forceinline__ u32 block_excl_scan(u32 v, u32* total) {
+    __shared__ u32 wsum[kWaves];
+    u32 inc = wave_incl_scan(v);
+    int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    u32 off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+        u32 s = wsum[i];
+        off += (i < w) ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ void __launch_bounds__(kThreads) k_scan_reduce(const u32* in, u32* sums, size_t count) {
+    size_t base = (size_t)blockIdx.x * kTile;
+    u32 s = 0;
+    for (int it = 0; it < kItems; ++it) {
+        size_t e = base + (size_t)it * kThreads + threadIdx.x;
+        if (e < count) s += in[e];
+    }
+    u32 tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Scan each tile with its block offset; thread t owns elements t*kItems..+kItems.
+__global__ void __launch_bounds__(kThreads) k_scan_apply(const u32* in, u32* out, const u32* offs, size_t count,
+                                                         int inclusive) {
+    size_t base = (size_t)blockIdx.x * kTile + (size_t)threadIdx.x * kItems;
+    u32 v[kItems];
+    u32 s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        v[i] = (base + i < count) ? in[base + i] : 0u;
+        s += v[i];
+    }
+    u32 tot;
+    u32 run = block_excl_scan(s, &tot) + (offs ? offs[blockIdx.x] : 0u);
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        u32 x = v[i];
+        if (base + i < count) out[base + i] = inclusive ? run + x : run;
+        run += x;
+    }
+}
+
+void scan_impl(const u32* in, u32* out, size_t count, u32* temp, int inclusive, hipStream_t s) {
+    if (count == 0) return;
+    size_t nb = cdiv(count, kTile);
+    if (nb == 1) {
+        k_scan_apply<<<1, kThreads, 0, s>>>(in, out, nullptr, count, inclusive);
+        return;
+    }
+    u32* sums = temp;
+    u32* rest = temp + cdiv(nb, 64) * 64;
+    k_scan_reduce<<<(unsigned)nb, kThreads, 0, s>>>(in, sums, count);
+    scan_impl(sums, sums, nb, rest, 0, s);
+    k_scan_apply<<<(unsigned)nb, kThreads, 0, s>>>(in, out, sums, count, inclusive);
+}
+
+// ---------------------------------------------------------------- radix
+struct PairKeys {
+    const u64* key;
+    __device__ __forceinline__ u32 digit(size_t e, int shift) const { return (u32)(key[e] >> shift) & 255u; }
+};
+struct IndexKeys {
+    const u64* w;
+    const u32* idx;
+    __device__ __forceinline__ u32 digit(size_t e, int shift) const { return (u32)(w[idx[e]] >> shift) & 255u; }
+};
+
+template <class K>
+__global__ void __launch_bounds__(kThreads) k_radix_hist(K keys, size_t count, int shift, u32* hist, u32 nblocks) {
+    __shared__ u32 h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    size_t base = (size_t)blockIdx.x * kTile;
+    for (int it = 0; it < kItems; ++it) {
+        size_t e = base + (size_t)it * kThreads + threadIdx.x;
+        if (e < count) atomicAdd(&h[keys.digit(e, shift)], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Moves element e to its stable position.  MoveKV supplies the payload copy.
+template <class K, class M>
+__global__ void __launch_bounds__(kThreads) k_radix_scatter(K keys, M mv, size_t count, int shift,
+                                                            const u32* offs, u32 nblocks) {
+    __shared__ u32 run[256];
+    __shared__ u32 wcnt[kWaves][256];
+    int t = threadIdx.x;
+    int w = t / kWave;
+    run[t] = offs[(size_t)t * nblocks + blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) wcnt[i][t] = 0;
+    __syncthreads();
+    size_t base = (size_t)blockIdx.x * kTile;
+    for (int it = 0; it < kItems; ++it) {
+        size_t e = base + (size_t)it * kThreads + t;
+        bool valid = e < count;
+        u32 dg = valid ? keys.digit(e, shift) : 0u;
+        u64 vmask = __ballot(valid);
+        u64 peers = valid ? vmask : ~vmask;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (dg >> b) & 1u;
+            u64 bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        u32 rank = (u32)__popcll(peers & lanemask_lt());
+        if (valid && rank == 0) wcnt[w][dg] = (u32)__popcll(peers);
+        __syncthreads();
+        u32 pos = 0;
+        if (valid) {
+            pos = run[dg] + rank;
+            for (int i = 0; i < w; ++i) pos += wcnt[i][dg];
+        }
+        __syncthreads();
+        u32 add = 0;
+#pragma unroll
+        for (int i = 0; i < kWaves; ++i) {
+            add += wcnt[i][t];
+            wcnt[i][t] = 0;
+        }
+        run[t] += add;
+        if (valid) mv.move(e, pos);
+        __syncthreads();
+    }
+}
+
+struct MovePairs {
+    const u64* ki;
+    const u32* vi;
+    u64* ko;
+    u32* vo;
+    __device__ __forceinline__ void move(size_t e, u32 pos) const {
+        ko[pos] = ki[e];
+        vo[pos] = vi[e];
+    }
+};
+struct MoveIndex {
+    const u32* ii;
+    u32* io;
+    __device__ __forceinline__ void move(size_t e, u32 pos) const { io[pos] = ii[e]; }
+};
+
+}  // namespace
+
+size_t scan_temp_bytes(size_t count) {
+    size_t tot = 0;
+    size_t c = count;
+    while (c > (size_t)kTile) {
+        c = cdiv(c, kTile);
+        tot += cdiv(c, 64) * 64;
+    }
+    return (tot + 64) * sizeof(u32);
+}
+
+size_t radix_temp_bytes(size_t count) {
+    size_t nb = cdiv(count ? count : 1, kTile);
+    size_t h = nb * 256;
+    return (cdiv(h, 64) * 64) * sizeof(u32) + scan_temp_bytes(h);
+}
+
+void scan_exclusive_u32(const u32* in, u32* out, size_t count, void* temp, hipStream_t s) {
+    scan_impl(in, out, count, (u32*)temp, 0, s);
+}
+void scan_inclusive_u32(const u32* in, u32* out, size_t count, void* temp, hipStream_t s) {
+    scan_impl(in, out, count, (u32*)temp, 1, s);
+}
+
+int radix_sort_pairs(u64* key, u32* val, u64* key2, u32* val2, size_t count, int bits, void* temp,
+                     hipStream_t s) {
+    if (count <= 1 || bits <= 0) return 0;
+    u32 nb = (u32)cdiv(count, kTile);
+    u32* hist = (u32*)temp;
+    void* stemp = (char*)temp + cdiv((size_t)nb * 256, 64) * 64 * sizeof(u32);
+    int flip = 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        u64* ki = flip ? key2 : key;
+        u32* vi = flip ? val2 : val;
+        u64* ko = flip ? key : key2;
+        u32* vo = flip ? val : val2;
+        PairKeys K{ki};
+        k_radix_hist<<<nb, kThreads, 0, s>>>(K, count, shift, hist, nb);
+        scan_exclusive_u32(hist, hist, (size_t)nb * 256, stemp, s);
+        MovePairs M{ki, vi, ko, vo};
+        k_radix_scatter<<<nb, kThreads, 0, s>>>(K, M, count, shift, hist, nb);
+        flip ^= 1;
+    }
+    return flip;
+}
+
+int radix_sort_index(const u64* w, u32* idx, u32* idx2, size_t count, int bits, void* temp, hipStream_t s) {
+    if (count <= 1 || bits <= 0) return 0;
+    u32 nb = (u32)cdiv(count, kTile);
+    u32* hist = (u32*)temp;
+    void* stemp = (char*)temp + cdiv((size_t)nb * 256, 64) * 64 * sizeof(u32);
+    int flip = 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        u32* ii = flip ? idx2 : idx;
+        u32* io = flip ? idx : idx2;
+        IndexKeys K{w, ii};
+        k_radix_hist<<<nb, kThreads, 0, s>>>(K, count, shift, hist, nb);
+        scan_exclusive_u32(hist, hist, (size_t)nb * 256, stemp, s);
+        MoveIndex M{ii, io};
+        k_radix_scatter<<<nb, kThreads, 0, s>>>(K, M, count, shift, hist, nb);
+        flip ^= 1;
+    }
+    return flip;
+}
+
+}  // namespace geomst

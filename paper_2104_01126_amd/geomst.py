@@ -1,0 +1,203 @@
+"""Thin ctypes binding of libgeomst (argument marshalling only).
+
+Every step of a solve runs inside the HIP library; this module converts
+arguments and raises on error.  There is no CPU fallback: if the library is
+missing or no GPU is present, the calls fail.
+
+* ``emst(points)`` / ``hdbscan(points, min_pts)`` take a numpy array (host
+  path: the library copies in and out) or a float64 CUDA tensor (device path,
+  queued on torch's current stream, outputs returned as CUDA tensors).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgeomst.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "geomst.h")
+
+OK, EINVAL, EDOM, ENOMEM, EDEVICE, EINTERNAL = 0, -1, -2, -3, -4, -8
+_NAMES = {EINVAL: "EINVAL", EDOM: "EDOM", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", EINTERNAL: "EINTERNAL"}
+
+
+class GeomstError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"geomst error {_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("d", ctypes.c_int32), ("min_pts", ctypes.c_int32),
+        ("rounds", ctypes.c_int64), ("pair_visits", ctypes.c_int64), ("bccp_pairs", ctypes.c_int64),
+        ("bccp_evals", ctypes.c_int64), ("big_pairs", ctypes.c_int64), ("committed_edges", ctypes.c_int64),
+        ("max_frontier", ctypes.c_int64), ("ms_total", ctypes.c_double), ("ms_tree", ctypes.c_double),
+        ("ms_core", ctypes.c_double), ("ms_rounds", ctypes.c_double), ("ms_final", ctypes.c_double),
+        ("big_evals", ctypes.c_int64), ("sort_elems", ctypes.c_int64),
+        ("kernel_ms", ctypes.c_double * 16), ("kernel_launches", ctypes.c_int64 * 16),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgeomst.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2104_01126_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.geomst_emst.argtypes = [P, i64, i32, P, P]
+    lib.geomst_hdbscan.argtypes = [P, i64, i32, i32, P, P, P]
+    lib.geomst_emst_dev.argtypes = [P, i64, i32, P, P, P, P]
+    lib.geomst_hdbscan_dev.argtypes = [P, i64, i32, i32, P, P, P, P, P, P]
+    lib.geomst_get_stats.argtypes = [ctypes.POINTER(_Stats)]
+    lib.geomst_set_option.argtypes = [ctypes.c_char_p, dbl]
+    lib.geomst_last_error.restype = ctypes.c_char_p
+    for f in (lib.geomst_emst, lib.geomst_hdbscan, lib.geomst_emst_dev, lib.geomst_hdbscan_dev,
+              lib.geomst_get_stats, lib.geomst_set_option, lib.geomst_version):
+        f.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def declared_symbols(header: str = HEADER):
+    """Function names declared in include/geomst.h."""
+    txt = open(header).read()
+    return sorted(set(re.findall(r"\b(geomst_\w+)\s*\(", txt)))
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise GeomstError(rc, load().geomst_last_error().decode())
+
+
+def last_error() -> str:
+    return load().geomst_last_error().decode()
+
+
+def version() -> int:
+    return int(load().geomst_version())
+
+
+def set_option(name: str, value: float):
+    _check(load().geomst_set_option(name.encode(), float(value)))
+
+
+@dataclass
+class Stats:
+    n: int
+    d: int
+    min_pts: int
+    rounds: int
+    pair_visits: int
+    bccp_pairs: int
+    bccp_evals: int
+    big_pairs: int
+    committed_edges: int
+    max_frontier: int
+    ms_total: float
+    ms_tree: float
+    ms_core: float
+    ms_rounds: float
+    ms_final: float
+    big_evals: int
+    sort_elems: int
+    kernel_ms: list
+    kernel_launches: list
+
+
+# kernel families (GEOMST_K_* in include/geomst.h)
+KERNEL_FAMILIES = ["tree", "sort", "core", "split", "expand", "bccp", "kruskal", "refresh", "output"]
+
+
+def stats() -> Stats:
+    s = _Stats()
+    _check(load().geomst_get_stats(ctypes.byref(s)))
+    vals = {}
+    for f, _ in _Stats._fields_:
+        v = getattr(s, f)
+        vals[f] = list(v) if f in ("kernel_ms", "kernel_launches") else v
+    return Stats(**vals)
+
+
+def _is_cuda_tensor(x) -> bool:
+    return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
+
+
+def _stream_ptr():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def emst(points, want_sq: bool = False):
+    """EMST -> (edges int64 [n-1,2], weights float64 [n-1][, weights_sq]).
+
+    numpy in -> numpy out (host path); CUDA tensor in -> CUDA tensors out."""
+    lib = load()
+    if _is_cuda_tensor(points):
+        import torch
+        p = points.contiguous()
+        if p.dtype != torch.float64 or p.dim() != 2:
+            raise ValueError("points must be a float64 [n, d] tensor")
+        n, d = p.shape
+        m = max(n - 1, 0)
+        e = torch.empty((m, 2), dtype=torch.int64, device=p.device)
+        w = torch.empty(m, dtype=torch.float64, device=p.device)
+        w2 = torch.empty(m, dtype=torch.float64, device=p.device) if want_sq else None
+        _check(lib.geomst_emst_dev(p.data_ptr(), n, d, e.data_ptr(), w.data_ptr(),
+                                   w2.data_ptr() if w2 is not None else None, _stream_ptr()))
+        return (e, w, w2) if want_sq else (e, w)
+    p = np.ascontiguousarray(points, dtype=np.float64)
+    if p.ndim != 2:
+        raise ValueError("points must be [n, d]")
+    n, d = p.shape
+    m = max(n - 1, 0)
+    e = np.zeros((m, 2), np.int64)
+    w = np.zeros(m)
+    _check(lib.geomst_emst(p.ctypes.data, n, d, e.ctypes.data, w.ctypes.data))
+    return e, w
+
+
+def hdbscan(points, min_pts: int, want_sq: bool = False):
+    """HDBSCAN* -> (core_dist [n], edges [n-1,2], weights [n-1]
+    [, core_dist_sq, weights_sq])."""
+    lib = load()
+    if _is_cuda_tensor(points):
+        import torch
+        p = points.contiguous()
+        if p.dtype != torch.float64 or p.dim() != 2:
+            raise ValueError("points must be a float64 [n, d] tensor")
+        n, d = p.shape
+        m = max(n - 1, 0)
+        dev = p.device
+        cd = torch.empty(n, dtype=torch.float64, device=dev)
+        e = torch.empty((m, 2), dtype=torch.int64, device=dev)
+        w = torch.empty(m, dtype=torch.float64, device=dev)
+        cd2 = torch.empty(n, dtype=torch.float64, device=dev) if want_sq else None
+        w2 = torch.empty(m, dtype=torch.float64, device=dev) if want_sq else None
+        _check(lib.geomst_hdbscan_dev(p.data_ptr(), n, d, int(min_pts), cd.data_ptr(),
+                                      cd2.data_ptr() if cd2 is not None else None, e.data_ptr(),
+                                      w.data_ptr(), w2.data_ptr() if w2 is not None else None,
+                                      _stream_ptr()))
+        return (cd, e, w, cd2, w2) if want_sq else (cd, e, w)
+    p = np.ascontiguousarray(points, dtype=np.float64)
+    if p.ndim != 2:
+        raise ValueError("points must be [n, d]")
+    n, d = p.shape
+    m = max(n - 1, 0)
+    cd = np.zeros(n)
+    e = np.zeros((m, 2), np.int64)
+    w = np.zeros(m)
+    _check(lib.geomst_hdbscan(p.ctypes.data, n, d, int(min_pts), cd.ctypes.data, e.ctypes.data,
+                              w.ctypes.data))
+    return cd, e, w

@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/geomst.h declares, and rejects bad arguments before
+touching the device."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2104_01126_amd import geomst as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(G.LIB_PATH):
+        from paper_2104_01126_amd import build
+        build.build()
+    return G.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = G.declared_symbols()
+    assert "geomst_emst" in declared and "geomst_hdbscan_dev" in declared
+    out = subprocess.run(["nm", "-D", "--defined-only", G.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    for name in declared:
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_header_compiles_as_c():
+    src = "#include \"geomst.h\"\nint main(void){ geomst_stats_t s; (void)s; int (*f)(void) = geomst_version; return f != 0 ? 0 : 1; }\n"
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), "-x", "c",
+                        "-", "-fsyntax-only"], input=src, text=True, capture_output=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_version(lib):
+    assert G.version() == 100
+
+
+def _emst_rc(lib, pts, n, d, edges):
+    return lib.geomst_emst(pts, n, d, edges, None)
+
+
+def test_rejects_bad_arguments_without_device(lib):
+    p = np.zeros((4, 3))
+    e = np.zeros((3, 2), np.int64)
+    assert _emst_rc(lib, None, 4, 3, e.ctypes.data) == G.EINVAL
+    assert _emst_rc(lib, p.ctypes.data, 0, 3, e.ctypes.data) == G.EINVAL
+    assert _emst_rc(lib, p.ctypes.data, 4, 0, e.ctypes.data) == G.EINVAL
+    assert _emst_rc(lib, p.ctypes.data, 4, 8, e.ctypes.data) == G.EINVAL
+    assert _emst_rc(lib, p.ctypes.data, 4, 3, None) == G.EINVAL
+    assert _emst_rc(lib, p.ctypes.data, (1 << 26) + 1, 3, e.ctypes.data) == G.EINVAL
+    assert "n must be" in G.last_error()
+    cd = np.zeros(4)
+    assert lib.geomst_hdbscan(p.ctypes.data, 4, 3, 0, cd.ctypes.data, e.ctypes.data, None) == G.EINVAL
+    assert lib.geomst_hdbscan(p.ctypes.data, 4, 3, 5, cd.ctypes.data, e.ctypes.data, None) == G.EINVAL
+    assert lib.geomst_hdbscan(p.ctypes.data, 4, 3, 65, cd.ctypes.data, e.ctypes.data, None) == G.EINVAL
+    assert lib.geomst_emst_dev(None, 4, 3, None, None, None, None) == G.EINVAL
+    with pytest.raises(G.GeomstError):
+        G.emst(np.zeros((4, 9)))
+
+
+def test_options(lib):
+    assert lib.geomst_set_option(b"beta_growth", 1.0) == G.EINVAL
+    assert lib.geomst_set_option(b"beta_growth", float("nan")) == G.EINVAL
+    assert lib.geomst_set_option(b"no_such_option", 2.0) == G.EINVAL
+    assert lib.geomst_set_option(b"beta_growth", 2.0) == G.OK
+
+
+def test_stats_struct_layout(lib):
+    s = G.stats()
+    assert isinstance(s.rounds, int)
+    # the ctypes mirror has the size of the C struct
+    src = ("#include <stdio.h>\n#include <stddef.h>\n#include \"geomst.h\"\n"
+           "int main(void){ printf(\"%zu %zu\", sizeof(geomst_stats_t), offsetof(geomst_stats_t, kernel_ms));"
+           " return 0; }\n")
+    exe = os.path.join(ROOT, "_build_stats_probe")
+    try:
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-x", "c", "-", "-o", exe],
+                       input=src, text=True, check=True)
+        size, off = map(int, subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split())
+    finally:
+        if os.path.exists(exe):
+            os.remove(exe)
+    assert ctypes.sizeof(G._Stats) == size
+    assert G._Stats.kernel_ms.offset == off
