@@ -129,6 +129,9 @@ int geomst_get_stats(geomst_stats_t* out);
  * Tuning knobs (they never change the result):
  *   "beta_growth"    factor applied to the weight threshold between rounds
  *                    (default 2: the threshold doubles each round), must be > 1.
+ *   "list_capacity_scale"  (0,1]: scale of the initial capacities of the
+ *                    internal pair and edge lists (default 1); small values make
+ *                    the lists overflow, grow and restart rounds (a testing aid).
  *   "kernel_timing"  1 = bracket every kernel family launch with HIP events on
  *                    the solve's stream and report device times in
  *                    geomst_stats_t.kernel_ms; 0 = off (default).

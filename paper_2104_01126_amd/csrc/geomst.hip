@@ -4,6 +4,7 @@
 // counters back and decides when the rounds end.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 #include <chrono>
 #include <mutex>
@@ -23,6 +24,11 @@ namespace {
 thread_local std::string g_err;
 thread_local geomst_stats_t g_stats;
 double g_beta_growth = 2.0;
+double g_capacity_scale = 1.0;
+constexpr int kMaxKeyLevels = 6;
+constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
+constexpr int kBoruvkaBatch = 4;  // Boruvka steps launched between host checks  // Morton key words per point (see k_morton_level)
+const bool g_trace = getenv("GEOMST_TRACE") != nullptr;
 
 struct Fail {
     int code;
@@ -90,11 +96,13 @@ struct Device {
     // input staging (host API)
     DBuf pin, eout, wout, cdout;
     // tree
-    DBuf part, bbox, key, val, key2, val2, stemp, X, orig, cd2, box, rad, rng, kids, npar, cdb, flags, comp;
+    DBuf keysA, keysB, gflag, gincl, gid, gstart, g64, gbox, hflag;
+    DBuf part, bbox, key, val, key2, val2, stemp, X, orig, cd2, nodes, npar, flags, comp;
     // union-find / component refresh
     DBuf uf, best, bnd, incl;
     // rounds
-    DBuf F[2], Q[2], big, ntask, toff, parts;
+    DBuf F[2], Q[2], big, ntask, toff, parts, qring;
+    size_t qmax_seen = 0;
     size_t capF[2] = {0, 0}, capQ[2] = {0, 0}, capBig = 0;
     EdgeBufs C, P[2], OUT;
     // Kruskal
@@ -233,6 +241,7 @@ struct Solver {
     bool hdb;
     TreeView t;
     geomst_stats_t& st;
+    int key_levels = 1;
 
     Solver(Device& dev, hipStream_t stream, int n_, int mp, geomst_stats_t& stats)
         : D(dev), s(stream), n(n_), minpts(mp), hdb(mp > 0), st(stats) {}
@@ -254,7 +263,7 @@ struct Solver {
         D.key2.ensure((size_t)n * 8);
         D.val.ensure((size_t)n * 4);
         D.val2.ensure((size_t)n * 4);
-        D.stemp.ensure(radix_temp_bytes(n));
+        D.stemp.ensure(std::max(radix_temp_bytes(n), scan_temp_bytes(n)));
         k_morton<D_><<<blocks(n, 256), 256, 0, s>>>(P, n, D.bbox.as<double>(), D.key.as<u64>(), D.val.as<u32>());
         LAUNCHCHK();
         int mb = (63 / D_) > 31 ? 31 : (63 / D_);
@@ -262,42 +271,90 @@ struct Solver {
         int flip = radix_sort_pairs(D.key.as<u64>(), D.val.as<u32>(), D.key2.as<u64>(), D.val2.as<u32>(), n,
                                     mb * D_, D.stemp.p, s);
         LAUNCHCHK();
-        const u64* skey = flip ? D.key2.as<u64>() : D.key.as<u64>();
-        const u32* sval = flip ? D.val2.as<u32>() : D.val.as<u32>();
+        // multi-level keys: keysA holds L words per position, level-major
+        D.keysA.ensure((size_t)kMaxKeyLevels * n * 8);
+        D.keysB.ensure((size_t)kMaxKeyLevels * n * 8);
+        u64* keys = D.keysA.as<u64>();
+        u64* keysB = D.keysB.as<u64>();
+        u32* vala = flip ? D.val2.as<u32>() : D.val.as<u32>();
+        u32* valb = flip ? D.val.as<u32>() : D.val2.as<u32>();
+        HIPCHK(hipMemcpyAsync(keys, flip ? D.key2.p : D.key.p, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+        int L = 1;
+        D.gflag.ensure((size_t)n * 4);
+        D.gincl.ensure((size_t)n * 4);
+        D.gid.ensure((size_t)n * 4);
+        D.gstart.ensure((size_t)n * 4);
+        D.g64.ensure((size_t)n * 8);
+        D.perm[0].ensure((size_t)n * 4);
+        D.perm[1].ensure((size_t)n * 4);
+        D.hflag.ensure(16);
+        while (L < kMaxKeyLevels && n > 1) {
+            HIPCHK(hipMemsetAsync(D.hflag.p, 0, 16, s));
+            k_key_flags<<<blocks(n, 256), 256, 0, s>>>(keys, n, L, D.gflag.as<u32>(), D.hflag.as<u32>());
+            LAUNCHCHK();
+            scan_inclusive_u32(D.gflag.as<u32>(), D.gincl.as<u32>(), n, D.stemp.p, s);
+            LAUNCHCHK();
+            u32 hv[2] = {0, 0};
+            HIPCHK(hipMemcpyAsync(hv, D.hflag.p, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(hv + 1, D.gincl.as<u32>() + n - 1, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (!hv[0]) break;  // every key is unique
+            u32 ngroups = hv[1];
+            D.gbox.ensure((size_t)ngroups * 2 * D_ * 8);
+            k_group_ids<<<blocks(n, 256), 256, 0, s>>>(D.gincl.as<u32>(), n, D.gid.as<u32>(), D.gstart.as<u32>());
+            LAUNCHCHK();
+            k_group_box<D_><<<blocks(ngroups, 4), 256, 0, s>>>(P, vala, n, D.gstart.as<u32>(), ngroups,
+                                                                D.gbox.as<double>(), D.hflag.as<u32>() + 1);
+            LAUNCHCHK();
+            u32 refinable = 0;
+            HIPCHK(hipMemcpyAsync(&refinable, D.hflag.as<u32>() + 1, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (!refinable) break;  // the remaining equal keys belong to coincident points
+            u64* kl = keys + (size_t)L * n;
+            k_morton_level<D_><<<blocks(n, 256), 256, 0, s>>>(P, vala, n, D.gid.as<u32>(), D.gstart.as<u32>(),
+                                                               ngroups, D.gbox.as<double>(), kl);
+            LAUNCHCHK();
+            // stable order by (group, new word)
+            u32* pa = D.perm[0].as<u32>();
+            u32* pb = D.perm[1].as<u32>();
+            k_iota<<<blocks(n, 256), 256, 0, s>>>(pa, n);
+            LAUNCHCHK();
+            if (radix_sort_index(kl, pa, pb, n, mb * D_, D.stemp.p, s)) std::swap(pa, pb);
+            LAUNCHCHK();
+            k_u32_to_u64<<<blocks(n, 256), 256, 0, s>>>(D.gid.as<u32>(), n, D.g64.as<u64>());
+            LAUNCHCHK();
+            if (radix_sort_index(D.g64.as<u64>(), pa, pb, n, id_bits((int)ngroups), D.stemp.p, s)) std::swap(pa, pb);
+            LAUNCHCHK();
+            g_stats.sort_elems += (int64_t)n * ((mb * D_ + 7) / 8 + (id_bits((int)ngroups) + 7) / 8);
+            k_apply_perm<<<blocks(n, 256), 256, 0, s>>>(pa, n, L + 1, vala, valb, keys, keysB);
+            LAUNCHCHK();
+            std::swap(keys, keysB);
+            std::swap(vala, valb);
+            ++L;
+        }
+        key_levels = L;
+        const u64* skey = keys;
+        const u32* sval = vala;
         D.X.ensure((size_t)n * D_ * 8);
         D.orig.ensure((size_t)n * 4);
         k_permute<D_><<<blocks(n, 256), 256, 0, s>>>(P, n, sval, D.X.as<double>(), D.orig.as<u32>());
         LAUNCHCHK();
-        D.box.ensure((size_t)nn * 2 * D_ * 8);
-        D.rad.ensure((size_t)nn * 8);
-        D.rng.ensure((size_t)nn * 8);
-        D.kids.ensure((size_t)std::max(n - 1, 1) * 8);
+        D.nodes.ensure((size_t)nn * sizeof(NodeRec<D_>));
         D.npar.ensure((size_t)nn * 4);
         D.flags.ensure((size_t)nn * 4);
         D.comp.ensure((size_t)nn * 4);
-        D.cdb.ensure((size_t)nn * 16);
-        if (n >= 2) {
-            k_karras<<<blocks(n - 1, 256), 256, 0, s>>>(skey, n, D.rng.as<int2>(), D.kids.as<int2>(),
-                                                         D.npar.as<int>());
-            LAUNCHCHK();
-        } else {
-            HIPCHK(hipMemsetAsync(D.npar.p, 0xff, 4, s));
-        }
-        HIPCHK(hipMemsetAsync(D.flags.p, 0, (size_t)nn * 4, s));
-        k_bounds<D_><<<blocks(n, 256), 256, 0, s>>>(n, D.X.as<double>(), nullptr, D.kids.as<int2>(),
-                                                    D.npar.as<int>(), D.box.as<double>(), D.rad.as<double>(),
-                                                    D.cdb.as<double2>(), D.rng.as<int2>(), D.flags.as<u32>(), 1,
-                                                    0);
+        NodeRec<D_>* nodes = D.nodes.as<NodeRec<D_>>();
+        k_karras<D_><<<blocks(n - 1, 256), 256, 0, s>>>(skey, n, L, nodes, D.npar.as<int>());
+        LAUNCHCHK();
+        HIPCHK(hipMemsetAsync(D.flags.p, 0, (size_t)(n - 1) * 4, s));
+        k_bounds<D_><<<blocks(n, kBoundsBlock), kBoundsBlock, 0, s>>>(n, D.X.as<double>(), nullptr,
+                                                                      D.npar.as<int>(), nodes, D.flags.as<u32>(), 1);
         LAUNCHCHK();
         t.n = n;
         t.X = D.X.as<double>();
         t.orig = D.orig.as<u32>();
         t.cd2 = nullptr;
-        t.box = D.box.as<double>();
-        t.rad = D.rad.as<double>();
-        t.rng = D.rng.as<int2>();
-        t.kids = D.kids.as<int2>();
-        t.cdb = D.cdb.as<double2>();
+        t.nodes = nodes;
         t.comp = D.comp.as<int>();
     }
 
@@ -315,11 +372,10 @@ struct Solver {
         else if (minpts <= 32) knn_k<32>();
         else knn_k<64>();
         t.cd2 = D.cd2.as<double>();
-        HIPCHK(hipMemsetAsync(D.flags.p, 0, (size_t)(2 * n - 1) * 4, s));
-        k_bounds<D_><<<blocks(n, 256), 256, 0, s>>>(n, D.X.as<double>(), D.cd2.as<double>(), D.kids.as<int2>(),
-                                                    D.npar.as<int>(), D.box.as<double>(), D.rad.as<double>(),
-                                                    D.cdb.as<double2>(), D.rng.as<int2>(), D.flags.as<u32>(), 0,
-                                                    1);
+        HIPCHK(hipMemsetAsync(D.flags.p, 0, (size_t)(n - 1) * 4, s));
+        k_bounds<D_><<<blocks(n, kBoundsBlock), kBoundsBlock, 0, s>>>(n, D.X.as<double>(), D.cd2.as<double>(),
+                                                                      D.npar.as<int>(), D.nodes.as<NodeRec<D_>>(),
+                                                                      D.flags.as<u32>(), 0);
         LAUNCHCHK();
     }
 
@@ -331,8 +387,8 @@ struct Solver {
         LAUNCHCHK();
         scan_inclusive_u32(D.bnd.as<u32>(), D.incl.as<u32>(), n, D.stemp.p, s);
         LAUNCHCHK();
-        k_node_comp<<<blocks(2 * n - 1, 256), 256, 0, s>>>(D.rng.as<int2>(), D.uf.as<u32>(), D.incl.as<u32>(),
-                                                           2 * n - 1, D.comp.as<int>());
+        k_node_comp<D_><<<blocks(2 * n - 1, 256), 256, 0, s>>>(D.nodes.as<NodeRec<D_>>(), D.uf.as<u32>(),
+                                                               D.incl.as<u32>(), 2 * n - 1, D.comp.as<int>());
         LAUNCHCHK();
     }
 
@@ -354,29 +410,31 @@ struct Solver {
         return r;
     }
 
-    // Grow whatever overflowed (keeping the entries that existed before the
-    // step) and restore the counters so the step can run again.
-    bool fix_overflow(const Counters& before, int fo, int qo, int po) {
+    // After an overflow: grow the round's output lists that ran out.  Their
+    // contents are not kept (the round restarts); the round's input frontier
+    // F[fc] and input pool P[pc] are never touched.
+    void grow_lists(int fo, int po) {
         const Counters& c = *D.hcnt;
-        if (!(c.c[C_ERR] & 1u)) return false;
-        auto grow_pairs = [&](DBuf& b, size_t& cap, u32 need, u32 keep) {
+        auto grow_pairs = [&](DBuf& b, size_t& cap, size_t need) {
             if (need > cap) {
-                size_t nc = std::max<size_t>((size_t)need + need / 2, cap * 2);
-                b.ensure(nc * sizeof(PairRec), (size_t)keep * sizeof(PairRec), s);
+                size_t nc = std::max<size_t>(need + need / 4, cap * 2);
+                b.ensure(nc * sizeof(PairRec));
                 cap = nc;
             }
         };
-        grow_pairs(D.F[fo], D.capF[fo], c.c[C_F], before.c[C_F]);
-        grow_pairs(D.Q[qo], D.capQ[qo], std::max(c.c[C_Q], c.c[C_QN]), 0);
+        grow_pairs(D.F[fo], D.capF[fo], c.c[C_F]);
+        // level queues: the split's count is exact (qmax_seen); an overflowing
+        // level's count may already be cleared, so then they double
+        size_t qneed = D.qmax_seen;
+        if (c.c[C_ERR] & 16u) qneed = std::max(qneed, std::max(D.capQ[0], D.capQ[1]) + 1);
+        for (int i = 0; i < 2; ++i) grow_pairs(D.Q[i], D.capQ[i], qneed);
         if (c.c[C_BIG] > D.capBig) {
-            size_t nc = std::max<size_t>((size_t)c.c[C_BIG] * 3 / 2, D.capBig * 2);
-            D.big.ensure(nc * 8, (size_t)before.c[C_BIG] * 8, s);
+            size_t nc = std::max<size_t>((size_t)c.c[C_BIG] * 5 / 4, D.capBig * 2);
+            D.big.ensure(nc * 8);
             D.capBig = nc;
         }
-        if (c.c[C_C] > D.C.cap) D.C.ensure((size_t)c.c[C_C] * 3 / 2, before.c[C_C], s);
-        if (c.c[C_P] > D.P[po].cap) D.P[po].ensure((size_t)c.c[C_P] * 3 / 2, before.c[C_P], s);
-        write_counters(D, before, s);
-        return true;
+        if (c.c[C_C] > D.C.cap) D.C.ensure(std::max<size_t>((size_t)c.c[C_C] * 5 / 4, D.C.cap * 2), 0, s);
+        if (c.c[C_P] > D.P[po].cap) D.P[po].ensure(std::max<size_t>((size_t)c.c[C_P] * 5 / 4, D.P[po].cap * 2), 0, s);
     }
 
     void run(const double* P, long long* edges, double* w, double* w2, double* cd, double* cd2out) {
@@ -391,6 +449,7 @@ struct Solver {
             throw Fail{GEOMST_EDOM};
         }
         auto t1 = clk::now();
+        if (g_trace) fprintf(stderr, "[geomst] key levels %d\n", key_levels);
         if (hdb) {
             core_distances();
             HIPCHK(hipStreamSynchronize(s));
@@ -415,26 +474,36 @@ struct Solver {
                 cap = want;
             }
         };
-        size_t nf0 = (size_t)(hdb ? 8 : 4) * n + 4096;
-        initcap(D.capF[0], D.F[0], nf0);
-        initcap(D.capF[1], D.F[1], nf0);
-        initcap(D.capQ[0], D.Q[0], (size_t)2 * n + 4096);
-        initcap(D.capQ[1], D.Q[1], (size_t)2 * n + 4096);
-        if (D.capBig < (size_t)n / 8 + 4096) {
-            D.capBig = (size_t)n / 8 + 4096;
+        auto sc = [&](double per_point) {
+            return std::max<size_t>(64, (size_t)(g_capacity_scale * (per_point * n + 4096)));
+        };
+        if (g_capacity_scale != 1.0) {  // testing aid: start from the given capacities
+            for (int i = 0; i < 2; ++i) {
+                D.capF[i] = D.capQ[i] = 0;
+                D.P[i].cap = 0;
+            }
+            D.capBig = 0;
+            D.C.cap = 0;
+        }
+        initcap(D.capF[0], D.F[0], sc(hdb ? 8 : 4));
+        initcap(D.capF[1], D.F[1], sc(hdb ? 8 : 4));
+        initcap(D.capQ[0], D.Q[0], sc(2));
+        initcap(D.capQ[1], D.Q[1], sc(2));
+        if (D.capBig < sc(0.125)) {
+            D.capBig = sc(0.125);
             D.big.ensure(D.capBig * 8);
         }
-        D.C.ensure((size_t)2 * n + 4096, 0, s);
-        D.P[0].ensure((size_t)n + 4096, 0, s);
-        D.P[1].ensure((size_t)n + 4096, 0, s);
+        D.C.ensure(sc(2), 0, s);
+        D.P[0].ensure(sc(1), 0, s);
+        D.P[1].ensure(sc(1), 0, s);
         D.OUT.ensure((size_t)n + 64, 0, s);
 
         // initial frontier: the children of every internal node
         int fc = 0, pc = 0;
         k_init_frontier<D_><<<blocks(n - 1, 256), 256, 0, s>>>(t, hdb, D.F[fc].as<PairRec>());
         LAUNCHCHK();
-        k_min_positive_lb<<<blocks(n - 1, 256), 256, 0, s>>>(D.F[fc].as<PairRec>(), (u32)(n - 1),
-                                                            D.cnt.as<Counters>());
+        k_min_positive_lb<<<std::min(blocks(n - 1, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
+            D.F[fc].as<PairRec>(), (u32)(n - 1), D.cnt.as<Counters>());
         LAUNCHCHK();
         read_counters(D, s);
         u64 b0 = D.hcnt->m[M_F];
@@ -444,94 +513,120 @@ struct Solver {
         u64 committed = 0, maxf = nF, big_pairs = 0;
         int rounds = 0;
         u32 nout = 0;
+        D.qring.ensure(kQRing * 4);
+        u32* ring = D.qring.as<u32>();
         while (true) {
             ++rounds;
             if (rounds > 100000) {
                 g_err = "round limit exceeded";
                 throw Fail{GEOMST_EINTERNAL};
             }
-            counters_reset_round(D, s);
             int fo = fc ^ 1, po = pc ^ 1;
-            // frontier and pool split
-            Counters before;
+            counters_reset_round(D, s);
             read_counters(D, s);
-            before = *D.hcnt;
-            while (true) {
-                RoundArgs r = args(beta2, fo, 0, po);
+            const Counters round_start = *D.hcnt;
+            int levels = 0;
+            u32 nbig = 0;
+            bool restart;
+            int restarts = 0;
+            do {
+                restart = false;
+                levels = 0;
+                D.qmax_seen = 0;
+                HIPCHK(hipMemsetAsync(ring, 0, kQRing * 4, s));
+                // frontier and pool split
                 {
-                TIMED(GEOMST_K_SPLIT);
-                if (nF) {
-                    k_split_frontier<<<blocks(nF, 256), 256, 0, s>>>(t, r, D.F[fc].as<PairRec>(), nF);
-                    LAUNCHCHK();
-                }
-                if (nP) {
-                    k_split_pool<<<blocks(nP, 256), 256, 0, s>>>(r, D.P[pc].list(), nP);
-                    LAUNCHCHK();
-                }
-                }
-                read_counters(D, s);
-                if (!fix_overflow(before, fo, 0, po)) break;
-            }
-            // expansion levels
-            u32 nq = D.hcnt->c[C_Q];
-            int qc = 0;
-            while (nq > 0) {
-                Counters b4 = *D.hcnt;
-                b4.c[C_QN] = 0;
-                write_counters(D, b4, s);
-                while (true) {
-                    RoundArgs r = args(beta2, fo, qc ^ 1, po);
-                    {
-                        TIMED(GEOMST_K_EXPAND);
-                        k_expand<D_><<<blocks(nq, 256), 256, 0, s>>>(t, r, hdb, D.Q[qc].as<PairRec>(), nq);
-                        LAUNCHCHK();
-                    }
-                    read_counters(D, s);
-                    if (!fix_overflow(b4, fo, qc ^ 1, po)) break;
-                }
-                nq = D.hcnt->c[C_QN];
-                qc ^= 1;
-            }
-            // large pairs
-            u32 nbig = D.hcnt->c[C_BIG];
-            if (nbig) {
-                big_pairs += nbig;
-                D.ntask.ensure((size_t)nbig * 4);
-                D.toff.ensure((size_t)nbig * 4);
-                D.stemp.ensure(std::max(scan_temp_bytes(nbig), radix_temp_bytes(n)));
-                k_big_ntasks<<<blocks(nbig, 256), 256, 0, s>>>(t, D.big.as<uint2>(), nbig, D.ntask.as<u32>());
-                LAUNCHCHK();
-                scan_exclusive_u32(D.ntask.as<u32>(), D.toff.as<u32>(), nbig, D.stemp.p, s);
-                LAUNCHCHK();
-                u32 last_off = 0, last_cnt = 0;
-                HIPCHK(hipMemcpyAsync(&last_off, D.toff.as<u32>() + nbig - 1, 4, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipMemcpyAsync(&last_cnt, D.ntask.as<u32>() + nbig - 1, 4, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                u32 ntasks = last_off + last_cnt;
-                D.parts.ensure((size_t)ntasks * sizeof(PartKey));
-                {
-                TIMED(GEOMST_K_BCCP);
-                if (hdb)
-                    k_big_bccp<D_, 1><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
-                                                           D.parts.as<PartKey>(), D.cnt.as<Counters>());
-                else
-                    k_big_bccp<D_, 0><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
-                                                           D.parts.as<PartKey>(), D.cnt.as<Counters>());
-                LAUNCHCHK();
-                }
-                Counters b4;
-                read_counters(D, s);
-                b4 = *D.hcnt;
-                while (true) {
+                    TIMED(GEOMST_K_SPLIT);
                     RoundArgs r = args(beta2, fo, 0, po);
-                    TIMED(GEOMST_K_BCCP);
-                    k_big_combine<<<blocks(nbig, 256), 256, 0, s>>>(r, nbig, D.toff.as<u32>(), D.ntask.as<u32>(),
-                                                                    D.parts.as<PartKey>());
+                    if (nF)
+                        k_split_frontier<<<std::min(blocks(nF, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
+                            t, r, D.F[fc].as<PairRec>(), nF, ring);
                     LAUNCHCHK();
-                    read_counters(D, s);
-                    if (!fix_overflow(b4, fo, 0, po)) break;
+                    if (nP)
+                        k_split_pool<<<std::min(blocks(nP, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
+                            r, D.P[pc].list(), nP);
+                    LAUNCHCHK();
                 }
-            }
+                read_counters(D, s);
+                u32 nq = 0;
+                HIPCHK(hipMemcpyAsync(&nq, ring, 4, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                D.hcnt->c[C_Q] = nq;
+                D.qmax_seen = nq;
+                if (D.hcnt->c[C_ERR] & 1u) {
+                    restart = true;
+                } else {
+                    // breadth-first levels, launched in batches without host syncs
+                    while (nq > 0) {
+                        for (int j = 0; j < kLevelBatch; ++j, ++levels) {
+                            TIMED(GEOMST_K_EXPAND);
+                            RoundArgs r = args(beta2, fo, (levels + 1) & 1, po);
+                            k_level<D_><<<kGrid, kBlock, 0, s>>>(t, r, hdb, D.Q[levels & 1].as<PairRec>(),
+                                                                 (u32)D.capQ[levels & 1], ring + (levels % kQRing),
+                                                                 ring + ((levels + 1) % kQRing),
+                                                                 ring + ((levels + 2) % kQRing));
+                            LAUNCHCHK();
+                        }
+                        read_counters(D, s);
+                        HIPCHK(hipMemcpyAsync(&nq, ring + (levels % kQRing), 4, hipMemcpyDeviceToHost, s));
+                        HIPCHK(hipStreamSynchronize(s));
+                        D.qmax_seen = std::max<size_t>(D.qmax_seen, nq);
+                        if (D.hcnt->c[C_ERR] & 1u) {
+                            restart = true;
+                            break;
+                        }
+                        if (levels > 1000000) {
+                            g_err = "level limit exceeded";
+                            throw Fail{GEOMST_EINTERNAL};
+                        }
+                    }
+                }
+                if (!restart) {
+                    nbig = D.hcnt->c[C_BIG];
+                    if (nbig) {
+                        D.ntask.ensure((size_t)nbig * 4);
+                        D.toff.ensure((size_t)nbig * 4);
+                        D.stemp.ensure(std::max(scan_temp_bytes(nbig), radix_temp_bytes(n)));
+                        k_big_ntasks<D_><<<blocks(nbig, 256), 256, 0, s>>>(t, D.big.as<uint2>(), nbig,
+                                                                            D.ntask.as<u32>());
+                        LAUNCHCHK();
+                        scan_exclusive_u32(D.ntask.as<u32>(), D.toff.as<u32>(), nbig, D.stemp.p, s);
+                        LAUNCHCHK();
+                        u32 last_off = 0, last_cnt = 0;
+                        HIPCHK(hipMemcpyAsync(&last_off, D.toff.as<u32>() + nbig - 1, 4, hipMemcpyDeviceToHost, s));
+                        HIPCHK(hipMemcpyAsync(&last_cnt, D.ntask.as<u32>() + nbig - 1, 4, hipMemcpyDeviceToHost, s));
+                        HIPCHK(hipStreamSynchronize(s));
+                        u32 ntasks = last_off + last_cnt;
+                        D.parts.ensure((size_t)ntasks * sizeof(PartKey));
+                        {
+                            TIMED(GEOMST_K_BCCP);
+                            if (hdb)
+                                k_big_bccp<D_, 1><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
+                                                                       D.parts.as<PartKey>(), D.cnt.as<Counters>());
+                            else
+                                k_big_bccp<D_, 0><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
+                                                                       D.parts.as<PartKey>(), D.cnt.as<Counters>());
+                            LAUNCHCHK();
+                            RoundArgs r = args(beta2, fo, 0, po);
+                            k_big_combine<<<std::min(blocks(nbig, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
+                                r, nbig, D.toff.as<u32>(), D.ntask.as<u32>(), D.parts.as<PartKey>());
+                            LAUNCHCHK();
+                        }
+                        read_counters(D, s);
+                        if (D.hcnt->c[C_ERR] & 1u) restart = true;
+                    }
+                }
+                if (restart) {
+                    if (++restarts > 64) {
+                        g_err = "internal lists kept overflowing";
+                        throw Fail{GEOMST_EINTERNAL};
+                    }
+                    if (g_trace) fprintf(stderr, "[geomst] round %d: list overflow, growing and restarting\n", rounds);
+                    grow_lists(fo, po);
+                    write_counters(D, round_start, s);
+                }
+            } while (restart);
+            big_pairs += nbig;
             // Kruskal on the committed edges
             u32 m = D.hcnt->c[C_C];
             committed += m;
@@ -547,31 +642,31 @@ struct Solver {
                 LAUNCHCHK();
                 k_set_u32<<<1, 1, 0, s>>>(D.nalive.as<u32>(), m);
                 LAUNCHCHK();
+                unsigned gk = std::min(blocks(m, kBlock), (unsigned)kGrid);
                 int ac = 0;
                 while (true) {
-                    u32* na_in = D.nalive.as<u32>() + ac;
-                    u32* na_out = D.nalive.as<u32>() + (ac ^ 1);
-                    {
-                    TIMED(GEOMST_K_KRUSKAL);
-                    k_set_u32<<<1, 1, 0, s>>>(na_out, 0);
-                    LAUNCHCHK();
-                    k_bor_pick<<<blocks(m, 256), 256, 0, s>>>(D.alive[ac].as<u32>(), na_in, perm, L, D.uf.as<u32>(),
-                                                              D.best.as<u32>(), D.ru.as<u32>(), D.rv.as<u32>(),
-                                                              D.cnt.as<Counters>());
-                    LAUNCHCHK();
-                    k_bor_hook<<<blocks(m, 256), 256, 0, s>>>(D.alive[ac].as<u32>(), na_in, perm, L, D.uf.as<u32>(),
-                                                              D.best.as<u32>(), D.ru.as<u32>(), D.rv.as<u32>(),
-                                                              D.alive[ac ^ 1].as<u32>(), na_out, D.OUT.list(),
-                                                              (u32)D.OUT.cap, D.cnt.as<Counters>());
-                    LAUNCHCHK();
-                    k_bor_reset<<<blocks(m, 256), 256, 0, s>>>(na_in, D.ru.as<u32>(), D.rv.as<u32>(),
-                                                               D.best.as<u32>());
-                    LAUNCHCHK();
+                    for (int j = 0; j < kBoruvkaBatch; ++j) {
+                        TIMED(GEOMST_K_KRUSKAL);
+                        u32* na_in = D.nalive.as<u32>() + ac;
+                        u32* na_out = D.nalive.as<u32>() + (ac ^ 1);
+                        k_set_u32<<<1, 1, 0, s>>>(na_out, 0);
+                        LAUNCHCHK();
+                        k_bor_pick<<<gk, kBlock, 0, s>>>(D.alive[ac].as<u32>(), na_in, m, perm, L, D.uf.as<u32>(),
+                                                        D.best.as<u32>(), D.ru.as<u32>(), D.rv.as<u32>(),
+                                                        D.cnt.as<Counters>());
+                        LAUNCHCHK();
+                        k_bor_hook<<<gk, kBlock, 0, s>>>(D.alive[ac].as<u32>(), na_in, m, perm, L, D.uf.as<u32>(),
+                                                        D.best.as<u32>(), D.ru.as<u32>(), D.rv.as<u32>(),
+                                                        D.alive[ac ^ 1].as<u32>(), na_out, D.OUT.list(),
+                                                        (u32)D.OUT.cap, D.cnt.as<Counters>());
+                        LAUNCHCHK();
+                        k_bor_reset<<<gk, kBlock, 0, s>>>(na_in, m, D.ru.as<u32>(), D.rv.as<u32>(), D.best.as<u32>());
+                        LAUNCHCHK();
+                        ac ^= 1;
                     }
                     u32 left = 0;
-                    HIPCHK(hipMemcpyAsync(&left, na_out, 4, hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipMemcpyAsync(&left, D.nalive.as<u32>() + ac, 4, hipMemcpyDeviceToHost, s));
                     HIPCHK(hipStreamSynchronize(s));
-                    ac ^= 1;
                     if (left == 0) break;
                 }
             }
@@ -589,6 +684,13 @@ struct Solver {
             maxf = std::max<u64>(maxf, nF);
             fc = fo;
             pc = po;
+            if (g_trace) {
+                fprintf(stderr,
+                        "[geomst] round %d beta2=%.6g levels=%d visits=%llu F=%u P=%u C=%u big=%u out=%u "
+                        "t=%.2fms\n",
+                        rounds, beta2, levels, (unsigned long long)c.c64[C64_VISITS], nF, nP, m, nbig, nout,
+                        std::chrono::duration<double, std::milli>(clk::now() - t2).count());
+            }
             if (nout >= (u32)(n - 1)) break;
             double mf = c.m[M_F] == ~0ull ? kInf : bits_to_double(c.m[M_F]);
             double mp = c.m[M_P] == ~0ull ? kInf : bits_to_double(c.m[M_P]);
@@ -828,6 +930,11 @@ int geomst_set_option(const char* name, double value) {
     if (!strcmp(name, "beta_growth")) {
         if (!(value > 1.0) || !(value < 1e6)) return GEOMST_EINVAL;
         g_beta_growth = value;
+        return GEOMST_OK;
+    }
+    if (!strcmp(name, "list_capacity_scale")) {
+        if (!(value > 0.0) || !(value <= 1.0)) return GEOMST_EINVAL;
+        g_capacity_scale = value;
         return GEOMST_OK;
     }
     if (!strcmp(name, "kernel_timing")) {

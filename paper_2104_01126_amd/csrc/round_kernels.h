@@ -72,36 +72,35 @@ struct RoundArgs {
 };
 
 constexpr int kTinyEvals = 16;   // pairs with at most this many point pairs are solved inline
-constexpr int kStackDepth = 16;  // per-lane DFS stack in LDS
-constexpr int kMaxSteps = 64;    // pairs one lane expands before spilling its stack
 
 // ------------------------------------------------------------ bounds
 template <int D>
-__device__ __forceinline__ double box_lb2(const double* A, const double* B) {
+__device__ __forceinline__ double box_lb2(const NodeRec<D>& A, const NodeRec<D>& B) {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        double g = fmax(fmax(B[k] - A[D + k], A[k] - B[D + k]), 0.0);
+        double g = fmax(fmax(B.lo[k] - A.hi[k], A.lo[k] - B.hi[k]), 0.0);
         s = s + g * g;
     }
     return s;
 }
 
 template <int D>
-__device__ __forceinline__ double box_diag2(const double* A) {
+__device__ __forceinline__ double box_diag2(const NodeRec<D>& A) {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        double t = A[D + k] - A[k];
+        double t = A.hi[k] - A.lo[k];
         s = s + t * t;
     }
     return s;
 }
 
+// Lower bound of the (squared) weight of any edge between the two nodes.
 template <int D>
-__device__ __forceinline__ double pair_wlb2(const TreeView& t, int hdb, u32 a, u32 b) {
-    double l = box_lb2<D>(t.box + (size_t)a * 2 * D, t.box + (size_t)b * 2 * D);
-    if (hdb) l = fmax(l, fmax(t.cdb[a].x, t.cdb[b].x));
+__device__ __forceinline__ double pair_wlb2(const NodeRec<D>& A, const NodeRec<D>& B, int hdb) {
+    double l = box_lb2<D>(A, B);
+    if (hdb) l = fmax(l, fmax(A.cdmin, B.cdmin));
     return l;
 }
 
@@ -119,28 +118,25 @@ __device__ __forceinline__ bool connected(const TreeView& t, u32 a, u32 b) {
 // BCCP edge of each pair contain the tree's edge exactly; a pair of two
 // single points is always separated.
 template <int D>
-__device__ __forceinline__ bool well_separated(const TreeView& t, int hdb, u32 a, u32 b, int ca, int cb) {
-    if (ca == 1 && cb == 1) return true;
-    const double* A = t.box + (size_t)a * 2 * D;
-    const double* B = t.box + (size_t)b * 2 * D;
+__device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRec<D>& B, int hdb) {
+    if (A.count == 1 && B.count == 1) return true;
     double L = box_lb2<D>(A, B);
     double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
-    double ra = t.rad[a], rb = t.rad[b];
+    double ra = A.rad, rb = B.rad;
     double c2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        double x = 0.5 * (A[k] + A[D + k]) - 0.5 * (B[k] + B[D + k]);
+        double x = 0.5 * (A.lo[k] + A.hi[k]) - 0.5 * (B.lo[k] + B.hi[k]);
         c2 = c2 + x * x;
     }
     double need = ra + rb + 2.0 * fmax(ra, rb);
     bool geo = (fmax(dA, dB) < L) && (c2 >= need * need);
     if (geo || !hdb) return geo;
-    double2 ka = t.cdb[a], kb = t.cdb[b];
     double gap = fmax(sqrt(c2) - ra - rb, 0.0);
-    double lhs_s = fmax(fmax(4.0 * ra * ra, 4.0 * rb * rb), fmax(ka.y, kb.y));
-    double rhs_s = fmax(gap * gap, fmax(ka.x, kb.x));
-    double lhs = fmax(fmax(dA, dB), fmax(ka.y, kb.y));
-    double rhs = fmax(L, fmax(ka.x, kb.x));
+    double lhs_s = fmax(fmax(4.0 * ra * ra, 4.0 * rb * rb), fmax(A.cdmax, B.cdmax));
+    double rhs_s = fmax(gap * gap, fmax(A.cdmin, B.cdmin));
+    double lhs = fmax(fmax(dA, dB), fmax(A.cdmax, B.cdmax));
+    double rhs = fmax(L, fmax(A.cdmin, B.cdmin));
     return (rhs_s >= lhs_s) && (lhs < rhs);
 }
 
@@ -186,6 +182,84 @@ __device__ __forceinline__ void put_edge_raw(EdgeList L, u32 s, double w2, doubl
 }
 
 __device__ __forceinline__ void flag_overflow(Counters* cnt) { atomicOr(&cnt->c[C_ERR], 1u); }
+// level-queue overflow: its count may be cleared before the host looks, so
+// it has a flag bit of its own
+__device__ __forceinline__ void flag_overflow_q(Counters* cnt) { atomicOr(&cnt->c[C_ERR], 1u | 16u); }
+
+// ------------------------------------------------------ block-level appends
+// Up to five output lists per block step.  Each thread passes how many
+// entries it adds to each list (packed 12 bits per list, at most 2 each);
+// one atomic per non-empty list per block reserves the space, and each
+// thread gets its slot offsets back.  All threads of the block must call it.
+constexpr int kLists = 5;
+struct BlockAlloc {
+    u64 wsum[4];
+    u32 base[kLists];
+};
+
+__device__ __forceinline__ u64 wave_incl_scan_u64(u64 v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        u64 t = __shfl_up(v, o);
+        if (lane_id() >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void block_alloc(BlockAlloc& S, u64 packed, u32* const* counters, u32 (&off)[kLists]) {
+    const int w = threadIdx.x / kWave;
+    u64 incl = wave_incl_scan_u64(packed);
+    if (lane_id() == kWave - 1) S.wsum[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 run = 0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+            u64 x = S.wsum[i];
+            S.wsum[i] = run;
+            run += x;
+        }
+        for (int l = 0; l < kLists; ++l) {
+            u32 c = (u32)((run >> (12 * l)) & 0xfff);
+            S.base[l] = (c && counters[l]) ? atomicAdd(counters[l], c) : 0u;
+        }
+    }
+    __syncthreads();
+    u64 excl = incl - packed + S.wsum[w];
+#pragma unroll
+    for (int l = 0; l < kLists; ++l) off[l] = S.base[l] + (u32)((excl >> (12 * l)) & 0xfff);
+    __syncthreads();
+}
+
+// Block-wide minimum of a non-negative double, one atomic per block.
+__device__ __forceinline__ void block_atomic_min(double v, u64* dst, double* sh) {
+    v = wave_min_f64(v);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) sh[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sh[0];
+        for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = fmin(m, sh[i]);
+        if (m < __longlong_as_double(0x7ff0000000000000ll)) atomic_min_pos_f64(dst, m);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) sh[w] = v;
+    __syncthreads();
+    unsigned long long s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+constexpr int kBlock = 256;
+constexpr int kGrid = 1024;      // blocks of the grid-stride round kernels
+constexpr int kQRing = 4;        // level queue counters (ring)
 
 // ------------------------------------------------------------ frontier
 // Initial frontier: the two children of every internal node (Alg. 1, Wspd).
@@ -193,93 +267,101 @@ template <int D>
 __global__ void k_init_frontier(TreeView t, int hdb, PairRec* f) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= t.n - 1) return;
-    int2 c = t.kids[i];
+    const NodeRec<D>* N = nodes_of<D>(t);
     PairRec p;
-    p.a = (u32)c.x;
-    p.b = (u32)c.y;
-    p.lb2 = pair_wlb2<D>(t, hdb, p.a, p.b);
+    p.a = (u32)N[i].left;
+    p.b = (u32)N[i].right;
+    p.lb2 = pair_wlb2<D>(N[p.a], N[p.b], hdb);
     f[i] = p;
 }
 
 // Smallest positive lower bound over a pair list (the first beta).
-__global__ void k_min_positive_lb(const PairRec* f, u32 nf, Counters* cnt) {
-    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBlock) k_min_positive_lb(const PairRec* f, u32 nf, Counters* cnt) {
+    __shared__ double sh[4];
     double v = __longlong_as_double(0x7ff0000000000000ll);
-    if (i < nf && f[i].lb2 > 0.0) v = f[i].lb2;
-    v = wave_min_f64(v);
-    if (lane_id() == 0 && v < __longlong_as_double(0x7ff0000000000000ll)) atomic_min_pos_f64(&cnt->m[M_F], v);
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x)
+        if (f[i].lb2 > 0.0) v = fmin(v, f[i].lb2);
+    block_atomic_min(v, &cnt->m[M_F], sh);
 }
 
 // Frontier split: drop connected pairs, queue the due ones, keep the rest.
-__global__ void __launch_bounds__(256) k_split_frontier(TreeView t, RoundArgs r, const PairRec* fin, u32 nfin) {
-    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool have = i < nfin;
-    PairRec p;
-    p.a = p.b = 0;
-    p.lb2 = 0.0;
-    if (have) p = fin[i];
-    bool keep = have && !connected(t, p.a, p.b);
-    bool due = keep && p.lb2 <= r.beta2;
-    bool wait = keep && !due;
-    u32 s = wave_append(&r.cnt->c[C_Q], due);
-    if (due) {
-        if (s < r.cap_q) r.q[s] = p;
-        else flag_overflow(r.cnt);
+__global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs r, const PairRec* fin, u32 nfin,
+                                                           u32* qcount) {
+    __shared__ BlockAlloc S;
+    __shared__ double shm[4];
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    u32* ctr[kLists] = {qcount, &r.cnt->c[C_F], nullptr, nullptr, nullptr};
+    double minf = inf;
+    for (u32 b0 = blockIdx.x * kBlock; b0 < nfin; b0 += gridDim.x * kBlock) {
+        u32 i = b0 + threadIdx.x;
+        bool have = i < nfin;
+        PairRec p;
+        p.a = p.b = 0;
+        p.lb2 = 0.0;
+        if (have) p = fin[i];
+        bool keep = have && !connected(t, p.a, p.b);
+        bool due = keep && p.lb2 <= r.beta2;
+        bool wait = keep && !due;
+        if (wait) minf = fmin(minf, p.lb2);
+        u32 off[kLists];
+        block_alloc(S, (u64)due | ((u64)wait << 12), ctr, off);
+        if (due) {
+            if (off[0] < r.cap_q) r.q[off[0]] = p;
+            else flag_overflow(r.cnt);
+        }
+        if (wait) {
+            if (off[1] < r.cap_f) r.fout[off[1]] = p;
+            else flag_overflow(r.cnt);
+        }
     }
-    s = wave_append(&r.cnt->c[C_F], wait);
-    if (wait) {
-        if (s < r.cap_f) r.fout[s] = p;
-        else flag_overflow(r.cnt);
-    }
-    double m = wait ? p.lb2 : __longlong_as_double(0x7ff0000000000000ll);
-    m = wave_min_f64(m);
-    if (lane_id() == 0 && m < __longlong_as_double(0x7ff0000000000000ll)) atomic_min_pos_f64(&r.cnt->m[M_F], m);
+    block_atomic_min(minf, &r.cnt->m[M_F], shm);
 }
 
 // ------------------------------------------------------------ expansion
-// One lane per queued pair; each lane walks the pair's FindPair recursion
-// depth-first with a small stack in LDS, solving tiny separated pairs inline
-// and emitting larger ones to the large-pair list.  After kMaxSteps pairs, or
-// when the stack is full, remaining work is spilled to the next queue.
+// One breadth-first level of the FindPair recursion (Alg. 1) over the due
+// pairs: a well-separated pair yields its BCCP edge (computed here when the
+// pair has at most kTinyEvals point pairs, else queued for the large-pair
+// kernel); otherwise the node with the larger bounding sphere is split and
+// each child pair is dropped (connected), queued for the next level (due) or
+// parked in the frontier (lower bound above beta).
 template <int D>
-__global__ void __launch_bounds__(256) k_expand(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 nq) {
-    __shared__ u64 stk[kStackDepth][256];
-    const int tid = threadIdx.x;
+__global__ void __launch_bounds__(kBlock) k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin,
+                                                  u32 cap_in, const u32* nq_p, u32* nq_next, u32* nq_clear) {
+    __shared__ BlockAlloc S;
+    __shared__ double shm[4];
+    __shared__ unsigned long long shs[4];
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
-    u32 gi = blockIdx.x * blockDim.x + tid;
-    int sp = 0;
-    if (gi < nq) {
-        PairRec p = qin[gi];
-        stk[0][tid] = ((u64)p.a << 32) | p.b;
-        sp = 1;
-    }
+    const NodeRec<D>* N = nodes_of<D>(t);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nq_clear = 0;
+    // an overflowed previous level counts more pairs than it stored: read
+    // only what the queue holds (the overflow flag makes the round restart)
+    const u32 nq = min(*nq_p, cap_in);
+    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], &r.cnt->c[C_BIG], &r.cnt->c[C_F], nq_next};
     double minf = inf, minp = inf;
     unsigned long long visits = 0, evals = 0, solved = 0;
-    for (int step = 0; step < kMaxSteps; ++step) {
-        bool have = sp > 0;
-        if (!__any(have)) break;
-        u32 a = 0, b = 0;
-        if (have) {
-            --sp;
-            u64 pr = stk[sp][tid];
-            a = (u32)(pr >> 32);
-            b = (u32)pr;
-        }
+    for (u32 b0 = blockIdx.x * kBlock; b0 < nq; b0 += gridDim.x * kBlock) {
+        u32 i = b0 + threadIdx.x;
+        bool have = i < nq;
         bool to_c = false, to_p = false, to_big = false;
         EdgeOut e;
-        u32 ch[2] = {0, 0}, oth = 0;
-        bool ch_front[2] = {false, false}, ch_spill[2] = {false, false};
-        double ch_lb[2] = {0.0, 0.0};
+        u32 a = 0, b = 0, oth = 0;
+        u32 ch[2] = {0, 0};
+        double lbc[2] = {0.0, 0.0};
+        int nfront = 0, nnext = 0;
+        bool cf[2] = {false, false}, cq[2] = {false, false};
         if (have) {
+            PairRec pr = qin[i];
+            a = pr.a;
+            b = pr.b;
             ++visits;
-            int2 ra = t.rng[a], rb = t.rng[b];
-            if (well_separated<D>(t, hdb, a, b, ra.y, rb.y)) {
-                u64 work = (u64)ra.y * (u64)rb.y;
+            NodeRec<D> A = N[a], B = N[b];
+            if (well_separated<D>(A, B, hdb)) {
+                u64 work = (u64)A.count * (u64)B.count;
                 if (work <= (u64)kTinyEvals) {
-                    e = point_edge<D>(t, hdb, (u32)ra.x, (u32)rb.x);
-                    for (int i = ra.x; i < ra.x + ra.y; ++i)
-                        for (int j = rb.x; j < rb.x + rb.y; ++j) {
-                            EdgeOut c = point_edge<D>(t, hdb, (u32)i, (u32)j);
+                    e = point_edge<D>(t, hdb, (u32)A.first, (u32)B.first);
+                    for (int x = A.first; x < A.first + A.count; ++x)
+                        for (int y = B.first; y < B.first + B.count; ++y) {
+                            EdgeOut c = point_edge<D>(t, hdb, (u32)x, (u32)y);
                             if (key_less(c.k, e.k)) e = c;
                         }
                     evals += work;
@@ -292,102 +374,68 @@ __global__ void __launch_bounds__(256) k_expand(TreeView t, RoundArgs r, int hdb
                 }
             } else {
                 // split the node with the larger bounding sphere (Alg. 1, FindPair)
-                bool split_a = (rb.y == 1) || (ra.y > 1 && (t.rad[a] > t.rad[b] ||
-                                                            (t.rad[a] == t.rad[b] && ra.y >= rb.y)));
-                u32 x = split_a ? a : b;
+                bool split_a = (B.count == 1) || (A.count > 1 && (A.rad > B.rad || (A.rad == B.rad && A.count >= B.count)));
+                const NodeRec<D>& X = split_a ? A : B;
+                const NodeRec<D>& O = split_a ? B : A;
                 oth = split_a ? b : a;
-                int2 kk = t.kids[x];
-                ch[0] = (u32)kk.x;
-                ch[1] = (u32)kk.y;
+                ch[0] = (u32)X.left;
+                ch[1] = (u32)X.right;
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     if (connected(t, ch[c], oth)) continue;
-                    double lb = pair_wlb2<D>(t, hdb, ch[c], oth);
-                    ch_lb[c] = lb;
+                    double lb = pair_wlb2<D>(N[ch[c]], O, hdb);
+                    lbc[c] = lb;
                     if (lb > r.beta2) {
-                        ch_front[c] = true;
+                        cf[c] = true;
+                        ++nfront;
                         minf = fmin(minf, lb);
-                    } else if (sp < kStackDepth) {
-                        stk[sp][tid] = ((u64)ch[c] << 32) | oth;
-                        ++sp;
                     } else {
-                        ch_spill[c] = true;
+                        cq[c] = true;
+                        ++nnext;
                     }
                 }
             }
         }
-        // appends (all lanes of the wave take part)
-        u32 s = wave_append(&r.cnt->c[C_C], to_c);
+        u64 packed = (u64)to_c | ((u64)to_p << 12) | ((u64)to_big << 24) | ((u64)nfront << 36) |
+                     ((u64)nnext << 48);
+        u32 off[kLists];
+        block_alloc(S, packed, ctr, off);
         if (to_c) {
-            if (s < r.cap_c) put_edge(r.c, s, e);
+            if (off[0] < r.cap_c) put_edge(r.c, off[0], e);
             else flag_overflow(r.cnt);
         }
-        s = wave_append(&r.cnt->c[C_P], to_p);
         if (to_p) {
-            if (s < r.cap_p) put_edge(r.pout, s, e);
+            if (off[1] < r.cap_p) put_edge(r.pout, off[1], e);
             else flag_overflow(r.cnt);
         }
-        s = wave_append(&r.cnt->c[C_BIG], to_big);
         if (to_big) {
-            if (s < r.cap_big) r.big[s] = make_uint2(a, b);
+            if (off[2] < r.cap_big) r.big[off[2]] = make_uint2(a, b);
             else flag_overflow(r.cnt);
         }
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            s = wave_append(&r.cnt->c[C_F], ch_front[c]);
-            if (ch_front[c]) {
-                if (s < r.cap_f) {
-                    PairRec p;
-                    p.a = ch[c];
-                    p.b = oth;
-                    p.lb2 = ch_lb[c];
-                    r.fout[s] = p;
-                } else {
-                    flag_overflow(r.cnt);
-                }
+            PairRec p;
+            p.a = ch[c];
+            p.b = oth;
+            p.lb2 = lbc[c];
+            if (cf[c]) {
+                if (off[3] < r.cap_f) r.fout[off[3]] = p;
+                else flag_overflow(r.cnt);
+                ++off[3];
             }
-            s = wave_append(&r.cnt->c[C_QN], ch_spill[c]);
-            if (ch_spill[c]) {
-                if (s < r.cap_q) {
-                    PairRec p;
-                    p.a = ch[c];
-                    p.b = oth;
-                    p.lb2 = ch_lb[c];
-                    r.q[s] = p;
-                } else {
-                    flag_overflow(r.cnt);
-                }
+            if (cq[c]) {
+                if (off[4] < r.cap_q) r.q[off[4]] = p;
+                else flag_overflow_q(r.cnt);
+                ++off[4];
             }
         }
     }
-    // spill what is left on the stacks
-    for (int i = 0; i < kStackDepth; ++i) {
-        bool sp_i = i < sp;
-        if (!__any(sp_i)) break;
-        u32 s = wave_append(&r.cnt->c[C_QN], sp_i);
-        if (sp_i) {
-            if (s < r.cap_q) {
-                u64 pr = stk[i][tid];
-                PairRec p;
-                p.a = (u32)(pr >> 32);
-                p.b = (u32)pr;
-                p.lb2 = 0.0;  // already known to be due
-                r.q[s] = p;
-            } else {
-                flag_overflow(r.cnt);
-            }
-        }
-    }
-    minf = wave_min_f64(minf);
-    minp = wave_min_f64(minp);
-    for (int o = 32; o > 0; o >>= 1) {
-        visits += __shfl_xor(visits, o);
-        evals += __shfl_xor(evals, o);
-        solved += __shfl_xor(solved, o);
-    }
-    if (lane_id() == 0) {
-        if (minf < inf) atomic_min_pos_f64(&r.cnt->m[M_F], minf);
-        if (minp < inf) atomic_min_pos_f64(&r.cnt->m[M_P], minp);
+    block_atomic_min(minf, &r.cnt->m[M_F], shm);
+    block_atomic_min(minp, &r.cnt->m[M_P], shm);
+    visits = block_sum_u64(visits, shs);
+    evals = block_sum_u64(evals, shs);
+    solved = block_sum_u64(solved, shs);
+    if (threadIdx.x == 0 && visits) {
         atomicAdd(&r.cnt->c64[C64_VISITS], visits);
         atomicAdd(&r.cnt->c64[C64_EVALS], evals);
         atomicAdd(&r.cnt->c64[C64_BCCP], solved);
@@ -409,9 +457,11 @@ struct PartKey {
     u64 ids, pos;
 };
 
+template <int D>
 __device__ __forceinline__ void big_orient(const TreeView& t, uint2 pr, int2& ra, int2& rb) {
-    ra = t.rng[pr.x];
-    rb = t.rng[pr.y];
+    const NodeRec<D>* N = nodes_of<D>(t);
+    ra = make_int2(N[pr.x].first, N[pr.x].count);
+    rb = make_int2(N[pr.y].first, N[pr.y].count);
     if (rb.y > ra.y) {
         int2 x = ra;
         ra = rb;
@@ -419,11 +469,12 @@ __device__ __forceinline__ void big_orient(const TreeView& t, uint2 pr, int2& ra
     }
 }
 
+template <int D>
 __global__ void k_big_ntasks(TreeView t, const uint2* big, u32 nbig, u32* ntask) {
     u32 i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nbig) return;
     int2 ra, rb;
-    big_orient(t, big[i], ra, rb);
+    big_orient<D>(t, big[i], ra, rb);
     ntask[i] = (u32)(((ra.y + kBigA - 1) / kBigA) * ((rb.y + kBigB - 1) / kBigB));
 }
 
@@ -442,7 +493,7 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
         else hi = mid - 1;
     }
     int2 ra, rb;
-    big_orient(t, big[lo], ra, rb);
+    big_orient<D>(t, big[lo], ra, rb);
     u32 local = task - toff[lo];
     int nbt = (rb.y + kBigB - 1) / kBigB;
     int ta = (int)(local / (u32)nbt), tb = (int)(local % (u32)nbt);
@@ -532,73 +583,86 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
     }
 }
 
-__global__ void k_big_combine(RoundArgs r, u32 nbig, const u32* toff, const u32* ntask, const PartKey* part) {
-    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool have = i < nbig;
-    PartKey b;
-    b.w2 = __longlong_as_double(0x7ff0000000000000ll);
-    b.e2 = b.w2;
-    b.ids = ~0ull;
-    b.pos = 0;
-    if (have) {
-        u32 o = toff[i], c = ntask[i];
-        b = part[o];
-        for (u32 k = 1; k < c; ++k) {
-            PartKey x = part[o + k];
-            bool less = (x.w2 != b.w2) ? (x.w2 < b.w2) : (x.e2 != b.e2) ? (x.e2 < b.e2) : (x.ids < b.ids);
-            if (less) b = x;
+__global__ void __launch_bounds__(kBlock) k_big_combine(RoundArgs r, u32 nbig, const u32* toff, const u32* ntask,
+                                                        const PartKey* part) {
+    __shared__ BlockAlloc S;
+    __shared__ double shm[4];
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], nullptr, nullptr, nullptr};
+    double minp = inf;
+    for (u32 b0 = blockIdx.x * kBlock; b0 < nbig; b0 += gridDim.x * kBlock) {
+        u32 i = b0 + threadIdx.x;
+        bool have = i < nbig;
+        PartKey b;
+        b.w2 = inf;
+        b.e2 = inf;
+        b.ids = ~0ull;
+        b.pos = 0;
+        if (have) {
+            u32 o = toff[i], c = ntask[i];
+            b = part[o];
+            for (u32 k = 1; k < c; ++k) {
+                PartKey x = part[o + k];
+                bool less = (x.w2 != b.w2) ? (x.w2 < b.w2) : (x.e2 != b.e2) ? (x.e2 < b.e2) : (x.ids < b.ids);
+                if (less) b = x;
+            }
+        }
+        bool to_c = have && b.w2 <= r.beta2;
+        bool to_p = have && !to_c;
+        if (to_p) minp = fmin(minp, b.w2);
+        u32 off[kLists];
+        block_alloc(S, (u64)to_c | ((u64)to_p << 12), ctr, off);
+        if (to_c) {
+            if (off[0] < r.cap_c) put_edge_raw(r.c, off[0], b.w2, b.e2, b.ids, b.pos);
+            else flag_overflow(r.cnt);
+        }
+        if (to_p) {
+            if (off[1] < r.cap_p) put_edge_raw(r.pout, off[1], b.w2, b.e2, b.ids, b.pos);
+            else flag_overflow(r.cnt);
         }
     }
-    bool to_c = have && b.w2 <= r.beta2;
-    bool to_p = have && !to_c;
-    u32 s = wave_append(&r.cnt->c[C_C], to_c);
-    if (to_c) {
-        if (s < r.cap_c) put_edge_raw(r.c, s, b.w2, b.e2, b.ids, b.pos);
-        else flag_overflow(r.cnt);
-    }
-    s = wave_append(&r.cnt->c[C_P], to_p);
-    if (to_p) {
-        if (s < r.cap_p) put_edge_raw(r.pout, s, b.w2, b.e2, b.ids, b.pos);
-        else flag_overflow(r.cnt);
-    }
-    double m = to_p ? b.w2 : __longlong_as_double(0x7ff0000000000000ll);
-    m = wave_min_f64(m);
-    if (lane_id() == 0 && m < __longlong_as_double(0x7ff0000000000000ll)) atomic_min_pos_f64(&r.cnt->m[M_P], m);
+    block_atomic_min(minp, &r.cnt->m[M_P], shm);
 }
 
 // ------------------------------------------------------------ pool split
 // Deferred BCCP edges: drop the ones whose ends are now connected, commit
 // those within the new beta, keep the rest.
-__global__ void __launch_bounds__(256) k_split_pool(RoundArgs r, EdgeList pin, u32 npin) {
-    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool have = i < npin;
-    double w2 = 0.0, e2 = 0.0;
-    u64 ids = 0, pos = 0;
-    bool keep = false;
-    if (have) {
-        pos = pin.pos[i];
-        keep = r.uf[(u32)(pos >> 32)] != r.uf[(u32)pos];
-        if (keep) {
-            w2 = pin.w2[i];
-            e2 = pin.e2[i];
-            ids = pin.ids[i];
+__global__ void __launch_bounds__(kBlock) k_split_pool(RoundArgs r, EdgeList pin, u32 npin) {
+    __shared__ BlockAlloc S;
+    __shared__ double shm[4];
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], nullptr, nullptr, nullptr};
+    double minp = inf;
+    for (u32 b0 = blockIdx.x * kBlock; b0 < npin; b0 += gridDim.x * kBlock) {
+        u32 i = b0 + threadIdx.x;
+        bool have = i < npin;
+        double w2 = 0.0, e2 = 0.0;
+        u64 ids = 0, pos = 0;
+        bool keep = false;
+        if (have) {
+            pos = pin.pos[i];
+            keep = r.uf[(u32)(pos >> 32)] != r.uf[(u32)pos];
+            if (keep) {
+                w2 = pin.w2[i];
+                e2 = pin.e2[i];
+                ids = pin.ids[i];
+            }
+        }
+        bool to_c = keep && w2 <= r.beta2;
+        bool to_p = keep && !to_c;
+        if (to_p) minp = fmin(minp, w2);
+        u32 off[kLists];
+        block_alloc(S, (u64)to_c | ((u64)to_p << 12), ctr, off);
+        if (to_c) {
+            if (off[0] < r.cap_c) put_edge_raw(r.c, off[0], w2, e2, ids, pos);
+            else flag_overflow(r.cnt);
+        }
+        if (to_p) {
+            if (off[1] < r.cap_p) put_edge_raw(r.pout, off[1], w2, e2, ids, pos);
+            else flag_overflow(r.cnt);
         }
     }
-    bool to_c = keep && w2 <= r.beta2;
-    bool to_p = keep && !to_c;
-    u32 s = wave_append(&r.cnt->c[C_C], to_c);
-    if (to_c) {
-        if (s < r.cap_c) put_edge_raw(r.c, s, w2, e2, ids, pos);
-        else flag_overflow(r.cnt);
-    }
-    s = wave_append(&r.cnt->c[C_P], to_p);
-    if (to_p) {
-        if (s < r.cap_p) put_edge_raw(r.pout, s, w2, e2, ids, pos);
-        else flag_overflow(r.cnt);
-    }
-    double m = to_p ? w2 : __longlong_as_double(0x7ff0000000000000ll);
-    m = wave_min_f64(m);
-    if (lane_id() == 0 && m < __longlong_as_double(0x7ff0000000000000ll)) atomic_min_pos_f64(&r.cnt->m[M_P], m);
+    block_atomic_min(minp, &r.cnt->m[M_P], shm);
 }
 
 // ------------------------------------------------------------ Kruskal
@@ -637,68 +701,75 @@ __device__ __forceinline__ u32 uf_find(u32* parent, u32 x, Counters* cnt) {
 // Boruvka step on the committed edges in key-rank order: every component
 // picks its lightest incident edge (atomic minimum of the rank); all picked
 // edges are tree edges by the cut property; components hook along them.
-__global__ void k_bor_pick(const u32* alive, const u32* nalive_p, const u32* perm, const EdgeList L, u32* parent,
-                           u32* best, u32* ru, u32* rv, Counters* cnt) {
-    u32 s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= *nalive_p) return;
+__global__ void k_bor_pick(const u32* alive, const u32* nalive_p, u32 cap, const u32* perm, const EdgeList L,
+                           u32* parent, u32* best, u32* ru, u32* rv, Counters* cnt) {
+    const u32 na = min(*nalive_p, cap);
+    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < na; s += gridDim.x * blockDim.x) {
     u32 rank = alive[s];
     u64 pos = L.pos[perm[rank]];
     u32 a = uf_find(parent, (u32)(pos >> 32), cnt);
     u32 b = uf_find(parent, (u32)pos, cnt);
     if (a == b) {
         ru[s] = kNone;
-        return;
+        continue;
     }
     ru[s] = a;
     rv[s] = b;
     atomicMin(&best[a], rank);
     atomicMin(&best[b], rank);
+    }
 }
 
-__global__ void k_bor_hook(const u32* alive, const u32* nalive_p, const u32* perm, const EdgeList L, u32* parent,
-                           const u32* best, const u32* ru, const u32* rv, u32* alive_next, u32* nalive_next,
-                           EdgeList out, u32 cap_out, Counters* cnt) {
-    u32 s = blockIdx.x * blockDim.x + threadIdx.x;
-    u32 na = *nalive_p;
-    bool have = s < na;
-    u32 a = have ? ru[s] : kNone;
-    bool live = have && a != kNone;
-    bool sel = false, keep = false;
-    u32 rank = 0, e = 0;
-    if (live) {
-        u32 b = rv[s];
-        rank = alive[s];
-        bool pa = best[a] == rank, pb = best[b] == rank;
-        sel = pa || pb;
-        keep = !sel;
-        if (sel) {
-            e = perm[rank];
-            if (pa && pb) {
-                u32 hi = a > b ? a : b, lo = a > b ? b : a;
-                parent[hi] = lo;
-            } else if (pa) {
-                parent[a] = b;
-            } else {
-                parent[b] = a;
+__global__ void __launch_bounds__(kBlock) k_bor_hook(const u32* alive, const u32* nalive_p, u32 cap, const u32* perm,
+                                                     const EdgeList L, u32* parent, const u32* best, const u32* ru,
+                                                     const u32* rv, u32* alive_next, u32* nalive_next, EdgeList out,
+                                                     u32 cap_out, Counters* cnt) {
+    __shared__ BlockAlloc S;
+    const u32 na = min(*nalive_p, cap);
+    u32* ctr[kLists] = {&cnt->c[C_OUT], nalive_next, nullptr, nullptr, nullptr};
+    for (u32 b0 = blockIdx.x * kBlock; b0 < na; b0 += gridDim.x * kBlock) {
+        u32 s = b0 + threadIdx.x;
+        bool have = s < na;
+        u32 a = have ? ru[s] : kNone;
+        bool live = have && a != kNone;
+        bool sel = false, keep = false;
+        u32 rank = 0, e = 0;
+        if (live) {
+            u32 b = rv[s];
+            rank = alive[s];
+            bool pa = best[a] == rank, pb = best[b] == rank;
+            sel = pa || pb;
+            keep = !sel;
+            if (sel) {
+                e = perm[rank];
+                if (pa && pb) {
+                    u32 hi = a > b ? a : b, lo = a > b ? b : a;
+                    parent[hi] = lo;
+                } else if (pa) {
+                    parent[a] = b;
+                } else {
+                    parent[b] = a;
+                }
             }
         }
+        u32 off[kLists];
+        block_alloc(S, (u64)sel | ((u64)keep << 12), ctr, off);
+        if (sel) {
+            if (off[0] < cap_out) put_edge_raw(out, off[0], L.w2[e], L.e2[e], L.ids[e], L.pos[e]);
+            else flag_overflow(cnt);
+        }
+        if (keep && off[1] < cap) alive_next[off[1]] = rank;
     }
-    u32 o = wave_append(&cnt->c[C_OUT], sel);
-    if (sel) {
-        if (o < cap_out) put_edge_raw(out, o, L.w2[e], L.e2[e], L.ids[e], L.pos[e]);
-        else flag_overflow(cnt);
-    }
-    u32 k = wave_append(nalive_next, keep);
-    if (keep) alive_next[k] = rank;
 }
 
-__global__ void k_bor_reset(const u32* nalive_p, const u32* ru, const u32* rv, u32* best) {
-    u32 s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= *nalive_p) return;
-    u32 a = ru[s];
-    if (a == kNone) return;
-    best[a] = kNone;
-    best[rv[s]] = kNone;
+__global__ void k_bor_reset(const u32* nalive_p, u32 cap, const u32* ru, const u32* rv, u32* best) {
+    const u32 na = min(*nalive_p, cap);
+    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < na; s += gridDim.x * blockDim.x) {
+        u32 a = ru[s];
+        if (a == kNone) continue;
+        best[a] = kNone;
+        best[rv[s]] = kNone;
+    }
 }
 
 __global__ void k_set_u32(u32* p, u32 v) { *p = v; }
@@ -724,10 +795,11 @@ __global__ void k_boundaries(const u32* uf, int n, u32* bnd) {
     bnd[p] = (p > 0 && uf[p] != uf[p - 1]) ? 1u : 0u;
 }
 
-__global__ void k_node_comp(const int2* rng, const u32* uf, const u32* incl, int nn, int* comp) {
+template <int D>
+__global__ void k_node_comp(const NodeRec<D>* nodes, const u32* uf, const u32* incl, int nn, int* comp) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nn) return;
-    int2 r = rng[v];
+    int2 r = make_int2(nodes[v].first, nodes[v].count);
     int last = r.x + r.y - 1;
     comp[v] = (incl[last] == incl[r.x]) ? (int)uf[r.x] : -1;
 }

@@ -14,20 +14,35 @@
 
 namespace geomst {
 
+// Per-node record, one or two cache lines: tight box of the node's points,
+// radius of the sphere about the box centre (a heuristic for which node to
+// split), min / max squared core distance (HDBSCAN*), the node's contiguous
+// range of sorted positions and its children (-1 for leaves).
+template <int D>
+struct alignas(16) NodeRec {
+    double lo[D];
+    double hi[D];
+    double rad;
+    double cdmin, cdmax;
+    int first, count;
+    int left, right;
+};
+
 struct TreeView {
     int n;              // points
     const double* X;    // sorted points, row-major [n][D]
     const u32* orig;    // sorted position -> caller row index
     const double* cd2;  // sorted position -> squared core distance, or null (EMST)
-    const double* box;  // [2n-1][2D]: lo[0..D) then hi[0..D)
-    const double* rad;  // [2n-1] radius of the sphere about the box centre
-    const int2* rng;    // [2n-1] (first sorted position, count)
-    const int2* kids;   // [n-1] (left, right) node ids of internal nodes
-    const double2* cdb; // [2n-1] (min cd2, max cd2) over the node (HDBSCAN*)
+    const void* nodes;  // NodeRec<D>[2n-1]
     const int* comp;    // [2n-1] component shared by all the node's points, or -1
 };
 // Node ids: internal nodes 0..n-2 (0 is the root), the leaf of sorted
 // position p is node n-1+p.
+
+template <int D>
+__device__ __forceinline__ const NodeRec<D>* nodes_of(const TreeView& t) {
+    return (const NodeRec<D>*)t.nodes;
+}
 
 // ------------------------------------------------------------ bounding box
 template <int D>
@@ -82,23 +97,25 @@ __global__ void k_bbox_final(const double* partial, int nb, double* bbox) {
 }
 
 // ------------------------------------------------------------ Morton code
+// Keys are built in levels.  Level 0 quantises every point in the global
+// bounding box; each later level takes the groups of points whose keys are
+// still equal and quantises them again inside the group's own bounding box,
+// so the tree keeps splitting space (at the midpoint of the quantisation
+// cell) however tightly points cluster.  The keys only shape the tree.
 template <int D>
 __device__ __forceinline__ int morton_bits() {
     return (63 / D) > 31 ? 31 : (63 / D);
 }
 
 template <int D>
-__global__ void k_morton(const double* P, int n, const double* bbox, u64* key, u32* val) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__device__ __forceinline__ u64 morton_code(const double* x, const double* lo, const double* hi) {
     const int b = morton_bits<D>();
     const double top = (double)((1ull << b) - 1);
     u64 q[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        double lo = bbox[k], hi = bbox[D + k];
-        double r = hi - lo;
-        double t = r > 0.0 ? (P[(size_t)i * D + k] - lo) / r : 0.0;
+        double r = hi[k] - lo[k];
+        double t = r > 0.0 ? (x[k] - lo[k]) / r : 0.0;
         double f = floor(t * top);
         f = f < 0.0 ? 0.0 : (f > top ? top : f);
         q[k] = (u64)f;
@@ -108,8 +125,115 @@ __global__ void k_morton(const double* P, int n, const double* bbox, u64* key, u
 #pragma unroll
         for (int k = 0; k < D; ++k) c = (c << 1) | ((q[k] >> bit) & 1ull);
     }
-    key[i] = c;
+    return c;
+}
+
+template <int D>
+__global__ void k_morton(const double* P, int n, const double* bbox, u64* key, u32* val) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = morton_code<D>(P + (size_t)i * D, bbox, bbox + D);
     val[i] = (u32)i;
+}
+
+// Group starts: flag[i] = 1 where the key words [0, L) of sorted positions i
+// and i-1 differ (and at i = 0).  any_dup gets 1 if some group has >1 point.
+__global__ void k_key_flags(const u64* keys, int n, int L, u32* flag, u32* any_dup) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool dup = false;
+    if (i < n) {
+        u32 f = 1;
+        if (i > 0) {
+            f = 0;
+            for (int l = 0; l < L; ++l)
+                if (keys[(size_t)l * n + i] != keys[(size_t)l * n + i - 1]) f = 1;
+        }
+        flag[i] = f;
+        dup = (f == 0);
+    }
+    if (__any(dup) && lane_id() == 0) atomicOr(any_dup, 1u);
+}
+
+// gid[i] = group of sorted position i (inclusive scan of flags minus one);
+// start[g] = first position of group g.
+__global__ void k_group_ids(const u32* incl, int n, u32* gid, u32* start) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    u32 g = incl[i] - 1;
+    gid[i] = g;
+    if (i == 0 || incl[i] != incl[i - 1]) start[g] = (u32)i;
+}
+
+// One wave per group with more than one point: its bounding box, and
+// whether it can still be split (non-zero extent).
+template <int D>
+__global__ void k_group_box(const double* P, const u32* val, int n, const u32* start, u32 ngroups, double* gbox,
+                            u32* refinable) {
+    u32 g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (g >= ngroups) return;
+    u32 s = start[g];
+    u32 e = (g + 1 < ngroups) ? start[g + 1] : (u32)n;
+    if (e - s < 2) return;
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    double lo[D], hi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        lo[k] = inf;
+        hi[k] = -inf;
+    }
+    for (u32 i = s + lane_id(); i < e; i += kWave) {
+        const double* x = P + (size_t)val[i] * D;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            lo[k] = fmin(lo[k], x[k]);
+            hi[k] = fmax(hi[k], x[k]);
+        }
+    }
+    bool ext = false;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        lo[k] = wave_min_f64(lo[k]);
+        hi[k] = -wave_min_f64(-hi[k]);
+        ext |= hi[k] > lo[k];
+    }
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            gbox[(size_t)g * 2 * D + k] = lo[k];
+            gbox[(size_t)g * 2 * D + D + k] = hi[k];
+        }
+        if (ext) atomicOr(refinable, 1u);
+    }
+}
+
+// Next key word of every sorted position: its point quantised inside its
+// group's box (0 for single-point groups).
+template <int D>
+__global__ void k_morton_level(const double* P, const u32* val, int n, const u32* gid, const u32* start,
+                               u32 ngroups, const double* gbox, u64* key) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    u32 g = gid[i];
+    u32 s = start[g];
+    u32 e = (g + 1 < ngroups) ? start[g + 1] : (u32)n;
+    u64 c = 0;
+    if (e - s > 1) c = morton_code<D>(P + (size_t)val[i] * D, gbox + (size_t)g * 2 * D, gbox + (size_t)g * 2 * D + D);
+    key[i] = c;
+}
+
+__global__ void k_u32_to_u64(const u32* a, int n, u64* b) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// Apply a permutation of sorted positions to the point ids and key words.
+__global__ void k_apply_perm(const u32* perm, int n, int L, const u32* val_in, u32* val_out, const u64* key_in,
+                             u64* key_out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    u32 p = perm[i];
+    val_out[i] = val_in[p];
+    for (int l = 0; l < L; ++l) key_out[(size_t)l * n + i] = key_in[(size_t)l * n + p];
 }
 
 template <int D>
@@ -123,95 +247,176 @@ __global__ void k_permute(const double* P, int n, const u32* val, double* X, u32
 }
 
 // ------------------------------------------------------ binary radix tree
-// Common-prefix length of the codes at sorted positions i and j (equal codes
-// are told apart by their positions), -1 outside [0, n).
-__device__ __forceinline__ int prefix_len(const u64* k, int n, int i, int j) {
+// Common-prefix length of the multi-word keys at sorted positions i and j
+// (equal keys are told apart by their positions), -1 outside [0, n).
+__device__ __forceinline__ int prefix_len(const u64* k, int n, int L, int i, int j) {
     if (j < 0 || j >= n) return -1;
-    u64 a = k[i], b = k[j];
-    if (a == b) return 64 + __clz((int)(i ^ j));
-    return __clzll((long long)(a ^ b));
+    for (int l = 0; l < L; ++l) {
+        u64 a = k[(size_t)l * n + i], b = k[(size_t)l * n + j];
+        if (a != b) return 64 * l + __clzll((long long)(a ^ b));
+    }
+    return 64 * L + __clz((int)(i ^ j));
 }
 
-__global__ void k_karras(const u64* k, int n, int2* rng, int2* kids, int* parent) {
+template <int D>
+__global__ void k_karras(const u64* k, int n, int L, NodeRec<D>* nodes, int* parent) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
-    int dir = (prefix_len(k, n, i, i + 1) - prefix_len(k, n, i, i - 1)) > 0 ? 1 : -1;
-    int dmin = prefix_len(k, n, i, i - dir);
+    int dir = (prefix_len(k, n, L, i, i + 1) - prefix_len(k, n, L, i, i - 1)) > 0 ? 1 : -1;
+    int dmin = prefix_len(k, n, L, i, i - dir);
     int lmax = 2;
-    while (prefix_len(k, n, i, i + lmax * dir) > dmin) lmax <<= 1;
+    while (prefix_len(k, n, L, i, i + lmax * dir) > dmin) lmax <<= 1;
     int l = 0;
     for (int t = lmax >> 1; t >= 1; t >>= 1)
-        if (prefix_len(k, n, i, i + (l + t) * dir) > dmin) l += t;
+        if (prefix_len(k, n, L, i, i + (l + t) * dir) > dmin) l += t;
     int j = i + l * dir;
-    int dnode = prefix_len(k, n, i, j);
+    int dnode = prefix_len(k, n, L, i, j);
     int s = 0;
     int t = l;
     do {
         t = (t + 1) >> 1;
-        if (prefix_len(k, n, i, i + (s + t) * dir) > dnode) s += t;
+        if (prefix_len(k, n, L, i, i + (s + t) * dir) > dnode) s += t;
     } while (t > 1);
     int g = i + s * dir + (dir < 0 ? -1 : 0);
     int first = min(i, j), last = max(i, j);
     int left = (first == g) ? (n - 1 + g) : g;
     int right = (last == g + 1) ? (n - 1 + g + 1) : (g + 1);
-    rng[i] = make_int2(first, last - first + 1);
-    kids[i] = make_int2(left, right);
+    nodes[i].first = first;
+    nodes[i].count = last - first + 1;
+    nodes[i].left = left;
+    nodes[i].right = right;
     parent[left] = i;
     parent[right] = i;
     if (i == 0) parent[0] = -1;
 }
 
 // ------------------------------------------------------------ node bounds
-// Leaves take their point's box; every internal node is finished by the
-// second of its two children to arrive (bottom-up climb with arrival counters).
+// Bottom-up: every internal node is finished by the second of its two
+// children to arrive.  A block owns 256 consecutive leaves; nodes whose range
+// lies inside the block's leaves are merged through LDS (arrival counters and
+// boxes, workgroup-scope ordering only), and only the few nodes spanning
+// several blocks use global arrival counters with device-scope fences.
+constexpr int kBoundsBlock = 256;
+
 template <int D>
-__device__ __forceinline__ void merge_node(int v, const int2* kids, double* box, double* rad, double2* cdb,
-                                           bool geometry, bool cdbounds) {
-    int2 c = kids[v];
-    if (geometry) {
-        double s = 0.0;
+__device__ __forceinline__ void leaf_rec(const double* X, const double* cd2, int p, double* lo, double* hi,
+                                         double2& cd) {
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            double lo = fmin(box[(size_t)c.x * 2 * D + k], box[(size_t)c.y * 2 * D + k]);
-            double hi = fmax(box[(size_t)c.x * 2 * D + D + k], box[(size_t)c.y * 2 * D + D + k]);
-            box[(size_t)v * 2 * D + k] = lo;
-            box[(size_t)v * 2 * D + D + k] = hi;
-            double t = hi - lo;
-            s = s + t * t;
-        }
-        rad[v] = 0.5 * sqrt(s);
-    }
-    if (cdbounds) {
-        double2 a = cdb[c.x], b = cdb[c.y];
-        cdb[v] = make_double2(fmin(a.x, b.x), fmax(a.y, b.y));
-    }
+    for (int k = 0; k < D; ++k) lo[k] = hi[k] = X[(size_t)p * D + k];
+    double c = cd2 ? cd2[p] : 0.0;
+    cd = make_double2(c, c);
 }
 
 template <int D>
-__global__ void k_bounds(int n, const double* X, const double* cd2, const int2* kids, const int* parent,
-                         double* box, double* rad, double2* cdb, int2* rng, u32* flags, int geometry,
-                         int cdbounds) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBoundsBlock) k_bounds(int n, const double* X, const double* cd2,
+                                                         const int* parent, NodeRec<D>* nodes, u32* gflags,
+                                                         int geometry) {
+    __shared__ u32 lflag[kBoundsBlock];
+    __shared__ double slo[kBoundsBlock][D], shi[kBoundsBlock][D];
+    __shared__ double2 scd[kBoundsBlock];
+    const int base = blockIdx.x * kBoundsBlock;
+    const int end = min(base + kBoundsBlock, n);  // leaves [base, end)
+    lflag[threadIdx.x] = 0;
+    __syncthreads();
+    int p = base + threadIdx.x;
     if (p >= n) return;
     int leaf = n - 1 + p;
-    if (geometry) {
+    {
+        NodeRec<D>& L = nodes[leaf];
+        double lo[D], hi[D];
+        double2 cd;
+        leaf_rec<D>(X, cd2, p, lo, hi, cd);
+        if (geometry) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                L.lo[k] = lo[k];
+                L.hi[k] = hi[k];
+            }
+            L.rad = 0.0;
+            L.first = p;
+            L.count = 1;
+            L.left = -1;
+            L.right = -1;
+        }
+        L.cdmin = cd.x;
+        L.cdmax = cd.y;
+    }
+    int v = parent[leaf];
+    bool global_phase = false;
+    while (v >= 0) {
+        NodeRec<D>& V = nodes[v];
+        int f = V.first, c = V.count;
+        bool inblock = !global_phase && f >= base && f + c <= end;
+        int2 ch = make_int2(V.left, V.right);
+        double lo[D], hi[D], lo2[D], hi2[D];
+        double2 ca, cb;
+        if (inblock) {
+            __threadfence_block();
+            if (atomicAdd(&lflag[v - base], 1u) == 0) return;
+            __threadfence_block();
+            // children lie in this block: leaves from X, internal nodes from LDS
+            if (ch.x >= n - 1) leaf_rec<D>(X, cd2, ch.x - (n - 1), lo, hi, ca);
+            else {
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    lo[k] = slo[ch.x - base][k];
+                    hi[k] = shi[ch.x - base][k];
+                }
+                ca = scd[ch.x - base];
+            }
+            if (ch.y >= n - 1) leaf_rec<D>(X, cd2, ch.y - (n - 1), lo2, hi2, cb);
+            else {
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    lo2[k] = slo[ch.y - base][k];
+                    hi2[k] = shi[ch.y - base][k];
+                }
+                cb = scd[ch.y - base];
+            }
+        } else {
+            global_phase = true;
+            __threadfence();
+            if (atomicAdd(&gflags[v], 1u) == 0) return;
+            __threadfence();
+            const volatile NodeRec<D>* A = nodes + ch.x;
+            const volatile NodeRec<D>* B = nodes + ch.y;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                lo[k] = A->lo[k];
+                hi[k] = A->hi[k];
+                lo2[k] = B->lo[k];
+                hi2[k] = B->hi[k];
+            }
+            ca = make_double2(A->cdmin, A->cdmax);
+            cb = make_double2(B->cdmin, B->cdmax);
+        }
+        double s = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            double x = X[(size_t)p * D + k];
-            box[(size_t)leaf * 2 * D + k] = x;
-            box[(size_t)leaf * 2 * D + D + k] = x;
+            lo[k] = fmin(lo[k], lo2[k]);
+            hi[k] = fmax(hi[k], hi2[k]);
+            double x = hi[k] - lo[k];
+            s = s + x * x;
         }
-        rad[leaf] = 0.0;
-        rng[leaf] = make_int2(p, 1);
-    }
-    if (cdbounds) cdb[leaf] = make_double2(cd2[p], cd2[p]);
-    int v = parent[leaf];
-    while (v >= 0) {
-        __threadfence();
-        u32 old = atomicAdd(&flags[v], 1u);
-        if (old == 0) return;  // the sibling's thread finishes this node
-        __threadfence();
-        merge_node<D>(v, kids, box, rad, cdb, geometry, cdbounds);
+        double2 cd = make_double2(fmin(ca.x, cb.x), fmax(ca.y, cb.y));
+        if (inblock) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                slo[v - base][k] = lo[k];
+                shi[v - base][k] = hi[k];
+            }
+            scd[v - base] = cd;
+        }
+        if (geometry) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                V.lo[k] = lo[k];
+                V.hi[k] = hi[k];
+            }
+            V.rad = 0.5 * sqrt(s);
+        }
+        V.cdmin = cd.x;
+        V.cdmax = cd.y;
         v = parent[v];
     }
 }
@@ -247,11 +452,11 @@ __device__ __forceinline__ double sqdist(const double (&a)[D], const double* b) 
 // Squared distance from a point to a box, computed so that it never exceeds
 // the computed squared distance to any point of the box.
 template <int D>
-__device__ __forceinline__ double point_box_lb2(const double (&q)[D], const double* bx) {
+__device__ __forceinline__ double point_box_lb2(const double (&q)[D], const double* lo, const double* hi) {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        double g = fmax(fmax(bx[k] - q[k], q[k] - bx[D + k]), 0.0);
+        double g = fmax(fmax(lo[k] - q[k], q[k] - hi[k]), 0.0);
         s = s + g * g;
     }
     return s;
@@ -281,10 +486,11 @@ __global__ void __launch_bounds__(64) k_knn(TreeView t, int kk, double* cd2_out,
         --sp;
         int v = stack[sp];
         __syncthreads();
-        double lb = point_box_lb2<D>(q, t.box + (size_t)v * 2 * D);
+        const NodeRec<D>* N = nodes_of<D>(t);
+        double lb = point_box_lb2<D>(q, N[v].lo, N[v].hi);
         bool want = live && lb < kth;
         if (!__any(want)) continue;
-        int2 r = t.rng[v];
+        int2 r = make_int2(N[v].first, N[v].count);
         if (r.y <= kKnnLeaf) {
             for (int j = r.x; j < r.x + r.y; ++j) {
                 double dd = sqdist<D>(q, t.X + (size_t)j * D);
@@ -298,10 +504,10 @@ __global__ void __launch_bounds__(64) k_knn(TreeView t, int kk, double* cd2_out,
                 if (lane_id() == 0) atomicOr(err, 4u);
                 continue;
             }
-            int2 c = t.kids[v];
+            int2 c = make_int2(N[v].left, N[v].right);
             // visit first the child nearer to lane 0's query
-            double la = point_box_lb2<D>(q, t.box + (size_t)c.x * 2 * D);
-            double lr = point_box_lb2<D>(q, t.box + (size_t)c.y * 2 * D);
+            double la = point_box_lb2<D>(q, N[c.x].lo, N[c.x].hi);
+            double lr = point_box_lb2<D>(q, N[c.y].lo, N[c.y].hi);
             bool leftfirst = __shfl(la <= lr ? 1 : 0, 0) != 0;
             if (lane_id() == 0) {
                 stack[sp] = leftfirst ? c.y : c.x;

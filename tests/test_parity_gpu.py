@@ -197,6 +197,25 @@ def test_repeatable_and_schedule_independent(G):
         G.set_option("beta_growth", 2.0)
 
 
+def test_list_overflow_restarts(G):
+    """Tiny initial list capacities force overflow, growth and round restarts;
+    the result must not change."""
+    p = W.mixture(12000, 3, seed=51, k=7, noise_frac=0.05)
+    q = W.mixture(6000, 5, seed=52, k=7, noise_frac=0.05)
+    ref = run_emst(G, p)
+    refh = run_hdb(G, q, 8)
+    try:
+        G.set_option("list_capacity_scale", 1e-4)
+        out = run_emst(G, p)
+        outh = run_hdb(G, q, 8)
+    finally:
+        G.set_option("list_capacity_scale", 1.0)
+    assert all(same(a, b) for a, b in zip(ref, out))
+    assert all(same(a, b) for a, b in zip(refh, outh))
+    eo, w2o, _ = oracle.emst(p)
+    assert np.array_equal(out[0], eo) and same(out[2], w2o)
+
+
 # ------------------------------------------------------------ full sizes
 def tree_order(n, e):
     """DFS preorder, parent and subtree sizes of the returned spanning tree
