@@ -69,11 +69,42 @@ def unit_model(fam, st, d):
     return None, None, None
 
 
+FAMILY_KERNEL = {"expand": "k_level", "bccp": "k_big_bccp", "sort": "k_radix", "kruskal": "k_bor"}
+
+
+def source_sha():
+    """Hash of the library sources (a traffic figure measured on other sources is stale)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2104_01126_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(family, workload):
+    """HBM bytes per launch of the family's kernel from the committed rocprofv3
+    PMC summary, or None when there is none or the sources changed since."""
+    k = FAMILY_KERNEL.get(family)
+    path = os.path.join(ROOT, "profiles", f"{k}_{workload}_traffic.txt")
+    if not k or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            a, b = line.strip().split("=", 1)
+            kv[a] = b
+    if kv.get("source_sha") != source_sha():
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(name, pts, min_pts, target_s=15.0):
     import oracle
     oracle.build(force=False)
     n = len(pts)
-    m0 = min(n, 12000)
+    m0 = min(n, 30000)
     t = time.perf_counter()
     if min_pts:
         oracle.hdbscan(pts[:m0], min_pts)
@@ -101,6 +132,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="emst_1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy three times (reference for PMC byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the library has no multi-GPU path.",
@@ -118,12 +151,21 @@ def main():
     G.load()
     x = torch.from_numpy(pts).to("cuda:0")
     torch.cuda.synchronize()
+    if a.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 x 1 GiB device-to-device copies done")
     for i in range(a.warmup):
         solve(G, x, mp)
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{a.warmup}: {G.stats().ms_total:.2f} ms")
     G.set_option("kernel_timing", 1)
     kms = np.zeros(16)
+    kl = np.zeros(16)
     agg = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -131,6 +173,7 @@ def main():
         solve(G, x, mp)
         st = G.stats()
         kms += np.array(st.kernel_ms)
+        kl += np.array(st.kernel_launches)
         if agg is None:
             agg = {k: 0 for k in ("pair_visits", "bccp_evals", "big_evals", "sort_elems", "committed_edges",
                                   "bccp_pairs", "rounds")}
@@ -166,8 +209,12 @@ def main():
             ach, peak = amount / secs / 1e12, FP64_PEAK_TFLOPS
         else:
             ach, peak = amount / secs / 1e9, HBM_PEAK_GBS
+        launches = max(int(kl[i]), 1)
         roof = {"kernel": fams[i], "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-                "frac": round(ach / peak, 5), "traffic": None,
+                "frac": round(ach / peak, 5), "traffic": measured_traffic(fams[i], a.workload),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-scaled)",
+                "algorithmic_per_launch": round(amount / launches, 1),
+                "launches_per_step": launches / a.steps,
                 "device_ms_per_step": round(kms[i] / a.steps, 4),
                 "share_of_device_time": round(kms[i] / max(kms.sum(), 1e-9), 4)}
         break

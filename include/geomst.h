@@ -127,8 +127,9 @@ int geomst_get_stats(geomst_stats_t* out);
 
 /*
  * Tuning knobs (they never change the result):
- *   "beta_growth"    factor applied to the weight threshold between rounds
- *                    (default 2: the threshold doubles each round), must be > 1.
+ *   "beta_growth"    factor applied to the weight threshold between rounds,
+ *                    > 1; 0 restores the default (2 for EMST: the threshold
+ *                    doubles each round; sqrt(2) for HDBSCAN*).
  *   "list_capacity_scale"  (0,1]: scale of the initial capacities of the
  *                    internal pair and edge lists (default 1); small values make
  *                    the lists overflow, grow and restart rounds (a testing aid).

@@ -23,7 +23,7 @@ namespace {
 
 thread_local std::string g_err;
 thread_local geomst_stats_t g_stats;
-double g_beta_growth = 2.0;
+double g_beta_growth = 0.0;  // 0: 2 for EMST, sqrt(2) for HDBSCAN*
 double g_capacity_scale = 1.0;
 constexpr int kMaxKeyLevels = 6;
 constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
@@ -509,7 +509,8 @@ struct Solver {
         u64 b0 = D.hcnt->m[M_F];
         double beta2 = (b0 == ~0ull) ? 0.0 : bits_to_double(b0);
         u32 nF = (u32)(n - 1), nP = 0;
-        const double g2 = g_beta_growth * g_beta_growth;
+        const double growth = g_beta_growth > 0.0 ? g_beta_growth : (hdb ? 1.4142135623730951 : 2.0);
+        const double g2 = growth * growth;
         u64 committed = 0, maxf = nF, big_pairs = 0;
         int rounds = 0;
         u32 nout = 0;
@@ -928,7 +929,7 @@ int geomst_get_stats(geomst_stats_t* out) {
 int geomst_set_option(const char* name, double value) {
     if (!name) return GEOMST_EINVAL;
     if (!strcmp(name, "beta_growth")) {
-        if (!(value > 1.0) || !(value < 1e6)) return GEOMST_EINVAL;
+        if (value != 0.0 && (!(value > 1.0) || !(value < 1e6))) return GEOMST_EINVAL;
         g_beta_growth = value;
         return GEOMST_OK;
     }

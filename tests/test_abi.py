@@ -71,6 +71,9 @@ def test_options(lib):
     assert lib.geomst_set_option(b"beta_growth", float("nan")) == G.EINVAL
     assert lib.geomst_set_option(b"no_such_option", 2.0) == G.EINVAL
     assert lib.geomst_set_option(b"beta_growth", 2.0) == G.OK
+    assert lib.geomst_set_option(b"beta_growth", 0.0) == G.OK
+    assert lib.geomst_set_option(b"list_capacity_scale", 0.0) == G.EINVAL
+    assert lib.geomst_set_option(b"kernel_timing", 2.0) == G.EINVAL
 
 
 def test_stats_struct_layout(lib):

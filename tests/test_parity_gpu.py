@@ -194,7 +194,7 @@ def test_repeatable_and_schedule_independent(G):
         h2 = run_hdb(G, p, 7)
         assert all(same(a, b) for a, b in zip(h1, h2))
     finally:
-        G.set_option("beta_growth", 2.0)
+        G.set_option("beta_growth", 0)
 
 
 def test_list_overflow_restarts(G):
