@@ -97,7 +97,7 @@ struct Device {
     DBuf pin, eout, wout, cdout;
     // tree
     DBuf keysA, keysB, gflag, gincl, gid, gstart, g64, gbox, hflag;
-    DBuf part, bbox, key, val, key2, val2, stemp, X, orig, cd2, nodes, npar, flags, comp;
+    DBuf part, bbox, key, val, key2, val2, stemp, X, orig, cd2, nodes, npar, flags, comp, cdr, btop;
     // union-find / component refresh
     DBuf uf, best, bnd, incl;
     // rounds
@@ -106,7 +106,7 @@ struct Device {
     size_t capF[2] = {0, 0}, capQ[2] = {0, 0}, capBig = 0;
     EdgeBufs C, P[2], OUT;
     // Kruskal
-    DBuf kid, ke2, kw2, perm[2], alive[2], ru, rv, nalive;
+    DBuf kid, ke2, kw2, perm[2], alive[2], ru, rv, nalive, minmax;
     struct Prof* prof = nullptr;
 };
 
@@ -206,30 +206,79 @@ int id_bits(int n) {
     return b < 1 ? 1 : b;
 }
 
-// Sort m edges of L by K; returns the permutation (sorted rank -> edge).
+// Sort m edges of L by K = (w2, d2, lo, hi); returns the permutation (sorted
+// rank -> edge).  Each key word is gathered once and then sorted as (key,
+// index) pairs with sequential passes, least significant word first, over
+// only the bits below the highest bit where the word's min and max differ
+// (every key shares the bits above).  Fast path: sort by w2 alone and keep
+// that order when no two w2 are equal.
 u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_t s) {
     D.kid.ensure((size_t)m * 8);
     D.kw2.ensure((size_t)m * 8);
-    if (hdb) D.ke2.ensure((size_t)m * 8);
     D.perm[0].ensure((size_t)m * 4);
     D.perm[1].ensure((size_t)m * 4);
     D.stemp.ensure(radix_temp_bytes(m));
+    D.minmax.ensure(64);
     int B = id_bits(n);
     TIMED(GEOMST_K_SORT);
-    g_stats.sort_elems += (int64_t)m * ((2 * B + 7) / 8 + (hdb ? 8 : 0) + 8);
-    k_sortkeys<<<blocks(m, 256), 256, 0, s>>>(L, m, B, D.kid.as<u64>(), hdb ? D.ke2.as<u64>() : nullptr,
-                                              D.kw2.as<u64>(), D.perm[0].as<u32>());
-    LAUNCHCHK();
-    u32* a = D.perm[0].as<u32>();
-    u32* b = D.perm[1].as<u32>();
-    auto pass = [&](const u64* w, int bits) {
-        if (radix_sort_index(w, a, b, m, bits, D.stemp.p, s)) std::swap(a, b);
+    u64* ka = D.kid.as<u64>();
+    u64* kb = D.kw2.as<u64>();
+    u32* va = D.perm[0].as<u32>();
+    u32* vb = D.perm[1].as<u32>();
+    unsigned gg = std::min(blocks(m, kBlock), (unsigned)kGrid);
+    u64* mm = D.minmax.as<u64>();
+    u32* tieflag = D.minmax.as<u32>() + 8;
+    // one word: gather through the current permutation (in place), then sort
+    auto word = [&](const u32* perm, int kind, bool check_ties) -> bool {
+        HIPCHK(hipMemsetAsync(mm, 0xff, 8, s));
+        HIPCHK(hipMemsetAsync(mm + 1, 0, 8, s));
+        HIPCHK(hipMemsetAsync(tieflag, 0, 4, s));
+        k_gather_word<<<gg, kBlock, 0, s>>>(L, perm, m, kind, B, ka, va, mm);
         LAUNCHCHK();
+        u64 h[2];
+        HIPCHK(hipMemcpyAsync(h, mm, 16, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        u64 diff = h[0] ^ h[1];
+        int bits = 0;
+        while (bits < 64 && (diff >> bits)) ++bits;
+        g_stats.sort_elems += (int64_t)m * ((bits + 7) / 8);
+        if (radix_sort_pairs(ka, va, kb, vb, m, bits, D.stemp.p, s)) {
+            std::swap(ka, kb);
+            std::swap(va, vb);
+        }
+        LAUNCHCHK();
+        if (!check_ties) return false;
+        k_flag_ties<<<gg, kBlock, 0, s>>>(ka, m, tieflag);
+        LAUNCHCHK();
+        u32 tie = 0;
+        HIPCHK(hipMemcpyAsync(&tie, tieflag, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return tie != 0;
     };
-    pass(D.kid.as<u64>(), 2 * B);
-    if (hdb) pass(D.ke2.as<u64>(), 64);
-    pass(D.kw2.as<u64>(), 64);
-    return a;
+    // after sorting by (w2, d2): does any neighbour pair tie on both?
+    auto tied2 = [&]() -> bool {
+        HIPCHK(hipMemsetAsync(tieflag, 0, 4, s));
+        k_flag_ties2<<<gg, kBlock, 0, s>>>(L, va, m, tieflag);
+        LAUNCHCHK();
+        u32 tie = 0;
+        HIPCHK(hipMemcpyAsync(&tie, tieflag, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return tie != 0;
+    };
+    // fast path: order by w2 (EMST) or (w2, d2) (HDBSCAN*) and keep it when no
+    // two keys tie; otherwise the full order, least significant word first
+    if (!hdb) {
+        if (!word(nullptr, 2, true)) return va;
+        word(nullptr, 0, false);
+        word(va, 2, false);
+        return va;
+    }
+    word(nullptr, 1, false);
+    if (!word(va, 2, true) || !tied2()) return va;
+    word(nullptr, 0, false);
+    word(va, 1, false);
+    word(va, 2, false);
+    return va;
 }
 
 template <int D_>
@@ -346,16 +395,32 @@ struct Solver {
         NodeRec<D_>* nodes = D.nodes.as<NodeRec<D_>>();
         k_karras<D_><<<blocks(n - 1, 256), 256, 0, s>>>(skey, n, L, nodes, D.npar.as<int>());
         LAUNCHCHK();
-        HIPCHK(hipMemsetAsync(D.flags.p, 0, (size_t)(n - 1) * 4, s));
-        k_bounds<D_><<<blocks(n, kBoundsBlock), kBoundsBlock, 0, s>>>(n, D.X.as<double>(), nullptr,
-                                                                      D.npar.as<int>(), nodes, D.flags.as<u32>(), 1);
-        LAUNCHCHK();
+        bounds(false);
         t.n = n;
         t.X = D.X.as<double>();
         t.orig = D.orig.as<u32>();
         t.cd2 = nullptr;
         t.nodes = nodes;
+        t.cdr = nullptr;
         t.comp = D.comp.as<int>();
+    }
+
+    // Node boxes (and, with cd2, core-distance ranges): block-local phase,
+    // then one workgroup for the nodes spanning blocks.
+    void bounds(bool cd) {
+        D.btop.ensure((size_t)n * 4 + 64);
+        D.flags.ensure((size_t)n * 4 + 8);
+        u32* ntop = D.flags.as<u32>() + n;  // counter after the arrival flags
+        HIPCHK(hipMemsetAsync(D.flags.p, 0, ((size_t)n + 1) * 4, s));
+        if (cd) D.cdr.ensure((size_t)(2 * n - 1) * 16);
+        k_bounds_local<D_><<<blocks(n, kBoundsBlock), kBoundsBlock, 0, s>>>(
+            n, D.X.as<double>(), cd ? D.cd2.as<double>() : nullptr, D.npar.as<int>(), D.nodes.as<NodeRec<D_>>(),
+            cd ? D.cdr.as<double2>() : nullptr, cd ? 0 : 1, D.btop.as<u32>(), ntop);
+        LAUNCHCHK();
+        k_bounds_top<D_><<<1, kBoundsTop, 0, s>>>(n, D.npar.as<int>(), D.nodes.as<NodeRec<D_>>(),
+                                                  cd ? D.cdr.as<double2>() : nullptr, cd ? 0 : 1, cd ? 1 : 0,
+                                                  D.btop.as<u32>(), ntop, D.flags.as<u32>());
+        LAUNCHCHK();
     }
 
     template <int KMAX>
@@ -372,11 +437,8 @@ struct Solver {
         else if (minpts <= 32) knn_k<32>();
         else knn_k<64>();
         t.cd2 = D.cd2.as<double>();
-        HIPCHK(hipMemsetAsync(D.flags.p, 0, (size_t)(n - 1) * 4, s));
-        k_bounds<D_><<<blocks(n, kBoundsBlock), kBoundsBlock, 0, s>>>(n, D.X.as<double>(), D.cd2.as<double>(),
-                                                                      D.npar.as<int>(), D.nodes.as<NodeRec<D_>>(),
-                                                                      D.flags.as<u32>(), 0);
-        LAUNCHCHK();
+        bounds(true);
+        t.cdr = D.cdr.as<double2>();
     }
 
     void refresh_components() {

@@ -96,11 +96,13 @@ __device__ __forceinline__ double box_diag2(const NodeRec<D>& A) {
     return s;
 }
 
-// Lower bound of the (squared) weight of any edge between the two nodes.
+// Lower bound of the (squared) weight of any edge between the two nodes;
+// ca/cb are the nodes' (min, max) squared core distances (HDBSCAN*).
 template <int D>
-__device__ __forceinline__ double pair_wlb2(const NodeRec<D>& A, const NodeRec<D>& B, int hdb) {
+__device__ __forceinline__ double pair_wlb2(const NodeRec<D>& A, const NodeRec<D>& B, int hdb, double2 ca,
+                                            double2 cb) {
     double l = box_lb2<D>(A, B);
-    if (hdb) l = fmax(l, fmax(A.cdmin, B.cdmin));
+    if (hdb) l = fmax(l, fmax(ca.x, cb.x));
     return l;
 }
 
@@ -118,7 +120,8 @@ __device__ __forceinline__ bool connected(const TreeView& t, u32 a, u32 b) {
 // BCCP edge of each pair contain the tree's edge exactly; a pair of two
 // single points is always separated.
 template <int D>
-__device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRec<D>& B, int hdb) {
+__device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRec<D>& B, int hdb, double2 ca,
+                                               double2 cb) {
     if (A.count == 1 && B.count == 1) return true;
     double L = box_lb2<D>(A, B);
     double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
@@ -133,10 +136,10 @@ __device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRe
     bool geo = (fmax(dA, dB) < L) && (c2 >= need * need);
     if (geo || !hdb) return geo;
     double gap = fmax(sqrt(c2) - ra - rb, 0.0);
-    double lhs_s = fmax(fmax(4.0 * ra * ra, 4.0 * rb * rb), fmax(A.cdmax, B.cdmax));
-    double rhs_s = fmax(gap * gap, fmax(A.cdmin, B.cdmin));
-    double lhs = fmax(fmax(dA, dB), fmax(A.cdmax, B.cdmax));
-    double rhs = fmax(L, fmax(A.cdmin, B.cdmin));
+    double lhs_s = fmax(fmax(4.0 * ra * ra, 4.0 * rb * rb), fmax(ca.y, cb.y));
+    double rhs_s = fmax(gap * gap, fmax(ca.x, cb.x));
+    double lhs = fmax(fmax(dA, dB), fmax(ca.y, cb.y));
+    double rhs = fmax(L, fmax(ca.x, cb.x));
     return (rhs_s >= lhs_s) && (lhs < rhs);
 }
 
@@ -268,10 +271,12 @@ __global__ void k_init_frontier(TreeView t, int hdb, PairRec* f) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= t.n - 1) return;
     const NodeRec<D>* N = nodes_of<D>(t);
+    int2 c = node_kids(t.n, N[i].first, N[i].count, N[i].split);
     PairRec p;
-    p.a = (u32)N[i].left;
-    p.b = (u32)N[i].right;
-    p.lb2 = pair_wlb2<D>(N[p.a], N[p.b], hdb);
+    p.a = (u32)c.x;
+    p.b = (u32)c.y;
+    double2 z = make_double2(0.0, 0.0);
+    p.lb2 = pair_wlb2<D>(N[p.a], N[p.b], hdb, hdb ? t.cdr[p.a] : z, hdb ? t.cdr[p.b] : z);
     f[i] = p;
 }
 
@@ -284,7 +289,9 @@ __global__ void __launch_bounds__(kBlock) k_min_positive_lb(const PairRec* f, u3
     block_atomic_min(v, &cnt->m[M_F], sh);
 }
 
-// Frontier split: drop connected pairs, queue the due ones, keep the rest.
+// Frontier split: queue the pairs whose lower bound is within beta, keep the
+// rest.  A pair's connectivity is checked when it is expanded, so this pass
+// only streams the records.
 __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs r, const PairRec* fin, u32 nfin,
                                                            u32* qcount) {
     __shared__ BlockAlloc S;
@@ -299,9 +306,8 @@ __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs
         p.a = p.b = 0;
         p.lb2 = 0.0;
         if (have) p = fin[i];
-        bool keep = have && !connected(t, p.a, p.b);
-        bool due = keep && p.lb2 <= r.beta2;
-        bool wait = keep && !due;
+        bool due = have && p.lb2 <= r.beta2;
+        bool wait = have && !due;
         if (wait) minf = fmin(minf, p.lb2);
         u32 off[kLists];
         block_alloc(S, (u64)due | ((u64)wait << 12), ctr, off);
@@ -318,12 +324,14 @@ __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs
 }
 
 // ------------------------------------------------------------ expansion
-// One breadth-first level of the FindPair recursion (Alg. 1) over the due
-// pairs: a well-separated pair yields its BCCP edge (computed here when the
-// pair has at most kTinyEvals point pairs, else queued for the large-pair
-// kernel); otherwise the node with the larger bounding sphere is split and
-// each child pair is dropped (connected), queued for the next level (due) or
-// parked in the frontier (lower bound above beta).
+// One breadth-first level of the FindPair recursion (Alg. 1).  Each lane
+// takes one pair: a pair whose points are all in one component is dropped; a
+// pair whose weight lower bound exceeds beta is parked in the frontier; a
+// well-separated pair yields its BCCP edge (computed here when it has at most
+// kTinyEvals point pairs, else queued for the large-pair kernel); otherwise
+// the node with the larger bounding sphere is split, and each child pair goes
+// to the frontier (bound above beta) or to the next level.  Connectivity of a
+// child pair is checked when it is expanded.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin,
                                                   u32 cap_in, const u32* nq_p, u32* nq_next, u32* nq_clear) {
@@ -342,61 +350,78 @@ __global__ void __launch_bounds__(kBlock) k_level(TreeView t, RoundArgs r, int h
     for (u32 b0 = blockIdx.x * kBlock; b0 < nq; b0 += gridDim.x * kBlock) {
         u32 i = b0 + threadIdx.x;
         bool have = i < nq;
-        bool to_c = false, to_p = false, to_big = false;
+        bool to_c = false, to_p = false, to_big = false, to_f = false;
         EdgeOut e;
         u32 a = 0, b = 0, oth = 0;
-        u32 ch[2] = {0, 0};
+        int2 ch = make_int2(0, 0);
+        double lb = 0.0;
         double lbc[2] = {0.0, 0.0};
-        int nfront = 0, nnext = 0;
         bool cf[2] = {false, false}, cq[2] = {false, false};
+        int nfront = 0, nnext = 0;
         if (have) {
             PairRec pr = qin[i];
             a = pr.a;
             b = pr.b;
             ++visits;
-            NodeRec<D> A = N[a], B = N[b];
-            if (well_separated<D>(A, B, hdb)) {
-                u64 work = (u64)A.count * (u64)B.count;
-                if (work <= (u64)kTinyEvals) {
-                    e = point_edge<D>(t, hdb, (u32)A.first, (u32)B.first);
-                    for (int x = A.first; x < A.first + A.count; ++x)
-                        for (int y = B.first; y < B.first + B.count; ++y) {
-                            EdgeOut c = point_edge<D>(t, hdb, (u32)x, (u32)y);
-                            if (key_less(c.k, e.k)) e = c;
-                        }
-                    evals += work;
-                    ++solved;
-                    to_c = e.k.w2 <= r.beta2;
-                    to_p = !to_c;
-                    if (to_p) minp = fmin(minp, e.k.w2);
-                } else {
-                    to_big = true;
-                }
-            } else {
-                // split the node with the larger bounding sphere (Alg. 1, FindPair)
-                bool split_a = (B.count == 1) || (A.count > 1 && (A.rad > B.rad || (A.rad == B.rad && A.count >= B.count)));
-                const NodeRec<D>& X = split_a ? A : B;
-                const NodeRec<D>& O = split_a ? B : A;
-                oth = split_a ? b : a;
-                ch[0] = (u32)X.left;
-                ch[1] = (u32)X.right;
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    if (connected(t, ch[c], oth)) continue;
-                    double lb = pair_wlb2<D>(N[ch[c]], O, hdb);
-                    lbc[c] = lb;
-                    if (lb > r.beta2) {
-                        cf[c] = true;
-                        ++nfront;
-                        minf = fmin(minf, lb);
+            const int ka = t.comp[a], kb = t.comp[b];
+            if (!(ka >= 0 && ka == kb)) {
+                NodeRec<D> A = N[a], B = N[b];
+                double2 z = make_double2(0.0, 0.0);
+                double2 ca = hdb ? t.cdr[a] : z, cb = hdb ? t.cdr[b] : z;
+                lb = pair_wlb2<D>(A, B, hdb, ca, cb);
+                if (lb > r.beta2) {
+                    to_f = true;
+                    minf = fmin(minf, lb);
+                } else if (well_separated<D>(A, B, hdb, ca, cb)) {
+                    u64 work = (u64)A.count * (u64)B.count;
+                    if (work <= (u64)kTinyEvals) {
+                        e = point_edge<D>(t, hdb, (u32)A.first, (u32)B.first);
+                        for (int x = A.first; x < A.first + A.count; ++x)
+                            for (int y = B.first; y < B.first + B.count; ++y) {
+                                EdgeOut c = point_edge<D>(t, hdb, (u32)x, (u32)y);
+                                if (key_less(c.k, e.k)) e = c;
+                            }
+                        evals += work;
+                        ++solved;
+                        to_c = e.k.w2 <= r.beta2;
+                        to_p = !to_c;
+                        if (to_p) minp = fmin(minp, e.k.w2);
                     } else {
-                        cq[c] = true;
-                        ++nnext;
+                        to_big = true;
+                    }
+                } else {
+                    // split the node with the larger bounding sphere (Alg. 1, FindPair)
+                    bool split_a = (B.count == 1) ||
+                                   (A.count > 1 && (A.rad > B.rad || (A.rad == B.rad && A.count >= B.count)));
+                    const NodeRec<D>& X = split_a ? A : B;
+                    const NodeRec<D>& O = split_a ? B : A;
+                    double2 co = split_a ? cb : ca;
+                    const int kother = split_a ? kb : ka;
+                    oth = split_a ? b : a;
+                    ch = node_kids(t.n, X.first, X.count, X.split);
+                    // the two children are usually adjacent records (and
+                    // adjacent component entries): drop connected child
+                    // pairs, bound the others, park the far ones
+                    int kc[2] = {t.comp[ch.x], t.comp[ch.y]};
+                    double2 c0 = hdb ? t.cdr[ch.x] : z, c1 = hdb ? t.cdr[ch.y] : z;
+                    lbc[0] = pair_wlb2<D>(N[ch.x], O, hdb, c0, co);
+                    lbc[1] = pair_wlb2<D>(N[ch.y], O, hdb, c1, co);
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        if (kc[c] >= 0 && kc[c] == kother) continue;
+                        if (lbc[c] > r.beta2) {
+                            cf[c] = true;
+                            ++nfront;
+                            minf = fmin(minf, lbc[c]);
+                        } else {
+                            cq[c] = true;
+                            ++nnext;
+                        }
                     }
                 }
             }
         }
-        u64 packed = (u64)to_c | ((u64)to_p << 12) | ((u64)to_big << 24) | ((u64)nfront << 36) |
+        u64 packed = (u64)to_c | ((u64)to_p << 12) | ((u64)to_big << 24) | ((u64)(to_f + nfront) << 36) |
                      ((u64)nnext << 48);
         u32 off[kLists];
         block_alloc(S, packed, ctr, off);
@@ -412,10 +437,19 @@ __global__ void __launch_bounds__(kBlock) k_level(TreeView t, RoundArgs r, int h
             if (off[2] < r.cap_big) r.big[off[2]] = make_uint2(a, b);
             else flag_overflow(r.cnt);
         }
+        if (to_f) {
+            PairRec p;
+            p.a = a;
+            p.b = b;
+            p.lb2 = lb;
+            if (off[3] < r.cap_f) r.fout[off[3]] = p;
+            else flag_overflow(r.cnt);
+            ++off[3];
+        }
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             PairRec p;
-            p.a = ch[c];
+            p.a = (u32)(c == 0 ? ch.x : ch.y);
             p.b = oth;
             p.lb2 = lbc[c];
             if (cf[c]) {
@@ -678,6 +712,68 @@ __global__ void k_sortkeys(const EdgeList L, u32 m, int B, u64* kid, u64* ke2, u
     perm[i] = i;
 }
 
+// One key word of the edge order, gathered through the current permutation
+// (identity when perm is null; perm may alias val): 0 = ids packed as
+// (lo << B) | hi, 1 = d2 bits, 2 = w2 bits (non-negative doubles order like
+// their bits).  Also records the word's min and max.
+__global__ void __launch_bounds__(kBlock) k_gather_word(const EdgeList L, const u32* perm, u32 m, int kind, int B,
+                                                        u64* key, u32* val, u64* minmax) {
+    __shared__ u64 smin[4], smax[4];
+    u64 mn = ~0ull, mx = 0;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        u32 e = perm ? perm[i] : i;
+        u64 w;
+        if (kind == 0) {
+            u64 ids = L.ids[e];
+            w = ((ids >> 32) << B) | (ids & 0xffffffffull);
+        } else if (kind == 1) {
+            w = dbits(L.e2[e]);
+        } else {
+            w = dbits(L.w2[e]);
+        }
+        key[i] = w;
+        val[i] = e;
+        mn = w < mn ? w : mn;
+        mx = w > mx ? w : mx;
+    }
+    mn = wave_min_u64(mn);
+    mx = ~wave_min_u64(~mx);
+    const int wv = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        smin[wv] = mn;
+        smax[wv] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x / kWave); ++i) {
+            mn = smin[i] < mn ? smin[i] : mn;
+            mx = smax[i] > mx ? smax[i] : mx;
+        }
+        mn = smin[0] < mn ? smin[0] : mn;
+        mx = smax[0] > mx ? smax[0] : mx;
+        atomicMin((unsigned long long*)&minmax[0], (unsigned long long)mn);
+        atomicMax((unsigned long long*)&minmax[1], (unsigned long long)mx);
+    }
+}
+
+// Flags whether two neighbours of a sorted key array are equal.
+__global__ void k_flag_ties(const u64* key, u32 m, u32* flag) {
+    bool tie = false;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x + 1; i < m; i += gridDim.x * blockDim.x)
+        tie |= key[i] == key[i - 1];
+    if (__any(tie) && lane_id() == 0) atomicOr(flag, 1u);
+}
+
+// Flags whether two neighbours of a permutation tie on both w2 and d2.
+__global__ void k_flag_ties2(const EdgeList L, const u32* perm, u32 m, u32* flag) {
+    bool tie = false;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x + 1; i < m; i += gridDim.x * blockDim.x) {
+        u32 a = perm[i - 1], b = perm[i];
+        tie |= L.w2[a] == L.w2[b] && L.e2[a] == L.e2[b];
+    }
+    if (__any(tie) && lane_id() == 0) atomicOr(flag, 1u);
+}
+
 __global__ void k_iota(u32* a, u32 m) {
     u32 i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m) a[i] = i;
@@ -715,8 +811,9 @@ __global__ void k_bor_pick(const u32* alive, const u32* nalive_p, u32 cap, const
     }
     ru[s] = a;
     rv[s] = b;
-    atomicMin(&best[a], rank);
-    atomicMin(&best[b], rank);
+    // read first: most candidates already lose to a smaller rank
+    if (rank < best[a]) atomicMin(&best[a], rank);
+    if (rank < best[b]) atomicMin(&best[b], rank);
     }
 }
 

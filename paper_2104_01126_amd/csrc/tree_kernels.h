@@ -14,18 +14,24 @@
 
 namespace geomst {
 
-// Per-node record, one or two cache lines: tight box of the node's points,
-// radius of the sphere about the box centre (a heuristic for which node to
-// split), min / max squared core distance (HDBSCAN*), the node's contiguous
-// range of sorted positions and its children (-1 for leaves).
+// Per-node record, exactly one 64-byte (d <= 3) or 128-byte line: tight box
+// of the node's points, its contiguous range of sorted positions, the split
+// position of the radix tree (children follow from it), and the radius of
+// the sphere about the box centre (only a heuristic for which node to split,
+// so single precision).  Core-distance ranges (HDBSCAN*) live in their own
+// array so that EMST never reads them.
 template <int D>
-struct alignas(16) NodeRec {
+struct NodeAlign {
+    static constexpr int value = (16 * D + 16 <= 64) ? 64 : 128;
+};
+
+template <int D>
+struct alignas(NodeAlign<D>::value) NodeRec {
     double lo[D];
     double hi[D];
-    double rad;
-    double cdmin, cdmax;
     int first, count;
-    int left, right;
+    int split;  // radix-tree split position g of an internal node; -1 for a leaf
+    float rad;
 };
 
 struct TreeView {
@@ -34,6 +40,7 @@ struct TreeView {
     const u32* orig;    // sorted position -> caller row index
     const double* cd2;  // sorted position -> squared core distance, or null (EMST)
     const void* nodes;  // NodeRec<D>[2n-1]
+    const double2* cdr; // [2n-1] (min cd2, max cd2) of the node's points (HDBSCAN*)
     const int* comp;    // [2n-1] component shared by all the node's points, or -1
 };
 // Node ids: internal nodes 0..n-2 (0 is the root), the leaf of sorted
@@ -42,6 +49,14 @@ struct TreeView {
 template <int D>
 __device__ __forceinline__ const NodeRec<D>* nodes_of(const TreeView& t) {
     return (const NodeRec<D>*)t.nodes;
+}
+
+// Children of an internal node from its range [f, f+c) and split g: the left
+// child covers [f, g], the right [g+1, f+c-1]; a one-point side is a leaf.
+__device__ __forceinline__ int2 node_kids(int n, int f, int c, int g) {
+    int left = (f == g) ? (n - 1 + g) : g;
+    int right = (f + c - 1 == g + 1) ? (n - 1 + g + 1) : (g + 1);
+    return make_int2(left, right);
 }
 
 // ------------------------------------------------------------ bounding box
@@ -283,8 +298,7 @@ __global__ void k_karras(const u64* k, int n, int L, NodeRec<D>* nodes, int* par
     int right = (last == g + 1) ? (n - 1 + g + 1) : (g + 1);
     nodes[i].first = first;
     nodes[i].count = last - first + 1;
-    nodes[i].left = left;
-    nodes[i].right = right;
+    nodes[i].split = g;
     parent[left] = i;
     parent[right] = i;
     if (i == 0) parent[0] = -1;
@@ -292,25 +306,30 @@ __global__ void k_karras(const u64* k, int n, int L, NodeRec<D>* nodes, int* par
 
 // ------------------------------------------------------------ node bounds
 // Bottom-up: every internal node is finished by the second of its two
-// children to arrive.  A block owns 256 consecutive leaves; nodes whose range
-// lies inside the block's leaves are merged through LDS (arrival counters and
-// boxes, workgroup-scope ordering only), and only the few nodes spanning
-// several blocks use global arrival counters with device-scope fences.
+// children to arrive.  Phase 1: a block owns 256 consecutive leaves and
+// merges every node whose range lies inside them through LDS (arrival
+// counters and boxes; workgroup-scope ordering only).  A thread whose climb
+// reaches a node spanning several blocks records the child it came from.
+// Phase 2: one workgroup finishes the spanning nodes (about 2n/256 of them)
+// starting from those children, again with workgroup-scope ordering only,
+// since every arrival counter and record it touches is its own.
 constexpr int kBoundsBlock = 256;
+constexpr int kBoundsTop = 1024;  // threads of the phase-2 workgroup
 
 template <int D>
-__device__ __forceinline__ void leaf_rec(const double* X, const double* cd2, int p, double* lo, double* hi,
-                                         double2& cd) {
+__device__ __forceinline__ void write_box(NodeRec<D>& V, const double* lo, const double* hi, double s) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) lo[k] = hi[k] = X[(size_t)p * D + k];
-    double c = cd2 ? cd2[p] : 0.0;
-    cd = make_double2(c, c);
+    for (int k = 0; k < D; ++k) {
+        V.lo[k] = lo[k];
+        V.hi[k] = hi[k];
+    }
+    V.rad = (float)(0.5 * sqrt(s));
 }
 
 template <int D>
-__global__ void __launch_bounds__(kBoundsBlock) k_bounds(int n, const double* X, const double* cd2,
-                                                         const int* parent, NodeRec<D>* nodes, u32* gflags,
-                                                         int geometry) {
+__global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const double* X, const double* cd2,
+                                                               const int* parent, NodeRec<D>* nodes, double2* cdr,
+                                                               int geometry, u32* top, u32* ntop) {
     __shared__ u32 lflag[kBoundsBlock];
     __shared__ double slo[kBoundsBlock][D], shi[kBoundsBlock][D];
     __shared__ double2 scd[kBoundsBlock];
@@ -321,103 +340,102 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds(int n, const double* X,
     int p = base + threadIdx.x;
     if (p >= n) return;
     int leaf = n - 1 + p;
-    {
+    if (geometry) {
         NodeRec<D>& L = nodes[leaf];
-        double lo[D], hi[D];
-        double2 cd;
-        leaf_rec<D>(X, cd2, p, lo, hi, cd);
-        if (geometry) {
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                L.lo[k] = lo[k];
-                L.hi[k] = hi[k];
-            }
-            L.rad = 0.0;
-            L.first = p;
-            L.count = 1;
-            L.left = -1;
-            L.right = -1;
-        }
-        L.cdmin = cd.x;
-        L.cdmax = cd.y;
+        for (int k = 0; k < D; ++k) L.lo[k] = L.hi[k] = X[(size_t)p * D + k];
+        L.first = p;
+        L.count = 1;
+        L.split = -1;
+        L.rad = 0.0f;
     }
+    if (cd2) cdr[leaf] = make_double2(cd2[p], cd2[p]);
+    int child = leaf;
     int v = parent[leaf];
-    bool global_phase = false;
     while (v >= 0) {
         NodeRec<D>& V = nodes[v];
         int f = V.first, c = V.count;
-        bool inblock = !global_phase && f >= base && f + c <= end;
-        int2 ch = make_int2(V.left, V.right);
-        double lo[D], hi[D], lo2[D], hi2[D];
-        double2 ca, cb;
-        if (inblock) {
-            __threadfence_block();
-            if (atomicAdd(&lflag[v - base], 1u) == 0) return;
-            __threadfence_block();
-            // children lie in this block: leaves from X, internal nodes from LDS
-            if (ch.x >= n - 1) leaf_rec<D>(X, cd2, ch.x - (n - 1), lo, hi, ca);
-            else {
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    lo[k] = slo[ch.x - base][k];
-                    hi[k] = shi[ch.x - base][k];
-                }
-                ca = scd[ch.x - base];
-            }
-            if (ch.y >= n - 1) leaf_rec<D>(X, cd2, ch.y - (n - 1), lo2, hi2, cb);
-            else {
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    lo2[k] = slo[ch.y - base][k];
-                    hi2[k] = shi[ch.y - base][k];
-                }
-                cb = scd[ch.y - base];
-            }
-        } else {
-            global_phase = true;
+        if (!(f >= base && f + c <= end)) {
+            // spanning node: hand the climb over to phase 2
             __threadfence();
-            if (atomicAdd(&gflags[v], 1u) == 0) return;
-            __threadfence();
-            const volatile NodeRec<D>* A = nodes + ch.x;
-            const volatile NodeRec<D>* B = nodes + ch.y;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                lo[k] = A->lo[k];
-                hi[k] = A->hi[k];
-                lo2[k] = B->lo[k];
-                hi2[k] = B->hi[k];
-            }
-            ca = make_double2(A->cdmin, A->cdmax);
-            cb = make_double2(B->cdmin, B->cdmax);
+            u32 s = atomicAdd(ntop, 1u);
+            top[s] = (u32)child;
+            return;
         }
-        double s = 0.0;
+        __threadfence_block();
+        if (atomicAdd(&lflag[v - base], 1u) == 0) return;
+        __threadfence_block();
+        int2 ch = node_kids(n, f, c, V.split);
+        double lo[D], hi[D], s = 0.0;
+        double2 cd = make_double2(0.0, 0.0);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            lo[k] = fmin(lo[k], lo2[k]);
-            hi[k] = fmax(hi[k], hi2[k]);
+            double a0, a1, b0, b1;
+            if (ch.x >= n - 1) a0 = a1 = X[(size_t)(ch.x - (n - 1)) * D + k];
+            else {
+                a0 = slo[ch.x - base][k];
+                a1 = shi[ch.x - base][k];
+            }
+            if (ch.y >= n - 1) b0 = b1 = X[(size_t)(ch.y - (n - 1)) * D + k];
+            else {
+                b0 = slo[ch.y - base][k];
+                b1 = shi[ch.y - base][k];
+            }
+            lo[k] = fmin(a0, b0);
+            hi[k] = fmax(a1, b1);
             double x = hi[k] - lo[k];
             s = s + x * x;
+            slo[v - base][k] = lo[k];
+            shi[v - base][k] = hi[k];
         }
-        double2 cd = make_double2(fmin(ca.x, cb.x), fmax(ca.y, cb.y));
-        if (inblock) {
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                slo[v - base][k] = lo[k];
-                shi[v - base][k] = hi[k];
-            }
+        if (cd2) {
+            double2 ca = (ch.x >= n - 1) ? make_double2(cd2[ch.x - (n - 1)], cd2[ch.x - (n - 1)]) : scd[ch.x - base];
+            double2 cb = (ch.y >= n - 1) ? make_double2(cd2[ch.y - (n - 1)], cd2[ch.y - (n - 1)]) : scd[ch.y - base];
+            cd = make_double2(fmin(ca.x, cb.x), fmax(ca.y, cb.y));
             scd[v - base] = cd;
+            cdr[v] = cd;
         }
-        if (geometry) {
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                V.lo[k] = lo[k];
-                V.hi[k] = hi[k];
-            }
-            V.rad = 0.5 * sqrt(s);
-        }
-        V.cdmin = cd.x;
-        V.cdmax = cd.y;
+        if (geometry) write_box<D>(V, lo, hi, s);
+        child = v;
         v = parent[v];
+    }
+}
+
+// Phase 2 (one workgroup): climb from the recorded children through the
+// spanning nodes; gflags holds one arrival counter per internal node.
+template <int D>
+__global__ void __launch_bounds__(kBoundsTop) k_bounds_top(int n, const int* parent, NodeRec<D>* nodes, double2* cdr,
+                                                           int geometry, int hdb, const u32* top, const u32* ntop,
+                                                           u32* gflags) {
+    const u32 m = *ntop;
+    for (u32 i = threadIdx.x; i < m; i += blockDim.x) {
+        int v = parent[top[i]];
+        while (v >= 0) {
+            __threadfence_block();
+            if (atomicAdd(&gflags[v], 1u) == 0) break;
+            __threadfence_block();
+            NodeRec<D>& V = nodes[v];
+            int2 ch = node_kids(n, V.first, V.count, V.split);
+            const volatile NodeRec<D>* A = nodes + ch.x;
+            const volatile NodeRec<D>* B = nodes + ch.y;
+            if (geometry) {
+                double lo[D], hi[D], s = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    lo[k] = fmin(A->lo[k], B->lo[k]);
+                    hi[k] = fmax(A->hi[k], B->hi[k]);
+                    double x = hi[k] - lo[k];
+                    s = s + x * x;
+                }
+                write_box<D>(V, lo, hi, s);
+            }
+            if (hdb) {
+                const volatile double2* ca = cdr + ch.x;
+                const volatile double2* cb = cdr + ch.y;
+                cdr[v] = make_double2(fmin(ca->x, cb->x), fmax(ca->y, cb->y));
+            }
+            v = parent[v];
+        }
     }
 }
 
@@ -504,7 +522,7 @@ __global__ void __launch_bounds__(64) k_knn(TreeView t, int kk, double* cd2_out,
                 if (lane_id() == 0) atomicOr(err, 4u);
                 continue;
             }
-            int2 c = make_int2(N[v].left, N[v].right);
+            int2 c = node_kids(n, N[v].first, N[v].count, N[v].split);
             // visit first the child nearer to lane 0's query
             double la = point_box_lb2<D>(q, N[c.x].lo, N[c.x].hi);
             double lr = point_box_lb2<D>(q, N[c.y].lo, N[c.y].hi);
