@@ -85,6 +85,52 @@ int geomst_hdbscan_dev(const double* d_points, int64_t n, int32_t d, int32_t min
                        double* d_core_dist_sq, int64_t* d_edges, double* d_weights, double* d_weights_sq,
                        void* stream);
 
+/*
+ * Batched solve: `count` independent instances in one device arena, solved
+ * together as a forest (one tree build and one set of round launches for all
+ * of them; pairs never cross instances).  Results are exactly those of solving
+ * each instance alone.
+ *
+ *   d_points   device f64 [N][stride], N = sum of n_i; instance i occupies rows
+ *              [offset_i, offset_i + n_i) with offset_0 = 0 and
+ *              offset_{i+1} = offset_i + n_i (packed in order).  Columns at and
+ *              beyond the instance's d must be 0.0 (a zero coordinate leaves
+ *              every squared distance bit-identical).
+ *   items      host array of `count` descriptors (offset, n, d <= stride, min_pts:
+ *              0 = EMST, else HDBSCAN* with 1 <= min_pts <= min(n, 64)).
+ *   d_edges    device int64 [N - count][2]; instance i's n_i - 1 edges start at
+ *              row offset_i - i, with ids local to the instance (0..n_i-1),
+ *              sorted by K as in the single-instance calls.
+ *   d_weights, d_weights_sq   device f64 [N - count] (either may be NULL).
+ *   d_core_dist, d_core_dist_sq   device f64 [N] (may be NULL; 0 for EMST rows).
+ *   stream     hipStream_t (NULL = legacy default stream).
+ * Errors as for the single calls (EINVAL names the first bad item).
+ */
+typedef struct {
+    int64_t offset;
+    int64_t n;
+    int32_t d;
+    int32_t min_pts;
+} geomst_batch_item_t;
+
+int geomst_batch_dev(const double* d_points, int32_t stride, const geomst_batch_item_t* items, int64_t count,
+                     int64_t* d_edges, double* d_weights, double* d_weights_sq, double* d_core_dist,
+                     double* d_core_dist_sq, void* stream);
+
+/* Host-pointer batch: per-instance host arrays, packed by the library. */
+typedef struct {
+    const double* points; /* [n][d] host, row-major */
+    int64_t n;
+    int32_t d;
+    int32_t min_pts;      /* 0 = EMST */
+    double* core_dist;    /* [n] out or NULL */
+    int64_t* edges;       /* [n-1][2] out */
+    double* weights;      /* [n-1] out or NULL */
+    int32_t status;       /* out: GEOMST_OK or the error of this item */
+} geomst_instance_t;
+
+int geomst_batch(geomst_instance_t* inst, int64_t count);
+
 /* Kernel families timed by the "kernel_timing" option (index into
  * geomst_stats_t.kernel_ms / kernel_launches). */
 enum {

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <string>
 
 #include "../../include/geomst.h"
 #include "internal.h"
@@ -27,6 +28,8 @@ double g_beta_growth = 0.0;  // 0: 2 for EMST, sqrt(2) for HDBSCAN*
 double g_capacity_scale = 1.0;
 constexpr int kMaxKeyLevels = 6;
 constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
+constexpr u32 kSmallSwitch = 8192;  // queues up to this size go to the one-workgroup level kernel
+constexpr u32 kSmallMax = 32768;    // ... which keeps going while a level stays this small
 constexpr int kBoruvkaBatch = 4;  // Boruvka steps launched between host checks  // Morton key words per point (see k_morton_level)
 const bool g_trace = getenv("GEOMST_TRACE") != nullptr;
 
@@ -101,12 +104,15 @@ struct Device {
     // union-find / component refresh
     DBuf uf, best, bnd, incl;
     // rounds
-    DBuf F[2], Q[2], big, ntask, toff, parts, qring;
+    DBuf F[2], Q[2], big, ntask, toff, parts, qring, lstate;
     size_t qmax_seen = 0;
     size_t capF[2] = {0, 0}, capQ[2] = {0, 0}, capBig = 0;
+    DBuf FF[2];  // far frontier (see the round loop)
+    size_t capFF[2] = {0, 0};
     EdgeBufs C, P[2], OUT;
     // Kruskal
     DBuf kid, ke2, kw2, perm[2], alive[2], ru, rv, nalive, minmax;
+    DBuf birange, bik, browinst;  // batched solves: instance table and row -> instance
     struct Prof* prof = nullptr;
 };
 
@@ -212,7 +218,7 @@ int id_bits(int n) {
 // only the bits below the highest bit where the word's min and max differ
 // (every key shares the bits above).  Fast path: sort by w2 alone and keep
 // that order when no two w2 are equal.
-u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_t s) {
+u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_t s, const u32* pinst = nullptr) {
     D.kid.ensure((size_t)m * 8);
     D.kw2.ensure((size_t)m * 8);
     D.perm[0].ensure((size_t)m * 4);
@@ -233,7 +239,7 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
         HIPCHK(hipMemsetAsync(mm, 0xff, 8, s));
         HIPCHK(hipMemsetAsync(mm + 1, 0, 8, s));
         HIPCHK(hipMemsetAsync(tieflag, 0, 4, s));
-        k_gather_word<<<gg, kBlock, 0, s>>>(L, perm, m, kind, B, ka, va, mm);
+        k_gather_word<<<gg, kBlock, 0, s>>>(L, perm, m, kind, B, pinst, ka, va, mm);
         LAUNCHCHK();
         u64 h[2];
         HIPCHK(hipMemcpyAsync(h, mm, 16, hipMemcpyDeviceToHost, s));
@@ -266,19 +272,24 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
         return tie != 0;
     };
     // fast path: order by w2 (EMST) or (w2, d2) (HDBSCAN*) and keep it when no
-    // two keys tie; otherwise the full order, least significant word first
+    // two keys tie; otherwise the full order, least significant word first.
+    // Batched output: the instance is the most significant word.
+    auto finish = [&]() -> u32* {
+        if (pinst) word(va, 3, false);
+        return va;
+    };
     if (!hdb) {
-        if (!word(nullptr, 2, true)) return va;
+        if (!word(nullptr, 2, true)) return finish();
         word(nullptr, 0, false);
         word(va, 2, false);
-        return va;
+        return finish();
     }
     word(nullptr, 1, false);
-    if (!word(va, 2, true) || !tied2()) return va;
+    if (!word(va, 2, true) || !tied2()) return finish();
     word(nullptr, 0, false);
     word(va, 1, false);
     word(va, 2, false);
-    return va;
+    return finish();
 }
 
 template <int D_>
@@ -291,9 +302,15 @@ struct Solver {
     TreeView t;
     geomst_stats_t& st;
     int key_levels = 1;
+    // batched solve (forest of instances); all null for a single instance
+    int ninst = 1;
+    const u32* pinst = nullptr;   // instance of each row / sorted position
+    const int2* irange = nullptr; // (first row, rows) per instance
+    const int* ik = nullptr;      // k-NN k per instance
+    u32 target_edges = 0;         // edges of the whole forest
 
     Solver(Device& dev, hipStream_t stream, int n_, int mp, geomst_stats_t& stats)
-        : D(dev), s(stream), n(n_), minpts(mp), hdb(mp > 0), st(stats) {}
+        : D(dev), s(stream), n(n_), minpts(mp), hdb(mp > 0), st(stats), target_edges((u32)(n_ - 1)) {}
 
     void build_tree(const double* P) {
         int nn = 2 * n - 1;
@@ -313,12 +330,18 @@ struct Solver {
         D.val.ensure((size_t)n * 4);
         D.val2.ensure((size_t)n * 4);
         D.stemp.ensure(std::max(radix_temp_bytes(n), scan_temp_bytes(n)));
-        k_morton<D_><<<blocks(n, 256), 256, 0, s>>>(P, n, D.bbox.as<double>(), D.key.as<u64>(), D.val.as<u32>());
-        LAUNCHCHK();
         int mb = (63 / D_) > 31 ? 31 : (63 / D_);
-        g_stats.sort_elems += (int64_t)n * ((mb * D_ + 7) / 8);
+        int bits0 = mb * D_;
+        if (pinst) {
+            k_inst_key<<<blocks(n, 256), 256, 0, s>>>(pinst, n, D.key.as<u64>(), D.val.as<u32>());
+            bits0 = id_bits(ninst);
+        } else {
+            k_morton<D_><<<blocks(n, 256), 256, 0, s>>>(P, n, D.bbox.as<double>(), D.key.as<u64>(), D.val.as<u32>());
+        }
+        LAUNCHCHK();
+        g_stats.sort_elems += (int64_t)n * ((bits0 + 7) / 8);
         int flip = radix_sort_pairs(D.key.as<u64>(), D.val.as<u32>(), D.key2.as<u64>(), D.val2.as<u32>(), n,
-                                    mb * D_, D.stemp.p, s);
+                                    bits0, D.stemp.p, s);
         LAUNCHCHK();
         // multi-level keys: keysA holds L words per position, level-major
         D.keysA.ensure((size_t)kMaxKeyLevels * n * 8);
@@ -425,7 +448,8 @@ struct Solver {
 
     template <int KMAX>
     void knn_k() {
-        k_knn<D_, KMAX><<<blocks(n, 64), 64, 0, s>>>(t, minpts, D.cd2.as<double>(), &D.cnt.as<Counters>()->c[C_ERR]);
+        k_knn<D_, KMAX><<<blocks(n, 64), 64, 0, s>>>(t, minpts, pinst, irange, ik, D.cd2.as<double>(),
+                                                      &D.cnt.as<Counters>()->c[C_ERR]);
         LAUNCHCHK();
     }
 
@@ -454,10 +478,16 @@ struct Solver {
         LAUNCHCHK();
     }
 
+    double t_near = 0.0;  // edge of the near frontier band
+    int ffo = 0;          // far list receiving appends this round
+
     RoundArgs args(double beta2, int fo, int qo, int po) {
         RoundArgs r;
         r.cnt = D.cnt.as<Counters>();
         r.beta2 = beta2;
+        r.t_near = t_near;
+        r.ffar = D.FF[ffo].as<PairRec>();
+        r.cap_far = (u32)D.capFF[ffo];
         r.uf = D.uf.as<u32>();
         r.fout = D.F[fo].as<PairRec>();
         r.cap_f = (u32)D.capF[fo];
@@ -475,7 +505,7 @@ struct Solver {
     // After an overflow: grow the round's output lists that ran out.  Their
     // contents are not kept (the round restarts); the round's input frontier
     // F[fc] and input pool P[pc] are never touched.
-    void grow_lists(int fo, int po) {
+    void grow_lists(int fo, int po, size_t keep_far) {
         const Counters& c = *D.hcnt;
         auto grow_pairs = [&](DBuf& b, size_t& cap, size_t need) {
             if (need > cap) {
@@ -485,6 +515,11 @@ struct Solver {
             }
         };
         grow_pairs(D.F[fo], D.capF[fo], c.c[C_F]);
+        if (c.c[C_FAR] > D.capFF[ffo]) {  // keeps the far pairs retained from earlier rounds
+            size_t nc = std::max<size_t>((size_t)c.c[C_FAR] + c.c[C_FAR] / 4, D.capFF[ffo] * 2);
+            D.FF[ffo].ensure(nc * sizeof(PairRec), keep_far * sizeof(PairRec), s);
+            D.capFF[ffo] = nc;
+        }
         // level queues: the split's count is exact (qmax_seen); an overflowing
         // level's count may already be cleared, so then they double
         size_t qneed = D.qmax_seen;
@@ -541,14 +576,16 @@ struct Solver {
         };
         if (g_capacity_scale != 1.0) {  // testing aid: start from the given capacities
             for (int i = 0; i < 2; ++i) {
-                D.capF[i] = D.capQ[i] = 0;
+                D.capF[i] = D.capQ[i] = D.capFF[i] = 0;
                 D.P[i].cap = 0;
             }
             D.capBig = 0;
             D.C.cap = 0;
         }
-        initcap(D.capF[0], D.F[0], sc(hdb ? 8 : 4));
-        initcap(D.capF[1], D.F[1], sc(hdb ? 8 : 4));
+        initcap(D.capF[0], D.F[0], sc(hdb ? 4 : 2));
+        initcap(D.capF[1], D.F[1], sc(hdb ? 4 : 2));
+        initcap(D.capFF[0], D.FF[0], sc(hdb ? 8 : 4));
+        initcap(D.capFF[1], D.FF[1], sc(hdb ? 8 : 4));
         initcap(D.capQ[0], D.Q[0], sc(2));
         initcap(D.capQ[1], D.Q[1], sc(2));
         if (D.capBig < sc(0.125)) {
@@ -561,22 +598,30 @@ struct Solver {
         D.OUT.ensure((size_t)n + 64, 0, s);
 
         // initial frontier: the children of every internal node
-        int fc = 0, pc = 0;
-        k_init_frontier<D_><<<blocks(n - 1, 256), 256, 0, s>>>(t, hdb, D.F[fc].as<PairRec>());
+        // Waiting pairs live in two lists: "near" (bound up to t_near, due
+        // within a few rounds; streamed every round) and "far" (re-split, with
+        // connectivity pruning, only when beta passes t_near).  The initial
+        // pairs start in the far list.
+        int fc = 0, pc = 0, ffc = 0;
+        k_init_frontier<D_><<<blocks(n - 1, 256), 256, 0, s>>>(t, hdb, pinst, D.FF[ffc].as<PairRec>());
         LAUNCHCHK();
         k_min_positive_lb<<<std::min(blocks(n - 1, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
-            D.F[fc].as<PairRec>(), (u32)(n - 1), D.cnt.as<Counters>());
+            D.FF[ffc].as<PairRec>(), (u32)(n - 1), D.cnt.as<Counters>());
         LAUNCHCHK();
         read_counters(D, s);
         u64 b0 = D.hcnt->m[M_F];
         double beta2 = (b0 == ~0ull) ? 0.0 : bits_to_double(b0);
-        u32 nF = (u32)(n - 1), nP = 0;
+        u32 nF = 0, nFF = (u32)(n - 1), nP = 0;
+        t_near = -1.0;  // the first round starts a band
+        double far_min = beta2;
         const double growth = g_beta_growth > 0.0 ? g_beta_growth : (hdb ? 1.4142135623730951 : 2.0);
         const double g2 = growth * growth;
         u64 committed = 0, maxf = nF, big_pairs = 0;
         int rounds = 0;
         u32 nout = 0;
+        int stale_rounds = 0;
         D.qring.ensure(kQRing * 4);
+        D.lstate.ensure(64);
         u32* ring = D.qring.as<u32>();
         while (true) {
             ++rounds;
@@ -585,8 +630,13 @@ struct Solver {
                 throw Fail{GEOMST_EINTERNAL};
             }
             int fo = fc ^ 1, po = pc ^ 1;
+            const bool epoch = beta2 > t_near;
+            if (epoch) t_near = beta2 * g2 * g2 * g2;  // the band covers about three rounds
+            ffo = epoch ? (ffc ^ 1) : ffc;
             counters_reset_round(D, s);
             read_counters(D, s);
+            D.hcnt->c[C_FAR] = epoch ? 0u : nFF;  // far appends go after the retained pairs
+            write_counters(D, *D.hcnt, s);
             const Counters round_start = *D.hcnt;
             int levels = 0;
             u32 nbig = 0;
@@ -609,6 +659,10 @@ struct Solver {
                         k_split_pool<<<std::min(blocks(nP, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
                             r, D.P[pc].list(), nP);
                     LAUNCHCHK();
+                    if (epoch && nFF)
+                        k_split_far<<<std::min(blocks(nFF, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
+                            t, r, D.FF[ffc].as<PairRec>(), nFF, ring);
+                    LAUNCHCHK();
                 }
                 read_counters(D, s);
                 u32 nq = 0;
@@ -619,19 +673,45 @@ struct Solver {
                 if (D.hcnt->c[C_ERR] & 1u) {
                     restart = true;
                 } else {
-                    // breadth-first levels, launched in batches without host syncs
+                    // breadth-first levels: thin chains run inside one
+                    // workgroup; wide levels run grid-wide in batches launched
+                    // without host syncs.  Q[lv & 1] holds the queue and
+                    // ring[lv % 4] its count.
+                    int lv = 0;
                     while (nq > 0) {
-                        for (int j = 0; j < kLevelBatch; ++j, ++levels) {
+                        if (nq <= kSmallSwitch) {
+                            {
+                                TIMED(GEOMST_K_EXPAND);
+                                RoundArgs r = args(beta2, fo, 0, po);
+                                k_level_small<D_><<<1, kSmallBlock, 0, s>>>(
+                                    t, r, hdb, D.Q[0].as<PairRec>(), (u32)D.capQ[0], D.Q[1].as<PairRec>(),
+                                    (u32)D.capQ[1], lv & 1, ring, (u32)(lv % kQRing), kSmallMax, D.lstate.as<u32>());
+                                LAUNCHCHK();
+                            }
+                            u32 st2[2];
+                            HIPCHK(hipMemcpyAsync(st2, D.lstate.p, 8, hipMemcpyDeviceToHost, s));
+                            read_counters(D, s);
+                            ++levels;
+                            if (D.hcnt->c[C_ERR] & 1u) {
+                                restart = true;
+                                break;
+                            }
+                            nq = st2[0];
+                            lv = (int)st2[1];
+                            D.qmax_seen = std::max<size_t>(D.qmax_seen, nq);
+                            continue;
+                        }
+                        for (int j = 0; j < kLevelBatch; ++j, ++lv, ++levels) {
                             TIMED(GEOMST_K_EXPAND);
-                            RoundArgs r = args(beta2, fo, (levels + 1) & 1, po);
-                            k_level<D_><<<kGrid, kBlock, 0, s>>>(t, r, hdb, D.Q[levels & 1].as<PairRec>(),
-                                                                 (u32)D.capQ[levels & 1], ring + (levels % kQRing),
-                                                                 ring + ((levels + 1) % kQRing),
-                                                                 ring + ((levels + 2) % kQRing));
+                            RoundArgs r = args(beta2, fo, (lv + 1) & 1, po);
+                            k_level<D_><<<kGrid, kBlock, 0, s>>>(t, r, hdb, D.Q[lv & 1].as<PairRec>(),
+                                                                 (u32)D.capQ[lv & 1], ring + (lv % kQRing),
+                                                                 ring + ((lv + 1) % kQRing),
+                                                                 ring + ((lv + 2) % kQRing));
                             LAUNCHCHK();
                         }
                         read_counters(D, s);
-                        HIPCHK(hipMemcpyAsync(&nq, ring + (levels % kQRing), 4, hipMemcpyDeviceToHost, s));
+                        HIPCHK(hipMemcpyAsync(&nq, ring + (lv % kQRing), 4, hipMemcpyDeviceToHost, s));
                         HIPCHK(hipStreamSynchronize(s));
                         D.qmax_seen = std::max<size_t>(D.qmax_seen, nq);
                         if (D.hcnt->c[C_ERR] & 1u) {
@@ -685,7 +765,7 @@ struct Solver {
                         throw Fail{GEOMST_EINTERNAL};
                     }
                     if (g_trace) fprintf(stderr, "[geomst] round %d: list overflow, growing and restarting\n", rounds);
-                    grow_lists(fo, po);
+                    grow_lists(fo, po, epoch ? 0 : nFF);
                     write_counters(D, round_start, s);
                 }
             } while (restart);
@@ -733,7 +813,17 @@ struct Solver {
                     if (left == 0) break;
                 }
             }
-            refresh_components();
+            // Refresh the node components unless this round merged almost
+            // nothing (stale labels only miss some pruning: components only
+            // grow, so a node labelled with one component still is in one).
+            read_counters(D, s);
+            u32 merged = D.hcnt->c[C_OUT] - nout;
+            if ((u64)merged * 4096 >= (u64)n || stale_rounds >= 3 || D.hcnt->c[C_OUT] >= target_edges) {
+                refresh_components();
+                stale_rounds = 0;
+            } else {
+                ++stale_rounds;
+            }
             read_counters(D, s);
             const Counters& c = *D.hcnt;
             if (c.c[C_ERR] & (1u | 4u | 8u)) {
@@ -743,39 +833,46 @@ struct Solver {
             }
             nout = c.c[C_OUT];
             nF = c.c[C_F];
+            nFF = c.c[C_FAR];
+            ffc = ffo;
+            double mfar = c.m[M_FAR] == ~0ull ? kInf : bits_to_double(c.m[M_FAR]);
+            far_min = epoch ? mfar : std::min(far_min, mfar);
             nP = c.c[C_P];
-            maxf = std::max<u64>(maxf, nF);
+            maxf = std::max<u64>(maxf, (u64)nF + nFF);
             fc = fo;
             pc = po;
             if (g_trace) {
                 fprintf(stderr,
-                        "[geomst] round %d beta2=%.6g levels=%d visits=%llu F=%u P=%u C=%u big=%u out=%u "
+                        "[geomst] round %d beta2=%.6g levels=%d visits=%llu F=%u+%u P=%u C=%u big=%u out=%u "
                         "t=%.2fms\n",
-                        rounds, beta2, levels, (unsigned long long)c.c64[C64_VISITS], nF, nP, m, nbig, nout,
+                        rounds, beta2, levels, (unsigned long long)c.c64[C64_VISITS], nF, nFF, nP, m, nbig, nout,
                         std::chrono::duration<double, std::milli>(clk::now() - t2).count());
             }
-            if (nout >= (u32)(n - 1)) break;
+            if (nout >= target_edges) break;
             double mf = c.m[M_F] == ~0ull ? kInf : bits_to_double(c.m[M_F]);
             double mp = c.m[M_P] == ~0ull ? kInf : bits_to_double(c.m[M_P]);
-            double nxt = std::min(mf, mp);
+            double nxt = std::min(std::min(mf, mp), far_min);
             if (nxt == kInf) {
                 g_err = "no pairs left before the tree was complete";
                 throw Fail{GEOMST_EINTERNAL};
             }
             beta2 = std::max(beta2 * g2, nxt);
         }
-        if (nout != (u32)(n - 1)) {
+        if (nout != target_edges) {
             g_err = "wrong number of tree edges";
             throw Fail{GEOMST_EINTERNAL};
         }
         auto t3 = clk::now();
         // output: sort the tree edges by K and write them
         EdgeList O = D.OUT.list();
-        u32* perm = sort_edges(D, O, n - 1, n, hdb, s);
+        u32* perm = target_edges ? sort_edges(D, O, target_edges, n, hdb, s, pinst) : nullptr;
         {
         TIMED(GEOMST_K_OUTPUT);
-        k_write_edges<<<blocks(n - 1, 256), 256, 0, s>>>(O, perm, (u32)(n - 1), edges, w, w2);
-        LAUNCHCHK();
+        if (target_edges) {
+            k_write_edges<<<blocks(target_edges, 256), 256, 0, s>>>(O, perm, target_edges, pinst, irange, edges, w,
+                                                                    w2);
+            LAUNCHCHK();
+        }
         }
         if (hdb && (cd || cd2out)) {
             TIMED(GEOMST_K_OUTPUT);
@@ -895,6 +992,99 @@ void solve_dev(Device& D, hipStream_t s, const double* P, int n, int d, int minp
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Batched solve over a packed device arena (see geomst_batch_dev).
+void solve_batch_dev(Device& D, hipStream_t s, const double* P, int stride, const geomst_batch_item_t* items,
+                     int64_t count, long long* edges, double* w, double* w2, double* cd, double* cd2) {
+    memset(&g_stats, 0, sizeof(g_stats));
+    D.prof->begin(g_kernel_timing);
+    auto t0 = std::chrono::steady_clock::now();
+    int64_t N = 0;
+    int maxk = 0;
+    bool hdb = false;
+    std::vector<int2> hr((size_t)count);
+    std::vector<int> hk((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        hr[i] = make_int2((int)items[i].offset, (int)items[i].n);
+        N += items[i].n;
+        hdb |= items[i].min_pts > 0;
+        maxk = std::max(maxk, (int)items[i].min_pts);
+    }
+    for (int64_t i = 0; i < count; ++i) hk[i] = items[i].min_pts > 0 ? items[i].min_pts : 1;
+    g_stats.n = N;
+    g_stats.d = stride;
+    g_stats.min_pts = maxk;
+    D.birange.ensure((size_t)count * 8);
+    D.bik.ensure((size_t)count * 4);
+    D.browinst.ensure((size_t)N * 4);
+    HIPCHK(hipMemcpyAsync(D.birange.p, hr.data(), (size_t)count * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(D.bik.p, hk.data(), (size_t)count * 4, hipMemcpyHostToDevice, s));
+    k_row_instance<<<blocks(N, 256), 256, 0, s>>>(D.birange.as<int2>(), (u32)count, (u32)N, D.browinst.as<u32>());
+    LAUNCHCHK();
+    if (N == count) {
+        // every instance is a single point: no edges, core distances 0
+        if (cd) HIPCHK(hipMemsetAsync(cd, 0, (size_t)N * 8, s));
+        if (cd2) HIPCHK(hipMemsetAsync(cd2, 0, (size_t)N * 8, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return;
+    }
+    switch (stride) {
+#define CASE(K)                                                   \
+    case K: {                                                     \
+        Solver<K> sv(D, s, (int)N, hdb ? maxk : 0, g_stats);      \
+        sv.ninst = (int)count;                                    \
+        sv.pinst = D.browinst.as<u32>();                          \
+        sv.irange = D.birange.as<int2>();                         \
+        sv.ik = D.bik.as<int>();                                  \
+        sv.target_edges = (u32)(N - count);                       \
+        sv.run(P, edges, w, w2, cd, cd2);                         \
+        break;                                                    \
+    }
+        CASE(1)
+        CASE(2)
+        CASE(3)
+        CASE(4)
+        CASE(5)
+        CASE(6)
+        CASE(7)
+#undef CASE
+        default:
+            g_err = "unsupported stride";
+            throw Fail{GEOMST_EINVAL};
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    g_stats.ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+int validate_batch(int32_t stride, const geomst_batch_item_t* items, int64_t count) {
+    if (!items || count < 1) {
+        g_err = "items is NULL or count < 1";
+        return GEOMST_EINVAL;
+    }
+    if (stride < 1 || stride > kMaxDim) {
+        g_err = "stride must be in [1, 7]";
+        return GEOMST_EINVAL;
+    }
+    int64_t off = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const geomst_batch_item_t& it = items[i];
+        bool bad = it.offset != off || it.n < 1 || it.d < 1 || it.d > stride || it.min_pts < 0 || it.min_pts > 64 ||
+                   it.min_pts > it.n;
+        if (bad) {
+            g_err = "batch item " + std::to_string(i) +
+                    " is invalid (items must be packed in order; n >= 1; 1 <= d <= stride; 0 <= min_pts <= "
+                    "min(n, 64))";
+            return GEOMST_EINVAL;
+        }
+        off += it.n;
+    }
+    if (off > (1ll << 26)) {
+        g_err = "total points must be at most 2^26";
+        return GEOMST_EINVAL;
+    }
+    return GEOMST_OK;
+}
+
 int run_dev(const double* P, int64_t n, int32_t d, int32_t minpts, long long* edges, double* w, double* w2,
             double* cd, double* cd2, void* stream) {
     g_err.clear();
@@ -980,6 +1170,126 @@ int geomst_hdbscan_dev(const double* d_points, int64_t n, int32_t d, int32_t min
     }
     return run_dev(d_points, n, d, min_pts, (long long*)d_edges, d_weights, d_weights_sq, d_core_dist,
                    d_core_dist_sq, stream);
+}
+
+int geomst_batch_dev(const double* d_points, int32_t stride, const geomst_batch_item_t* items, int64_t count,
+                     int64_t* d_edges, double* d_weights, double* d_weights_sq, double* d_core_dist,
+                     double* d_core_dist_sq, void* stream) {
+    g_err.clear();
+    if (!d_points) {
+        g_err = "points is NULL";
+        return GEOMST_EINVAL;
+    }
+    int rc = validate_batch(stride, items, count);
+    if (rc) return rc;
+    int64_t N = items[count - 1].offset + items[count - 1].n;
+    if (N > count && !d_edges) {
+        g_err = "edges is NULL";
+        return GEOMST_EINVAL;
+    }
+    try {
+        int dev;
+        Device& D = device_ctx(&dev);
+        std::lock_guard<std::mutex> lk(D.mu);
+        ensure_init(D);
+        solve_batch_dev(D, (hipStream_t)stream, d_points, stride, items, count, (long long*)d_edges, d_weights,
+                        d_weights_sq, d_core_dist, d_core_dist_sq);
+    } catch (const Fail& f) {
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return GEOMST_ENOMEM;
+    }
+    return GEOMST_OK;
+}
+
+int geomst_batch(geomst_instance_t* inst, int64_t count) {
+    g_err.clear();
+    if (!inst || count < 1) {
+        g_err = "inst is NULL or count < 1";
+        return GEOMST_EINVAL;
+    }
+    // validate and pack (stride = largest d; missing columns are 0.0)
+    int stride = 0;
+    int64_t N = 0;
+    int bad = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        geomst_instance_t& q = inst[i];
+        q.status = GEOMST_OK;
+        if (!q.points || q.n < 1 || q.d < 1 || q.d > kMaxDim || q.min_pts < 0 || q.min_pts > 64 ||
+            q.min_pts > q.n || (q.n > 1 && !q.edges)) {
+            q.status = GEOMST_EINVAL;
+            ++bad;
+            continue;
+        }
+        for (int64_t j = 0; j < q.n * q.d; ++j)
+            if (!(fabs(q.points[j]) <= 3.273390607896142e150)) {
+                q.status = GEOMST_EDOM;
+                ++bad;
+                break;
+            }
+        stride = std::max(stride, (int)q.d);
+        N += q.n;
+    }
+    if (bad) {
+        g_err = "invalid batch items (see their status)";
+        for (int64_t i = 0; i < count; ++i)
+            if (inst[i].status == GEOMST_EDOM) return GEOMST_EDOM;
+        return GEOMST_EINVAL;
+    }
+    try {
+        std::vector<double> host((size_t)N * stride, 0.0);
+        std::vector<geomst_batch_item_t> items((size_t)count);
+        int64_t off = 0;
+        for (int64_t i = 0; i < count; ++i) {
+            const geomst_instance_t& q = inst[i];
+            for (int64_t r = 0; r < q.n; ++r)
+                for (int k = 0; k < q.d; ++k) host[(size_t)(off + r) * stride + k] = q.points[r * q.d + k];
+            items[i] = geomst_batch_item_t{off, q.n, q.d, q.min_pts};
+            off += q.n;
+        }
+        int rc = validate_batch(stride, items.data(), count);
+        if (rc) return rc;
+        int dev;
+        Device& D = device_ctx(&dev);
+        std::lock_guard<std::mutex> lk(D.mu);
+        ensure_init(D);
+        hipStream_t s = D.own;
+        size_t m = (size_t)(N - count);
+        D.pin.ensure((size_t)N * stride * 8);
+        D.eout.ensure(m * 16 + 16);
+        D.wout.ensure(m * 8 + 8);
+        D.cdout.ensure((size_t)N * 8);
+        HIPCHK(hipMemcpyAsync(D.pin.p, host.data(), (size_t)N * stride * 8, hipMemcpyHostToDevice, s));
+        solve_batch_dev(D, s, D.pin.as<double>(), stride, items.data(), count, D.eout.as<long long>(),
+                        D.wout.as<double>(), nullptr, D.cdout.as<double>(), nullptr);
+        std::vector<long long> e(m * 2);
+        std::vector<double> w(m), cd((size_t)N);
+        if (m) {
+            HIPCHK(hipMemcpyAsync(e.data(), D.eout.p, m * 16, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(w.data(), D.wout.p, m * 8, hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(hipMemcpyAsync(cd.data(), D.cdout.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < count; ++i) {
+            geomst_instance_t& q = inst[i];
+            size_t eo = (size_t)(items[i].offset - i);
+            for (int64_t k = 0; k < q.n - 1; ++k) {
+                q.edges[2 * k] = e[2 * (eo + k)];
+                q.edges[2 * k + 1] = e[2 * (eo + k) + 1];
+                if (q.weights) q.weights[k] = w[eo + k];
+            }
+            if (q.core_dist)
+                for (int64_t r = 0; r < q.n; ++r) q.core_dist[r] = q.min_pts > 0 ? cd[items[i].offset + r] : 0.0;
+        }
+    } catch (const Fail& f) {
+        for (int64_t i = 0; i < count; ++i) inst[i].status = f.code;
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return GEOMST_ENOMEM;
+    }
+    return GEOMST_OK;
 }
 
 int geomst_get_stats(geomst_stats_t* out) {

@@ -32,10 +32,11 @@ enum CounterSlot {
     C_OUT,     // spanning-tree edges found so far
     C_ALIVE,   // Boruvka: edges still undecided after this step
     C_ERR,     // device-side error flags
+    C_FAR,     // far frontier out
     C_NUM
 };
 enum CounterSlot64 { C64_EVALS = 0, C64_VISITS, C64_BCCP, C64_BIGEVALS, C64_NUM };
-enum MinSlot { M_F = 0, M_P, M_NUM };
+enum MinSlot { M_F = 0, M_P, M_FAR, M_NUM };
 
 struct Counters {
     u32 c[16];
@@ -58,6 +59,9 @@ struct EdgeList {
 struct RoundArgs {
     Counters* cnt;
     double beta2;
+    double t_near;   // waiting pairs with bounds up to this go to the near list
+    PairRec* ffar;   // far list (appended)
+    u32 cap_far;
     const u32* uf;  // sorted position -> component root (fully compressed)
     PairRec* fout;
     u32 cap_f;
@@ -190,13 +194,13 @@ __device__ __forceinline__ void flag_overflow(Counters* cnt) { atomicOr(&cnt->c[
 __device__ __forceinline__ void flag_overflow_q(Counters* cnt) { atomicOr(&cnt->c[C_ERR], 1u | 16u); }
 
 // ------------------------------------------------------ block-level appends
-// Up to five output lists per block step.  Each thread passes how many
-// entries it adds to each list (packed 12 bits per list, at most 2 each);
-// one atomic per non-empty list per block reserves the space, and each
-// thread gets its slot offsets back.  All threads of the block must call it.
-constexpr int kLists = 5;
+// Up to six output lists per block step.  Each thread passes how many
+// entries it adds to each list (at most 2 each); one atomic per non-empty
+// list per block reserves the space, and each thread gets its slot offsets
+// back.  All threads of the block must call it.
+constexpr int kLists = 6;
 struct BlockAlloc {
-    u64 wsum[4];
+    u64 wsum[2][16];
     u32 base[kLists];
 };
 
@@ -209,31 +213,42 @@ __device__ __forceinline__ u64 wave_incl_scan_u64(u64 v) {
     return v;
 }
 
-__device__ __forceinline__ void block_alloc(BlockAlloc& S, u64 packed, u32* const* counters, u32 (&off)[kLists]) {
+// counts: lists 0-2 and 3-5 packed 16 bits apiece in two words
+__device__ __forceinline__ void block_alloc(BlockAlloc& S, const u32 (&cnt)[kLists], u32* const* counters,
+                                            u32 (&off)[kLists]) {
     const int w = threadIdx.x / kWave;
-    u64 incl = wave_incl_scan_u64(packed);
-    if (lane_id() == kWave - 1) S.wsum[w] = incl;
+    u64 p0 = (u64)cnt[0] | ((u64)cnt[1] << 16) | ((u64)cnt[2] << 32);
+    u64 p1 = (u64)cnt[3] | ((u64)cnt[4] << 16) | ((u64)cnt[5] << 32);
+    u64 i0 = wave_incl_scan_u64(p0), i1 = wave_incl_scan_u64(p1);
+    if (lane_id() == kWave - 1) {
+        S.wsum[0][w] = i0;
+        S.wsum[1][w] = i1;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        u64 run = 0;
+        u64 r0 = 0, r1 = 0;
         for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
-            u64 x = S.wsum[i];
-            S.wsum[i] = run;
-            run += x;
+            u64 x0 = S.wsum[0][i], x1 = S.wsum[1][i];
+            S.wsum[0][i] = r0;
+            S.wsum[1][i] = r1;
+            r0 += x0;
+            r1 += x1;
         }
         for (int l = 0; l < kLists; ++l) {
-            u32 c = (u32)((run >> (12 * l)) & 0xfff);
+            u32 c = (u32)(((l < 3 ? r0 : r1) >> (16 * (l % 3))) & 0xffff);
             S.base[l] = (c && counters[l]) ? atomicAdd(counters[l], c) : 0u;
         }
     }
     __syncthreads();
-    u64 excl = incl - packed + S.wsum[w];
+    u64 e0 = i0 - p0 + S.wsum[0][w], e1 = i1 - p1 + S.wsum[1][w];
 #pragma unroll
-    for (int l = 0; l < kLists; ++l) off[l] = S.base[l] + (u32)((excl >> (12 * l)) & 0xfff);
+    for (int l = 0; l < kLists; ++l)
+        off[l] = S.base[l] + (u32)(((l < 3 ? e0 : e1) >> (16 * (l % 3))) & 0xffff);
     __syncthreads();
 }
 
 // Block-wide minimum of a non-negative double, one atomic per block.
+// sh holds one slot per wave.
 __device__ __forceinline__ void block_atomic_min(double v, u64* dst, double* sh) {
     v = wave_min_f64(v);
     const int w = threadIdx.x / kWave;
@@ -266,8 +281,11 @@ constexpr int kQRing = 4;        // level queue counters (ring)
 
 // ------------------------------------------------------------ frontier
 // Initial frontier: the two children of every internal node (Alg. 1, Wspd).
+// In a batched solve (pinst non-null) the two children of a node that joins
+// several instances belong to different instances: such a pair is never
+// expanded (bound +inf, dropped by the far split).
 template <int D>
-__global__ void k_init_frontier(TreeView t, int hdb, PairRec* f) {
+__global__ void k_init_frontier(TreeView t, int hdb, const u32* pinst, PairRec* f) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= t.n - 1) return;
     const NodeRec<D>* N = nodes_of<D>(t);
@@ -277,6 +295,7 @@ __global__ void k_init_frontier(TreeView t, int hdb, PairRec* f) {
     p.b = (u32)c.y;
     double2 z = make_double2(0.0, 0.0);
     p.lb2 = pair_wlb2<D>(N[p.a], N[p.b], hdb, hdb ? t.cdr[p.a] : z, hdb ? t.cdr[p.b] : z);
+    if (pinst && pinst[N[p.a].first] != pinst[N[p.b].first]) p.lb2 = __longlong_as_double(0x7ff0000000000000ll);
     f[i] = p;
 }
 
@@ -285,19 +304,19 @@ __global__ void __launch_bounds__(kBlock) k_min_positive_lb(const PairRec* f, u3
     __shared__ double sh[4];
     double v = __longlong_as_double(0x7ff0000000000000ll);
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x)
-        if (f[i].lb2 > 0.0) v = fmin(v, f[i].lb2);
+        if (f[i].lb2 > 0.0) v = fmin(v, f[i].lb2);  // +inf (cross-instance) never wins
     block_atomic_min(v, &cnt->m[M_F], sh);
 }
 
-// Frontier split: queue the pairs whose lower bound is within beta, keep the
-// rest.  A pair's connectivity is checked when it is expanded, so this pass
-// only streams the records.
+// Near-frontier split: queue the pairs whose lower bound is within beta,
+// keep the rest in the near list.  A pair's connectivity is checked when it
+// is expanded, so this pass only streams the records.
 __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs r, const PairRec* fin, u32 nfin,
                                                            u32* qcount) {
     __shared__ BlockAlloc S;
     __shared__ double shm[4];
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
-    u32* ctr[kLists] = {qcount, &r.cnt->c[C_F], nullptr, nullptr, nullptr};
+    u32* ctr[kLists] = {qcount, &r.cnt->c[C_F], nullptr, nullptr, nullptr, nullptr};
     double minf = inf;
     for (u32 b0 = blockIdx.x * kBlock; b0 < nfin; b0 += gridDim.x * kBlock) {
         u32 i = b0 + threadIdx.x;
@@ -309,8 +328,9 @@ __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs
         bool due = have && p.lb2 <= r.beta2;
         bool wait = have && !due;
         if (wait) minf = fmin(minf, p.lb2);
+        u32 cnt[kLists] = {(u32)due, (u32)wait, 0, 0, 0, 0};
         u32 off[kLists];
-        block_alloc(S, (u64)due | ((u64)wait << 12), ctr, off);
+        block_alloc(S, cnt, ctr, off);
         if (due) {
             if (off[0] < r.cap_q) r.q[off[0]] = p;
             else flag_overflow(r.cnt);
@@ -323,6 +343,49 @@ __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs
     block_atomic_min(minf, &r.cnt->m[M_F], shm);
 }
 
+// Far-frontier split at the start of a band: drop pairs whose points are now
+// in one component, queue the due ones, move those within the new band edge
+// to the near list and keep the rest far.
+__global__ void __launch_bounds__(kBlock) k_split_far(TreeView t, RoundArgs r, const PairRec* fin, u32 nfin,
+                                                      u32* qcount) {
+    __shared__ BlockAlloc S;
+    __shared__ double shm[4];
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    u32* ctr[kLists] = {qcount, &r.cnt->c[C_F], &r.cnt->c[C_FAR], nullptr, nullptr, nullptr};
+    double minf = inf, minfar = inf;
+    for (u32 b0 = blockIdx.x * kBlock; b0 < nfin; b0 += gridDim.x * kBlock) {
+        u32 i = b0 + threadIdx.x;
+        bool have = i < nfin;
+        PairRec p;
+        p.a = p.b = 0;
+        p.lb2 = 0.0;
+        if (have) p = fin[i];
+        bool keep = have && p.lb2 < __longlong_as_double(0x7ff0000000000000ll) && !connected(t, p.a, p.b);
+        bool due = keep && p.lb2 <= r.beta2;
+        bool near = keep && !due && p.lb2 <= r.t_near;
+        bool far = keep && !due && !near;
+        if (near) minf = fmin(minf, p.lb2);
+        if (far) minfar = fmin(minfar, p.lb2);
+        u32 cnt[kLists] = {(u32)due, (u32)near, (u32)far, 0, 0, 0};
+        u32 off[kLists];
+        block_alloc(S, cnt, ctr, off);
+        if (due) {
+            if (off[0] < r.cap_q) r.q[off[0]] = p;
+            else flag_overflow(r.cnt);
+        }
+        if (near) {
+            if (off[1] < r.cap_f) r.fout[off[1]] = p;
+            else flag_overflow(r.cnt);
+        }
+        if (far) {
+            if (off[2] < r.cap_far) r.ffar[off[2]] = p;
+            else flag_overflow(r.cnt);
+        }
+    }
+    block_atomic_min(minf, &r.cnt->m[M_F], shm);
+    block_atomic_min(minfar, &r.cnt->m[M_FAR], shm);
+}
+
 // ------------------------------------------------------------ expansion
 // One breadth-first level of the FindPair recursion (Alg. 1).  Each lane
 // takes one pair: a pair whose points are all in one component is dropped; a
@@ -332,147 +395,229 @@ __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs
 // the node with the larger bounding sphere is split, and each child pair goes
 // to the frontier (bound above beta) or to the next level.  Connectivity of a
 // child pair is checked when it is expanded.
+struct LevelAcc {
+    double minf, minp, minfar;
+    unsigned long long visits, evals, solved;
+};
+
+// One block step of a level: the block's threads take pairs b0.. of qin
+// (count nq); child pairs due in this round go to qout through counter
+// ctr[4].  All threads of the block must call it.
+template <int D>
+__device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r, int hdb, const PairRec* qin, u32 nq,
+                                           u32 b0, PairRec* qout, u32 cap_qout, u32* const* ctr, BlockAlloc& S,
+                                           LevelAcc& acc) {
+    const NodeRec<D>* N = nodes_of<D>(t);
+    u32 i = b0 + threadIdx.x;
+    bool have = i < nq;
+    bool to_c = false, to_p = false, to_big = false, to_f = false;
+    EdgeOut e;
+    u32 a = 0, b = 0, oth = 0;
+    int2 ch = make_int2(0, 0);
+    double lb = 0.0;
+    double lbc[2] = {0.0, 0.0};
+    bool cf[2] = {false, false}, cq[2] = {false, false};
+    if (have) {
+        PairRec pr = qin[i];
+        a = pr.a;
+        b = pr.b;
+        ++acc.visits;
+        const int ka = t.comp[a], kb = t.comp[b];
+        if (!(ka >= 0 && ka == kb)) {
+            NodeRec<D> A = N[a], B = N[b];
+            double2 z = make_double2(0.0, 0.0);
+            double2 ca = hdb ? t.cdr[a] : z, cb = hdb ? t.cdr[b] : z;
+            lb = pair_wlb2<D>(A, B, hdb, ca, cb);
+            if (lb > r.beta2) {
+                to_f = true;
+            } else if (well_separated<D>(A, B, hdb, ca, cb)) {
+                u64 work = (u64)A.count * (u64)B.count;
+                if (work <= (u64)kTinyEvals) {
+                    e = point_edge<D>(t, hdb, (u32)A.first, (u32)B.first);
+                    for (int x = A.first; x < A.first + A.count; ++x)
+                        for (int y = B.first; y < B.first + B.count; ++y) {
+                            EdgeOut c = point_edge<D>(t, hdb, (u32)x, (u32)y);
+                            if (key_less(c.k, e.k)) e = c;
+                        }
+                    acc.evals += work;
+                    ++acc.solved;
+                    to_c = e.k.w2 <= r.beta2;
+                    to_p = !to_c;
+                    if (to_p) acc.minp = fmin(acc.minp, e.k.w2);
+                } else {
+                    to_big = true;
+                }
+            } else {
+                // split the node with the larger bounding sphere (Alg. 1, FindPair)
+                bool split_a = (B.count == 1) ||
+                               (A.count > 1 && (A.rad > B.rad || (A.rad == B.rad && A.count >= B.count)));
+                const NodeRec<D>& X = split_a ? A : B;
+                const NodeRec<D>& O = split_a ? B : A;
+                double2 co = split_a ? cb : ca;
+                const int kother = split_a ? kb : ka;
+                oth = split_a ? b : a;
+                ch = node_kids(t.n, X.first, X.count, X.split);
+                // the two children are usually adjacent records (and adjacent
+                // component entries): drop connected child pairs, bound the
+                // others, park the far ones
+                int kc[2] = {t.comp[ch.x], t.comp[ch.y]};
+                double2 c0 = hdb ? t.cdr[ch.x] : z, c1 = hdb ? t.cdr[ch.y] : z;
+                lbc[0] = pair_wlb2<D>(N[ch.x], O, hdb, c0, co);
+                lbc[1] = pair_wlb2<D>(N[ch.y], O, hdb, c1, co);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    if (kc[c] >= 0 && kc[c] == kother) continue;
+                    if (lbc[c] > r.beta2) cf[c] = true;
+                    else cq[c] = true;
+                }
+            }
+        }
+    }
+    // waiting pairs: the pair itself (to_f) or its children (cf)
+    PairRec wp[3];
+    bool wnear[3] = {false, false, false}, wfar[3] = {false, false, false};
+    u32 nn = 0, nf = 0, nq2 = 0;
+    wp[0].a = a;
+    wp[0].b = b;
+    wp[0].lb2 = lb;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        wp[1 + c].a = (u32)(c == 0 ? ch.x : ch.y);
+        wp[1 + c].b = oth;
+        wp[1 + c].lb2 = lbc[c];
+        nq2 += cq[c] ? 1 : 0;
+    }
+    bool wait[3] = {to_f, cf[0], cf[1]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (!wait[k]) continue;
+        if (wp[k].lb2 <= r.t_near) {
+            wnear[k] = true;
+            ++nn;
+            acc.minf = fmin(acc.minf, wp[k].lb2);
+        } else {
+            wfar[k] = true;
+            ++nf;
+            acc.minfar = fmin(acc.minfar, wp[k].lb2);
+        }
+    }
+    u32 cnt[kLists] = {(u32)to_c, (u32)to_p, (u32)to_big, nn, nf, nq2};
+    u32 off[kLists];
+    block_alloc(S, cnt, ctr, off);
+    if (to_c) {
+        if (off[0] < r.cap_c) put_edge(r.c, off[0], e);
+        else flag_overflow(r.cnt);
+    }
+    if (to_p) {
+        if (off[1] < r.cap_p) put_edge(r.pout, off[1], e);
+        else flag_overflow(r.cnt);
+    }
+    if (to_big) {
+        if (off[2] < r.cap_big) r.big[off[2]] = make_uint2(a, b);
+        else flag_overflow(r.cnt);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (wnear[k]) {
+            if (off[3] < r.cap_f) r.fout[off[3]] = wp[k];
+            else flag_overflow(r.cnt);
+            ++off[3];
+        }
+        if (wfar[k]) {
+            if (off[4] < r.cap_far) r.ffar[off[4]] = wp[k];
+            else flag_overflow(r.cnt);
+            ++off[4];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if (cq[c]) {
+            if (off[5] < cap_qout) qout[off[5]] = wp[1 + c];
+            else flag_overflow_q(r.cnt);
+            ++off[5];
+        }
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void level_flush(const RoundArgs& r, LevelAcc& acc) {
+    __shared__ double shm[NT / kWave];
+    __shared__ unsigned long long shs[NT / kWave];
+    block_atomic_min(acc.minf, &r.cnt->m[M_F], shm);
+    block_atomic_min(acc.minp, &r.cnt->m[M_P], shm);
+    block_atomic_min(acc.minfar, &r.cnt->m[M_FAR], shm);
+    unsigned long long v = block_sum_u64(acc.visits, shs);
+    unsigned long long ev = block_sum_u64(acc.evals, shs);
+    unsigned long long so = block_sum_u64(acc.solved, shs);
+    if (threadIdx.x == 0 && v) {
+        atomicAdd(&r.cnt->c64[C64_VISITS], v);
+        atomicAdd(&r.cnt->c64[C64_EVALS], ev);
+        atomicAdd(&r.cnt->c64[C64_BCCP], so);
+    }
+}
+
+// One breadth-first level over the whole grid.  Blocks beyond the queue
+// leave at once.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin,
                                                   u32 cap_in, const u32* nq_p, u32* nq_next, u32* nq_clear) {
     __shared__ BlockAlloc S;
-    __shared__ double shm[4];
-    __shared__ unsigned long long shs[4];
-    const double inf = __longlong_as_double(0x7ff0000000000000ll);
-    const NodeRec<D>* N = nodes_of<D>(t);
     if (blockIdx.x == 0 && threadIdx.x == 0) *nq_clear = 0;
     // an overflowed previous level counts more pairs than it stored: read
     // only what the queue holds (the overflow flag makes the round restart)
     const u32 nq = min(*nq_p, cap_in);
-    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], &r.cnt->c[C_BIG], &r.cnt->c[C_F], nq_next};
-    double minf = inf, minp = inf;
-    unsigned long long visits = 0, evals = 0, solved = 0;
-    for (u32 b0 = blockIdx.x * kBlock; b0 < nq; b0 += gridDim.x * kBlock) {
-        u32 i = b0 + threadIdx.x;
-        bool have = i < nq;
-        bool to_c = false, to_p = false, to_big = false, to_f = false;
-        EdgeOut e;
-        u32 a = 0, b = 0, oth = 0;
-        int2 ch = make_int2(0, 0);
-        double lb = 0.0;
-        double lbc[2] = {0.0, 0.0};
-        bool cf[2] = {false, false}, cq[2] = {false, false};
-        int nfront = 0, nnext = 0;
-        if (have) {
-            PairRec pr = qin[i];
-            a = pr.a;
-            b = pr.b;
-            ++visits;
-            const int ka = t.comp[a], kb = t.comp[b];
-            if (!(ka >= 0 && ka == kb)) {
-                NodeRec<D> A = N[a], B = N[b];
-                double2 z = make_double2(0.0, 0.0);
-                double2 ca = hdb ? t.cdr[a] : z, cb = hdb ? t.cdr[b] : z;
-                lb = pair_wlb2<D>(A, B, hdb, ca, cb);
-                if (lb > r.beta2) {
-                    to_f = true;
-                    minf = fmin(minf, lb);
-                } else if (well_separated<D>(A, B, hdb, ca, cb)) {
-                    u64 work = (u64)A.count * (u64)B.count;
-                    if (work <= (u64)kTinyEvals) {
-                        e = point_edge<D>(t, hdb, (u32)A.first, (u32)B.first);
-                        for (int x = A.first; x < A.first + A.count; ++x)
-                            for (int y = B.first; y < B.first + B.count; ++y) {
-                                EdgeOut c = point_edge<D>(t, hdb, (u32)x, (u32)y);
-                                if (key_less(c.k, e.k)) e = c;
-                            }
-                        evals += work;
-                        ++solved;
-                        to_c = e.k.w2 <= r.beta2;
-                        to_p = !to_c;
-                        if (to_p) minp = fmin(minp, e.k.w2);
-                    } else {
-                        to_big = true;
-                    }
-                } else {
-                    // split the node with the larger bounding sphere (Alg. 1, FindPair)
-                    bool split_a = (B.count == 1) ||
-                                   (A.count > 1 && (A.rad > B.rad || (A.rad == B.rad && A.count >= B.count)));
-                    const NodeRec<D>& X = split_a ? A : B;
-                    const NodeRec<D>& O = split_a ? B : A;
-                    double2 co = split_a ? cb : ca;
-                    const int kother = split_a ? kb : ka;
-                    oth = split_a ? b : a;
-                    ch = node_kids(t.n, X.first, X.count, X.split);
-                    // the two children are usually adjacent records (and
-                    // adjacent component entries): drop connected child
-                    // pairs, bound the others, park the far ones
-                    int kc[2] = {t.comp[ch.x], t.comp[ch.y]};
-                    double2 c0 = hdb ? t.cdr[ch.x] : z, c1 = hdb ? t.cdr[ch.y] : z;
-                    lbc[0] = pair_wlb2<D>(N[ch.x], O, hdb, c0, co);
-                    lbc[1] = pair_wlb2<D>(N[ch.y], O, hdb, c1, co);
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        if (kc[c] >= 0 && kc[c] == kother) continue;
-                        if (lbc[c] > r.beta2) {
-                            cf[c] = true;
-                            ++nfront;
-                            minf = fmin(minf, lbc[c]);
-                        } else {
-                            cq[c] = true;
-                            ++nnext;
-                        }
-                    }
-                }
-            }
+    if (blockIdx.x * kBlock >= nq) return;
+    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR], nq_next};
+    const double inf_ = __longlong_as_double(0x7ff0000000000000ll);
+    LevelAcc acc = {inf_, inf_, inf_, 0, 0, 0};
+    for (u32 b0 = blockIdx.x * kBlock; b0 < nq; b0 += gridDim.x * kBlock)
+        level_step<D>(t, r, hdb, qin, nq, b0, r.q, r.cap_q, ctr, S, acc);
+    level_flush<kBlock>(r, acc);
+}
+
+// Many small levels in one workgroup: the level barrier is __syncthreads and
+// the next queue's counter lives in LDS, so a chain of thin levels costs no
+// kernel launches or host round trips.  Stops when the queue is empty or
+// grows beyond `small_max` (then the grid-wide level kernel takes over).
+// The queue ping-pongs between q[0] and q[1]; on exit ring[b] holds the
+// remaining count of the buffer b it ends in (other ring slots are zeroed),
+// and state = {remaining, b}.
+constexpr int kSmallBlock = 1024;
+
+template <int D>
+__global__ void __launch_bounds__(kSmallBlock) k_level_small(TreeView t, RoundArgs r, int hdb, PairRec* q0, u32 cap0,
+                                                             PairRec* q1, u32 cap1, int b_in, u32* ring,
+                                                             u32 ring_in, u32 small_max, u32* state) {
+    __shared__ BlockAlloc S;
+    __shared__ u32 qn;
+    const double inf_ = __longlong_as_double(0x7ff0000000000000ll);
+    LevelAcc acc = {inf_, inf_, inf_, 0, 0, 0};
+    int b = b_in;
+    u32 nq = min(ring[ring_in], b ? cap1 : cap0);
+    while (nq > 0 && nq <= small_max) {
+        if (threadIdx.x == 0) qn = 0;
+        __syncthreads();
+        u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR], &qn};
+        const PairRec* qin = b ? q1 : q0;
+        PairRec* qout = b ? q0 : q1;
+        u32 capo = b ? cap0 : cap1;
+        for (u32 b0 = 0; b0 < nq; b0 += kSmallBlock) level_step<D>(t, r, hdb, qin, nq, b0, qout, capo, ctr, S, acc);
+        __syncthreads();
+        u32 nn = qn;
+        b ^= 1;
+        if (nn > capo) {  // overflowed (flagged): stop, the round restarts
+            nq = 0;
+            break;
         }
-        u64 packed = (u64)to_c | ((u64)to_p << 12) | ((u64)to_big << 24) | ((u64)(to_f + nfront) << 36) |
-                     ((u64)nnext << 48);
-        u32 off[kLists];
-        block_alloc(S, packed, ctr, off);
-        if (to_c) {
-            if (off[0] < r.cap_c) put_edge(r.c, off[0], e);
-            else flag_overflow(r.cnt);
-        }
-        if (to_p) {
-            if (off[1] < r.cap_p) put_edge(r.pout, off[1], e);
-            else flag_overflow(r.cnt);
-        }
-        if (to_big) {
-            if (off[2] < r.cap_big) r.big[off[2]] = make_uint2(a, b);
-            else flag_overflow(r.cnt);
-        }
-        if (to_f) {
-            PairRec p;
-            p.a = a;
-            p.b = b;
-            p.lb2 = lb;
-            if (off[3] < r.cap_f) r.fout[off[3]] = p;
-            else flag_overflow(r.cnt);
-            ++off[3];
-        }
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            PairRec p;
-            p.a = (u32)(c == 0 ? ch.x : ch.y);
-            p.b = oth;
-            p.lb2 = lbc[c];
-            if (cf[c]) {
-                if (off[3] < r.cap_f) r.fout[off[3]] = p;
-                else flag_overflow(r.cnt);
-                ++off[3];
-            }
-            if (cq[c]) {
-                if (off[4] < r.cap_q) r.q[off[4]] = p;
-                else flag_overflow_q(r.cnt);
-                ++off[4];
-            }
-        }
+        nq = nn;
+        __syncthreads();
     }
-    block_atomic_min(minf, &r.cnt->m[M_F], shm);
-    block_atomic_min(minp, &r.cnt->m[M_P], shm);
-    visits = block_sum_u64(visits, shs);
-    evals = block_sum_u64(evals, shs);
-    solved = block_sum_u64(solved, shs);
-    if (threadIdx.x == 0 && visits) {
-        atomicAdd(&r.cnt->c64[C64_VISITS], visits);
-        atomicAdd(&r.cnt->c64[C64_EVALS], evals);
-        atomicAdd(&r.cnt->c64[C64_BCCP], solved);
+    level_flush<kSmallBlock>(r, acc);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < kQRing; ++k) ring[k] = 0;
+        ring[b] = nq;
+        state[0] = nq;
+        state[1] = (u32)b;
     }
 }
 
@@ -485,6 +630,7 @@ __global__ void __launch_bounds__(kBlock) k_level(TreeView t, RoundArgs r, int h
 // that hold the minimum.  Per-task partial keys are then combined per pair.
 constexpr int kBigA = 128;
 constexpr int kBigB = 2048;
+constexpr int kMidMax = 4096;  // pairs up to this many point pairs: one wave, flattened products
 
 struct PartKey {
     double w2, e2;
@@ -509,7 +655,8 @@ __global__ void k_big_ntasks(TreeView t, const uint2* big, u32 nbig, u32* ntask)
     if (i >= nbig) return;
     int2 ra, rb;
     big_orient<D>(t, big[i], ra, rb);
-    ntask[i] = (u32)(((ra.y + kBigA - 1) / kBigA) * ((rb.y + kBigB - 1) / kBigB));
+    u64 work = (u64)ra.y * (u64)rb.y;
+    ntask[i] = work <= (u64)kMidMax ? 1u : (u32)(((ra.y + kBigA - 1) / kBigA) * ((rb.y + kBigB - 1) / kBigB));
 }
 
 template <int D, int HDB>
@@ -528,6 +675,41 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
     }
     int2 ra, rb;
     big_orient<D>(t, big[lo], ra, rb);
+    if ((u64)ra.y * (u64)rb.y <= (u64)kMidMax) {
+        // medium pair: the lanes stride over the flattened A x B products
+        // with the exact key compare
+        const u32 nb = (u32)rb.y, tot = (u32)ra.y * nb;
+        EdgeOut best;
+        best.k = key_none();
+        best.i = best.j = kNone;
+        for (u32 idx = (u32)lane; idx < tot; idx += kWave) {
+            u32 ia = idx / nb;
+            EdgeOut c = point_edge<D>(t, HDB, (u32)ra.x + ia, (u32)rb.x + (idx - ia * nb));
+            if (key_less(c.k, best.k)) best = c;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            EdgeOut w;
+            w.k.w2 = __shfl_xor(best.k.w2, o);
+            w.k.e2 = __shfl_xor(best.k.e2, o);
+            w.k.lo = __shfl_xor(best.k.lo, o);
+            w.k.hi = __shfl_xor(best.k.hi, o);
+            w.i = __shfl_xor(best.i, o);
+            w.j = __shfl_xor(best.j, o);
+            if (key_less(w.k, best.k)) best = w;
+        }
+        if (lane == 0) {
+            PartKey pk;
+            pk.w2 = best.k.w2;
+            pk.e2 = best.k.e2;
+            pk.ids = ((u64)best.k.lo << 32) | best.k.hi;
+            pk.pos = ((u64)best.i << 32) | best.j;
+            part[task] = pk;
+            atomicAdd(&cnt->c64[C64_EVALS], (unsigned long long)tot);
+            atomicAdd(&cnt->c64[C64_BIGEVALS], (unsigned long long)tot);
+        }
+        return;
+    }
     u32 local = task - toff[lo];
     int nbt = (rb.y + kBigB - 1) / kBigB;
     int ta = (int)(local / (u32)nbt), tb = (int)(local % (u32)nbt);
@@ -622,7 +804,7 @@ __global__ void __launch_bounds__(kBlock) k_big_combine(RoundArgs r, u32 nbig, c
     __shared__ BlockAlloc S;
     __shared__ double shm[4];
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
-    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], nullptr, nullptr, nullptr};
+    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], nullptr, nullptr, nullptr, nullptr};
     double minp = inf;
     for (u32 b0 = blockIdx.x * kBlock; b0 < nbig; b0 += gridDim.x * kBlock) {
         u32 i = b0 + threadIdx.x;
@@ -645,7 +827,8 @@ __global__ void __launch_bounds__(kBlock) k_big_combine(RoundArgs r, u32 nbig, c
         bool to_p = have && !to_c;
         if (to_p) minp = fmin(minp, b.w2);
         u32 off[kLists];
-        block_alloc(S, (u64)to_c | ((u64)to_p << 12), ctr, off);
+        u32 cnt[kLists] = {(u32)to_c, (u32)to_p, 0, 0, 0, 0};
+        block_alloc(S, cnt, ctr, off);
         if (to_c) {
             if (off[0] < r.cap_c) put_edge_raw(r.c, off[0], b.w2, b.e2, b.ids, b.pos);
             else flag_overflow(r.cnt);
@@ -665,7 +848,7 @@ __global__ void __launch_bounds__(kBlock) k_split_pool(RoundArgs r, EdgeList pin
     __shared__ BlockAlloc S;
     __shared__ double shm[4];
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
-    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], nullptr, nullptr, nullptr};
+    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], nullptr, nullptr, nullptr, nullptr};
     double minp = inf;
     for (u32 b0 = blockIdx.x * kBlock; b0 < npin; b0 += gridDim.x * kBlock) {
         u32 i = b0 + threadIdx.x;
@@ -686,7 +869,8 @@ __global__ void __launch_bounds__(kBlock) k_split_pool(RoundArgs r, EdgeList pin
         bool to_p = keep && !to_c;
         if (to_p) minp = fmin(minp, w2);
         u32 off[kLists];
-        block_alloc(S, (u64)to_c | ((u64)to_p << 12), ctr, off);
+        u32 cnt[kLists] = {(u32)to_c, (u32)to_p, 0, 0, 0, 0};
+        block_alloc(S, cnt, ctr, off);
         if (to_c) {
             if (off[0] < r.cap_c) put_edge_raw(r.c, off[0], w2, e2, ids, pos);
             else flag_overflow(r.cnt);
@@ -717,7 +901,7 @@ __global__ void k_sortkeys(const EdgeList L, u32 m, int B, u64* kid, u64* ke2, u
 // (lo << B) | hi, 1 = d2 bits, 2 = w2 bits (non-negative doubles order like
 // their bits).  Also records the word's min and max.
 __global__ void __launch_bounds__(kBlock) k_gather_word(const EdgeList L, const u32* perm, u32 m, int kind, int B,
-                                                        u64* key, u32* val, u64* minmax) {
+                                                        const u32* pinst, u64* key, u32* val, u64* minmax) {
     __shared__ u64 smin[4], smax[4];
     u64 mn = ~0ull, mx = 0;
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
@@ -728,8 +912,10 @@ __global__ void __launch_bounds__(kBlock) k_gather_word(const EdgeList L, const 
             w = ((ids >> 32) << B) | (ids & 0xffffffffull);
         } else if (kind == 1) {
             w = dbits(L.e2[e]);
-        } else {
+        } else if (kind == 2) {
             w = dbits(L.w2[e]);
+        } else {
+            w = pinst[(u32)(L.pos[e] >> 32)];  // instance of the edge (batched solves)
         }
         key[i] = w;
         val[i] = e;
@@ -772,6 +958,20 @@ __global__ void k_flag_ties2(const EdgeList L, const u32* perm, u32 m, u32* flag
         tie |= L.w2[a] == L.w2[b] && L.e2[a] == L.e2[b];
     }
     if (__any(tie) && lane_id() == 0) atomicOr(flag, 1u);
+}
+
+// Instance of every arena row (instances packed in order; binary search in
+// their first rows).
+__global__ void k_row_instance(const int2* irange, u32 count, u32 n, u32* row_inst) {
+    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    u32 lo = 0, hi = count - 1;
+    while (lo < hi) {
+        u32 mid = (lo + hi + 1) >> 1;
+        if ((u32)irange[mid].x <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    row_inst[i] = lo;
 }
 
 __global__ void k_iota(u32* a, u32 m) {
@@ -823,7 +1023,7 @@ __global__ void __launch_bounds__(kBlock) k_bor_hook(const u32* alive, const u32
                                                      u32 cap_out, Counters* cnt) {
     __shared__ BlockAlloc S;
     const u32 na = min(*nalive_p, cap);
-    u32* ctr[kLists] = {&cnt->c[C_OUT], nalive_next, nullptr, nullptr, nullptr};
+    u32* ctr[kLists] = {&cnt->c[C_OUT], nalive_next, nullptr, nullptr, nullptr, nullptr};
     for (u32 b0 = blockIdx.x * kBlock; b0 < na; b0 += gridDim.x * kBlock) {
         u32 s = b0 + threadIdx.x;
         bool have = s < na;
@@ -850,7 +1050,8 @@ __global__ void __launch_bounds__(kBlock) k_bor_hook(const u32* alive, const u32
             }
         }
         u32 off[kLists];
-        block_alloc(S, (u64)sel | ((u64)keep << 12), ctr, off);
+        u32 cn[kLists] = {(u32)sel, (u32)keep, 0, 0, 0, 0};
+        block_alloc(S, cn, ctr, off);
         if (sel) {
             if (off[0] < cap_out) put_edge_raw(out, off[0], L.w2[e], L.e2[e], L.ids[e], L.pos[e]);
             else flag_overflow(cnt);
@@ -960,13 +1161,17 @@ __device__ double sqrt_rn(double x) {
     return y * scale;
 }
 
-__global__ void k_write_edges(const EdgeList L, const u32* perm, u32 m, long long* edges, double* w, double* w2) {
+// Output edge k of the sorted order; batched solves subtract the instance's
+// first row so that ids are local to the instance.
+__global__ void k_write_edges(const EdgeList L, const u32* perm, u32 m, const u32* pinst, const int2* irange,
+                              long long* edges, double* w, double* w2) {
     u32 k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     u32 e = perm[k];
     u64 ids = L.ids[e];
-    edges[2 * (size_t)k] = (long long)(ids >> 32);
-    edges[2 * (size_t)k + 1] = (long long)(ids & 0xffffffffull);
+    long long base = pinst ? (long long)irange[pinst[(u32)(L.pos[e] >> 32)]].x : 0ll;
+    edges[2 * (size_t)k] = (long long)(ids >> 32) - base;
+    edges[2 * (size_t)k + 1] = (long long)(ids & 0xffffffffull) - base;
     double x = L.w2[e];
     if (w) w[k] = sqrt_rn(x);
     if (w2) w2[k] = x;

@@ -151,6 +151,16 @@ __global__ void k_morton(const double* P, int n, const double* bbox, u64* key, u
     val[i] = (u32)i;
 }
 
+// Batched solves: the first key word is the point's instance, so every
+// instance becomes one contiguous subtree and the refinement levels quantise
+// each instance inside its own box.
+__global__ void k_inst_key(const u32* row_inst, int n, u64* key, u32* val) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = row_inst[i];
+    val[i] = (u32)i;
+}
+
 // Group starts: flag[i] = 1 where the key words [0, L) of sorted positions i
 // and i-1 differ (and at i = 0).  any_dup gets 1 if some group has >1 point.
 __global__ void k_key_flags(const u64* keys, int n, int L, u32* flag, u32* any_dup) {
@@ -306,14 +316,14 @@ __global__ void k_karras(const u64* k, int n, int L, NodeRec<D>* nodes, int* par
 
 // ------------------------------------------------------------ node bounds
 // Bottom-up: every internal node is finished by the second of its two
-// children to arrive.  Phase 1: a block owns 256 consecutive leaves and
+// children to arrive.  Phase 1: a block owns 1024 consecutive leaves and
 // merges every node whose range lies inside them through LDS (arrival
 // counters and boxes; workgroup-scope ordering only).  A thread whose climb
 // reaches a node spanning several blocks records the child it came from.
-// Phase 2: one workgroup finishes the spanning nodes (about 2n/256 of them)
+// Phase 2: one workgroup finishes the spanning nodes (about 2n/1024 of them)
 // starting from those children, again with workgroup-scope ordering only,
 // since every arrival counter and record it touches is its own.
-constexpr int kBoundsBlock = 256;
+constexpr int kBoundsBlock = 1024;
 constexpr int kBoundsTop = 1024;  // threads of the phase-2 workgroup
 
 template <int D>
@@ -480,14 +490,26 @@ __device__ __forceinline__ double point_box_lb2(const double (&q)[D], const doub
     return s;
 }
 
+// Batched solves pass the instance of each sorted position and each
+// instance's (first position, size) and k: a lane only accepts points of its
+// own instance (the sorted positions of an instance are contiguous).
 template <int D, int KMAX>
-__global__ void __launch_bounds__(64) k_knn(TreeView t, int kk, double* cd2_out, u32* err) {
+__global__ void __launch_bounds__(64) k_knn(TreeView t, int kk_all, const u32* pinst, const int2* irange,
+                                           const int* ik, double* cd2_out, u32* err) {
     __shared__ int stack[kKnnStack];
     const int n = t.n;
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
     int p = blockIdx.x * kWave + lane_id();
     bool live = p < n;
     int pq = live ? p : n - 1;
+    int lo_r = 0, hi_r = n, kk = kk_all;
+    if (pinst) {
+        u32 ins = pinst[pq];
+        int2 rg = irange[ins];
+        lo_r = rg.x;
+        hi_r = rg.x + rg.y;
+        kk = ik[ins];
+    }
     double q[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) q[k] = t.X[(size_t)pq * D + k];
@@ -506,13 +528,13 @@ __global__ void __launch_bounds__(64) k_knn(TreeView t, int kk, double* cd2_out,
         __syncthreads();
         const NodeRec<D>* N = nodes_of<D>(t);
         double lb = point_box_lb2<D>(q, N[v].lo, N[v].hi);
-        bool want = live && lb < kth;
-        if (!__any(want)) continue;
         int2 r = make_int2(N[v].first, N[v].count);
+        bool want = live && lb < kth && r.x < hi_r && r.x + r.y > lo_r;
+        if (!__any(want)) continue;
         if (r.y <= kKnnLeaf) {
             for (int j = r.x; j < r.x + r.y; ++j) {
                 double dd = sqdist<D>(q, t.X + (size_t)j * D);
-                if (dd < kth) {
+                if (dd < kth && j >= lo_r && j < hi_r) {
                     topk_insert<KMAX>(top, dd);
                     kth = top[KMAX - 1];
                 }

@@ -44,6 +44,17 @@ class _Stats(ctypes.Structure):
     ]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("min_pts", ctypes.c_int32)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("min_pts", ctypes.c_int32), ("core_dist", ctypes.c_void_p), ("edges", ctypes.c_void_p),
+                ("weights", ctypes.c_void_p), ("status", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -60,6 +71,10 @@ def load(path: str = LIB_PATH):
     lib.geomst_hdbscan.argtypes = [P, i64, i32, i32, P, P, P]
     lib.geomst_emst_dev.argtypes = [P, i64, i32, P, P, P, P]
     lib.geomst_hdbscan_dev.argtypes = [P, i64, i32, i32, P, P, P, P, P, P]
+    lib.geomst_batch_dev.argtypes = [P, i32, ctypes.POINTER(BatchItem), i64, P, P, P, P, P, P]
+    lib.geomst_batch.argtypes = [ctypes.POINTER(Instance), i64]
+    lib.geomst_batch_dev.restype = ctypes.c_int
+    lib.geomst_batch.restype = ctypes.c_int
     lib.geomst_get_stats.argtypes = [ctypes.POINTER(_Stats)]
     lib.geomst_set_option.argtypes = [ctypes.c_char_p, dbl]
     lib.geomst_last_error.restype = ctypes.c_char_p
@@ -201,3 +216,83 @@ def hdbscan(points, min_pts: int, want_sq: bool = False):
     _check(lib.geomst_hdbscan(p.ctypes.data, n, d, int(min_pts), cd.ctypes.data, e.ctypes.data,
                               w.ctypes.data))
     return cd, e, w
+
+
+# ------------------------------------------------------------------ batches
+def pack(instances, min_pts=0):
+    """Pack a list of [n_i][d_i] arrays into one zero-padded [N][stride]
+    arena (instances in order) -> (arena, items, stride).  min_pts: one int
+    for all instances or a list (0 = EMST)."""
+    mps = list(min_pts) if hasattr(min_pts, "__len__") else [int(min_pts)] * len(instances)
+    stride = max(int(np.asarray(x).shape[1]) for x in instances)
+    N = sum(len(x) for x in instances)
+    arena = np.zeros((N, stride))
+    items = (BatchItem * len(instances))()
+    off = 0
+    for i, x in enumerate(instances):
+        x = np.asarray(x, dtype=np.float64)
+        arena[off:off + len(x), :x.shape[1]] = x
+        items[i].offset, items[i].n, items[i].d, items[i].min_pts = off, len(x), x.shape[1], mps[i]
+        off += len(x)
+    return arena, items, stride
+
+
+def batch_dev(arena, items, stride, want_sq=False):
+    """Batched solve of a packed arena already on the GPU (float64 CUDA
+    tensor [N][stride]) -> dict of CUDA tensors: edges [N-count,2] (instance-
+    local ids, instance i's edges start at row offset_i - i), weights,
+    core_dist [N] (and weights_sq, core_dist_sq)."""
+    import torch
+    lib = load()
+    a = arena.contiguous()
+    N, count = a.shape[0], len(items)
+    dev = a.device
+    m = N - count
+    out = {"edges": torch.empty((m, 2), dtype=torch.int64, device=dev),
+           "weights": torch.empty(m, dtype=torch.float64, device=dev),
+           "core_dist": torch.empty(N, dtype=torch.float64, device=dev)}
+    if want_sq:
+        out["weights_sq"] = torch.empty(m, dtype=torch.float64, device=dev)
+        out["core_dist_sq"] = torch.empty(N, dtype=torch.float64, device=dev)
+    ptr = lambda k: out[k].data_ptr() if k in out else None
+    _check(lib.geomst_batch_dev(a.data_ptr(), int(stride), items, count, ptr("edges"), ptr("weights"),
+                                ptr("weights_sq"), ptr("core_dist"), ptr("core_dist_sq"), _stream_ptr()))
+    return out
+
+
+def unpack(out, items):
+    """Split batch_dev outputs per instance -> list of dicts (numpy)."""
+    res = []
+    e = out["edges"].cpu().numpy()
+    w = out["weights"].cpu().numpy()
+    cd = out["core_dist"].cpu().numpy()
+    w2 = out["weights_sq"].cpu().numpy() if "weights_sq" in out else None
+    cd2 = out["core_dist_sq"].cpu().numpy() if "core_dist_sq" in out else None
+    for i, it in enumerate(items):
+        eo, n, off = it.offset - i, it.n, it.offset
+        r = {"edges": e[eo:eo + n - 1], "weights": w[eo:eo + n - 1], "core_dist": cd[off:off + n]}
+        if w2 is not None:
+            r["weights_sq"] = w2[eo:eo + n - 1]
+            r["core_dist_sq"] = cd2[off:off + n]
+        res.append(r)
+    return res
+
+
+def batch(instances, min_pts=0):
+    """Host-pointer batch (geomst_batch): list of numpy arrays -> list of
+    (edges, weights, core_dist)."""
+    lib = load()
+    mps = list(min_pts) if hasattr(min_pts, "__len__") else [int(min_pts)] * len(instances)
+    arr = (Instance * len(instances))()
+    keep = []
+    for i, x in enumerate(instances):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        n, d = x.shape
+        e = np.zeros((max(n - 1, 0), 2), np.int64)
+        w = np.zeros(max(n - 1, 0))
+        cd = np.zeros(n)
+        keep.append((x, e, w, cd))
+        arr[i].points, arr[i].n, arr[i].d, arr[i].min_pts = x.ctypes.data, n, d, mps[i]
+        arr[i].core_dist, arr[i].edges, arr[i].weights = cd.ctypes.data, e.ctypes.data, w.ctypes.data
+    _check(lib.geomst_batch(arr, len(instances)))
+    return [(k[1], k[2], k[3]) for k in keep]

@@ -93,3 +93,32 @@ def test_stats_struct_layout(lib):
             os.remove(exe)
     assert ctypes.sizeof(G._Stats) == size
     assert G._Stats.kernel_ms.offset == off
+
+
+def test_batch_validation_without_device(lib):
+    items = (G.BatchItem * 2)()
+    items[0].offset, items[0].n, items[0].d, items[0].min_pts = 0, 5, 2, 0
+    items[1].offset, items[1].n, items[1].d, items[1].min_pts = 6, 5, 2, 0   # not packed
+    p = np.zeros((11, 2))
+    assert lib.geomst_batch_dev(p.ctypes.data, 2, items, 2, p.ctypes.data, None, None, None, None, None) == G.EINVAL
+    assert "batch item 1" in G.last_error()
+    items[1].offset = 5
+    items[1].d = 3   # d above the stride
+    assert lib.geomst_batch_dev(p.ctypes.data, 2, items, 2, p.ctypes.data, None, None, None, None, None) == G.EINVAL
+    items[1].d, items[1].min_pts = 2, 6   # min_pts above n
+    assert lib.geomst_batch_dev(p.ctypes.data, 2, items, 2, p.ctypes.data, None, None, None, None, None) == G.EINVAL
+    assert lib.geomst_batch_dev(p.ctypes.data, 8, items, 2, p.ctypes.data, None, None, None, None, None) == G.EINVAL
+    inst = (G.Instance * 1)()
+    x = np.array([[0.0, np.inf], [1.0, 1.0]])
+    e = np.zeros((1, 2), np.int64)
+    inst[0].points, inst[0].n, inst[0].d, inst[0].min_pts, inst[0].edges = x.ctypes.data, 2, 2, 0, e.ctypes.data
+    assert lib.geomst_batch(inst, 1) == G.EDOM and inst[0].status == G.EDOM
+
+
+def test_pack_layout():
+    a = np.arange(6.0).reshape(3, 2)
+    b = np.arange(9.0).reshape(3, 3) + 100
+    arena, items, stride = G.pack([a, b], [0, 2])
+    assert stride == 3 and arena.shape == (6, 3)
+    assert np.array_equal(arena[:3, :2], a) and np.all(arena[:3, 2] == 0.0) and np.array_equal(arena[3:], b)
+    assert (items[1].offset, items[1].n, items[1].d, items[1].min_pts) == (3, 3, 3, 2)
