@@ -30,6 +30,13 @@ WORKLOADS = {
                             "(centres uniform in [0,1e4)^5, sigma log-uniform [0.5,20]) + 5% uniform noise, seed 2",
                        n=2_000_000, d=5, min_pts=10),
     "emst_small": dict(desc="EMST, 2,000 points i.i.d. uniform in [0,1)^2, seed 0", n=2000, d=2, min_pts=0),
+    "batch_4096": dict(desc="Batched: 4,096 independent EMST instances, n log-uniform in [100,50000], d in {2,3}, "
+                            "half uniform in the unit cube, half 8-Gaussian mixtures (sigma in [0.01,0.1]), seed 3",
+                       n=None, d=3, min_pts=0),
+    "serve_poisson": dict(desc="Serving: Poisson stream at 2,000 requests/s, 70% EMST / 30% HDBSCAN* (minPts in "
+                               "{5,10,16}), n log-uniform in [1e3,1e6], d in {2..7}, half uniform, half 8-Gaussian "
+                               "mixtures, seed 4; 200 GB admission budget",
+                          n=None, d=None, min_pts=None),
 }
 
 
@@ -125,6 +132,136 @@ def cpu_baseline(name, pts, min_pts, target_s=15.0):
             "seconds": dt}
 
 
+def bench_batch(a, G, torch, np):
+    """Batched path (one forest solve of all instances) against the plain
+    path (one solve call per instance), both on device-resident points."""
+    from paper_2104_01126_amd import workloads as W
+    wl = WORKLOADS[a.workload]
+    log("workload batch_4096: generating")
+    inst = W.batch_4096()
+    arena, items, stride = G.pack(inst, 0)
+    N = arena.shape[0]
+    x = torch.from_numpy(arena).to("cuda:0")
+    singles = [torch.from_numpy(np.ascontiguousarray(p)).to("cuda:0") for p in inst]
+    torch.cuda.synchronize()
+    for i in range(a.warmup):
+        G.batch_dev(x, items, stride)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{a.warmup}: {G.stats().ms_total:.1f} ms")
+    G.set_option("kernel_timing", 1)
+    kms = np.zeros(16)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        G.batch_dev(x, items, stride)
+        kms += np.array(G.stats().kernel_ms)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    G.set_option("kernel_timing", 0)
+    st = G.stats()
+    value = N * a.steps / dt
+    log(f"batched: {dt * 1000 / a.steps:.1f} ms/step, {value / 1e6:.2f} Mpoints/s")
+    # plain path: every instance alone, one call each (one pass, after one warm call)
+    G.emst(singles[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in singles:
+        G.emst(s)
+    torch.cuda.synchronize()
+    dplain = time.perf_counter() - t0
+    plain = N / dplain
+    log(f"plain: {dplain:.2f} s for {len(singles)} calls, {plain / 1e6:.2f} Mpoints/s")
+    fams = G.KERNEL_FAMILIES
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(dt * 1000 / a.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["desc"], "instances": len(inst), "total_points": N, "stride": stride,
+                   "parallelism": "single GPU"},
+        "instances_per_s": round(len(inst) * a.steps / dt, 1),
+        "plain_points_per_s": round(plain, 1), "plain_seconds": round(dplain, 3),
+        "batched_vs_plain": round(value / plain, 2),
+        "kernel_ms_per_step": {fams[i]: round(kms[i] / a.steps, 3) for i in range(len(fams))},
+        "rounds": st.rounds,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def replay(G, trace, pts, server_kw, label):
+    """Open-loop replay of a request trace against a server: a submitter
+    thread submits each request at its arrival time; latency = completion -
+    scheduled arrival (submission lag included)."""
+    import threading
+    import numpy as np
+    S = G.Server(**server_kw)
+    # warm the workspaces on the first requests (not timed)
+    for t in [S.submit(pts[i], trace[i].min_pts) for i in range(min(8, len(trace)))]:
+        S.wait(t)
+    tickets = [None] * len(trace)
+    lag = np.zeros(len(trace))
+    t0 = time.perf_counter()
+
+    def submitter():
+        for i, r in enumerate(trace):
+            now = time.perf_counter() - t0
+            if r.arrival_s > now:
+                time.sleep(r.arrival_s - now)
+            lag[i] = max(0.0, time.perf_counter() - t0 - r.arrival_s)
+            tickets[i] = S.submit(pts[i], r.min_pts)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat = np.zeros(len(trace))
+    qdepth = 0
+    done_at = 0.0
+    for i in range(len(trace)):
+        while tickets[i] is None:
+            time.sleep(0.0005)
+        e, w, cd, info = S.wait(tickets[i])
+        lat[i] = lag[i] * 1000.0 + info["latency_ms"]
+        done_at = max(done_at, trace[i].arrival_s + lat[i] / 1000.0)
+        if (i + 1) % 100 == 0:
+            st = S.stats()
+            qdepth = max(qdepth, st["queued"])
+            log(f"{label}: {i + 1}/{len(trace)} done, queued {st['queued']}, batches {st['batches']}")
+    th.join()
+    st = S.stats()
+    S.close()
+    span = done_at - trace[0].arrival_s
+    npts = sum(r.n for r in trace)
+    return {"solves_per_s": round(len(trace) / span, 2), "points_per_s": round(npts / span, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "mean_ms": round(float(lat.mean()), 2), "makespan_s": round(span, 3),
+            "batches_incl_warmup": st["batches"], "max_batch_requests": st["max_batch_requests"],
+            "peak_reserved_gb": round(st["peak_reserved_bytes"] / 1e9, 2), "max_queue_seen": qdepth}
+
+
+def bench_serve(a, G):
+    """Serving: a prefix of the Poisson request stream replayed open-loop
+    against the continuous-batching server and against the plain path (one
+    instance per launch, FIFO, one worker), measured the same way."""
+    from paper_2104_01126_amd import workloads as W
+    wl = WORKLOADS[a.workload]
+    trace = W.serving_trace(duration_s=a.serve_seconds)
+    log(f"serving: {len(trace)} requests in the first {a.serve_seconds} s of the stream, "
+        f"{sum(r.n for r in trace) / 1e6:.1f} M points; generating")
+    pts = [W.serving_points(r) for r in trace]
+    served = replay(G, trace, pts, dict(hbm_budget_bytes=200_000_000_000, workers=a.serve_workers), "served")
+    log("served:", served)
+    plain = replay(G, trace, pts, dict(hbm_budget_bytes=200_000_000_000, workers=1, max_batch_requests=1),
+                   "plain")
+    log("plain:", plain)
+    out = {
+        "metric": METRIC, "value": served["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": round(served["makespan_s"] * 1000, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["desc"], "requests": len(trace), "trace_seconds": a.serve_seconds,
+                   "offered_req_per_s": 2000, "workers": a.serve_workers, "parallelism": "single GPU"},
+        "served": served, "plain": plain,
+        "served_vs_plain_solves": round(served["solves_per_s"] / plain["solves_per_s"], 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +269,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="emst_1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=0.25,
+                    help="serve_poisson: length of the replayed prefix of the 60 s request stream")
+    ap.add_argument("--serve-workers", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy three times (reference for PMC byte counters)")
     a = ap.parse_args()
@@ -143,6 +283,12 @@ def main():
     import torch
     from paper_2104_01126_amd import geomst as G
 
+    if a.workload == "batch_4096":
+        G.load()
+        return bench_batch(a, G, torch, np)
+    if a.workload == "serve_poisson":
+        G.load()
+        return bench_serve(a, G)
     wl = WORKLOADS[a.workload]
     log(f"workload {a.workload}: generating")
     pts = gen(a.workload)

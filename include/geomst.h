@@ -47,6 +47,8 @@ extern "C" {
 #define GEOMST_EDOM (-2)     /* a coordinate is not finite or |x| > 2^500 */
 #define GEOMST_ENOMEM (-3)   /* device or host allocation failed */
 #define GEOMST_EDEVICE (-4)  /* a HIP runtime call failed */
+#define GEOMST_ETIMEDOUT (-5)/* geomst_wait: the request is not done yet */
+#define GEOMST_ENOENT (-6)   /* unknown or already released ticket */
 #define GEOMST_EINTERNAL (-8)/* an internal consistency check failed */
 
 /*
@@ -130,6 +132,82 @@ typedef struct {
 } geomst_instance_t;
 
 int geomst_batch(geomst_instance_t* inst, int64_t count);
+
+/*
+ * Serving: a request loop with continuous batching over independent EMST and
+ * HDBSCAN* solves (each request is the problem of Sec. 2.1 on its own points).
+ * Worker threads each own a device workspace and a stream; an idle worker
+ * takes the requests queued at the front, in arrival order, up to its share
+ * of the device-memory budget (hbm_budget_bytes / workers, by the estimate
+ * below) and the batch limits, and solves them like geomst_batch, one forest
+ * per group of equal d and kind (EMST or HDBSCAN*).  Requests that arrive
+ * while batches run form the next batch; the batches of different workers
+ * overlap on the device.  Each result is the unique tree of its own points,
+ * identical to solving it alone.
+ *
+ * Admission estimate per request (device bytes):
+ *   n * (640 + 2 * node + 16 * d + (min_pts > 0 ? 320 : 0)),
+ *   node = 64 for d <= 3, else 128.
+ * Workspaces only grow, so the device memory held by a server is at most
+ * about hbm_budget_bytes plus the workspaces' growth beyond the estimate.
+ */
+typedef struct geomst_server geomst_server_t;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;  /* 0 = 200 GB */
+    int32_t workers;            /* concurrent batches, 1..16; 0 = 2 */
+    int32_t device;             /* HIP device index; -1 = the caller's current */
+    int32_t max_batch_requests; /* 0 = 4096 */
+    int32_t reserved;           /* must be 0 */
+    int64_t max_batch_points;   /* 0 = 2^24; at most 2^26 */
+} geomst_server_cfg_t;
+
+/* Timings of one request, filled by geomst_wait (milliseconds). */
+typedef struct {
+    int32_t status;         /* the request's result code */
+    int32_t batch_requests; /* requests in the batch it ran in */
+    int64_t batch_points;   /* points in that batch */
+    double queue_ms;        /* submit -> its batch started */
+    double service_ms;      /* batch start -> batch done (copies included) */
+    double latency_ms;      /* submit -> done */
+} geomst_request_info_t;
+
+/* Server counters (a snapshot). */
+typedef struct {
+    int64_t submitted, queued, running, completed, batches;
+    int64_t reserved_bytes;      /* estimate held by the running batches */
+    int64_t peak_reserved_bytes;
+    int64_t max_batch_requests, max_batch_points;
+} geomst_server_stats_t;
+
+/* Creates a server; cfg may be NULL for the defaults.  EINVAL on bad fields,
+ * EDEVICE if the device cannot be selected. */
+int geomst_server_create(const geomst_server_cfg_t* cfg, geomst_server_t** out);
+
+/* Queues one request.  req->points is copied, so the caller may reuse it at
+ * once; req->edges, req->weights and req->core_dist (as in geomst_batch) must
+ * stay valid until geomst_wait returns the request's result or geomst_cancel
+ * returns.  req->status is set to the admission result.  EINVAL / EDOM as for
+ * geomst_batch; ENOMEM if the request alone exceeds a worker's share of the
+ * budget or the batch point limit. */
+int geomst_submit(geomst_server_t* srv, geomst_instance_t* req, uint64_t* ticket);
+
+/* Waits up to timeout_us microseconds (< 0: forever; 0: poll).  When the
+ * request is done: fills info (may be NULL), releases the ticket and returns
+ * the request's result code.  Otherwise returns ETIMEDOUT and keeps the
+ * ticket.  ENOENT for an unknown ticket. */
+int geomst_wait(geomst_server_t* srv, uint64_t ticket, int64_t timeout_us, geomst_request_info_t* info);
+
+/* Withdraws a request and releases its ticket.  A queued request is removed
+ * without running; one already in a batch is waited for (its outputs may have
+ * been written).  Returns OK, or ENOENT for an unknown ticket. */
+int geomst_cancel(geomst_server_t* srv, uint64_t ticket);
+
+int geomst_server_stats(geomst_server_t* srv, geomst_server_stats_t* out);
+
+/* Finishes the running batches, drops the queued requests unsolved, joins the
+ * workers and frees the workspaces.  Tickets become invalid. */
+void geomst_server_destroy(geomst_server_t* srv);
 
 /* Kernel families timed by the "kernel_timing" option (index into
  * geomst_stats_t.kernel_ms / kernel_launches). */

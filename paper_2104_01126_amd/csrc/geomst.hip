@@ -8,6 +8,12 @@
 #include <string.h>
 #include <chrono>
 #include <mutex>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+#include <memory>
+#include <algorithm>
 #include <string>
 #include <vector>
 #include <algorithm>
@@ -23,6 +29,7 @@ namespace geomst {
 namespace {
 
 thread_local std::string g_err;
+thread_local hipStream_t g_cur_stream = nullptr;  // stream of the solve running on this thread
 thread_local geomst_stats_t g_stats;
 double g_beta_growth = 0.0;  // 0: 2 for EMST, sqrt(2) for HDBSCAN*
 double g_capacity_scale = 1.0;
@@ -54,12 +61,20 @@ inline unsigned blocks(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() {
+        if (p) (void)hipFree(p);
+    }
     void ensure(size_t need, size_t keep = 0, hipStream_t s = 0) {
         if (need <= bytes) return;
         size_t nb = std::max(need, bytes + bytes / 2);
         nb = (nb + 255) & ~(size_t)255;
         void* q = nullptr;
-        if (p) HIPCHK(hipDeviceSynchronize());  // queued kernels may still use p
+        // queued kernels of this solve may still use p (solves leave no work
+        // queued behind them, so this solve's stream is the only one to wait for)
+        if (p) HIPCHK(hipStreamSynchronize(g_cur_stream));
         HIPCHK(hipMalloc(&q, nb));
         if (keep && p) {
             HIPCHK(hipMemcpyAsync(q, p, std::min(keep, bytes), hipMemcpyDeviceToDevice, s));
@@ -72,6 +87,42 @@ struct DBuf {
     template <class T>
     T* as() const {
         return (T*)p;
+    }
+};
+
+// Optional device timing of kernel families: event pairs recorded on the
+// solve's stream around each launch group, resolved after the final sync.
+struct Prof {
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, size_t>> pend;  // (family, first event index)
+    size_t used = 0;
+    bool on = false;
+    ~Prof() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+    void begin(bool enable) {
+        on = enable;
+        used = 0;
+        pend.clear();
+    }
+    size_t rec(hipStream_t s) {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        HIPCHK(hipEventRecord(pool[used], s));
+        return used++;
+    }
+    void finish(geomst_stats_t& st) {
+        for (auto& p : pend) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, pool[p.second], pool[p.second + 1]));
+            st.kernel_ms[p.first] += ms;
+            st.kernel_launches[p.first] += 1;
+        }
+        pend.clear();
+        used = 0;
     }
 };
 
@@ -113,45 +164,20 @@ struct Device {
     // Kruskal
     DBuf kid, ke2, kw2, perm[2], alive[2], ru, rv, nalive, minmax;
     DBuf birange, bik, browinst;  // batched solves: instance table and row -> instance
-    struct Prof* prof = nullptr;
+    Prof profm;
+    Prof* prof = nullptr;
+    ~Device() {
+        if (own) (void)hipStreamDestroy(own);
+        if (hcnt) (void)hipHostFree(hcnt);
+    }
 };
 
-Device g_dev[16];
+// Per-device workspaces of the plain and batched calls; never destroyed (the
+// runtime may already be gone at static destruction).
+Device* const g_dev = new Device[16];
 bool g_kernel_timing = false;
 
-// Optional device timing of kernel families: event pairs recorded on the
-// solve's stream around each launch group, resolved after the final sync.
-struct Prof {
-    std::vector<hipEvent_t> pool;
-    std::vector<std::pair<int, size_t>> pend;  // (family, first event index)
-    size_t used = 0;
-    bool on = false;
-    void begin(bool enable) {
-        on = enable;
-        used = 0;
-        pend.clear();
-    }
-    size_t rec(hipStream_t s) {
-        if (used == pool.size()) {
-            hipEvent_t e;
-            HIPCHK(hipEventCreate(&e));
-            pool.push_back(e);
-        }
-        HIPCHK(hipEventRecord(pool[used], s));
-        return used++;
-    }
-    void finish(geomst_stats_t& st) {
-        for (auto& p : pend) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, pool[p.second], pool[p.second + 1]));
-            st.kernel_ms[p.first] += ms;
-            st.kernel_launches[p.first] += 1;
-        }
-        pend.clear();
-        used = 0;
-    }
-};
-Prof g_prof[16];
+
 
 struct TimedScope {
     Prof& P;
@@ -916,7 +942,7 @@ void ensure_init(Device& D) {
     HIPCHK(hipStreamCreateWithFlags(&D.own, hipStreamNonBlocking));
     HIPCHK(hipHostMalloc((void**)&D.hcnt, sizeof(Counters), hipHostMallocDefault));
     D.cnt.ensure(sizeof(Counters));
-    D.prof = &g_prof[&D - g_dev];
+    D.prof = &D.profm;
     D.init = true;
 }
 
@@ -947,6 +973,7 @@ int validate(const void* pts, int64_t n, int32_t d, int32_t min_pts, const void*
 // Solve with device pointers on stream s (device context locked by caller).
 void solve_dev(Device& D, hipStream_t s, const double* P, int n, int d, int minpts, long long* edges, double* w,
                double* w2, double* cd, double* cd2) {
+    g_cur_stream = s;
     memset(&g_stats, 0, sizeof(g_stats));
     g_stats.n = n;
     g_stats.d = d;
@@ -995,6 +1022,7 @@ void solve_dev(Device& D, hipStream_t s, const double* P, int n, int d, int minp
 // Batched solve over a packed device arena (see geomst_batch_dev).
 void solve_batch_dev(Device& D, hipStream_t s, const double* P, int stride, const geomst_batch_item_t* items,
                      int64_t count, long long* edges, double* w, double* w2, double* cd, double* cd2) {
+    g_cur_stream = s;
     memset(&g_stats, 0, sizeof(g_stats));
     D.prof->begin(g_kernel_timing);
     auto t0 = std::chrono::steady_clock::now();
@@ -1085,6 +1113,79 @@ int validate_batch(int32_t stride, const geomst_batch_item_t* items, int64_t cou
     return GEOMST_OK;
 }
 
+// One instance of a host-side batch: caller-owned arrays.
+struct HostItem {
+    const double* points;
+    int64_t n;
+    int d, min_pts;
+    int64_t* edges;
+    double* weights;
+    double* core_dist;
+};
+
+// Host-side check of one instance: GEOMST_OK, GEOMST_EINVAL for a bad shape
+// or pointer, GEOMST_EDOM for a coordinate that is not finite or exceeds 2^500.
+int check_host_item(const HostItem& q) {
+    if (!q.points || q.n < 1 || q.n > (1ll << 26) || q.d < 1 || q.d > kMaxDim || q.min_pts < 0 || q.min_pts > 64 ||
+        q.min_pts > q.n || (q.n > 1 && !q.edges))
+        return GEOMST_EINVAL;
+    for (int64_t j = 0; j < q.n * q.d; ++j)
+        if (!(fabs(q.points[j]) <= 0x1p500)) return GEOMST_EDOM;
+    return GEOMST_OK;
+}
+
+// Packs host instances into one arena (stride = largest d, missing columns
+// 0.0), solves them as one forest on the workspace's stream and scatters the
+// edges (local ids), weights and core distances back. Throws Fail.
+void solve_host_items(Device& D, const HostItem* it, int64_t count) {
+    int stride = 0;
+    int64_t N = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        stride = std::max(stride, it[i].d);
+        N += it[i].n;
+    }
+    std::vector<double> host((size_t)N * stride, 0.0);
+    std::vector<geomst_batch_item_t> items((size_t)count);
+    int64_t off = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const HostItem& q = it[i];
+        for (int64_t r = 0; r < q.n; ++r)
+            for (int k = 0; k < q.d; ++k) host[(size_t)(off + r) * stride + k] = q.points[r * q.d + k];
+        items[i] = geomst_batch_item_t{off, q.n, q.d, q.min_pts};
+        off += q.n;
+    }
+    if (int rc = validate_batch(stride, items.data(), count)) throw Fail{rc};
+    hipStream_t s = D.own;
+    g_cur_stream = s;
+    size_t m = (size_t)(N - count);
+    D.pin.ensure((size_t)N * stride * 8);
+    D.eout.ensure(m * 16 + 16);
+    D.wout.ensure(m * 8 + 8);
+    D.cdout.ensure((size_t)N * 8);
+    HIPCHK(hipMemcpyAsync(D.pin.p, host.data(), (size_t)N * stride * 8, hipMemcpyHostToDevice, s));
+    solve_batch_dev(D, s, D.pin.as<double>(), stride, items.data(), count, D.eout.as<long long>(),
+                    D.wout.as<double>(), nullptr, D.cdout.as<double>(), nullptr);
+    std::vector<long long> e(m * 2);
+    std::vector<double> w(m), cd((size_t)N);
+    if (m) {
+        HIPCHK(hipMemcpyAsync(e.data(), D.eout.p, m * 16, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(w.data(), D.wout.p, m * 8, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipMemcpyAsync(cd.data(), D.cdout.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < count; ++i) {
+        const HostItem& q = it[i];
+        size_t eo = (size_t)(items[i].offset - i);
+        for (int64_t k = 0; k < q.n - 1; ++k) {
+            q.edges[2 * k] = e[2 * (eo + k)];
+            q.edges[2 * k + 1] = e[2 * (eo + k) + 1];
+            if (q.weights) q.weights[k] = w[eo + k];
+        }
+        if (q.core_dist)
+            for (int64_t r = 0; r < q.n; ++r) q.core_dist[r] = q.min_pts > 0 ? cd[items[i].offset + r] : 0.0;
+    }
+}
+
 int run_dev(const double* P, int64_t n, int32_t d, int32_t minpts, long long* edges, double* w, double* w2,
             double* cd, double* cd2, void* stream) {
     g_err.clear();
@@ -1136,10 +1237,154 @@ int run_host(const double* P, int64_t n, int32_t d, int32_t minpts, int64_t* edg
     return GEOMST_OK;
 }
 
+// ------------------------------------------------------------ serving
+// Continuous batching: requests queue up with their arrival time; each worker
+// thread owns a workspace and a stream, takes what is queued at the front (up
+// to its share of the device-memory budget and the batch limits) and solves it
+// as one forest batch. Batches of different workers overlap on the device, and
+// requests that arrive meanwhile form the next batch.
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    std::vector<double> pts;  // copied at submit
+    HostItem item{};
+    size_t footprint = 0;
+    int status = GEOMST_OK;
+    std::string err;  // the worker's error message when status != OK
+    bool started = false, done = false;
+    Clock::time_point t_arrive, t_start, t_done;
+    int batch_requests = 0;
+    int64_t batch_points = 0;
+};
+
+// Device-memory estimate of one request inside a batch: staged points and
+// outputs, multi-level sort keys and temporaries, 2n node records, union-find
+// and component arrays, the pair lists and edge pools at their initial
+// capacities and, for HDBSCAN*, core distances and node core-distance ranges.
+size_t request_footprint(int64_t n, int d, int min_pts) {
+    size_t node = d <= 3 ? 64 : 128;
+    return (size_t)n * (640 + 2 * node + 16 * (size_t)d + (min_pts > 0 ? 320 : 0));
+}
+
+struct Server {
+    int device = 0;
+    size_t budget = 0, cap_per_worker = 0;
+    int max_req = 0;
+    int64_t max_pts = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request*> queue;
+    std::unordered_map<uint64_t, Request*> all;
+    std::vector<std::thread> workers;
+    std::vector<std::unique_ptr<Device>> ws;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    geomst_server_stats_t st{};
+};
+
+// Solves a taken batch as forests of equal dimension and kind (EMST or
+// HDBSCAN*), so that no instance pays for padded coordinates or for the
+// other kind's separation test; the groups run in the order of their oldest
+// request; each group's requests are done as soon as the group is.
+void run_batch(Server* S, Device& D, std::vector<Request*>& batch) {
+    std::vector<std::vector<Request*>> groups;
+    std::vector<int> gkey;
+    for (Request* r : batch) {
+        int k = r->item.d * 2 + (r->item.min_pts > 0);
+        size_t gi = std::find(gkey.begin(), gkey.end(), k) - gkey.begin();
+        if (gi == gkey.size()) {
+            gkey.push_back(k);
+            groups.emplace_back();
+        }
+        groups[gi].push_back(r);
+    }
+    for (auto& grp : groups) {
+        std::vector<HostItem> it(grp.size());
+        int64_t N = 0;
+        for (size_t i = 0; i < grp.size(); ++i) {
+            it[i] = grp[i]->item;
+            N += it[i].n;
+        }
+        int status = GEOMST_OK;
+        g_err.clear();
+        try {
+            ensure_init(D);
+            solve_host_items(D, it.data(), (int64_t)it.size());
+        } catch (const Fail& f) {
+            status = f.code;
+        } catch (const std::bad_alloc&) {
+            status = GEOMST_ENOMEM;
+        } catch (...) {
+            g_err = "unexpected exception in a server worker";
+            status = GEOMST_EINTERNAL;
+        }
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            auto now = Clock::now();
+            for (Request* r : grp) {
+                r->status = status;
+                if (status) r->err = g_err.empty() ? "batch failed" : g_err;
+                r->batch_requests = (int)grp.size();
+                r->batch_points = N;
+                r->done = true;
+                r->t_done = now;
+            }
+            S->st.running -= (int64_t)grp.size();
+            S->st.completed += (int64_t)grp.size();
+        }
+        S->cv_done.notify_all();
+    }
+}
+
+void worker_loop(Server* S, int wi) {
+    (void)hipSetDevice(S->device);
+    Device& D = *S->ws[wi];
+    while (true) {
+        std::vector<Request*> batch;
+        size_t fp = 0;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+            if (S->stop) break;
+            int64_t pts = 0;
+            auto now = Clock::now();
+            while (!S->queue.empty()) {
+                Request* r = S->queue.front();
+                bool fits = fp + r->footprint <= S->cap_per_worker && (int)batch.size() < S->max_req &&
+                            pts + r->item.n <= S->max_pts;
+                if (!batch.empty() && !fits) break;  // the first request always fits (checked at submit)
+                S->queue.pop_front();
+                r->started = true;
+                r->t_start = now;
+                batch.push_back(r);
+                fp += r->footprint;
+                pts += r->item.n;
+            }
+            S->st.queued -= (int64_t)batch.size();
+            S->st.running += (int64_t)batch.size();
+            S->st.batches += 1;
+            S->st.reserved_bytes += (int64_t)fp;
+            S->st.peak_reserved_bytes = std::max(S->st.peak_reserved_bytes, S->st.reserved_bytes);
+            S->st.max_batch_requests = std::max<int64_t>(S->st.max_batch_requests, (int64_t)batch.size());
+            S->st.max_batch_points = std::max(S->st.max_batch_points, pts);
+        }
+        if (!batch.empty()) run_batch(S, D, batch);
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->st.reserved_bytes -= (int64_t)fp;
+    }
+}
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
 }  // namespace
 }  // namespace geomst
 
 using namespace geomst;
+
+struct geomst_server : Server {};
 
 extern "C" {
 
@@ -1209,27 +1454,13 @@ int geomst_batch(geomst_instance_t* inst, int64_t count) {
         g_err = "inst is NULL or count < 1";
         return GEOMST_EINVAL;
     }
-    // validate and pack (stride = largest d; missing columns are 0.0)
-    int stride = 0;
-    int64_t N = 0;
+    std::vector<HostItem> it((size_t)count);
     int bad = 0;
     for (int64_t i = 0; i < count; ++i) {
         geomst_instance_t& q = inst[i];
-        q.status = GEOMST_OK;
-        if (!q.points || q.n < 1 || q.d < 1 || q.d > kMaxDim || q.min_pts < 0 || q.min_pts > 64 ||
-            q.min_pts > q.n || (q.n > 1 && !q.edges)) {
-            q.status = GEOMST_EINVAL;
-            ++bad;
-            continue;
-        }
-        for (int64_t j = 0; j < q.n * q.d; ++j)
-            if (!(fabs(q.points[j]) <= 3.273390607896142e150)) {
-                q.status = GEOMST_EDOM;
-                ++bad;
-                break;
-            }
-        stride = std::max(stride, (int)q.d);
-        N += q.n;
+        it[i] = HostItem{q.points, q.n, q.d, q.min_pts, q.edges, q.weights, q.core_dist};
+        q.status = check_host_item(it[i]);
+        bad += q.status != GEOMST_OK;
     }
     if (bad) {
         g_err = "invalid batch items (see their status)";
@@ -1238,50 +1469,11 @@ int geomst_batch(geomst_instance_t* inst, int64_t count) {
         return GEOMST_EINVAL;
     }
     try {
-        std::vector<double> host((size_t)N * stride, 0.0);
-        std::vector<geomst_batch_item_t> items((size_t)count);
-        int64_t off = 0;
-        for (int64_t i = 0; i < count; ++i) {
-            const geomst_instance_t& q = inst[i];
-            for (int64_t r = 0; r < q.n; ++r)
-                for (int k = 0; k < q.d; ++k) host[(size_t)(off + r) * stride + k] = q.points[r * q.d + k];
-            items[i] = geomst_batch_item_t{off, q.n, q.d, q.min_pts};
-            off += q.n;
-        }
-        int rc = validate_batch(stride, items.data(), count);
-        if (rc) return rc;
         int dev;
         Device& D = device_ctx(&dev);
         std::lock_guard<std::mutex> lk(D.mu);
         ensure_init(D);
-        hipStream_t s = D.own;
-        size_t m = (size_t)(N - count);
-        D.pin.ensure((size_t)N * stride * 8);
-        D.eout.ensure(m * 16 + 16);
-        D.wout.ensure(m * 8 + 8);
-        D.cdout.ensure((size_t)N * 8);
-        HIPCHK(hipMemcpyAsync(D.pin.p, host.data(), (size_t)N * stride * 8, hipMemcpyHostToDevice, s));
-        solve_batch_dev(D, s, D.pin.as<double>(), stride, items.data(), count, D.eout.as<long long>(),
-                        D.wout.as<double>(), nullptr, D.cdout.as<double>(), nullptr);
-        std::vector<long long> e(m * 2);
-        std::vector<double> w(m), cd((size_t)N);
-        if (m) {
-            HIPCHK(hipMemcpyAsync(e.data(), D.eout.p, m * 16, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(w.data(), D.wout.p, m * 8, hipMemcpyDeviceToHost, s));
-        }
-        HIPCHK(hipMemcpyAsync(cd.data(), D.cdout.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int64_t i = 0; i < count; ++i) {
-            geomst_instance_t& q = inst[i];
-            size_t eo = (size_t)(items[i].offset - i);
-            for (int64_t k = 0; k < q.n - 1; ++k) {
-                q.edges[2 * k] = e[2 * (eo + k)];
-                q.edges[2 * k + 1] = e[2 * (eo + k) + 1];
-                if (q.weights) q.weights[k] = w[eo + k];
-            }
-            if (q.core_dist)
-                for (int64_t r = 0; r < q.n; ++r) q.core_dist[r] = q.min_pts > 0 ? cd[items[i].offset + r] : 0.0;
-        }
+        solve_host_items(D, it.data(), count);
     } catch (const Fail& f) {
         for (int64_t i = 0; i < count; ++i) inst[i].status = f.code;
         return f.code;
@@ -1290,6 +1482,192 @@ int geomst_batch(geomst_instance_t* inst, int64_t count) {
         return GEOMST_ENOMEM;
     }
     return GEOMST_OK;
+}
+
+int geomst_server_create(const geomst_server_cfg_t* cfg, geomst_server_t** out) {
+    g_err.clear();
+    if (!out) {
+        g_err = "out is NULL";
+        return GEOMST_EINVAL;
+    }
+    *out = nullptr;
+    geomst_server_cfg_t c{};
+    if (cfg) c = *cfg;
+    if (c.workers < 0 || c.workers > 16 || c.max_batch_requests < 0 || c.reserved != 0 || c.max_batch_points < 0 ||
+        c.max_batch_points > (1ll << 26) || c.device < -1 || c.device >= 16) {
+        g_err = "bad server configuration";
+        return GEOMST_EINVAL;
+    }
+    int dev = c.device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) {
+        g_err = "no current HIP device";
+        return GEOMST_EDEVICE;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || dev >= ndev) {
+        g_err = "device index out of range";
+        return GEOMST_EDEVICE;
+    }
+    try {
+        std::unique_ptr<geomst_server> S(new geomst_server());
+        S->device = dev;
+        int w = c.workers ? c.workers : 2;
+        S->budget = c.hbm_budget_bytes ? (size_t)c.hbm_budget_bytes : (size_t)200e9;
+        S->cap_per_worker = S->budget / (size_t)w;
+        S->max_req = c.max_batch_requests ? c.max_batch_requests : 4096;
+        S->max_pts = c.max_batch_points ? c.max_batch_points : (1ll << 24);
+        for (int i = 0; i < w; ++i) S->ws.emplace_back(new Device());
+        for (int i = 0; i < w; ++i) S->workers.emplace_back(worker_loop, S.get(), i);
+        *out = S.release();
+    } catch (const std::exception& e) {
+        g_err = std::string("server start failed: ") + e.what();
+        return GEOMST_ENOMEM;
+    }
+    return GEOMST_OK;
+}
+
+int geomst_submit(geomst_server_t* srv, geomst_instance_t* req, uint64_t* ticket) {
+    g_err.clear();
+    if (!srv || !req || !ticket) {
+        g_err = "srv, req or ticket is NULL";
+        return GEOMST_EINVAL;
+    }
+    HostItem it{req->points, req->n, req->d, req->min_pts, req->edges, req->weights, req->core_dist};
+    int rc = check_host_item(it);
+    if (rc) {
+        g_err = rc == GEOMST_EDOM ? "a coordinate is not finite or exceeds 2^500 in magnitude"
+                                  : "invalid request (n, d, min_pts or a NULL pointer)";
+        req->status = rc;
+        return rc;
+    }
+    size_t fp = request_footprint(it.n, it.d, it.min_pts);
+    if (fp > srv->cap_per_worker || it.n > srv->max_pts) {
+        g_err = "request exceeds a worker's share of the memory budget or the batch point limit";
+        req->status = GEOMST_ENOMEM;
+        return GEOMST_ENOMEM;
+    }
+    try {
+        std::unique_ptr<Request> r(new Request());
+        r->pts.assign(it.points, it.points + it.n * it.d);
+        r->item = it;
+        r->item.points = r->pts.data();
+        r->footprint = fp;
+        r->t_arrive = Clock::now();
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (srv->stop) {
+                g_err = "server is stopping";
+                return GEOMST_EINVAL;
+            }
+            r->ticket = srv->next_ticket++;
+            *ticket = r->ticket;
+            srv->all[r->ticket] = r.get();
+            srv->queue.push_back(r.get());
+            srv->st.submitted += 1;
+            srv->st.queued += 1;
+            r.release();
+        }
+        srv->cv_work.notify_one();
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        req->status = GEOMST_ENOMEM;
+        return GEOMST_ENOMEM;
+    }
+    req->status = GEOMST_OK;
+    return GEOMST_OK;
+}
+
+int geomst_wait(geomst_server_t* srv, uint64_t ticket, int64_t timeout_us, geomst_request_info_t* info) {
+    g_err.clear();
+    if (!srv) {
+        g_err = "srv is NULL";
+        return GEOMST_EINVAL;
+    }
+    std::unique_lock<std::mutex> lk(srv->mu);
+    // the ticket is looked up again after every wake-up: another thread's
+    // wait or cancel may have released it meanwhile
+    auto ready = [&] {
+        auto f = srv->all.find(ticket);
+        return f == srv->all.end() || f->second->done;
+    };
+    if (timeout_us < 0)
+        srv->cv_done.wait(lk, ready);
+    else if (!srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
+        return GEOMST_ETIMEDOUT;
+    auto f = srv->all.find(ticket);
+    if (f == srv->all.end()) {
+        g_err = "unknown ticket";
+        return GEOMST_ENOENT;
+    }
+    Request* r = f->second;
+    srv->all.erase(f);
+    lk.unlock();
+    int rc = r->status;
+    if (info) {
+        info->status = rc;
+        info->batch_requests = r->batch_requests;
+        info->batch_points = r->batch_points;
+        info->queue_ms = ms_between(r->t_arrive, r->t_start);
+        info->service_ms = ms_between(r->t_start, r->t_done);
+        info->latency_ms = ms_between(r->t_arrive, r->t_done);
+    }
+    if (rc) g_err = r->err;
+    delete r;
+    srv->cv_done.notify_all();  // wake other waiters of this ticket
+    return rc;
+}
+
+int geomst_cancel(geomst_server_t* srv, uint64_t ticket) {
+    g_err.clear();
+    if (!srv) {
+        g_err = "srv is NULL";
+        return GEOMST_EINVAL;
+    }
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv_done.wait(lk, [&] {
+        auto f = srv->all.find(ticket);
+        return f == srv->all.end() || !f->second->started || f->second->done;
+    });
+    auto f = srv->all.find(ticket);
+    if (f == srv->all.end()) {
+        g_err = "unknown ticket";
+        return GEOMST_ENOENT;
+    }
+    Request* r = f->second;
+    if (!r->started) {
+        srv->queue.erase(std::find(srv->queue.begin(), srv->queue.end(), r));
+        srv->st.queued -= 1;
+    }
+    srv->all.erase(f);
+    lk.unlock();
+    delete r;
+    srv->cv_done.notify_all();
+    return GEOMST_OK;
+}
+
+int geomst_server_stats(geomst_server_t* srv, geomst_server_stats_t* out) {
+    if (!srv || !out) return GEOMST_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = srv->st;
+    return GEOMST_OK;
+}
+
+void geomst_server_destroy(geomst_server_t* srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        srv->queue.clear();
+    }
+    srv->cv_work.notify_all();
+    for (auto& t : srv->workers) t.join();
+    for (auto& kv : srv->all) delete kv.second;
+    int cur = 0;
+    bool have = hipGetDevice(&cur) == hipSuccess;
+    (void)hipSetDevice(srv->device);
+    srv->ws.clear();
+    if (have) (void)hipSetDevice(cur);
+    delete srv;
 }
 
 int geomst_get_stats(geomst_stats_t* out) {

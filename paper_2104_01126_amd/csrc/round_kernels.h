@@ -1193,7 +1193,7 @@ __global__ void k_check_input(const double* P, size_t m, Counters* cnt) {
     bool bad = false;
     for (; i < m; i += (size_t)gridDim.x * blockDim.x) {
         double x = P[i];
-        bad |= !(fabs(x) <= 3.273390607896142e150);  // 2^500; false for NaN
+        bad |= !(fabs(x) <= 0x1p500);  // false for NaN
     }
     if (__any(bad) && lane_id() == 0) atomicOr(&cnt->c[C_ERR], 2u);
 }

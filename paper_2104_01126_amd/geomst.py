@@ -22,8 +22,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgeomst.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "geomst.h")
 
-OK, EINVAL, EDOM, ENOMEM, EDEVICE, EINTERNAL = 0, -1, -2, -3, -4, -8
-_NAMES = {EINVAL: "EINVAL", EDOM: "EDOM", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", EINTERNAL: "EINTERNAL"}
+OK, EINVAL, EDOM, ENOMEM, EDEVICE, ETIMEDOUT, ENOENT, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -8
+_NAMES = {EINVAL: "EINVAL", EDOM: "EDOM", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ETIMEDOUT: "ETIMEDOUT",
+          ENOENT: "ENOENT", EINTERNAL: "EINTERNAL"}
 
 
 class GeomstError(RuntimeError):
@@ -55,6 +56,23 @@ class Instance(ctypes.Structure):
                 ("weights", ctypes.c_void_p), ("status", ctypes.c_int32)]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("workers", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("max_batch_requests", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_batch_points", ctypes.c_int64)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_requests", ctypes.c_int32), ("batch_points", ctypes.c_int64),
+                ("queue_ms", ctypes.c_double), ("service_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "queued", "running", "completed", "batches",
+                                              "reserved_bytes", "peak_reserved_bytes", "max_batch_requests",
+                                              "max_batch_points")]
+
+
 _lib = None
 
 
@@ -75,6 +93,16 @@ def load(path: str = LIB_PATH):
     lib.geomst_batch.argtypes = [ctypes.POINTER(Instance), i64]
     lib.geomst_batch_dev.restype = ctypes.c_int
     lib.geomst_batch.restype = ctypes.c_int
+    lib.geomst_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(P)]
+    lib.geomst_submit.argtypes = [P, ctypes.POINTER(Instance), ctypes.POINTER(ctypes.c_uint64)]
+    lib.geomst_wait.argtypes = [P, ctypes.c_uint64, i64, ctypes.POINTER(RequestInfo)]
+    lib.geomst_cancel.argtypes = [P, ctypes.c_uint64]
+    lib.geomst_server_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    lib.geomst_server_destroy.argtypes = [P]
+    lib.geomst_server_destroy.restype = None
+    for f in (lib.geomst_server_create, lib.geomst_submit, lib.geomst_wait, lib.geomst_cancel,
+              lib.geomst_server_stats):
+        f.restype = ctypes.c_int
     lib.geomst_get_stats.argtypes = [ctypes.POINTER(_Stats)]
     lib.geomst_set_option.argtypes = [ctypes.c_char_p, dbl]
     lib.geomst_last_error.restype = ctypes.c_char_p
@@ -296,3 +324,75 @@ def batch(instances, min_pts=0):
         arr[i].core_dist, arr[i].edges, arr[i].weights = cd.ctypes.data, e.ctypes.data, w.ctypes.data
     _check(lib.geomst_batch(arr, len(instances)))
     return [(k[1], k[2], k[3]) for k in keep]
+
+
+# ------------------------------------------------------------------ serving
+class Server:
+    """Request loop with continuous batching (geomst_server_*).
+
+    ``submit(points, min_pts)`` copies the points and returns a ticket;
+    ``wait(ticket)`` returns (edges, weights, core_dist, info) once the
+    request's batch is done.  The output arrays are allocated here and kept
+    alive until the ticket is released."""
+
+    def __init__(self, hbm_budget_bytes=0, workers=0, device=-1, max_batch_requests=0, max_batch_points=0):
+        lib = load()
+        cfg = ServerCfg(int(hbm_budget_bytes), int(workers), int(device), int(max_batch_requests), 0,
+                        int(max_batch_points))
+        h = ctypes.c_void_p()
+        _check(lib.geomst_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._out = {}
+
+    def submit(self, points, min_pts=0) -> int:
+        lib = load()
+        x = np.ascontiguousarray(points, dtype=np.float64)
+        n, d = x.shape
+        e = np.zeros((max(n - 1, 0), 2), np.int64)
+        w = np.zeros(max(n - 1, 0))
+        cd = np.zeros(n)
+        req = Instance(x.ctypes.data, n, d, int(min_pts), cd.ctypes.data, e.ctypes.data, w.ctypes.data, 0)
+        t = ctypes.c_uint64()
+        _check(lib.geomst_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._out[t.value] = (e, w, cd)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        """-> (edges, weights, core_dist, info dict); raises GeomstError
+        (ETIMEDOUT if not done within timeout_us)."""
+        info = RequestInfo()
+        rc = load().geomst_wait(self._h, ticket, int(timeout_us), ctypes.byref(info))
+        if rc == ETIMEDOUT:
+            raise GeomstError(rc, "not done yet")
+        out = self._out.pop(ticket, None)
+        _check(rc)
+        d = {k: getattr(info, k) for k, _ in RequestInfo._fields_}
+        return out[0], out[1], out[2], d
+
+    def cancel(self, ticket: int):
+        rc = load().geomst_cancel(self._h, ticket)
+        self._out.pop(ticket, None)
+        _check(rc)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(load().geomst_server_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            load().geomst_server_destroy(self._h)
+            self._h = None
+            self._out.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -20,10 +20,16 @@ Gaussian mixtures with log-uniform widths for the latter):
                    log-uniform in [0.5,20]) and 5% uniform noise, seed 2.
 * ``batch_4096``   4,096 EMST instances, n log-uniform in [100,50000], d in
                    {2,3}, half uniform, half 8-Gaussian mixtures, seed 3.
+* ``serving_trace`` a Poisson request stream at 2,000 requests/s for 60 s
+                   (seed 4): 70% EMST, 30% HDBSCAN* with minPts in {5,10,16},
+                   n log-uniform in [1e3,1e6], d in {2..7}, half uniform and
+                   half 8-Gaussian mixtures; request i's points come from
+                   seed (4, i) so any request can be drawn alone.
 """
 from __future__ import annotations
 
 import math
+from dataclasses import dataclass
 from typing import List, Tuple
 
 import numpy as np
@@ -31,6 +37,7 @@ import numpy as np
 __all__ = [
     "emst_small", "emst_1m", "hdbscan_2m", "batch_4096", "batch_instance",
     "uniform", "mixture", "grid", "collinear", "with_duplicates", "subsample",
+    "ServingRequest", "serving_trace", "serving_points",
 ]
 
 
@@ -93,6 +100,47 @@ def batch_4096(count: int = 4096) -> List[np.ndarray]:
 
 def batch_instance(i: int) -> np.ndarray:
     return batch_4096(i + 1)[i]
+
+
+@dataclass(frozen=True)
+class ServingRequest:
+    index: int
+    arrival_s: float
+    n: int
+    d: int
+    min_pts: int      # 0 = EMST
+    mixture: bool     # False: uniform in [0,1)^d
+
+
+def serving_trace(duration_s: float = 60.0, rate: float = 2000.0, n_lo: float = 1e3,
+                  n_hi: float = 1e6) -> List[ServingRequest]:
+    """Arrivals of the serving stream up to ``duration_s`` (a prefix of the
+    60 s stream for smaller values; ``n_lo``/``n_hi`` other than the defaults
+    give a scaled-down stream of the same shape)."""
+    rng = np.random.default_rng(4)
+    out: List[ServingRequest] = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration_s:
+            break
+        emst = rng.random() < 0.7
+        mp = 0 if emst else int(rng.choice([5, 10, 16]))
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        d = int(rng.integers(2, 8))
+        mix = bool(rng.random() < 0.5)
+        out.append(ServingRequest(len(out), t, n, d, mp, mix))
+    return out
+
+
+def serving_points(req: ServingRequest) -> np.ndarray:
+    rng = np.random.default_rng([4, req.index])
+    if not req.mixture:
+        return _c(rng.random((req.n, req.d)))
+    cen = rng.random((8, req.d))
+    sg = rng.uniform(0.01, 0.1, 8)
+    lab = rng.integers(0, 8, req.n)
+    return _c(cen[lab] + sg[lab][:, None] * rng.standard_normal((req.n, req.d)))
 
 
 # ------------------------------------------------------- small test shapes

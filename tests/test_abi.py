@@ -76,23 +76,60 @@ def test_options(lib):
     assert lib.geomst_set_option(b"kernel_timing", 2.0) == G.EINVAL
 
 
-def test_stats_struct_layout(lib):
-    s = G.stats()
-    assert isinstance(s.rounds, int)
-    # the ctypes mirror has the size of the C struct
+def _c_layout(exprs):
+    """Evaluate size_t expressions over include/geomst.h with gcc."""
+    body = " ".join(f'printf("%zu ", (size_t)({e}));' for e in exprs)
     src = ("#include <stdio.h>\n#include <stddef.h>\n#include \"geomst.h\"\n"
-           "int main(void){ printf(\"%zu %zu\", sizeof(geomst_stats_t), offsetof(geomst_stats_t, kernel_ms));"
-           " return 0; }\n")
+           f"int main(void){{ {body} return 0; }}\n")
     exe = os.path.join(ROOT, "_build_stats_probe")
     try:
         subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-x", "c", "-", "-o", exe],
                        input=src, text=True, check=True)
-        size, off = map(int, subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split())
+        return list(map(int, subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()))
     finally:
         if os.path.exists(exe):
             os.remove(exe)
+
+
+def test_stats_struct_layout(lib):
+    s = G.stats()
+    assert isinstance(s.rounds, int)
+    # the ctypes mirror has the size of the C struct
+    size, off = _c_layout(["sizeof(geomst_stats_t)", "offsetof(geomst_stats_t, kernel_ms)"])
     assert ctypes.sizeof(G._Stats) == size
     assert G._Stats.kernel_ms.offset == off
+
+
+def test_server_struct_layouts():
+    structs = [("geomst_server_cfg_t", G.ServerCfg), ("geomst_request_info_t", G.RequestInfo),
+               ("geomst_server_stats_t", G.ServerStats), ("geomst_instance_t", G.Instance),
+               ("geomst_batch_item_t", G.BatchItem)]
+    exprs = []
+    for cname, py in structs:
+        exprs.append(f"sizeof({cname})")
+        exprs += [f"offsetof({cname}, {f})" for f, _ in py._fields_]
+    vals = iter(_c_layout(exprs))
+    for cname, py in structs:
+        assert next(vals) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert next(vals) == getattr(py, f).offset, (cname, f)
+
+
+def test_server_validation_without_device(lib):
+    h = ctypes.c_void_p()
+    bad = [G.ServerCfg(0, 17, -1, 0, 0, 0), G.ServerCfg(0, 2, -1, 0, 1, 0), G.ServerCfg(0, 2, -1, 0, 0, (1 << 26) + 1),
+           G.ServerCfg(0, 2, -2, 0, 0, 0), G.ServerCfg(0, -1, -1, 0, 0, 0)]
+    for cfg in bad:
+        assert lib.geomst_server_create(ctypes.byref(cfg), ctypes.byref(h)) == G.EINVAL
+        assert not h.value
+    assert lib.geomst_server_create(None, None) == G.EINVAL
+    t = ctypes.c_uint64()
+    req = G.Instance()
+    assert lib.geomst_submit(None, ctypes.byref(req), ctypes.byref(t)) == G.EINVAL
+    assert lib.geomst_wait(None, 1, 0, None) == G.EINVAL
+    assert lib.geomst_cancel(None, 1) == G.EINVAL
+    assert lib.geomst_server_stats(None, None) == G.EINVAL
+    lib.geomst_server_destroy(None)  # no-op
 
 
 def test_batch_validation_without_device(lib):

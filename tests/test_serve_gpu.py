@@ -1,0 +1,181 @@
+"""GPU tests of the serving loop (geomst_server_* / geomst_submit / geomst_wait):
+every request's result in the mix must be byte-identical to the same request
+solved alone by the plain call, batching must actually happen, and admission,
+cancellation and error paths must behave as the header states."""
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_01126_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2104_01126_amd import geomst as g
+    g.load()
+    return g
+
+
+def same(a, b):
+    return a.shape == b.shape and np.array_equal(np.ascontiguousarray(a).view(np.uint8),
+                                                 np.ascontiguousarray(b).view(np.uint8))
+
+
+def alone(G, x, mp):
+    if mp:
+        cd, e, w = G.hdbscan(x, mp)
+        return e, w, cd
+    e, w = G.emst(x)
+    return e, w, np.zeros(len(x))
+
+
+def footprint(n, d, mp):
+    node = 64 if d <= 3 else 128
+    return n * (640 + 2 * node + 16 * d + (320 if mp else 0))
+
+
+def small_trace(seconds, n_hi):
+    return W.serving_trace(duration_s=seconds, n_lo=50, n_hi=n_hi)
+
+
+def test_mix_identical_to_alone(G):
+    trace = small_trace(0.06, 20000)
+    say("serving mix", len(trace), "requests")
+    pts = [W.serving_points(r) for r in trace]
+    with G.Server(workers=2) as S:
+        tickets = [S.submit(x, r.min_pts) for x, r in zip(pts, trace)]
+        got = [S.wait(t) for t in tickets]
+        st = S.stats()
+    assert st["submitted"] == st["completed"] == len(trace) and st["queued"] == 0 and st["running"] == 0
+    assert st["max_batch_requests"] > 1, st  # requests were batched
+    assert max(g[3]["batch_requests"] for g in got) > 1
+    for r, x, (e, w, cd, info) in zip(trace, pts, got):
+        assert info["status"] == 0 and info["latency_ms"] >= info["service_ms"] >= 0.0
+        e0, w0, cd0 = alone(G, x, r.min_pts)
+        assert same(e, e0) and same(w, w0), r
+        if r.min_pts:
+            assert same(cd, cd0), r
+    # a few small ones against the checker as well
+    for r, x, (e, w, cd, info) in list(zip(trace, pts, got))[:40]:
+        if r.n > 3000:
+            continue
+        if r.min_pts:
+            _, cdo, eo, _, _, wo = oracle.hdbscan(x, r.min_pts)
+            assert same(cd, cdo), r
+        else:
+            eo, _, wo = oracle.emst(x)
+        assert np.array_equal(e, eo) and same(w, wo), r
+
+
+def test_concurrent_submitters(G):
+    trace = small_trace(0.03, 5000)
+    pts = [W.serving_points(r) for r in trace]
+    say("concurrent submitters", len(trace))
+    results = [None] * len(trace)
+    errors = []
+    with G.Server(workers=3) as S:
+        def client(k):
+            try:
+                for i in range(k, len(trace), 4):
+                    t = S.submit(pts[i], trace[i].min_pts)
+                    results[i] = S.wait(t)
+            except Exception as ex:  # reported below
+                errors.append(ex)
+        th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+    assert not errors, errors
+    for r, x, res in zip(trace, pts, results):
+        e0, w0, cd0 = alone(G, x, r.min_pts)
+        assert same(res[0], e0) and same(res[1], w0), r
+
+
+def test_cancel_timeout_and_errors(G):
+    x = [W.uniform(int(n), 3, seed=900 + i) for i, n in enumerate(np.linspace(2000, 30000, 24))]
+    say("cancel / errors")
+    with G.Server(workers=1, max_batch_requests=2) as S:
+        tickets = [S.submit(p, 0) for p in x]
+        cancelled = tickets[-8:]
+        for t in cancelled:
+            S.cancel(t)
+        for t in cancelled:
+            with pytest.raises(G.GeomstError) as ex:
+                S.wait(t)
+            assert ex.value.code == G.ENOENT
+        # poll: either done or not yet
+        try:
+            S.wait(tickets[0], timeout_us=0)
+            polled = True
+        except G.GeomstError as err:
+            assert err.code == G.ETIMEDOUT
+            polled = False
+        for i, t in enumerate(tickets[:-8]):
+            if i == 0 and polled:
+                continue
+            e, w, cd, info = S.wait(t)
+            assert info["batch_requests"] <= 2
+            e0, w0 = G.emst(x[i])
+            assert same(e, e0) and same(w, w0)
+        with pytest.raises(G.GeomstError) as ex:
+            S.wait(tickets[1])  # already released
+        assert ex.value.code == G.ENOENT
+        with pytest.raises(G.GeomstError) as ex:
+            S.submit(np.zeros((10, 8)), 0)
+        assert ex.value.code == G.EINVAL
+        bad = np.zeros((10, 2))
+        bad[3, 1] = np.nan
+        with pytest.raises(G.GeomstError) as ex:
+            S.submit(bad, 0)
+        assert ex.value.code == G.EDOM
+        with pytest.raises(G.GeomstError) as ex:
+            S.submit(np.zeros((10, 2)), 11)  # min_pts > n
+        assert ex.value.code == G.EINVAL
+        st = S.stats()
+        assert st["queued"] == 0 and st["running"] == 0
+
+
+def test_admission_budget(G):
+    budget = footprint(24000, 3, 0)
+    sizes = [3000, 9000, 5000, 12000, 7000, 4000, 11000, 6000, 2500, 8000, 10000, 3500]
+    x = [W.mixture(n, 3, seed=700 + i) for i, n in enumerate(sizes)]
+    say("admission budget", budget)
+    with G.Server(hbm_budget_bytes=budget, workers=1) as S:
+        with pytest.raises(G.GeomstError) as ex:
+            S.submit(W.uniform(30000, 3, seed=1), 0)  # alone above the budget
+        assert ex.value.code == G.ENOMEM
+        tickets = [S.submit(p, 0) for p in x]
+        got = [S.wait(t) for t in tickets]
+        st = S.stats()
+    assert 0 < st["peak_reserved_bytes"] <= budget, st
+    assert st["max_batch_points"] <= 24000
+    for p, (e, w, cd, info) in zip(x, got):
+        assert info["batch_points"] <= 24000
+        e0, w0 = G.emst(p)
+        assert same(e, e0) and same(w, w0)
+
+
+def test_destroy_with_queued_requests(G):
+    x = [W.uniform(20000, 4, seed=500 + i) for i in range(12)]
+    say("destroy with queue")
+    S = G.Server(workers=1, max_batch_requests=1)
+    for p in x:
+        S.submit(p, 0)
+    S.close()  # finishes the running batch, drops the rest
+    S.close()  # idempotent
+    # the plain path still works afterwards
+    e, w = G.emst(x[0])
+    assert len(e) == len(x[0]) - 1
