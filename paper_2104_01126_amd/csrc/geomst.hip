@@ -32,6 +32,8 @@ thread_local std::string g_err;
 thread_local hipStream_t g_cur_stream = nullptr;  // stream of the solve running on this thread
 thread_local geomst_stats_t g_stats;
 double g_beta_growth = 0.0;  // 0: 2 for EMST, sqrt(2) for HDBSCAN*
+double g_separation = 2.0;   // s of the sphere separation test
+int g_bccp_chunk = kBigBDefault;  // B points per large-pair BCCP task
 double g_capacity_scale = 1.0;
 constexpr int kMaxKeyLevels = 6;
 constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
@@ -507,10 +509,49 @@ struct Solver {
     double t_near = 0.0;  // edge of the near frontier band
     int ffo = 0;          // far list receiving appends this round
 
+    // Diagnostic (GEOMST_TRACE): size classes of the round's large pairs and
+    // how well their BCCP tasks fill the lanes.
+    void trace_big_pairs(u32 nbig, u32 ntasks) {
+        std::vector<uint2> bp(nbig);
+        std::vector<NodeRec<D_>> nd((size_t)2 * n - 1);
+        HIPCHK(hipMemcpyAsync(bp.data(), D.big.p, (size_t)nbig * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(nd.data(), D.nodes.p, nd.size() * sizeof(NodeRec<D_>), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double mid_ev = 0, big_ev = 0, slots = 0;
+        u64 nmid = 0, nlarge = 0;
+        u64 hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // large pairs by min side: <64,<256,<1k,<4k,<16k,<64k,more
+        double hev[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (u32 i = 0; i < nbig; ++i) {
+            double a = nd[bp[i].x].count, b = nd[bp[i].y].count;
+            if (b > a) std::swap(a, b);
+            double w = a * b;
+            if (w <= kMidMax) {
+                ++nmid;
+                mid_ev += w;
+                continue;
+            }
+            ++nlarge;
+            big_ev += w;
+            double ta = std::ceil(a / kBigA), tbn = std::ceil(b / g_bccp_chunk);
+            slots += ta * kBigA * (tbn > 1 ? b : b);  // lanes x B points each task row covers
+            int h = b < 64 ? 0 : b < 256 ? 1 : b < 1024 ? 2 : b < 4096 ? 3 : b < 16384 ? 4 : b < 65536 ? 5 : 6;
+            ++hist[h];
+            hev[h] += w;
+        }
+        fprintf(stderr,
+                "[geomst]   big pairs: %u (%llu medium, %.3g evals; %llu large, %.3g evals, A-lane fill %.2f) "
+                "tasks %u; large by smaller side <64/<256/<1k/<4k/<16k/<64k/more:",
+                nbig, (unsigned long long)nmid, mid_ev, (unsigned long long)nlarge, big_ev,
+                slots > 0 ? big_ev / slots : 0.0, ntasks);
+        for (int h = 0; h < 7; ++h) fprintf(stderr, " %llu(%.2g)", (unsigned long long)hist[h], hev[h]);
+        fprintf(stderr, "\n");
+    }
+
     RoundArgs args(double beta2, int fo, int qo, int po) {
         RoundArgs r;
         r.cnt = D.cnt.as<Counters>();
         r.beta2 = beta2;
+        r.sep = g_separation;
         r.t_near = t_near;
         r.ffar = D.FF[ffo].as<PairRec>();
         r.cap_far = (u32)D.capFF[ffo];
@@ -756,29 +797,41 @@ struct Solver {
                         D.ntask.ensure((size_t)nbig * 4);
                         D.toff.ensure((size_t)nbig * 4);
                         D.stemp.ensure(std::max(scan_temp_bytes(nbig), radix_temp_bytes(n)));
+                        HIPCHK(hipMemsetAsync(&D.cnt.as<Counters>()->c64[C64_TASKS], 0, 8, s));
                         k_big_ntasks<D_><<<blocks(nbig, 256), 256, 0, s>>>(t, D.big.as<uint2>(), nbig,
-                                                                            D.ntask.as<u32>());
+                                                                            D.ntask.as<u32>(), g_bccp_chunk,
+                                                                            D.cnt.as<Counters>());
                         LAUNCHCHK();
                         scan_exclusive_u32(D.ntask.as<u32>(), D.toff.as<u32>(), nbig, D.stemp.p, s);
                         LAUNCHCHK();
                         u32 last_off = 0, last_cnt = 0;
                         HIPCHK(hipMemcpyAsync(&last_off, D.toff.as<u32>() + nbig - 1, 4, hipMemcpyDeviceToHost, s));
                         HIPCHK(hipMemcpyAsync(&last_cnt, D.ntask.as<u32>() + nbig - 1, 4, hipMemcpyDeviceToHost, s));
-                        HIPCHK(hipStreamSynchronize(s));
+                        read_counters(D, s);  // synchronises
+                        if (D.hcnt->c64[C64_TASKS] >= (1ull << 31)) {
+                            g_err = "the separated pairs of one round need more than 2^31 BCCP tasks";
+                            throw Fail{GEOMST_EINTERNAL};
+                        }
                         u32 ntasks = last_off + last_cnt;
+                        if (g_trace) trace_big_pairs(nbig, ntasks);
                         D.parts.ensure((size_t)ntasks * sizeof(PartKey));
                         {
                             TIMED(GEOMST_K_BCCP);
                             if (hdb)
                                 k_big_bccp<D_, 1><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
-                                                                       D.parts.as<PartKey>(), D.cnt.as<Counters>());
+                                                                       D.parts.as<PartKey>(), D.cnt.as<Counters>(),
+                                                                       g_bccp_chunk);
                             else
                                 k_big_bccp<D_, 0><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
-                                                                       D.parts.as<PartKey>(), D.cnt.as<Counters>());
+                                                                       D.parts.as<PartKey>(), D.cnt.as<Counters>(),
+                                                                       g_bccp_chunk);
+                            LAUNCHCHK();
+                            k_big_reduce<<<blocks(nbig, kBlock / kWave), kBlock, 0, s>>>(
+                                nbig, D.toff.as<u32>(), D.ntask.as<u32>(), D.parts.as<PartKey>());
                             LAUNCHCHK();
                             RoundArgs r = args(beta2, fo, 0, po);
                             k_big_combine<<<std::min(blocks(nbig, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
-                                r, nbig, D.toff.as<u32>(), D.ntask.as<u32>(), D.parts.as<PartKey>());
+                                r, nbig, D.toff.as<u32>(), D.parts.as<PartKey>());
                             LAUNCHCHK();
                         }
                         read_counters(D, s);
@@ -1681,6 +1734,17 @@ int geomst_set_option(const char* name, double value) {
     if (!strcmp(name, "beta_growth")) {
         if (value != 0.0 && (!(value > 1.0) || !(value < 1e6))) return GEOMST_EINVAL;
         g_beta_growth = value;
+        return GEOMST_OK;
+    }
+    if (!strcmp(name, "bccp_chunk")) {
+        if (value == 0.0) value = kBigBDefault;
+        if (!(value >= 64.0) || !(value <= 65536.0) || value != (double)(64 * (int)(value / 64.0))) return GEOMST_EINVAL;
+        g_bccp_chunk = (int)value;
+        return GEOMST_OK;
+    }
+    if (!strcmp(name, "separation")) {
+        if (!(value >= 0.0) || !(value <= 16.0)) return GEOMST_EINVAL;
+        g_separation = value;
         return GEOMST_OK;
     }
     if (!strcmp(name, "list_capacity_scale")) {

@@ -35,12 +35,12 @@ enum CounterSlot {
     C_FAR,     // far frontier out
     C_NUM
 };
-enum CounterSlot64 { C64_EVALS = 0, C64_VISITS, C64_BCCP, C64_BIGEVALS, C64_NUM };
+enum CounterSlot64 { C64_EVALS = 0, C64_VISITS, C64_BCCP, C64_BIGEVALS, C64_TASKS, C64_NUM };
 enum MinSlot { M_F = 0, M_P, M_FAR, M_NUM };
 
 struct Counters {
     u32 c[16];
-    unsigned long long c64[4];
+    unsigned long long c64[C64_NUM];
     u64 m[4];  // bit patterns of non-negative doubles (all ones = none)
 };
 
@@ -59,6 +59,7 @@ struct EdgeList {
 struct RoundArgs {
     Counters* cnt;
     double beta2;
+    double sep;      // separation constant s of the sphere test
     double t_near;   // waiting pairs with bounds up to this go to the near list
     PairRec* ffar;   // far list (appended)
     u32 cap_far;
@@ -125,7 +126,7 @@ __device__ __forceinline__ bool connected(const TreeView& t, u32 a, u32 b) {
 // single points is always separated.
 template <int D>
 __device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRec<D>& B, int hdb, double2 ca,
-                                               double2 cb) {
+                                               double2 cb, double s) {
     if (A.count == 1 && B.count == 1) return true;
     double L = box_lb2<D>(A, B);
     double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
@@ -136,7 +137,7 @@ __device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRe
         double x = 0.5 * (A.lo[k] + A.hi[k]) - 0.5 * (B.lo[k] + B.hi[k]);
         c2 = c2 + x * x;
     }
-    double need = ra + rb + 2.0 * fmax(ra, rb);
+    double need = ra + rb + s * fmax(ra, rb);
     bool geo = (fmax(dA, dB) < L) && (c2 >= need * need);
     if (geo || !hdb) return geo;
     double gap = fmax(sqrt(c2) - ra - rb, 0.0);
@@ -430,7 +431,7 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
             lb = pair_wlb2<D>(A, B, hdb, ca, cb);
             if (lb > r.beta2) {
                 to_f = true;
-            } else if (well_separated<D>(A, B, hdb, ca, cb)) {
+            } else if (well_separated<D>(A, B, hdb, ca, cb, r.sep)) {
                 u64 work = (u64)A.count * (u64)B.count;
                 if (work <= (u64)kTinyEvals) {
                     e = point_edge<D>(t, hdb, (u32)A.first, (u32)B.first);
@@ -623,13 +624,23 @@ __global__ void __launch_bounds__(kSmallBlock) k_level_small(TreeView t, RoundAr
 
 // ------------------------------------------------------------ large pairs
 // A large separated pair is cut into tasks of up to kBigA points of the
-// larger node (two per lane) by up to kBigB points of the other; one wave per
-// task.  B points are staged in LDS 64 at a time and broadcast to all lanes;
-// the inner loop keeps only the running minimum weight per lane, and the
-// exact key (w2, e2, ids) is resolved afterwards by rescanning the few lanes
-// that hold the minimum.  Per-task partial keys are then combined per pair.
-constexpr int kBigA = 128;
-constexpr int kBigB = 2048;
+// larger node (kBigAPL per lane) by up to bchunk points of the other (a
+// multiple of 64, a launch parameter); one wave
+// per task.  B points are staged in LDS 64 at a time (double-buffered: the
+// next block is loaded into registers while the current one is used) and
+// broadcast to all lanes.  The inner loop keeps only the running minimum
+// weight per A point, plus the 64-point block where it was reached and
+// whether a later block tied it; the exact key (w2, e2, ids) is then resolved
+// by the whole wave rescanning only that block (or the task's whole B range
+// after a tie) for each A point that holds the wave minimum.  Per-task
+// partial keys are reduced per pair afterwards, one wave per pair.
+//
+// For BCCP* the weight max(cd(a), cd(b), d) is minimised over b as
+// max(cd(a), min_b max(cd(b), d)), which is the same value (max with a
+// constant is monotone) at one max per distance instead of two.
+constexpr int kBigAPL = 4;
+constexpr int kBigA = 64 * kBigAPL;
+constexpr int kBigBDefault = 2048;
 constexpr int kMidMax = 4096;  // pairs up to this many point pairs: one wave, flattened products
 
 struct PartKey {
@@ -650,20 +661,22 @@ __device__ __forceinline__ void big_orient(const TreeView& t, uint2 pr, int2& ra
 }
 
 template <int D>
-__global__ void k_big_ntasks(TreeView t, const uint2* big, u32 nbig, u32* ntask) {
+__global__ void k_big_ntasks(TreeView t, const uint2* big, u32 nbig, u32* ntask, int bchunk, Counters* cnt) {
     u32 i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nbig) return;
     int2 ra, rb;
     big_orient<D>(t, big[i], ra, rb);
     u64 work = (u64)ra.y * (u64)rb.y;
-    ntask[i] = work <= (u64)kMidMax ? 1u : (u32)(((ra.y + kBigA - 1) / kBigA) * ((rb.y + kBigB - 1) / kBigB));
+    u64 c = work <= (u64)kMidMax ? 1ull : (u64)((ra.y + kBigA - 1) / kBigA) * (u64)((rb.y + bchunk - 1) / bchunk);
+    atomicAdd(&cnt->c64[C64_TASKS], (unsigned long long)c);  // the host rejects totals beyond 2^31
+    ntask[i] = c < (1ull << 31) ? (u32)c : 1u;
 }
 
 template <int D, int HDB>
 __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u32 nbig, const u32* toff,
-                                                  PartKey* part, Counters* cnt) {
-    __shared__ double sb[64 * D];
-    __shared__ double scd[64];
+                                                  PartKey* part, Counters* cnt, int bchunk) {
+    __shared__ double sbuf[2][64 * D];
+    __shared__ double scd[2][64];
     const int lane = lane_id();
     const u32 task = blockIdx.x;
     // pair owning this task: last i with toff[i] <= task
@@ -711,66 +724,123 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
         return;
     }
     u32 local = task - toff[lo];
-    int nbt = (rb.y + kBigB - 1) / kBigB;
+    int nbt = (rb.y + bchunk - 1) / bchunk;
     int ta = (int)(local / (u32)nbt), tb = (int)(local % (u32)nbt);
-    int aend = ra.x + ra.y;
-    int a0 = ra.x + ta * kBigA + lane, a1 = a0 + 64;
-    bool v0 = a0 < aend, v1 = a1 < aend;
-    int a0c = v0 ? a0 : ra.x, a1c = v1 ? a1 : ra.x;
-    double p0[D], p1[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        p0[k] = t.X[(size_t)a0c * D + k];
-        p1[k] = t.X[(size_t)a1c * D + k];
-    }
-    double c0 = HDB ? t.cd2[a0c] : 0.0, c1 = HDB ? t.cd2[a1c] : 0.0;
+    const int aend = ra.x + ra.y;
+    const int abase = ra.x + ta * kBigA;
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
-    double m0 = inf, m1 = inf;
-    int jb0 = rb.x + tb * kBigB;
-    int jb1 = min(jb0 + kBigB, rb.x + rb.y);
-    for (int js = jb0; js < jb1; js += 64) {
-        int cntb = min(64, jb1 - js);
-        if (lane < cntb) {
+    double p[kBigAPL][D], ca[kBigAPL], m[kBigAPL];
+    int blk[kBigAPL];
+    bool tie[kBigAPL];
 #pragma unroll
-            for (int k = 0; k < D; ++k) sb[lane * D + k] = t.X[(size_t)(js + lane) * D + k];
-            if (HDB) scd[lane] = t.cd2[js + lane];
+    for (int r = 0; r < kBigAPL; ++r) {
+        int ai = abase + r * 64 + lane;
+        int aic = ai < aend ? ai : ra.x;
+#pragma unroll
+        for (int k = 0; k < D; ++k) p[r][k] = t.X[(size_t)aic * D + k];
+        ca[r] = HDB ? t.cd2[aic] : 0.0;
+        m[r] = inf;
+        tie[r] = false;
+    }
+    const int jb0 = rb.x + tb * bchunk;
+    const int jb1 = min(jb0 + bchunk, rb.x + rb.y);
+#pragma unroll
+    for (int r = 0; r < kBigAPL; ++r) blk[r] = jb0;
+    // stage the first block
+    if (lane < jb1 - jb0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) sbuf[0][lane * D + k] = t.X[(size_t)(jb0 + lane) * D + k];
+        if (HDB) scd[0][lane] = t.cd2[jb0 + lane];
+    }
+    // every load above has landed: keeps the compiler from placing waits for
+    // them inside the inner loop, where they would also wait for the prefetch
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    int buf = 0;
+    for (int js = jb0; js < jb1; js += 64, buf ^= 1) {
+        const int cntb = min(64, jb1 - js);
+        // prefetch the next block into registers
+        const int jn = js + 64;
+        const bool hn = jn < jb1 && lane < jb1 - jn;
+        double nx[D], ncd = 0.0;
+        if (hn) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) nx[k] = t.X[(size_t)(jn + lane) * D + k];
+            if (HDB) ncd = t.cd2[jn + lane];
         }
-        __syncthreads();
+        double bm[kBigAPL];
+#pragma unroll
+        for (int r = 0; r < kBigAPL; ++r) bm[r] = inf;
+        const double* sb = sbuf[buf];
+#pragma unroll 4
         for (int j = 0; j < cntb; ++j) {
             double q[D];
 #pragma unroll
             for (int k = 0; k < D; ++k) q[k] = sb[j * D + k];
-            double d0 = 0.0, d1 = 0.0;
+            const double cb = HDB ? scd[buf][j] : 0.0;
+            // dimension-major, so that the kBigAPL independent sums
+            // interleave (each still adds its terms in dimension order)
+            double d2[kBigAPL];
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                double x0 = p0[k] - q[k];
-                double x1 = p1[k] - q[k];
-                d0 = d0 + x0 * x0;
-                d1 = d1 + x1 * x1;
+            for (int r = 0; r < kBigAPL; ++r) {
+                double x = p[r][0] - q[0];
+                d2[r] = x * x;
             }
-            if (HDB) {
-                double cb = scd[j];
-                d0 = fmax(fmax(c0, cb), d0);
-                d1 = fmax(fmax(c1, cb), d1);
+#pragma unroll
+            for (int k = 1; k < D; ++k)
+#pragma unroll
+                for (int r = 0; r < kBigAPL; ++r) {
+                    double x = p[r][k] - q[k];
+                    d2[r] = d2[r] + x * x;
+                }
+#pragma unroll
+            for (int r = 0; r < kBigAPL; ++r) {
+                if (HDB) d2[r] = fmax(cb, d2[r]);
+                bm[r] = fmin(bm[r], d2[r]);
             }
-            m0 = fmin(m0, d0);
-            m1 = fmin(m1, d1);
+        }
+#pragma unroll
+        for (int r = 0; r < kBigAPL; ++r) {
+            double w = HDB ? fmax(ca[r], bm[r]) : bm[r];
+            if (w < m[r]) {
+                m[r] = w;
+                blk[r] = js;
+                tie[r] = false;
+            } else if (w == m[r]) {
+                tie[r] = true;
+            }
+        }
+        if (hn) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) sbuf[buf ^ 1][lane * D + k] = nx[k];
+            if (HDB) scd[buf ^ 1][lane] = ncd;
         }
         __syncthreads();
     }
-    double m = fmin(v0 ? m0 : inf, v1 ? m1 : inf);
-    double M = wave_min_f64(m);
-    // exact key among the entries that reach the minimum weight
+    double mm = inf;
+#pragma unroll
+    for (int r = 0; r < kBigAPL; ++r)
+        if (abase + r * 64 + lane < aend) mm = fmin(mm, m[r]);
+    const double M = wave_min_f64(mm);
+    // exact key: for each A point at the minimum, the wave rescans the block
+    // where it was reached (the whole B range after a tie)
     EdgeOut best;
     best.k = key_none();
     best.i = best.j = kNone;
-    for (int r = 0; r < 2; ++r) {
-        bool mine = r == 0 ? (v0 && m0 == M) : (v1 && m1 == M);
-        if (!mine) continue;
-        u32 ai = (u32)(r == 0 ? a0 : a1);
-        for (int j = jb0; j < jb1; ++j) {
-            EdgeOut c = point_edge<D>(t, HDB, ai, (u32)j);
-            if (c.k.w2 == M && key_less(c.k, best.k)) best = c;
+#pragma unroll
+    for (int r = 0; r < kBigAPL; ++r) {
+        const int ai = abase + r * 64 + lane;
+        u64 mask = __ballot(ai < aend && m[r] == M);
+        while (mask) {
+            const int c = __ffsll((long long)mask) - 1;
+            mask &= mask - 1;
+            const int a = __shfl(ai, c);
+            const int s0 = __shfl(tie[r] ? jb0 : blk[r], c);
+            const int s1 = __shfl(tie[r] ? jb1 : min(blk[r] + 64, jb1), c);
+            for (int j = s0 + lane; j < s1; j += 64) {
+                EdgeOut e = point_edge<D>(t, HDB, (u32)a, (u32)j);
+                if (key_less(e.k, best.k)) best = e;
+            }
         }
     }
     // wave minimum of the exact keys (carrying the positions)
@@ -792,14 +862,48 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
         pk.ids = ((u64)best.k.lo << 32) | best.k.hi;
         pk.pos = ((u64)best.i << 32) | best.j;
         part[task] = pk;
-        int na = min(kBigA, aend - (ra.x + ta * kBigA));
+        int na = min(kBigA, aend - abase);
         unsigned long long ev = (unsigned long long)na * (unsigned long long)(jb1 - jb0);
         atomicAdd(&cnt->c64[C64_EVALS], ev);
         atomicAdd(&cnt->c64[C64_BIGEVALS], ev);
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_big_combine(RoundArgs r, u32 nbig, const u32* toff, const u32* ntask,
+__device__ __forceinline__ bool part_less(const PartKey& x, const PartKey& b) {
+    return (x.w2 != b.w2) ? (x.w2 < b.w2) : (x.e2 != b.e2) ? (x.e2 < b.e2) : (x.ids < b.ids);
+}
+
+// Per pair, the minimum of its task keys, written into the pair's first
+// task slot; one wave per pair.
+__global__ void __launch_bounds__(kBlock) k_big_reduce(u32 nbig, const u32* toff, const u32* ntask, PartKey* part) {
+    const int lane = lane_id();
+    const u32 i = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (i >= nbig) return;
+    const u32 o = toff[i], c = ntask[i];
+    if (c == 1) return;
+    PartKey b;
+    b.w2 = b.e2 = __longlong_as_double(0x7ff0000000000000ll);
+    b.ids = ~0ull;
+    b.pos = 0;
+    for (u32 k = (u32)lane; k < c; k += kWave) {
+        PartKey x = part[o + k];
+        if (part_less(x, b)) b = x;
+    }
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) {
+        PartKey x;
+        x.w2 = __shfl_xor(b.w2, s);
+        x.e2 = __shfl_xor(b.e2, s);
+        x.ids = __shfl_xor(b.ids, s);
+        x.pos = __shfl_xor(b.pos, s);
+        if (part_less(x, b)) b = x;
+    }
+    if (lane == 0) part[o] = b;
+}
+
+// Commits or defers each large pair's BCCP edge (its key is in the pair's
+// first task slot after k_big_reduce).
+__global__ void __launch_bounds__(kBlock) k_big_combine(RoundArgs r, u32 nbig, const u32* toff,
                                                         const PartKey* part) {
     __shared__ BlockAlloc S;
     __shared__ double shm[4];
@@ -814,15 +918,7 @@ __global__ void __launch_bounds__(kBlock) k_big_combine(RoundArgs r, u32 nbig, c
         b.e2 = inf;
         b.ids = ~0ull;
         b.pos = 0;
-        if (have) {
-            u32 o = toff[i], c = ntask[i];
-            b = part[o];
-            for (u32 k = 1; k < c; ++k) {
-                PartKey x = part[o + k];
-                bool less = (x.w2 != b.w2) ? (x.w2 < b.w2) : (x.e2 != b.e2) ? (x.e2 < b.e2) : (x.ids < b.ids);
-                if (less) b = x;
-            }
-        }
+        if (have) b = part[toff[i]];
         bool to_c = have && b.w2 <= r.beta2;
         bool to_p = have && !to_c;
         if (to_p) minp = fmin(minp, b.w2);
