@@ -107,7 +107,7 @@ def measured_traffic(family, workload):
     return int(kv["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(name, pts, min_pts, target_s=15.0):
+def cpu_baseline(name, pts, min_pts, target_s=25.0):
     import oracle
     oracle.build(force=False)
     n = len(pts)

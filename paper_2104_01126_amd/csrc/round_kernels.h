@@ -84,7 +84,7 @@ __device__ __forceinline__ double box_lb2(const NodeRec<D>& A, const NodeRec<D>&
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        double g = fmax(fmax(B.lo[k] - A.hi[k], A.lo[k] - B.hi[k]), 0.0);
+        double g = fmax(fmax((double)B.lo[k] - (double)A.hi[k], (double)A.lo[k] - (double)B.hi[k]), 0.0);
         s = s + g * g;
     }
     return s;
@@ -95,7 +95,7 @@ __device__ __forceinline__ double box_diag2(const NodeRec<D>& A) {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        double t = A.hi[k] - A.lo[k];
+        double t = (double)A.hi[k] - (double)A.lo[k];
         s = s + t * t;
     }
     return s;
@@ -134,7 +134,7 @@ __device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRe
     double c2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        double x = 0.5 * (A.lo[k] + A.hi[k]) - 0.5 * (B.lo[k] + B.hi[k]);
+        double x = 0.5 * ((double)A.lo[k] + (double)A.hi[k]) - 0.5 * ((double)B.lo[k] + (double)B.hi[k]);
         c2 = c2 + x * x;
     }
     double need = ra + rb + s * fmax(ra, rb);

@@ -10,29 +10,53 @@
 // node's actual points, so the quantisation only shapes the tree and never
 // enters any distance.
 #pragma once
+#include <type_traits>
 #include "common.h"
 
 namespace geomst {
 
-// Per-node record, exactly one 64-byte (d <= 3) or 128-byte line: tight box
-// of the node's points, its contiguous range of sorted positions, the split
-// position of the radix tree (children follow from it), and the radius of
-// the sphere about the box centre (only a heuristic for which node to split,
-// so single precision).  Core-distance ranges (HDBSCAN*) live in their own
-// array so that EMST never reads them.
+// Per-node record: box of the node's points, its contiguous range of sorted
+// positions, the split position of the radix tree (children follow from it),
+// and the radius of the sphere about the box centre (only a heuristic for
+// which node to split, so single precision).  Core-distance ranges
+// (HDBSCAN*) live in their own array so that EMST never reads them.
+//
+// For d <= 3 the box is the tight binary64 box (the record is one 32- or
+// 64-byte line).  For d >= 4 it is stored in binary32, each bound rounded
+// outward from the tight box, so that it still contains every point exactly
+// and the record fits one 64-byte line (80 bytes for d = 7) instead of two;
+// every bound computed from it is then still a bound of the computed
+// point-to-point values, only looser by the rounding.
 template <int D>
-struct NodeAlign {
-    static constexpr int value = (16 * D + 16 <= 64) ? 64 : 128;
+struct NodeBox {
+    using type = typename std::conditional<(D >= 4), float, double>::type;
+    static constexpr int bytes = 2 * D * (int)sizeof(type) + 16;
+    static constexpr int align = bytes <= 32 ? 32 : bytes <= 64 ? 64 : 16;
 };
 
 template <int D>
-struct alignas(NodeAlign<D>::value) NodeRec {
-    double lo[D];
-    double hi[D];
+struct alignas(NodeBox<D>::align) NodeRec {
+    typename NodeBox<D>::type lo[D];
+    typename NodeBox<D>::type hi[D];
     int first, count;
     int split;  // radix-tree split position g of an internal node; -1 for a leaf
     float rad;
 };
+
+// Binary32 bounds rounded outward (towards -inf for a lower bound, +inf for
+// an upper bound); the comparisons with the binary64 value are exact.
+__device__ __forceinline__ float round_down_f32(double x) {
+    float f = (float)x;
+    return ((double)f > x) ? nextafterf(f, -__builtin_huge_valf()) : f;
+}
+__device__ __forceinline__ float round_up_f32(double x) {
+    float f = (float)x;
+    return ((double)f < x) ? nextafterf(f, __builtin_huge_valf()) : f;
+}
+__device__ __forceinline__ void store_lo(double& dst, double x) { dst = x; }
+__device__ __forceinline__ void store_hi(double& dst, double x) { dst = x; }
+__device__ __forceinline__ void store_lo(float& dst, double x) { dst = round_down_f32(x); }
+__device__ __forceinline__ void store_hi(float& dst, double x) { dst = round_up_f32(x); }
 
 struct TreeView {
     int n;              // points
@@ -330,10 +354,10 @@ template <int D>
 __device__ __forceinline__ void write_box(NodeRec<D>& V, const double* lo, const double* hi, double s) {
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        V.lo[k] = lo[k];
-        V.hi[k] = hi[k];
+        store_lo(V.lo[k], lo[k]);
+        store_hi(V.hi[k], hi[k]);
     }
-    V.rad = (float)(0.5 * sqrt(s));
+    V.rad = round_up_f32(0.5 * sqrt(s));
 }
 
 template <int D>
@@ -353,7 +377,10 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
     if (geometry) {
         NodeRec<D>& L = nodes[leaf];
 #pragma unroll
-        for (int k = 0; k < D; ++k) L.lo[k] = L.hi[k] = X[(size_t)p * D + k];
+        for (int k = 0; k < D; ++k) {
+            store_lo(L.lo[k], X[(size_t)p * D + k]);
+            store_hi(L.hi[k], X[(size_t)p * D + k]);
+        }
         L.first = p;
         L.count = 1;
         L.split = -1;
@@ -432,8 +459,8 @@ __global__ void __launch_bounds__(kBoundsTop) k_bounds_top(int n, const int* par
                 double lo[D], hi[D], s = 0.0;
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    lo[k] = fmin(A->lo[k], B->lo[k]);
-                    hi[k] = fmax(A->hi[k], B->hi[k]);
+                    lo[k] = fmin((double)A->lo[k], (double)B->lo[k]);
+                    hi[k] = fmax((double)A->hi[k], (double)B->hi[k]);
                     double x = hi[k] - lo[k];
                     s = s + x * x;
                 }
@@ -479,12 +506,12 @@ __device__ __forceinline__ double sqdist(const double (&a)[D], const double* b) 
 
 // Squared distance from a point to a box, computed so that it never exceeds
 // the computed squared distance to any point of the box.
-template <int D>
-__device__ __forceinline__ double point_box_lb2(const double (&q)[D], const double* lo, const double* hi) {
+template <int D, class B>
+__device__ __forceinline__ double point_box_lb2(const double (&q)[D], const B* lo, const B* hi) {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        double g = fmax(fmax(lo[k] - q[k], q[k] - hi[k]), 0.0);
+        double g = fmax(fmax((double)lo[k] - q[k], q[k] - (double)hi[k]), 0.0);
         s = s + g * g;
     }
     return s;
