@@ -77,6 +77,7 @@ def unit_model(fam, st, d):
 
 
 FAMILY_KERNEL = {"expand": "k_level", "bccp": "k_big_bccp", "sort": "k_radix", "kruskal": "k_bor"}
+# the library's "expand" timing brackets k_level and k_level_small launches
 
 
 def source_sha():
@@ -91,8 +92,9 @@ def source_sha():
 
 
 def measured_traffic(family, workload):
-    """HBM bytes per launch of the family's kernel from the committed rocprofv3
-    PMC summary, or None when there is none or the sources changed since."""
+    """HBM bytes per solve moved by the family's kernels, and their dispatches
+    per solve, from the committed rocprofv3 PMC summary; None when there is
+    none or the sources changed since it was taken."""
     k = FAMILY_KERNEL.get(family)
     path = os.path.join(ROOT, "profiles", f"{k}_{workload}_traffic.txt")
     if not k or not os.path.exists(path):
@@ -104,7 +106,7 @@ def measured_traffic(family, workload):
             kv[a] = b
     if kv.get("source_sha") != source_sha():
         return None
-    return int(kv["traffic_bytes_per_launch"])
+    return int(kv["traffic_bytes_per_solve"]), int(kv["dispatches_per_solve"])
 
 
 def cpu_baseline(name, pts, min_pts, target_s=25.0):
@@ -355,13 +357,21 @@ def main():
             ach, peak = amount / secs / 1e12, FP64_PEAK_TFLOPS
         else:
             ach, peak = amount / secs / 1e9, HBM_PEAK_GBS
-        launches = max(int(kl[i]), 1)
-        roof = {"kernel": fams[i], "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-                "frac": round(ach / peak, 5), "traffic": measured_traffic(fams[i], a.workload),
+        mt = measured_traffic(fams[i], a.workload)
+        # per launch = per solve / dispatches per solve (the ratio achieved =
+        # bytes per launch / average launch time is the same either way)
+        disp = mt[1] if mt else None
+        per = disp if disp else 1
+        roof = {"kernel": fams[i], "kernels": FAMILY_KERNEL.get(fams[i]), "bound": bound,
+                "achieved": round(ach, 3), "peak": peak, "unit": unit, "frac": round(ach / peak, 5),
+                "traffic": round(mt[0] / per) if mt else None,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-scaled)",
-                "algorithmic_per_launch": round(amount / launches, 1),
-                "launches_per_step": launches / a.steps,
+                "algorithmic_per_launch": round(amount / a.steps / per, 1),
+                "launches_per_step": disp,
+                "algorithmic_per_step": round(amount / a.steps, 1),
+                "traffic_per_step": mt[0] if mt else None,
                 "device_ms_per_step": round(kms[i] / a.steps, 4),
+                "avg_launch_us": round(kms[i] / a.steps / per * 1000, 3) if disp else None,
                 "share_of_device_time": round(kms[i] / max(kms.sum(), 1e-9), 4)}
         break
     out = {

@@ -153,7 +153,7 @@ struct Device {
     DBuf pin, eout, wout, cdout;
     // tree
     DBuf keysA, keysB, gflag, gincl, gid, gstart, g64, gbox, hflag;
-    DBuf part, bbox, key, val, key2, val2, stemp, X, orig, cd2, nodes, npar, flags, comp, cdr, btop;
+    DBuf part, bbox, key, val, key2, val2, stemp, X, orig, cd2, nodes, npar, flags, cdr, btop;
     // union-find / component refresh
     DBuf uf, best, bnd, incl;
     // rounds
@@ -442,7 +442,6 @@ struct Solver {
         D.nodes.ensure((size_t)nn * sizeof(NodeRec<D_>));
         D.npar.ensure((size_t)nn * 4);
         D.flags.ensure((size_t)nn * 4);
-        D.comp.ensure((size_t)nn * 4);
         NodeRec<D_>* nodes = D.nodes.as<NodeRec<D_>>();
         k_karras<D_><<<blocks(n - 1, 256), 256, 0, s>>>(skey, n, L, nodes, D.npar.as<int>());
         LAUNCHCHK();
@@ -453,7 +452,6 @@ struct Solver {
         t.cd2 = nullptr;
         t.nodes = nodes;
         t.cdr = nullptr;
-        t.comp = D.comp.as<int>();
     }
 
     // Node boxes (and, with cd2, core-distance ranges): block-local phase,
@@ -502,7 +500,7 @@ struct Solver {
         scan_inclusive_u32(D.bnd.as<u32>(), D.incl.as<u32>(), n, D.stemp.p, s);
         LAUNCHCHK();
         k_node_comp<D_><<<blocks(2 * n - 1, 256), 256, 0, s>>>(D.nodes.as<NodeRec<D_>>(), D.uf.as<u32>(),
-                                                               D.incl.as<u32>(), 2 * n - 1, D.comp.as<int>());
+                                                               D.incl.as<u32>(), 2 * n - 1);
         LAUNCHCHK();
     }
 
@@ -727,7 +725,7 @@ struct Solver {
                             r, D.P[pc].list(), nP);
                     LAUNCHCHK();
                     if (epoch && nFF)
-                        k_split_far<<<std::min(blocks(nFF, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
+                        k_split_far<D_><<<std::min(blocks(nFF, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
                             t, r, D.FF[ffc].as<PairRec>(), nFF, ring);
                     LAUNCHCHK();
                 }

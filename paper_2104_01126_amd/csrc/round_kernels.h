@@ -111,9 +111,11 @@ __device__ __forceinline__ double pair_wlb2(const NodeRec<D>& A, const NodeRec<D
     return l;
 }
 
+template <int D>
 __device__ __forceinline__ bool connected(const TreeView& t, u32 a, u32 b) {
-    int ca = t.comp[a];
-    return ca >= 0 && ca == t.comp[b];
+    const NodeRec<D>* N = nodes_of<D>(t);
+    int ca = N[a].comp;
+    return ca >= 0 && ca == N[b].comp;
 }
 
 // Well-separation test.  Geometric (Sec. 2.3, s = 2, in the form of
@@ -126,11 +128,12 @@ __device__ __forceinline__ bool connected(const TreeView& t, u32 a, u32 b) {
 // single points is always separated.
 template <int D>
 __device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRec<D>& B, int hdb, double2 ca,
-                                               double2 cb, double s) {
+                                               double2 cb, double s, double dA, double dB) {
     if (A.count == 1 && B.count == 1) return true;
     double L = box_lb2<D>(A, B);
-    double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
-    double ra = A.rad, rb = B.rad;
+    // sphere radii: half the box diagonals (single precision suffices, the
+    // sphere test only makes the strict box guard stricter)
+    double ra = 0.5f * __builtin_sqrtf((float)dA), rb = 0.5f * __builtin_sqrtf((float)dB);
     double c2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -141,7 +144,7 @@ __device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRe
     bool geo = (fmax(dA, dB) < L) && (c2 >= need * need);
     if (geo || !hdb) return geo;
     double gap = fmax(sqrt(c2) - ra - rb, 0.0);
-    double lhs_s = fmax(fmax(4.0 * ra * ra, 4.0 * rb * rb), fmax(ca.y, cb.y));
+    double lhs_s = fmax(fmax(dA, dB), fmax(ca.y, cb.y));
     double rhs_s = fmax(gap * gap, fmax(ca.x, cb.x));
     double lhs = fmax(fmax(dA, dB), fmax(ca.y, cb.y));
     double rhs = fmax(L, fmax(ca.x, cb.x));
@@ -347,6 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs
 // Far-frontier split at the start of a band: drop pairs whose points are now
 // in one component, queue the due ones, move those within the new band edge
 // to the near list and keep the rest far.
+template <int D>
 __global__ void __launch_bounds__(kBlock) k_split_far(TreeView t, RoundArgs r, const PairRec* fin, u32 nfin,
                                                       u32* qcount) {
     __shared__ BlockAlloc S;
@@ -361,7 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_split_far(TreeView t, RoundArgs r, c
         p.a = p.b = 0;
         p.lb2 = 0.0;
         if (have) p = fin[i];
-        bool keep = have && p.lb2 < __longlong_as_double(0x7ff0000000000000ll) && !connected(t, p.a, p.b);
+        bool keep = have && p.lb2 < __longlong_as_double(0x7ff0000000000000ll) && !connected<D>(t, p.a, p.b);
         bool due = keep && p.lb2 <= r.beta2;
         bool near = keep && !due && p.lb2 <= r.t_near;
         bool far = keep && !due && !near;
@@ -423,15 +427,16 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
         a = pr.a;
         b = pr.b;
         ++acc.visits;
-        const int ka = t.comp[a], kb = t.comp[b];
+        const NodeRec<D> A = N[a], B = N[b];
+        const int ka = A.comp, kb = B.comp;
         if (!(ka >= 0 && ka == kb)) {
-            NodeRec<D> A = N[a], B = N[b];
             double2 z = make_double2(0.0, 0.0);
             double2 ca = hdb ? t.cdr[a] : z, cb = hdb ? t.cdr[b] : z;
             lb = pair_wlb2<D>(A, B, hdb, ca, cb);
+            const double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
             if (lb > r.beta2) {
                 to_f = true;
-            } else if (well_separated<D>(A, B, hdb, ca, cb, r.sep)) {
+            } else if (well_separated<D>(A, B, hdb, ca, cb, r.sep, dA, dB)) {
                 u64 work = (u64)A.count * (u64)B.count;
                 if (work <= (u64)kTinyEvals) {
                     e = point_edge<D>(t, hdb, (u32)A.first, (u32)B.first);
@@ -450,8 +455,7 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
                 }
             } else {
                 // split the node with the larger bounding sphere (Alg. 1, FindPair)
-                bool split_a = (B.count == 1) ||
-                               (A.count > 1 && (A.rad > B.rad || (A.rad == B.rad && A.count >= B.count)));
+                bool split_a = (B.count == 1) || (A.count > 1 && (dA > dB || (dA == dB && A.count >= B.count)));
                 const NodeRec<D>& X = split_a ? A : B;
                 const NodeRec<D>& O = split_a ? B : A;
                 double2 co = split_a ? cb : ca;
@@ -461,10 +465,11 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
                 // the two children are usually adjacent records (and adjacent
                 // component entries): drop connected child pairs, bound the
                 // others, park the far ones
-                int kc[2] = {t.comp[ch.x], t.comp[ch.y]};
+                const NodeRec<D> C0 = N[ch.x], C1 = N[ch.y];
+                int kc[2] = {C0.comp, C1.comp};
                 double2 c0 = hdb ? t.cdr[ch.x] : z, c1 = hdb ? t.cdr[ch.y] : z;
-                lbc[0] = pair_wlb2<D>(N[ch.x], O, hdb, c0, co);
-                lbc[1] = pair_wlb2<D>(N[ch.y], O, hdb, c1, co);
+                lbc[0] = pair_wlb2<D>(C0, O, hdb, c0, co);
+                lbc[1] = pair_wlb2<D>(C1, O, hdb, c1, co);
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     if (kc[c] >= 0 && kc[c] == kother) continue;
@@ -1190,12 +1195,12 @@ __global__ void k_boundaries(const u32* uf, int n, u32* bnd) {
 }
 
 template <int D>
-__global__ void k_node_comp(const NodeRec<D>* nodes, const u32* uf, const u32* incl, int nn, int* comp) {
+__global__ void k_node_comp(NodeRec<D>* nodes, const u32* uf, const u32* incl, int nn) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nn) return;
     int2 r = make_int2(nodes[v].first, nodes[v].count);
     int last = r.x + r.y - 1;
-    comp[v] = (incl[last] == incl[r.x]) ? (int)uf[r.x] : -1;
+    nodes[v].comp = (incl[last] == incl[r.x]) ? (int)uf[r.x] : -1;
 }
 
 // ------------------------------------------------------------ output

@@ -17,9 +17,11 @@ namespace geomst {
 
 // Per-node record: box of the node's points, its contiguous range of sorted
 // positions, the split position of the radix tree (children follow from it),
-// and the radius of the sphere about the box centre (only a heuristic for
-// which node to split, so single precision).  Core-distance ranges
-// (HDBSCAN*) live in their own array so that EMST never reads them.
+// and the component shared by all its points (or -1), which the decomposition
+// reads together with the box (rewritten after Kruskal steps).  The sphere
+// radius about the box centre is half the box diagonal and is derived from
+// the box where needed.  Core-distance ranges (HDBSCAN*) live in their own
+// array so that EMST never reads them.
 //
 // For d <= 3 the box is the tight binary64 box (the record is one 32- or
 // 64-byte line).  For d >= 4 it is stored in binary32, each bound rounded
@@ -40,7 +42,7 @@ struct alignas(NodeBox<D>::align) NodeRec {
     typename NodeBox<D>::type hi[D];
     int first, count;
     int split;  // radix-tree split position g of an internal node; -1 for a leaf
-    float rad;
+    int comp;   // component of all the node's points, or -1
 };
 
 // Binary32 bounds rounded outward (towards -inf for a lower bound, +inf for
@@ -65,7 +67,6 @@ struct TreeView {
     const double* cd2;  // sorted position -> squared core distance, or null (EMST)
     const void* nodes;  // NodeRec<D>[2n-1]
     const double2* cdr; // [2n-1] (min cd2, max cd2) of the node's points (HDBSCAN*)
-    const int* comp;    // [2n-1] component shared by all the node's points, or -1
 };
 // Node ids: internal nodes 0..n-2 (0 is the root), the leaf of sorted
 // position p is node n-1+p.
@@ -351,13 +352,12 @@ constexpr int kBoundsBlock = 1024;
 constexpr int kBoundsTop = 1024;  // threads of the phase-2 workgroup
 
 template <int D>
-__device__ __forceinline__ void write_box(NodeRec<D>& V, const double* lo, const double* hi, double s) {
+__device__ __forceinline__ void write_box(NodeRec<D>& V, const double* lo, const double* hi) {
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         store_lo(V.lo[k], lo[k]);
         store_hi(V.hi[k], hi[k]);
     }
-    V.rad = round_up_f32(0.5 * sqrt(s));
 }
 
 template <int D>
@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
         L.first = p;
         L.count = 1;
         L.split = -1;
-        L.rad = 0.0f;
+        L.comp = -1;
     }
     if (cd2) cdr[leaf] = make_double2(cd2[p], cd2[p]);
     int child = leaf;
@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
         if (atomicAdd(&lflag[v - base], 1u) == 0) return;
         __threadfence_block();
         int2 ch = node_kids(n, f, c, V.split);
-        double lo[D], hi[D], s = 0.0;
+        double lo[D], hi[D];
         double2 cd = make_double2(0.0, 0.0);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -420,8 +420,6 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
             }
             lo[k] = fmin(a0, b0);
             hi[k] = fmax(a1, b1);
-            double x = hi[k] - lo[k];
-            s = s + x * x;
             slo[v - base][k] = lo[k];
             shi[v - base][k] = hi[k];
         }
@@ -432,7 +430,7 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
             scd[v - base] = cd;
             cdr[v] = cd;
         }
-        if (geometry) write_box<D>(V, lo, hi, s);
+        if (geometry) write_box<D>(V, lo, hi);
         child = v;
         v = parent[v];
     }
@@ -456,15 +454,13 @@ __global__ void __launch_bounds__(kBoundsTop) k_bounds_top(int n, const int* par
             const volatile NodeRec<D>* A = nodes + ch.x;
             const volatile NodeRec<D>* B = nodes + ch.y;
             if (geometry) {
-                double lo[D], hi[D], s = 0.0;
+                double lo[D], hi[D];
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
                     lo[k] = fmin((double)A->lo[k], (double)B->lo[k]);
                     hi[k] = fmax((double)A->hi[k], (double)B->hi[k]);
-                    double x = hi[k] - lo[k];
-                    s = s + x * x;
                 }
-                write_box<D>(V, lo, hi, s);
+                write_box<D>(V, lo, hi);
             }
             if (hdb) {
                 const volatile double2* ca = cdr + ch.x;
