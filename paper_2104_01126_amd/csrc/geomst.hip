@@ -216,10 +216,22 @@ void read_counters(Device& D, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
 }
 
+// Queues a copy of c to the device counters.  The pinned mirror is the copy
+// source, so the host leaves it alone until the next read_counters.
 void write_counters(Device& D, const Counters& c, hipStream_t s) {
     *D.hcnt = c;
     HIPCHK(hipMemcpyAsync(D.cnt.p, D.hcnt, sizeof(Counters), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
+}
+
+// Error flags the kernels raise (bit 1 list overflow is handled by round
+// restarts before this is reached).
+void check_errors(Device& D) {
+    u32 e = D.hcnt->c[C_ERR];
+    if (e & (1u | 4u | 8u)) {
+        g_err = (e & 8u) ? "union-find walk did not terminate"
+                : (e & 4u) ? "k-NN stack overflow" : "output edge overflow";
+        throw Fail{GEOMST_EINTERNAL};
+    }
 }
 
 double bits_to_double(u64 b) {
@@ -700,6 +712,7 @@ struct Solver {
             ffo = epoch ? (ffc ^ 1) : ffc;
             counters_reset_round(D, s);
             read_counters(D, s);
+            check_errors(D);  // flags raised by the previous round's last kernels
             D.hcnt->c[C_FAR] = epoch ? 0u : nFF;  // far appends go after the retained pairs
             write_counters(D, *D.hcnt, s);
             const Counters round_start = *D.hcnt;
@@ -886,27 +899,24 @@ struct Solver {
                     }
                     u32 left = 0;
                     HIPCHK(hipMemcpyAsync(&left, D.nalive.as<u32>() + ac, 4, hipMemcpyDeviceToHost, s));
-                    HIPCHK(hipStreamSynchronize(s));
+                    read_counters(D, s);  // one sync for both
                     if (left == 0) break;
                 }
             }
-            // Refresh the node components unless this round merged almost
-            // nothing (stale labels only miss some pruning: components only
-            // grow, so a node labelled with one component still is in one).
-            read_counters(D, s);
-            u32 merged = D.hcnt->c[C_OUT] - nout;
-            if ((u64)merged * 4096 >= (u64)n || stale_rounds >= 3 || D.hcnt->c[C_OUT] >= target_edges) {
+            // The counters read last (after the Kruskal steps, or after the
+            // expansion when nothing was committed) are this round's final
+            // values.  Refresh the node components unless this round merged
+            // almost nothing (stale labels only miss some pruning: components
+            // only grow, so a node labelled with one component still is in
+            // one); its error flags are checked at the next read.
+            const Counters& c = *D.hcnt;
+            check_errors(D);
+            u32 merged = c.c[C_OUT] - nout;
+            if ((u64)merged * 4096 >= (u64)n || stale_rounds >= 3 || c.c[C_OUT] >= target_edges) {
                 refresh_components();
                 stale_rounds = 0;
             } else {
                 ++stale_rounds;
-            }
-            read_counters(D, s);
-            const Counters& c = *D.hcnt;
-            if (c.c[C_ERR] & (1u | 4u | 8u)) {
-                g_err = (c.c[C_ERR] & 8u) ? "union-find walk did not terminate"
-                        : (c.c[C_ERR] & 4u) ? "k-NN stack overflow" : "output edge overflow";
-                throw Fail{GEOMST_EINTERNAL};
             }
             nout = c.c[C_OUT];
             nF = c.c[C_F];
@@ -957,6 +967,7 @@ struct Solver {
             LAUNCHCHK();
         }
         read_counters(D, s);
+        check_errors(D);
         auto t4 = clk::now();
         auto ms = [](clk::time_point a, clk::time_point b) {
             return std::chrono::duration<double, std::milli>(b - a).count();

@@ -562,11 +562,19 @@ __device__ __forceinline__ void level_flush(const RoundArgs& r, LevelAcc& acc) {
     }
 }
 
+// Occupancy targets: the expansion is bound by the latency of dependent
+// loads, so more resident waves help more than the few registers they cost.
+template <int D>
+struct LevelWaves {
+    static constexpr int value = D <= 5 ? 4 : 1;
+};
+
 // One breadth-first level over the whole grid.  Blocks beyond the queue
 // leave at once.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin,
-                                                  u32 cap_in, const u32* nq_p, u32* nq_next, u32* nq_clear) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LevelWaves<D>::value)))
+k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const u32* nq_p, u32* nq_next,
+        u32* nq_clear) {
     __shared__ BlockAlloc S;
     if (blockIdx.x == 0 && threadIdx.x == 0) *nq_clear = 0;
     // an overflowed previous level counts more pairs than it stored: read
