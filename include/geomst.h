@@ -260,6 +260,18 @@ int geomst_get_stats(geomst_stats_t* out);
  *   "kernel_timing"  1 = bracket every kernel family launch with HIP events on
  *                    the solve's stream and report device times in
  *                    geomst_stats_t.kernel_ms; 0 = off (default).
+ *   "kernel_timing_families"  bit mask of GEOMST_K_* families to time while
+ *                    "kernel_timing" is on (fewer events, less overhead);
+ *                    0 = all (default).
+ *   "separation"     the constant s of the sphere separation test (Sec. 2.3),
+ *                    in [0, 16]; default 2.
+ *   "bccp_chunk"     B points per large-pair BCCP task, a multiple of 64 in
+ *                    [64, 65536]; 0 restores the default 2048.
+ *   "small_level_switch", "small_level_max"  expansion levels with at most
+ *                    the first many pairs run in one workgroup, which keeps
+ *                    going while levels stay at most the second size
+ *                    (defaults 2048 and 4096).
+ * Options are process-wide; set them while no solve is running.
  * Returns GEOMST_EINVAL for an unknown name or a bad value.
  */
 int geomst_set_option(const char* name, double value);

@@ -37,8 +37,8 @@ int g_bccp_chunk = kBigBDefault;  // B points per large-pair BCCP task
 double g_capacity_scale = 1.0;
 constexpr int kMaxKeyLevels = 6;
 constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
-constexpr u32 kSmallSwitch = 8192;  // queues up to this size go to the one-workgroup level kernel
-constexpr u32 kSmallMax = 32768;    // ... which keeps going while a level stays this small
+u32 g_small_switch = 2048;  // queues up to this size go to the one-workgroup level kernel
+u32 g_small_max = 4096;     // ... which keeps going while a level stays this small
 constexpr int kBoruvkaBatch = 4;  // Boruvka steps launched between host checks  // Morton key words per point (see k_morton_level)
 const bool g_trace = getenv("GEOMST_TRACE") != nullptr;
 
@@ -99,11 +99,13 @@ struct Prof {
     std::vector<std::pair<int, size_t>> pend;  // (family, first event index)
     size_t used = 0;
     bool on = false;
+    u32 mask = 0;  // families timed while on
     ~Prof() {
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     }
-    void begin(bool enable) {
-        on = enable;
+    void begin(u32 families) {
+        on = families != 0;
+        mask = families;
         used = 0;
         pend.clear();
     }
@@ -177,7 +179,8 @@ struct Device {
 // Per-device workspaces of the plain and batched calls; never destroyed (the
 // runtime may already be gone at static destruction).
 Device* const g_dev = new Device[16];
-bool g_kernel_timing = false;
+u32 g_kernel_timing = 0;                    // families timed (bit per GEOMST_K_*); 0 = off
+u32 g_kernel_timing_families = 0xffffffffu;  // restriction set by "kernel_timing_families"
 
 
 
@@ -186,12 +189,13 @@ struct TimedScope {
     hipStream_t s;
     int fam;
     size_t a = 0;
-    TimedScope(Prof& p, hipStream_t st, int f) : P(p), s(st), fam(f) {
-        if (P.on) a = P.rec(s);
+    bool on;
+    TimedScope(Prof& p, hipStream_t st, int f) : P(p), s(st), fam(f), on(p.on && ((p.mask >> f) & 1u)) {
+        if (on) a = P.rec(s);
     }
     ~TimedScope() {
         // never throws: a failed record only loses this sample
-        if (P.on && P.used < P.pool.size() + 1) {
+        if (on && P.used < P.pool.size() + 1) {
             if (P.used == P.pool.size()) {
                 hipEvent_t e;
                 if (hipEventCreate(&e) != hipSuccess) return;
@@ -757,13 +761,13 @@ struct Solver {
                     // ring[lv % 4] its count.
                     int lv = 0;
                     while (nq > 0) {
-                        if (nq <= kSmallSwitch) {
+                        if (nq <= g_small_switch) {
                             {
                                 TIMED(GEOMST_K_EXPAND);
                                 RoundArgs r = args(beta2, fo, 0, po);
                                 k_level_small<D_><<<1, kSmallBlock, 0, s>>>(
                                     t, r, hdb, D.Q[0].as<PairRec>(), (u32)D.capQ[0], D.Q[1].as<PairRec>(),
-                                    (u32)D.capQ[1], lv & 1, ring, (u32)(lv % kQRing), kSmallMax, D.lstate.as<u32>());
+                                    (u32)D.capQ[1], lv & 1, ring, (u32)(lv % kQRing), g_small_max, D.lstate.as<u32>());
                                 LAUNCHCHK();
                             }
                             u32 st2[2];
@@ -1040,7 +1044,7 @@ void solve_dev(Device& D, hipStream_t s, const double* P, int n, int d, int minp
     g_stats.n = n;
     g_stats.d = d;
     g_stats.min_pts = minpts;
-    D.prof->begin(g_kernel_timing);
+    D.prof->begin(g_kernel_timing & g_kernel_timing_families);
     auto t0 = std::chrono::steady_clock::now();
     if (n == 1) {
         // one point: no edges; its core distance is 0 (minPts = 1)
@@ -1086,7 +1090,7 @@ void solve_batch_dev(Device& D, hipStream_t s, const double* P, int stride, cons
                      int64_t count, long long* edges, double* w, double* w2, double* cd, double* cd2) {
     g_cur_stream = s;
     memset(&g_stats, 0, sizeof(g_stats));
-    D.prof->begin(g_kernel_timing);
+    D.prof->begin(g_kernel_timing & g_kernel_timing_families);
     auto t0 = std::chrono::steady_clock::now();
     int64_t N = 0;
     int maxk = 0;
@@ -1745,6 +1749,12 @@ int geomst_set_option(const char* name, double value) {
         g_beta_growth = value;
         return GEOMST_OK;
     }
+    if (!strcmp(name, "small_level_switch") || !strcmp(name, "small_level_max")) {
+        if (!(value >= 0.0) || !(value <= 1048576.0) || value != (double)(u32)value) return GEOMST_EINVAL;
+        (name[12] == 's' ? g_small_switch : g_small_max) = (u32)value;
+        if (g_small_max < g_small_switch) g_small_max = g_small_switch;
+        return GEOMST_OK;
+    }
     if (!strcmp(name, "bccp_chunk")) {
         if (value == 0.0) value = kBigBDefault;
         if (!(value >= 64.0) || !(value <= 65536.0) || value != (double)(64 * (int)(value / 64.0))) return GEOMST_EINVAL;
@@ -1763,7 +1773,13 @@ int geomst_set_option(const char* name, double value) {
     }
     if (!strcmp(name, "kernel_timing")) {
         if (value != 0.0 && value != 1.0) return GEOMST_EINVAL;
-        g_kernel_timing = value != 0.0;
+        g_kernel_timing = value != 0.0 ? 0xffffffffu : 0u;
+        return GEOMST_OK;
+    }
+    if (!strcmp(name, "kernel_timing_families")) {
+        if (!(value >= 0.0) || !(value < (double)(1u << GEOMST_K_COUNT)) || value != (double)(u32)value)
+            return GEOMST_EINVAL;
+        g_kernel_timing_families = value == 0.0 ? 0xffffffffu : (u32)value;
         return GEOMST_OK;
     }
     return GEOMST_EINVAL;
