@@ -734,15 +734,15 @@ struct Solver {
                     TIMED(GEOMST_K_SPLIT);
                     RoundArgs r = args(beta2, fo, 0, po);
                     if (nF)
-                        k_split_frontier<<<std::min(blocks(nF, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
+                        k_split_frontier<<<std::min(blocks(nF, kSplitTile), (unsigned)kGrid), kBlock, 0, s>>>(
                             t, r, D.F[fc].as<PairRec>(), nF, ring);
                     LAUNCHCHK();
                     if (nP)
-                        k_split_pool<<<std::min(blocks(nP, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
+                        k_split_pool<<<std::min(blocks(nP, kSplitTile), (unsigned)kGrid), kBlock, 0, s>>>(
                             r, D.P[pc].list(), nP);
                     LAUNCHCHK();
                     if (epoch && nFF)
-                        k_split_far<D_><<<std::min(blocks(nFF, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
+                        k_split_far<D_><<<std::min(blocks(nFF, kSplitTile), (unsigned)kGrid), kBlock, 0, s>>>(
                             t, r, D.FF[ffc].as<PairRec>(), nFF, ring);
                     LAUNCHCHK();
                 }

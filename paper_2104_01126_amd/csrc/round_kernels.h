@@ -280,6 +280,8 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
 }
 
 constexpr int kBlock = 256;
+constexpr int kSplitItems = 8;  // list items per thread in the split kernels (one append per 2048)
+constexpr int kSplitTile = kSplitItems * kBlock;
 constexpr int kGrid = 1024;      // blocks of the grid-stride round kernels
 constexpr int kQRing = 4;        // level queue counters (ring)
 
@@ -322,26 +324,37 @@ __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
     u32* ctr[kLists] = {qcount, &r.cnt->c[C_F], nullptr, nullptr, nullptr, nullptr};
     double minf = inf;
-    for (u32 b0 = blockIdx.x * kBlock; b0 < nfin; b0 += gridDim.x * kBlock) {
-        u32 i = b0 + threadIdx.x;
-        bool have = i < nfin;
-        PairRec p;
-        p.a = p.b = 0;
-        p.lb2 = 0.0;
-        if (have) p = fin[i];
-        bool due = have && p.lb2 <= r.beta2;
-        bool wait = have && !due;
-        if (wait) minf = fmin(minf, p.lb2);
-        u32 cnt[kLists] = {(u32)due, (u32)wait, 0, 0, 0, 0};
+    for (u32 b0 = blockIdx.x * kSplitTile; b0 < nfin; b0 += gridDim.x * kSplitTile) {
+        PairRec p[kSplitItems];
+        u32 due = 0, wait = 0, nd = 0, nw = 0;
+#pragma unroll
+        for (int k = 0; k < kSplitItems; ++k) {
+            const u32 i = b0 + k * kBlock + threadIdx.x;
+            if (i < nfin) {
+                p[k] = fin[i];
+                const bool d = p[k].lb2 <= r.beta2;
+                due |= (u32)d << k;
+                wait |= (u32)!d << k;
+                nd += d;
+                nw += !d;
+                if (!d) minf = fmin(minf, p[k].lb2);
+            }
+        }
+        u32 cnt[kLists] = {nd, nw, 0, 0, 0, 0};
         u32 off[kLists];
         block_alloc(S, cnt, ctr, off);
-        if (due) {
-            if (off[0] < r.cap_q) r.q[off[0]] = p;
-            else flag_overflow(r.cnt);
-        }
-        if (wait) {
-            if (off[1] < r.cap_f) r.fout[off[1]] = p;
-            else flag_overflow(r.cnt);
+#pragma unroll
+        for (int k = 0; k < kSplitItems; ++k) {
+            if ((due >> k) & 1u) {
+                if (off[0] < r.cap_q) r.q[off[0]] = p[k];
+                else flag_overflow(r.cnt);
+                ++off[0];
+            }
+            if ((wait >> k) & 1u) {
+                if (off[1] < r.cap_f) r.fout[off[1]] = p[k];
+                else flag_overflow(r.cnt);
+                ++off[1];
+            }
         }
     }
     block_atomic_min(minf, &r.cnt->m[M_F], shm);
@@ -358,33 +371,46 @@ __global__ void __launch_bounds__(kBlock) k_split_far(TreeView t, RoundArgs r, c
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
     u32* ctr[kLists] = {qcount, &r.cnt->c[C_F], &r.cnt->c[C_FAR], nullptr, nullptr, nullptr};
     double minf = inf, minfar = inf;
-    for (u32 b0 = blockIdx.x * kBlock; b0 < nfin; b0 += gridDim.x * kBlock) {
-        u32 i = b0 + threadIdx.x;
-        bool have = i < nfin;
-        PairRec p;
-        p.a = p.b = 0;
-        p.lb2 = 0.0;
-        if (have) p = fin[i];
-        bool keep = have && p.lb2 < __longlong_as_double(0x7ff0000000000000ll) && !connected<D>(t, p.a, p.b);
-        bool due = keep && p.lb2 <= r.beta2;
-        bool near = keep && !due && p.lb2 <= r.t_near;
-        bool far = keep && !due && !near;
-        if (near) minf = fmin(minf, p.lb2);
-        if (far) minfar = fmin(minfar, p.lb2);
-        u32 cnt[kLists] = {(u32)due, (u32)near, (u32)far, 0, 0, 0};
+    for (u32 b0 = blockIdx.x * kSplitTile; b0 < nfin; b0 += gridDim.x * kSplitTile) {
+        PairRec p[kSplitItems];
+        u32 cls = 0;  // 2 bits per item: 1 due, 2 near, 3 far, 0 dropped
+        u32 nd = 0, nn = 0, nf = 0;
+#pragma unroll
+        for (int k = 0; k < kSplitItems; ++k) {
+            const u32 i = b0 + k * kBlock + threadIdx.x;
+            if (i < nfin) {
+                p[k] = fin[i];
+                const bool keep = p[k].lb2 < inf && !connected<D>(t, p[k].a, p[k].b);
+                const bool due = keep && p[k].lb2 <= r.beta2;
+                const bool near = keep && !due && p[k].lb2 <= r.t_near;
+                const bool far = keep && !due && !near;
+                if (near) minf = fmin(minf, p[k].lb2);
+                if (far) minfar = fmin(minfar, p[k].lb2);
+                cls |= (due ? 1u : near ? 2u : far ? 3u : 0u) << (2 * k);
+                nd += due;
+                nn += near;
+                nf += far;
+            }
+        }
+        u32 cnt[kLists] = {nd, nn, nf, 0, 0, 0};
         u32 off[kLists];
         block_alloc(S, cnt, ctr, off);
-        if (due) {
-            if (off[0] < r.cap_q) r.q[off[0]] = p;
-            else flag_overflow(r.cnt);
-        }
-        if (near) {
-            if (off[1] < r.cap_f) r.fout[off[1]] = p;
-            else flag_overflow(r.cnt);
-        }
-        if (far) {
-            if (off[2] < r.cap_far) r.ffar[off[2]] = p;
-            else flag_overflow(r.cnt);
+#pragma unroll
+        for (int k = 0; k < kSplitItems; ++k) {
+            const u32 c = (cls >> (2 * k)) & 3u;
+            if (c == 1u) {
+                if (off[0] < r.cap_q) r.q[off[0]] = p[k];
+                else flag_overflow(r.cnt);
+                ++off[0];
+            } else if (c == 2u) {
+                if (off[1] < r.cap_f) r.fout[off[1]] = p[k];
+                else flag_overflow(r.cnt);
+                ++off[1];
+            } else if (c == 3u) {
+                if (off[2] < r.cap_far) r.ffar[off[2]] = p[k];
+                else flag_overflow(r.cnt);
+                ++off[2];
+            }
         }
     }
     block_atomic_min(minf, &r.cnt->m[M_F], shm);
@@ -959,34 +985,44 @@ __global__ void __launch_bounds__(kBlock) k_split_pool(RoundArgs r, EdgeList pin
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
     u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], nullptr, nullptr, nullptr, nullptr};
     double minp = inf;
-    for (u32 b0 = blockIdx.x * kBlock; b0 < npin; b0 += gridDim.x * kBlock) {
-        u32 i = b0 + threadIdx.x;
-        bool have = i < npin;
-        double w2 = 0.0, e2 = 0.0;
-        u64 ids = 0, pos = 0;
-        bool keep = false;
-        if (have) {
-            pos = pin.pos[i];
-            keep = r.uf[(u32)(pos >> 32)] != r.uf[(u32)pos];
-            if (keep) {
-                w2 = pin.w2[i];
-                e2 = pin.e2[i];
-                ids = pin.ids[i];
+    for (u32 b0 = blockIdx.x * kSplitTile; b0 < npin; b0 += gridDim.x * kSplitTile) {
+        u64 pos[kSplitItems];
+        u32 tc = 0, tp = 0, nc = 0, np = 0;
+#pragma unroll
+        for (int k = 0; k < kSplitItems; ++k) {
+            const u32 i = b0 + k * kBlock + threadIdx.x;
+            pos[k] = 0;
+            if (i < npin) {
+                pos[k] = pin.pos[i];
+                if (r.uf[(u32)(pos[k] >> 32)] != r.uf[(u32)pos[k]]) {
+                    const double w2 = pin.w2[i];
+                    const bool c = w2 <= r.beta2;
+                    tc |= (u32)c << k;
+                    tp |= (u32)!c << k;
+                    nc += c;
+                    np += !c;
+                    if (!c) minp = fmin(minp, w2);
+                }
             }
         }
-        bool to_c = keep && w2 <= r.beta2;
-        bool to_p = keep && !to_c;
-        if (to_p) minp = fmin(minp, w2);
         u32 off[kLists];
-        u32 cnt[kLists] = {(u32)to_c, (u32)to_p, 0, 0, 0, 0};
+        u32 cnt[kLists] = {nc, np, 0, 0, 0, 0};
         block_alloc(S, cnt, ctr, off);
-        if (to_c) {
-            if (off[0] < r.cap_c) put_edge_raw(r.c, off[0], w2, e2, ids, pos);
-            else flag_overflow(r.cnt);
-        }
-        if (to_p) {
-            if (off[1] < r.cap_p) put_edge_raw(r.pout, off[1], w2, e2, ids, pos);
-            else flag_overflow(r.cnt);
+#pragma unroll
+        for (int k = 0; k < kSplitItems; ++k) {
+            if (!(((tc | tp) >> k) & 1u)) continue;
+            const u32 i = b0 + k * kBlock + threadIdx.x;
+            const double w2 = pin.w2[i], e2 = pin.e2[i];
+            const u64 ids = pin.ids[i];
+            if ((tc >> k) & 1u) {
+                if (off[0] < r.cap_c) put_edge_raw(r.c, off[0], w2, e2, ids, pos[k]);
+                else flag_overflow(r.cnt);
+                ++off[0];
+            } else {
+                if (off[1] < r.cap_p) put_edge_raw(r.pout, off[1], w2, e2, ids, pos[k]);
+                else flag_overflow(r.cnt);
+                ++off[1];
+            }
         }
     }
     block_atomic_min(minp, &r.cnt->m[M_P], shm);
