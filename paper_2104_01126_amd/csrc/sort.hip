@@ -167,16 +167,86 @@ __global__ void __launch_bounds__(kThreads) k_radix_scatter(K keys, M mv, size_t
     }
 }
 
-struct MovePairs {
-    const u64* ki;
-    const u32* vi;
-    u64* ko;
-    u32* vo;
-    __device__ __forceinline__ void move(size_t e, u32 pos) const {
-        ko[pos] = ki[e];
-        vo[pos] = vi[e];
+// Key-value scatter through LDS: the tile is first ranked into digit order in
+// LDS (stable, as above), then written out so that consecutive threads write
+// consecutive slots of one digit's run: coalesced stores instead of one
+// scattered store per element.
+__global__ void __launch_bounds__(kThreads) k_radix_scatter_lds(const u64* ki, const u32* vi, u64* ko, u32* vo,
+                                                                size_t count, int shift, const u32* offs,
+                                                                u32 nblocks) {
+    __shared__ u64 sk[kTile];
+    __shared__ u32 sv[kTile];
+    __shared__ u32 lstart[256], gbase[256], run[256];
+    __shared__ u32 wcnt[kWaves][256];
+    const int t = threadIdx.x;
+    const int w = t / kWave;
+    const size_t base = (size_t)blockIdx.x * kTile;
+    const u32 ntile = (u32)((count - base) < (size_t)kTile ? (count - base) : (size_t)kTile);
+    u64 key[kItems];
+    u32 val[kItems], dg[kItems];
+    run[t] = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) wcnt[i][t] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const u32 le = (u32)it * kThreads + t;
+        key[it] = 0;
+        val[it] = 0;
+        if (le < ntile) {
+            key[it] = ki[base + le];
+            val[it] = vi[base + le];
+            atomicAdd(&run[(u32)(key[it] >> shift) & 255u], 1u);
+        }
+        dg[it] = (u32)(key[it] >> shift) & 255u;
     }
-};
+    __syncthreads();
+    u32 tot;
+    const u32 ex = block_excl_scan(run[t], &tot);
+    lstart[t] = ex;
+    run[t] = ex;
+    gbase[t] = offs[(size_t)t * nblocks + blockIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const bool valid = (u32)it * kThreads + t < ntile;
+        const u32 d = dg[it];
+        const u64 vmask = __ballot(valid);
+        u64 peers = valid ? vmask : ~vmask;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const u64 bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const u32 rank = (u32)__popcll(peers & lanemask_lt());
+        if (valid && rank == 0) wcnt[w][d] = (u32)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            u32 pos = run[d] + rank;
+            for (int i = 0; i < w; ++i) pos += wcnt[i][d];
+            sk[pos] = key[it];
+            sv[pos] = val[it];
+        }
+        __syncthreads();
+        u32 add = 0;
+#pragma unroll
+        for (int i = 0; i < kWaves; ++i) {
+            add += wcnt[i][t];
+            wcnt[i][t] = 0;
+        }
+        run[t] += add;
+        __syncthreads();
+    }
+    for (u32 j = t; j < ntile; j += kThreads) {
+        const u64 k = sk[j];
+        const u32 d = (u32)(k >> shift) & 255u;
+        const size_t gp = (size_t)gbase[d] + (j - lstart[d]);
+        ko[gp] = k;
+        vo[gp] = sv[j];
+    }
+}
+
 struct MoveIndex {
     const u32* ii;
     u32* io;
@@ -223,8 +293,7 @@ int radix_sort_pairs(u64* key, u32* val, u64* key2, u32* val2, size_t count, int
         PairKeys K{ki};
         k_radix_hist<<<nb, kThreads, 0, s>>>(K, count, shift, hist, nb);
         scan_exclusive_u32(hist, hist, (size_t)nb * 256, stemp, s);
-        MovePairs M{ki, vi, ko, vo};
-        k_radix_scatter<<<nb, kThreads, 0, s>>>(K, M, count, shift, hist, nb);
+        k_radix_scatter_lds<<<nb, kThreads, 0, s>>>(ki, vi, ko, vo, count, shift, hist, nb);
         flip ^= 1;
     }
     return flip;
