@@ -473,18 +473,25 @@ struct Solver {
     // Node boxes (and, with cd2, core-distance ranges): block-local phase,
     // then one workgroup for the nodes spanning blocks.
     void bounds(bool cd) {
-        D.btop.ensure((size_t)n * 4 + 64);
-        D.flags.ensure((size_t)n * 4 + 8);
-        u32* ntop = D.flags.as<u32>() + n;  // counter after the arrival flags
-        HIPCHK(hipMemsetAsync(D.flags.p, 0, ((size_t)n + 1) * 4, s));
+        const u32 nsb = blocks(n, kBoundsSpan);
+        D.btop.ensure(((size_t)nsb * kBoundsSpanCap + (size_t)n + 64) * 4);
+        D.flags.ensure(((size_t)n + nsb + 2) * 4);
+        u32* ntop = D.flags.as<u32>() + n;  // per super-block counters after the arrival flags
+        u32* ntop2 = ntop + nsb;
+        u32* top2 = D.btop.as<u32>() + (size_t)nsb * kBoundsSpanCap;
+        HIPCHK(hipMemsetAsync(D.flags.p, 0, ((size_t)n + nsb + 1) * 4, s));
         if (cd) D.cdr.ensure((size_t)(2 * n - 1) * 16);
         k_bounds_local<D_><<<blocks(n, kBoundsBlock), kBoundsBlock, 0, s>>>(
             n, D.X.as<double>(), cd ? D.cd2.as<double>() : nullptr, D.npar.as<int>(), D.nodes.as<NodeRec<D_>>(),
             cd ? D.cdr.as<double2>() : nullptr, cd ? 0 : 1, D.btop.as<u32>(), ntop);
         LAUNCHCHK();
+        k_bounds_top<D_><<<nsb, kBoundsTop, 0, s>>>(n, D.npar.as<int>(), D.nodes.as<NodeRec<D_>>(),
+                                                    cd ? D.cdr.as<double2>() : nullptr, cd ? 0 : 1, cd ? 1 : 0,
+                                                    D.btop.as<u32>(), ntop, D.flags.as<u32>(), top2, ntop2);
+        LAUNCHCHK();
         k_bounds_top<D_><<<1, kBoundsTop, 0, s>>>(n, D.npar.as<int>(), D.nodes.as<NodeRec<D_>>(),
-                                                  cd ? D.cdr.as<double2>() : nullptr, cd ? 0 : 1, cd ? 1 : 0,
-                                                  D.btop.as<u32>(), ntop, D.flags.as<u32>());
+                                                  cd ? D.cdr.as<double2>() : nullptr, cd ? 0 : 1, cd ? 1 : 0, top2,
+                                                  ntop2, D.flags.as<u32>(), nullptr, nullptr);
         LAUNCHCHK();
     }
 

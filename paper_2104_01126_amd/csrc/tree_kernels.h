@@ -344,12 +344,17 @@ __global__ void k_karras(const u64* k, int n, int L, NodeRec<D>* nodes, int* par
 // children to arrive.  Phase 1: a block owns 1024 consecutive leaves and
 // merges every node whose range lies inside them through LDS (arrival
 // counters and boxes; workgroup-scope ordering only).  A thread whose climb
-// reaches a node spanning several blocks records the child it came from.
-// Phase 2: one workgroup finishes the spanning nodes (about 2n/1024 of them)
-// starting from those children, again with workgroup-scope ordering only,
-// since every arrival counter and record it touches is its own.
+// reaches a node spanning several blocks records the child it came from, in
+// the list of its super-block (kBoundsSpan leaves).  Phase 2: one workgroup
+// per super-block finishes the spanning nodes inside it, starting from those
+// children, and records the children of nodes that span super-blocks; then
+// one workgroup finishes those.  Every arrival counter and record a
+// workgroup touches is its own, so workgroup-scope ordering suffices
+// throughout.
 constexpr int kBoundsBlock = 1024;
-constexpr int kBoundsTop = 1024;  // threads of the phase-2 workgroup
+constexpr int kBoundsTop = 1024;            // threads of a phase-2 workgroup
+constexpr int kBoundsSpan = 64 * 1024;      // leaves per phase-2 super-block
+constexpr int kBoundsSpanCap = 2 * kBoundsSpan;  // list slots per super-block
 
 template <int D>
 __device__ __forceinline__ void write_box(NodeRec<D>& V, const double* lo, const double* hi) {
@@ -364,6 +369,7 @@ template <int D>
 __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const double* X, const double* cd2,
                                                                const int* parent, NodeRec<D>* nodes, double2* cdr,
                                                                int geometry, u32* top, u32* ntop) {
+    // top / ntop: per super-block lists of kBoundsSpanCap slots and counters
     __shared__ u32 lflag[kBoundsBlock];
     __shared__ double slo[kBoundsBlock][D], shi[kBoundsBlock][D];
     __shared__ double2 scd[kBoundsBlock];
@@ -394,9 +400,10 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
         int f = V.first, c = V.count;
         if (!(f >= base && f + c <= end)) {
             // spanning node: hand the climb over to phase 2
+            const u32 sb = (u32)base / kBoundsSpan;
             __threadfence();
-            u32 s = atomicAdd(ntop, 1u);
-            top[s] = (u32)child;
+            u32 s = atomicAdd(&ntop[sb], 1u);
+            top[(size_t)sb * kBoundsSpanCap + s] = (u32)child;
             return;
         }
         __threadfence_block();
@@ -436,16 +443,29 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
     }
 }
 
-// Phase 2 (one workgroup): climb from the recorded children through the
-// spanning nodes; gflags holds one arrival counter per internal node.
+// Phase 2: climb from the recorded children through the spanning nodes;
+// gflags holds one arrival counter per internal node.  With out != null,
+// workgroup g takes list g (top + g * kBoundsSpanCap, count ntop[g]) and
+// stops at nodes spanning super-blocks, recording the child in out;
+// otherwise one workgroup takes the single list and climbs to the root.
 template <int D>
 __global__ void __launch_bounds__(kBoundsTop) k_bounds_top(int n, const int* parent, NodeRec<D>* nodes, double2* cdr,
                                                            int geometry, int hdb, const u32* top, const u32* ntop,
-                                                           u32* gflags) {
-    const u32 m = *ntop;
+                                                           u32* gflags, u32* out, u32* nout) {
+    const u32 m = ntop[blockIdx.x];
+    const u32* list = top + (size_t)blockIdx.x * kBoundsSpanCap;
     for (u32 i = threadIdx.x; i < m; i += blockDim.x) {
-        int v = parent[top[i]];
+        int c = (int)list[i];
+        int v = parent[c];
         while (v >= 0) {
+            if (out) {
+                const int f = nodes[v].first, cnt = nodes[v].count;
+                if (f / kBoundsSpan != (f + cnt - 1) / kBoundsSpan) {
+                    u32 s = atomicAdd(nout, 1u);
+                    out[s] = (u32)c;
+                    break;
+                }
+            }
             __threadfence_block();
             if (atomicAdd(&gflags[v], 1u) == 0) break;
             __threadfence_block();
@@ -467,6 +487,7 @@ __global__ void __launch_bounds__(kBoundsTop) k_bounds_top(int n, const int* par
                 const volatile double2* cb = cdr + ch.y;
                 cdr[v] = make_double2(fmin(ca->x, cb->x), fmax(ca->y, cb->y));
             }
+            c = v;
             v = parent[v];
         }
     }
