@@ -154,7 +154,7 @@ struct Device {
     // input staging (host API)
     DBuf pin, eout, wout, cdout;
     // tree
-    DBuf keysA, keysB, gflag, gincl, gid, gstart, g64, gbox, hflag;
+    DBuf keysA, keysB, gflag, gincl, gid, gstart, gbox, hflag;
     DBuf part, bbox, key, val, key2, val2, stemp, X, orig, cd2, nodes, npar, flags, cdr, btop;
     // union-find / component refresh
     DBuf uf, best, bnd, incl;
@@ -400,7 +400,6 @@ struct Solver {
         D.gincl.ensure((size_t)n * 4);
         D.gid.ensure((size_t)n * 4);
         D.gstart.ensure((size_t)n * 4);
-        D.g64.ensure((size_t)n * 8);
         D.perm[0].ensure((size_t)n * 4);
         D.perm[1].ensure((size_t)n * 4);
         D.hflag.ensure(16);
@@ -430,16 +429,27 @@ struct Solver {
             k_morton_level<D_><<<blocks(n, 256), 256, 0, s>>>(P, vala, n, D.gid.as<u32>(), D.gstart.as<u32>(),
                                                                ngroups, D.gbox.as<double>(), kl);
             LAUNCHCHK();
-            // stable order by (group, new word)
+            // stable order by (group, new word): positions sorted by the new
+            // word, then stably by the group id gathered through that order
+            // (key-value sorts on contiguous keys)
             u32* pa = D.perm[0].as<u32>();
             u32* pb = D.perm[1].as<u32>();
+            u64* ka = D.key.as<u64>();
+            u64* kb = D.key2.as<u64>();
             k_iota<<<blocks(n, 256), 256, 0, s>>>(pa, n);
             LAUNCHCHK();
-            if (radix_sort_index(kl, pa, pb, n, mb * D_, D.stemp.p, s)) std::swap(pa, pb);
+            HIPCHK(hipMemcpyAsync(ka, kl, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+            if (radix_sort_pairs(ka, pa, kb, pb, n, mb * D_, D.stemp.p, s)) {
+                std::swap(ka, kb);
+                std::swap(pa, pb);
+            }
             LAUNCHCHK();
-            k_u32_to_u64<<<blocks(n, 256), 256, 0, s>>>(D.gid.as<u32>(), n, D.g64.as<u64>());
+            k_gather_u32_u64<<<blocks(n, 256), 256, 0, s>>>(D.gid.as<u32>(), pa, n, ka);
             LAUNCHCHK();
-            if (radix_sort_index(D.g64.as<u64>(), pa, pb, n, id_bits((int)ngroups), D.stemp.p, s)) std::swap(pa, pb);
+            if (radix_sort_pairs(ka, pa, kb, pb, n, id_bits((int)ngroups), D.stemp.p, s)) {
+                std::swap(ka, kb);
+                std::swap(pa, pb);
+            }
             LAUNCHCHK();
             g_stats.sort_elems += (int64_t)n * ((mb * D_ + 7) / 8 + (id_bits((int)ngroups) + 7) / 8);
             k_apply_perm<<<blocks(n, 256), 256, 0, s>>>(pa, n, L + 1, vala, valb, keys, keysB);

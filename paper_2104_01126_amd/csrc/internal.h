@@ -23,10 +23,5 @@ void scan_inclusive_u32(const u32* in, u32* out, size_t count, void* temp, hipSt
 int radix_sort_pairs(u64* key, u32* val, u64* key2, u32* val2, size_t count, int bits, void* temp,
                      hipStream_t s);
 
-// One stable LSD pass group: reorders the permutation idx by bits [0, bits)
-// of w[idx[i]].  Ping-pongs between idx and idx2; returns 1 when the result
-// ends in idx2.
-int radix_sort_index(const u64* w, u32* idx, u32* idx2, size_t count, int bits, void* temp,
-                     hipStream_t s);
 
 }  // namespace geomst

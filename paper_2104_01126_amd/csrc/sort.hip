@@ -4,7 +4,8 @@
 // an exclusive scan of the digit-major histogram table, a stable scatter).
 // Stability inside a tile comes from processing the tile in (iteration,
 // wave, lane) order, which is the element order, and ranking equal digits
-// inside a wave with ballots.
+// inside a wave with ballots; the scatter stages the ranked tile in LDS and
+// writes each digit's run with coalesced stores.
 #include <hip/hip_runtime.h>
 #include "internal.h"
 #include "common.h"
@@ -101,12 +102,6 @@ struct PairKeys {
     const u64* key;
     __device__ __forceinline__ u32 digit(size_t e, int shift) const { return (u32)(key[e] >> shift) & 255u; }
 };
-struct IndexKeys {
-    const u64* w;
-    const u32* idx;
-    __device__ __forceinline__ u32 digit(size_t e, int shift) const { return (u32)(w[idx[e]] >> shift) & 255u; }
-};
-
 template <class K>
 __global__ void __launch_bounds__(kThreads) k_radix_hist(K keys, size_t count, int shift, u32* hist, u32 nblocks) {
     __shared__ u32 h[256];
@@ -119,52 +114,6 @@ __global__ void __launch_bounds__(kThreads) k_radix_hist(K keys, size_t count, i
     }
     __syncthreads();
     hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
-}
-
-// Moves element e to its stable position.  MoveKV supplies the payload copy.
-template <class K, class M>
-__global__ void __launch_bounds__(kThreads) k_radix_scatter(K keys, M mv, size_t count, int shift,
-                                                            const u32* offs, u32 nblocks) {
-    __shared__ u32 run[256];
-    __shared__ u32 wcnt[kWaves][256];
-    int t = threadIdx.x;
-    int w = t / kWave;
-    run[t] = offs[(size_t)t * nblocks + blockIdx.x];
-#pragma unroll
-    for (int i = 0; i < kWaves; ++i) wcnt[i][t] = 0;
-    __syncthreads();
-    size_t base = (size_t)blockIdx.x * kTile;
-    for (int it = 0; it < kItems; ++it) {
-        size_t e = base + (size_t)it * kThreads + t;
-        bool valid = e < count;
-        u32 dg = valid ? keys.digit(e, shift) : 0u;
-        u64 vmask = __ballot(valid);
-        u64 peers = valid ? vmask : ~vmask;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            bool bit = (dg >> b) & 1u;
-            u64 bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
-        }
-        u32 rank = (u32)__popcll(peers & lanemask_lt());
-        if (valid && rank == 0) wcnt[w][dg] = (u32)__popcll(peers);
-        __syncthreads();
-        u32 pos = 0;
-        if (valid) {
-            pos = run[dg] + rank;
-            for (int i = 0; i < w; ++i) pos += wcnt[i][dg];
-        }
-        __syncthreads();
-        u32 add = 0;
-#pragma unroll
-        for (int i = 0; i < kWaves; ++i) {
-            add += wcnt[i][t];
-            wcnt[i][t] = 0;
-        }
-        run[t] += add;
-        if (valid) mv.move(e, pos);
-        __syncthreads();
-    }
 }
 
 // Key-value scatter through LDS: the tile is first ranked into digit order in
@@ -247,12 +196,6 @@ __global__ void __launch_bounds__(kThreads) k_radix_scatter_lds(const u64* ki, c
     }
 }
 
-struct MoveIndex {
-    const u32* ii;
-    u32* io;
-    __device__ __forceinline__ void move(size_t e, u32 pos) const { io[pos] = ii[e]; }
-};
-
 }  // namespace
 
 size_t scan_temp_bytes(size_t count) {
@@ -294,25 +237,6 @@ int radix_sort_pairs(u64* key, u32* val, u64* key2, u32* val2, size_t count, int
         k_radix_hist<<<nb, kThreads, 0, s>>>(K, count, shift, hist, nb);
         scan_exclusive_u32(hist, hist, (size_t)nb * 256, stemp, s);
         k_radix_scatter_lds<<<nb, kThreads, 0, s>>>(ki, vi, ko, vo, count, shift, hist, nb);
-        flip ^= 1;
-    }
-    return flip;
-}
-
-int radix_sort_index(const u64* w, u32* idx, u32* idx2, size_t count, int bits, void* temp, hipStream_t s) {
-    if (count <= 1 || bits <= 0) return 0;
-    u32 nb = (u32)cdiv(count, kTile);
-    u32* hist = (u32*)temp;
-    void* stemp = (char*)temp + cdiv((size_t)nb * 256, 64) * 64 * sizeof(u32);
-    int flip = 0;
-    for (int shift = 0; shift < bits; shift += 8) {
-        u32* ii = flip ? idx2 : idx;
-        u32* io = flip ? idx : idx2;
-        IndexKeys K{w, ii};
-        k_radix_hist<<<nb, kThreads, 0, s>>>(K, count, shift, hist, nb);
-        scan_exclusive_u32(hist, hist, (size_t)nb * 256, stemp, s);
-        MoveIndex M{ii, io};
-        k_radix_scatter<<<nb, kThreads, 0, s>>>(K, M, count, shift, hist, nb);
         flip ^= 1;
     }
     return flip;

@@ -271,9 +271,10 @@ __global__ void k_morton_level(const double* P, const u32* val, int n, const u32
     key[i] = c;
 }
 
-__global__ void k_u32_to_u64(const u32* a, int n, u64* b) {
+// b[i] = a[perm[i]] widened to 64 bits (the sort key of a gathered word).
+__global__ void k_gather_u32_u64(const u32* a, const u32* perm, int n, u64* b) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = a[i];
+    if (i < n) b[i] = a[perm[i]];
 }
 
 // Apply a permutation of sorted positions to the point ids and key words.
