@@ -35,11 +35,11 @@ double g_beta_growth = 0.0;  // 0: 2 for EMST, sqrt(2) for HDBSCAN*
 double g_separation = 2.0;   // s of the sphere separation test
 int g_bccp_chunk = kBigBDefault;  // B points per large-pair BCCP task
 double g_capacity_scale = 1.0;
-constexpr int kMaxKeyLevels = 6;
+constexpr int kMaxKeyLevels = 6;  // Morton key words per point (see k_morton_level)
 constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
 u32 g_small_switch = 2048;  // queues up to this size go to the one-workgroup level kernel
 u32 g_small_max = 4096;     // ... which keeps going while a level stays this small
-constexpr int kBoruvkaBatch = 4;  // Boruvka steps launched between host checks  // Morton key words per point (see k_morton_level)
+constexpr int kBoruvkaBatch = 4;  // Boruvka steps launched between host checks
 const bool g_trace = getenv("GEOMST_TRACE") != nullptr;
 
 struct Fail {
@@ -538,6 +538,7 @@ struct Solver {
     }
 
     double t_near = 0.0;  // edge of the near frontier band
+    u32 bstamp = 0;       // Boruvka step stamp (decreases by one per step)
     int ffo = 0;          // far list receiving appends this round
 
     // Diagnostic (GEOMST_TRACE): size classes of the round's large pairs and
@@ -653,13 +654,14 @@ struct Solver {
 
         // union-find and node components
         D.uf.ensure((size_t)n * 4);
-        D.best.ensure((size_t)n * 4);
+        D.best.ensure((size_t)n * 8);
         D.bnd.ensure((size_t)n * 4);
         D.incl.ensure((size_t)n * 4);
         D.stemp.ensure(std::max(radix_temp_bytes(n), scan_temp_bytes(n)));
         k_iota<<<blocks(n, 256), 256, 0, s>>>(D.uf.as<u32>(), n);
         LAUNCHCHK();
-        HIPCHK(hipMemsetAsync(D.best.p, 0xff, (size_t)n * 4, s));
+        HIPCHK(hipMemsetAsync(D.best.p, 0xff, (size_t)n * 8, s));
+        bstamp = 0xffffffffu;
         refresh_components();
 
         // lists
@@ -903,18 +905,15 @@ struct Solver {
                         TIMED(GEOMST_K_KRUSKAL);
                         u32* na_in = D.nalive.as<u32>() + ac;
                         u32* na_out = D.nalive.as<u32>() + (ac ^ 1);
-                        k_set_u32<<<1, 1, 0, s>>>(na_out, 0);
-                        LAUNCHCHK();
+                        const u32 stamp = --bstamp;  // decreasing: this step's keys beat older ones
                         k_bor_pick<<<gk, kBlock, 0, s>>>(D.alive[ac].as<u32>(), na_in, m, perm, L, D.uf.as<u32>(),
-                                                        D.best.as<u32>(), D.ru.as<u32>(), D.rv.as<u32>(),
-                                                        D.cnt.as<Counters>());
+                                                        D.best.as<u64>(), stamp, D.ru.as<u32>(), D.rv.as<u32>(),
+                                                        na_out, D.cnt.as<Counters>());
                         LAUNCHCHK();
                         k_bor_hook<<<gk, kBlock, 0, s>>>(D.alive[ac].as<u32>(), na_in, m, perm, L, D.uf.as<u32>(),
-                                                        D.best.as<u32>(), D.ru.as<u32>(), D.rv.as<u32>(),
+                                                        D.best.as<u64>(), stamp, D.ru.as<u32>(), D.rv.as<u32>(),
                                                         D.alive[ac ^ 1].as<u32>(), na_out, D.OUT.list(),
                                                         (u32)D.OUT.cap, D.cnt.as<Counters>());
-                        LAUNCHCHK();
-                        k_bor_reset<<<gk, kBlock, 0, s>>>(na_in, m, D.ru.as<u32>(), D.rv.as<u32>(), D.best.as<u32>());
                         LAUNCHCHK();
                         ac ^= 1;
                     }

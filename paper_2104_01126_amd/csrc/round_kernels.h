@@ -1142,11 +1142,16 @@ __device__ __forceinline__ u32 uf_find(u32* parent, u32 x, Counters* cnt) {
 // Boruvka step on the committed edges in key-rank order: every component
 // picks its lightest incident edge (atomic minimum of the rank); all picked
 // edges are tree edges by the cut property; components hook along them.
+// best[c] holds (stamp << 32 | rank) of component c's lightest edge in the
+// step with that stamp; stamps decrease step by step, so a new step's keys
+// win over stale ones without clearing the array between steps.
 __global__ void k_bor_pick(const u32* alive, const u32* nalive_p, u32 cap, const u32* perm, const EdgeList L,
-                           u32* parent, u32* best, u32* ru, u32* rv, Counters* cnt) {
+                           u32* parent, u64* best, u32 stamp, u32* ru, u32* rv, u32* nalive_next, Counters* cnt) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nalive_next = 0;  // the hook step appends after this kernel
     const u32 na = min(*nalive_p, cap);
     for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < na; s += gridDim.x * blockDim.x) {
     u32 rank = alive[s];
+    const u64 key = ((u64)stamp << 32) | rank;
     u64 pos = L.pos[perm[rank]];
     u32 a = uf_find(parent, (u32)(pos >> 32), cnt);
     u32 b = uf_find(parent, (u32)pos, cnt);
@@ -1157,15 +1162,15 @@ __global__ void k_bor_pick(const u32* alive, const u32* nalive_p, u32 cap, const
     ru[s] = a;
     rv[s] = b;
     // read first: most candidates already lose to a smaller rank
-    if (rank < best[a]) atomicMin(&best[a], rank);
-    if (rank < best[b]) atomicMin(&best[b], rank);
+    if (key < best[a]) atomicMin((unsigned long long*)&best[a], (unsigned long long)key);
+    if (key < best[b]) atomicMin((unsigned long long*)&best[b], (unsigned long long)key);
     }
 }
 
 __global__ void __launch_bounds__(kBlock) k_bor_hook(const u32* alive, const u32* nalive_p, u32 cap, const u32* perm,
-                                                     const EdgeList L, u32* parent, const u32* best, const u32* ru,
-                                                     const u32* rv, u32* alive_next, u32* nalive_next, EdgeList out,
-                                                     u32 cap_out, Counters* cnt) {
+                                                     const EdgeList L, u32* parent, const u64* best, u32 stamp,
+                                                     const u32* ru, const u32* rv, u32* alive_next, u32* nalive_next,
+                                                     EdgeList out, u32 cap_out, Counters* cnt) {
     __shared__ BlockAlloc S;
     const u32 na = min(*nalive_p, cap);
     u32* ctr[kLists] = {&cnt->c[C_OUT], nalive_next, nullptr, nullptr, nullptr, nullptr};
@@ -1179,7 +1184,8 @@ __global__ void __launch_bounds__(kBlock) k_bor_hook(const u32* alive, const u32
         if (live) {
             u32 b = rv[s];
             rank = alive[s];
-            bool pa = best[a] == rank, pb = best[b] == rank;
+            const u64 key = ((u64)stamp << 32) | rank;
+            bool pa = best[a] == key, pb = best[b] == key;
             sel = pa || pb;
             keep = !sel;
             if (sel) {
@@ -1202,16 +1208,6 @@ __global__ void __launch_bounds__(kBlock) k_bor_hook(const u32* alive, const u32
             else flag_overflow(cnt);
         }
         if (keep && off[1] < cap) alive_next[off[1]] = rank;
-    }
-}
-
-__global__ void k_bor_reset(const u32* nalive_p, u32 cap, const u32* ru, const u32* rv, u32* best) {
-    const u32 na = min(*nalive_p, cap);
-    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < na; s += gridDim.x * blockDim.x) {
-        u32 a = ru[s];
-        if (a == kNone) continue;
-        best[a] = kNone;
-        best[rv[s]] = kNone;
     }
 }
 
