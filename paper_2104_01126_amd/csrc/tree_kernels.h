@@ -501,6 +501,7 @@ __global__ void __launch_bounds__(kBoundsTop) k_bounds_top(int n, const int* par
 // scanned by all lanes (each lane against every point of the node).  The
 // per-lane k smallest values are kept sorted in registers.
 constexpr int kKnnLeaf = 32;
+constexpr int kKnnSeed = 64;  // sorted neighbours on each side of a wave's queries scanned first
 constexpr int kKnnStack = 192;
 
 template <int KMAX>
@@ -564,6 +565,20 @@ __global__ void __launch_bounds__(64) k_knn(TreeView t, int kk_all, const u32* p
 #pragma unroll
     for (int s = 0; s < KMAX; ++s) top[s] = (s < KMAX - kk) ? -inf : inf;
     double kth = inf;
+    // Seed the k smallest with the sorted neighbourhood of the wave's 64
+    // queries (Morton order keeps it close), so that the walk from the root
+    // prunes with a small k-th distance from its first levels; the walk then
+    // skips the positions scanned here.
+    const int w0 = blockIdx.x * kWave;
+    const int pre_lo = max(max(w0 - kKnnSeed, 0), lo_r);
+    const int pre_hi = min(min(w0 + kWave + kKnnSeed, n), hi_r);
+    for (int j = pre_lo; j < pre_hi; ++j) {
+        double dd = sqdist<D>(q, t.X + (size_t)j * D);
+        if (dd < kth) {
+            topk_insert<KMAX>(top, dd);
+            kth = top[KMAX - 1];
+        }
+    }
     if (lane_id() == 0) stack[0] = 0;  // root (the single leaf when n == 1)
     int sp = 1;
     __syncthreads();
@@ -578,6 +593,7 @@ __global__ void __launch_bounds__(64) k_knn(TreeView t, int kk_all, const u32* p
         if (!__any(want)) continue;
         if (r.y <= kKnnLeaf) {
             for (int j = r.x; j < r.x + r.y; ++j) {
+                if (j >= pre_lo && j < pre_hi) continue;  // seeded already
                 double dd = sqdist<D>(q, t.X + (size_t)j * D);
                 if (dd < kth && j >= lo_r && j < hi_r) {
                     topk_insert<KMAX>(top, dd);
