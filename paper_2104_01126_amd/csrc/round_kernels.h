@@ -700,15 +700,28 @@ __device__ __forceinline__ void big_orient(const TreeView& t, uint2 pr, int2& ra
 }
 
 template <int D>
-__global__ void k_big_ntasks(TreeView t, const uint2* big, u32 nbig, u32* ntask, int bchunk, Counters* cnt) {
+// Task count of every large pair; the pairs' distance evaluations and task
+// totals are summed per block (one atomic per block and counter: the tasks
+// themselves add nothing to shared counters).
+__global__ void __launch_bounds__(kBlock) k_big_ntasks(TreeView t, const uint2* big, u32 nbig, u32* ntask,
+                                                       int bchunk, Counters* cnt) {
+    __shared__ unsigned long long sh[kBlock / kWave];
     u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nbig) return;
-    int2 ra, rb;
-    big_orient<D>(t, big[i], ra, rb);
-    u64 work = (u64)ra.y * (u64)rb.y;
-    u64 c = work <= (u64)kMidMax ? 1ull : (u64)((ra.y + kBigA - 1) / kBigA) * (u64)((rb.y + bchunk - 1) / bchunk);
-    atomicAdd(&cnt->c64[C64_TASKS], (unsigned long long)c);  // the host rejects totals beyond 2^31
-    ntask[i] = c < (1ull << 31) ? (u32)c : 1u;
+    u64 c = 0, work = 0;
+    if (i < nbig) {
+        int2 ra, rb;
+        big_orient<D>(t, big[i], ra, rb);
+        work = (u64)ra.y * (u64)rb.y;
+        c = work <= (u64)kMidMax ? 1ull : (u64)((ra.y + kBigA - 1) / kBigA) * (u64)((rb.y + bchunk - 1) / bchunk);
+        ntask[i] = c < (1ull << 31) ? (u32)c : 1u;
+    }
+    const unsigned long long sc = block_sum_u64(c, sh);
+    const unsigned long long sw = block_sum_u64(work, sh);
+    if (threadIdx.x == 0) {
+        atomicAdd(&cnt->c64[C64_TASKS], sc);  // the host rejects totals beyond 2^31
+        atomicAdd(&cnt->c64[C64_EVALS], sw);
+        atomicAdd(&cnt->c64[C64_BIGEVALS], sw);
+    }
 }
 
 template <int D, int HDB>
@@ -757,8 +770,6 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
             pk.ids = ((u64)best.k.lo << 32) | best.k.hi;
             pk.pos = ((u64)best.i << 32) | best.j;
             part[task] = pk;
-            atomicAdd(&cnt->c64[C64_EVALS], (unsigned long long)tot);
-            atomicAdd(&cnt->c64[C64_BIGEVALS], (unsigned long long)tot);
         }
         return;
     }
@@ -901,10 +912,6 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
         pk.ids = ((u64)best.k.lo << 32) | best.k.hi;
         pk.pos = ((u64)best.i << 32) | best.j;
         part[task] = pk;
-        int na = min(kBigA, aend - abase);
-        unsigned long long ev = (unsigned long long)na * (unsigned long long)(jb1 - jb0);
-        atomicAdd(&cnt->c64[C64_EVALS], ev);
-        atomicAdd(&cnt->c64[C64_BIGEVALS], ev);
     }
 }
 
