@@ -805,7 +805,7 @@ struct Solver {
                         for (int j = 0; j < kLevelBatch; ++j, ++lv, ++levels) {
                             TIMED(GEOMST_K_EXPAND);
                             RoundArgs r = args(beta2, fo, (lv + 1) & 1, po);
-                            k_level<D_><<<kGrid, kBlock, 0, s>>>(t, r, hdb, D.Q[lv & 1].as<PairRec>(),
+                            k_level<D_><<<LevelShape<D_>::grid, LevelShape<D_>::block, 0, s>>>(t, r, hdb, D.Q[lv & 1].as<PairRec>(),
                                                                  (u32)D.capQ[lv & 1], ring + (lv % kQRing),
                                                                  ring + ((lv + 1) % kQRing),
                                                                  ring + ((lv + 2) % kQRing));

@@ -596,23 +596,34 @@ struct LevelWaves {
 };
 
 // One breadth-first level over the whole grid.  Blocks beyond the queue
-// leave at once.
+// leave at once.  Blocks are large because every step appends to the shared
+// lists with one atomic per list, and those few counters are the contended
+// addresses of the expansion: fewer, larger steps mean fewer atomics.
+// 1024 threads (one block per CU at four waves per SIMD) where the level
+// step fits 128 registers (d <= 5), else 512.
 template <int D>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LevelWaves<D>::value)))
+struct LevelShape {
+    static constexpr int block = D <= 5 ? 1024 : 512;
+    static constexpr int grid = D <= 5 ? 256 : 512;
+};
+
+template <int D>
+__global__ void __launch_bounds__(LevelShape<D>::block) __attribute__((amdgpu_waves_per_eu(LevelWaves<D>::value)))
 k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const u32* nq_p, u32* nq_next,
         u32* nq_clear) {
     __shared__ BlockAlloc S;
     if (blockIdx.x == 0 && threadIdx.x == 0) *nq_clear = 0;
     // an overflowed previous level counts more pairs than it stored: read
     // only what the queue holds (the overflow flag makes the round restart)
+    constexpr int NT = LevelShape<D>::block;
     const u32 nq = min(*nq_p, cap_in);
-    if (blockIdx.x * kBlock >= nq) return;
+    if (blockIdx.x * NT >= nq) return;
     u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR], nq_next};
     const double inf_ = __longlong_as_double(0x7ff0000000000000ll);
     LevelAcc acc = {inf_, inf_, inf_, 0, 0, 0};
-    for (u32 b0 = blockIdx.x * kBlock; b0 < nq; b0 += gridDim.x * kBlock)
+    for (u32 b0 = blockIdx.x * NT; b0 < nq; b0 += gridDim.x * NT)
         level_step<D>(t, r, hdb, qin, nq, b0, r.q, r.cap_q, ctr, S, acc);
-    level_flush<kBlock>(r, acc);
+    level_flush<NT>(r, acc);
 }
 
 // Many small levels in one workgroup: the level barrier is __syncthreads and
