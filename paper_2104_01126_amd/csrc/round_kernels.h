@@ -1185,29 +1185,35 @@ __global__ void k_bor_pick(const u32* alive, const u32* nalive_p, u32 cap, const
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_bor_hook(const u32* alive, const u32* nalive_p, u32 cap, const u32* perm,
-                                                     const EdgeList L, u32* parent, const u64* best, u32 stamp,
-                                                     const u32* ru, const u32* rv, u32* alive_next, u32* nalive_next,
-                                                     EdgeList out, u32 cap_out, Counters* cnt) {
+// Hook step: each component's lightest edge (its rank is in best) joins it
+// to the other end's component.  Four edges per thread and 1024-thread
+// blocks: one append per list per 4096 edges.
+constexpr int kHookBlock = 1024;
+constexpr int kHookItems = 4;
+constexpr int kHookTile = kHookBlock * kHookItems;
+
+__global__ void __launch_bounds__(kHookBlock) k_bor_hook(const u32* alive, const u32* nalive_p, u32 cap,
+                                                         const u32* perm, const EdgeList L, u32* parent,
+                                                         const u64* best, u32 stamp, const u32* ru, const u32* rv,
+                                                         u32* alive_next, u32* nalive_next, EdgeList out,
+                                                         u32 cap_out, Counters* cnt) {
     __shared__ BlockAlloc S;
     const u32 na = min(*nalive_p, cap);
     u32* ctr[kLists] = {&cnt->c[C_OUT], nalive_next, nullptr, nullptr, nullptr, nullptr};
-    for (u32 b0 = blockIdx.x * kBlock; b0 < na; b0 += gridDim.x * kBlock) {
-        u32 s = b0 + threadIdx.x;
-        bool have = s < na;
-        u32 a = have ? ru[s] : kNone;
-        bool live = have && a != kNone;
-        bool sel = false, keep = false;
-        u32 rank = 0, e = 0;
-        if (live) {
-            u32 b = rv[s];
-            rank = alive[s];
-            const u64 key = ((u64)stamp << 32) | rank;
-            bool pa = best[a] == key, pb = best[b] == key;
-            sel = pa || pb;
-            keep = !sel;
-            if (sel) {
-                e = perm[rank];
+    for (u32 b0 = blockIdx.x * kHookTile; b0 < na; b0 += gridDim.x * kHookTile) {
+        u32 sel = 0, keep = 0, ns = 0, nk = 0;
+        u32 rank[kHookItems];
+#pragma unroll
+        for (int k = 0; k < kHookItems; ++k) {
+            const u32 s = b0 + k * kHookBlock + threadIdx.x;
+            rank[k] = 0;
+            const u32 a = s < na ? ru[s] : kNone;
+            if (a == kNone) continue;
+            const u32 b = rv[s];
+            rank[k] = alive[s];
+            const u64 key = ((u64)stamp << 32) | rank[k];
+            const bool pa = best[a] == key, pb = best[b] == key;
+            if (pa || pb) {
                 if (pa && pb) {
                     u32 hi = a > b ? a : b, lo = a > b ? b : a;
                     parent[hi] = lo;
@@ -1216,16 +1222,29 @@ __global__ void __launch_bounds__(kBlock) k_bor_hook(const u32* alive, const u32
                 } else {
                     parent[b] = a;
                 }
+                sel |= 1u << k;
+                ++ns;
+            } else {
+                keep |= 1u << k;
+                ++nk;
             }
         }
         u32 off[kLists];
-        u32 cn[kLists] = {(u32)sel, (u32)keep, 0, 0, 0, 0};
+        u32 cn[kLists] = {ns, nk, 0, 0, 0, 0};
         block_alloc(S, cn, ctr, off);
-        if (sel) {
-            if (off[0] < cap_out) put_edge_raw(out, off[0], L.w2[e], L.e2[e], L.ids[e], L.pos[e]);
-            else flag_overflow(cnt);
+#pragma unroll
+        for (int k = 0; k < kHookItems; ++k) {
+            if ((sel >> k) & 1u) {
+                const u32 e = perm[rank[k]];
+                if (off[0] < cap_out) put_edge_raw(out, off[0], L.w2[e], L.e2[e], L.ids[e], L.pos[e]);
+                else flag_overflow(cnt);
+                ++off[0];
+            }
+            if ((keep >> k) & 1u) {
+                if (off[1] < cap) alive_next[off[1]] = rank[k];
+                ++off[1];
+            }
         }
-        if (keep && off[1] < cap) alive_next[off[1]] = rank;
     }
 }
 
