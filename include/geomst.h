@@ -267,6 +267,9 @@ int geomst_get_stats(geomst_stats_t* out);
  *                    in [0, 16]; default 2.
  *   "bccp_chunk"     B points per large-pair BCCP task, a multiple of 64 in
  *                    [64, 65536]; 0 restores the default 2048.
+ *   "refresh_divisor"  node components are refreshed after a round that
+ *                    merged at least n / this many components (and at least
+ *                    every fourth round); default 1024.
  *   "small_level_switch", "small_level_max"  expansion levels with at most
  *                    the first many pairs run in one workgroup, which keeps
  *                    going while levels stay at most the second size

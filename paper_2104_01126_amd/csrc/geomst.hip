@@ -37,6 +37,7 @@ int g_bccp_chunk = kBigBDefault;  // B points per large-pair BCCP task
 double g_capacity_scale = 1.0;
 constexpr int kMaxKeyLevels = 6;  // Morton key words per point (see k_morton_level)
 constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
+u32 g_refresh_div = 1024;    // refresh node components once a round merged n / this many
 u32 g_small_switch = 2048;  // queues up to this size go to the one-workgroup level kernel
 u32 g_small_max = 4096;     // ... which keeps going while a level stays this small
 constexpr int kBoruvkaBatch = 4;  // Boruvka steps launched between host checks
@@ -932,7 +933,7 @@ struct Solver {
             const Counters& c = *D.hcnt;
             check_errors(D);
             u32 merged = c.c[C_OUT] - nout;
-            if ((u64)merged * 4096 >= (u64)n || stale_rounds >= 3 || c.c[C_OUT] >= target_edges) {
+            if ((u64)merged * g_refresh_div >= (u64)n || stale_rounds >= 3 || c.c[C_OUT] >= target_edges) {
                 refresh_components();
                 stale_rounds = 0;
             } else {
@@ -1763,6 +1764,11 @@ int geomst_set_option(const char* name, double value) {
     if (!strcmp(name, "beta_growth")) {
         if (value != 0.0 && (!(value > 1.0) || !(value < 1e6))) return GEOMST_EINVAL;
         g_beta_growth = value;
+        return GEOMST_OK;
+    }
+    if (!strcmp(name, "refresh_divisor")) {
+        if (!(value >= 1.0) || !(value <= 1048576.0) || value != (double)(u32)value) return GEOMST_EINVAL;
+        g_refresh_div = (u32)value;
         return GEOMST_OK;
     }
     if (!strcmp(name, "small_level_switch") || !strcmp(name, "small_level_max")) {
