@@ -156,7 +156,7 @@ struct Device {
     DBuf pin, eout, wout, cdout;
     // tree
     DBuf keysA, keysB, gflag, gincl, gid, gstart, gbox, hflag;
-    DBuf part, bbox, key, val, key2, val2, stemp, X, orig, cd2, nodes, npar, flags, cdr, btop;
+    DBuf part, bbox, key, val, key2, val2, stemp, X, orig, cd2, nodes, npar, flags, cdr, btop, nrange;
     // union-find / component refresh
     DBuf uf, best, bnd, incl;
     // rounds
@@ -533,8 +533,8 @@ struct Solver {
         LAUNCHCHK();
         scan_inclusive_u32(D.bnd.as<u32>(), D.incl.as<u32>(), n, D.stemp.p, s);
         LAUNCHCHK();
-        k_node_comp<D_><<<blocks(2 * n - 1, 256), 256, 0, s>>>(D.nodes.as<NodeRec<D_>>(), D.uf.as<u32>(),
-                                                               D.incl.as<u32>(), 2 * n - 1);
+        k_node_comp<D_><<<blocks(2 * n - 1, 256), 256, 0, s>>>(D.nodes.as<NodeRec<D_>>(), D.nrange.as<int2>(),
+                                                               D.uf.as<u32>(), D.incl.as<u32>(), 2 * n - 1);
         LAUNCHCHK();
     }
 
@@ -654,6 +654,10 @@ struct Solver {
         auto t2 = clk::now();
 
         // union-find and node components
+        D.nrange.ensure((size_t)(2 * n - 1) * 8);
+        k_node_ranges<D_><<<blocks(2 * n - 1, 256), 256, 0, s>>>(D.nodes.as<NodeRec<D_>>(), 2 * n - 1,
+                                                                 D.nrange.as<int2>());
+        LAUNCHCHK();
         D.uf.ensure((size_t)n * 4);
         D.best.ensure((size_t)n * 8);
         D.bnd.ensure((size_t)n * 4);
