@@ -373,20 +373,22 @@ def main():
         else:
             ach, peak = amount / secs / 1e9, HBM_PEAK_GBS
         mt = measured_traffic(fams[i], a.workload)
-        # per launch = per solve / dispatches per solve (the ratio achieved =
-        # bytes per launch / average launch time is the same either way)
-        disp = mt[1] if mt else None
-        per = disp if disp else 1
+        # launches of the family's kernels per step, counted by the library
+        # (one timed scope per k_level / k_level_small launch); achieved =
+        # algorithmic bytes per launch / average launch duration
+        launches = kl[i] / a.steps
+        per = launches if launches > 0 else 1
         roof = {"kernel": fams[i], "kernels": FAMILY_KERNEL.get(fams[i]), "bound": bound,
                 "achieved": round(ach, 3), "peak": peak, "unit": unit, "frac": round(ach / peak, 5),
                 "traffic": round(mt[0] / per) if mt else None,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-scaled)",
                 "algorithmic_per_launch": round(amount / a.steps / per, 1),
-                "launches_per_step": disp,
+                "launches_per_step": round(launches, 2),
                 "algorithmic_per_step": round(amount / a.steps, 1),
                 "traffic_per_step": mt[0] if mt else None,
+                "traffic_dispatches_per_step": mt[1] if mt else None,
                 "device_ms_per_step": round(kms[i] / a.steps, 4),
-                "avg_launch_us": round(kms[i] / a.steps / per * 1000, 3) if disp else None,
+                "avg_launch_us": round(kms[i] / a.steps / per * 1000, 3),
                 "share_of_device_time": round(float(br[i] / max(br.sum(), 1e-9)), 4)}
         break
     out = {
