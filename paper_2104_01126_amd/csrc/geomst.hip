@@ -592,7 +592,7 @@ struct Solver {
         r.fout = D.F[fo].as<PairRec>();
         r.cap_f = (u32)D.capF[fo];
         r.q = D.Q[qo].as<PairRec>();
-        r.cap_q = (u32)D.capQ[qo];
+        r.cap_q = (u32)(D.capQ[qo] / kRegions);  // per region
         r.big = D.big.as<uint2>();
         r.cap_big = (u32)D.capBig;
         r.c = D.C.list();
@@ -602,28 +602,58 @@ struct Solver {
         return r;
     }
 
+    // Total and largest region count of level-queue ring slot `slot`.
+    void read_slot(const u32* ring, int slot, u32& total, u32& largest) {
+        u32 h[kSlotWords];
+        HIPCHK(hipMemcpyAsync(h, ring + slot * kSlotWords, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        total = largest = 0;
+        for (int x = 0; x < kRegions; ++x) {
+            total += h[x * kRegionStride];
+            largest = std::max(largest, h[x * kRegionStride]);
+        }
+    }
+
+    // List lengths are counted in 32 bits on the device.
+    static constexpr size_t kMaxListCap = 0xffffff00u;
+
     // After an overflow: grow the round's output lists that ran out.  Their
     // contents are not kept (the round restarts); the round's input frontier
     // F[fc] and input pool P[pc] are never touched.
     void grow_lists(int fo, int po, size_t keep_far) {
         const Counters& c = *D.hcnt;
+        if (g_trace)
+            fprintf(stderr,
+                    "[geomst] need/cap per point: F %.3f/%.3f far %.3f/%.3f queue %.3f/%.3f big %.4f/%.4f "
+                    "C %.3f/%.3f P %.3f/%.3f\n",
+                    (double)c.c[C_F] / n, (double)D.capF[fo] / n, (double)c.c[C_FAR] / n, (double)D.capFF[ffo] / n,
+                    (double)D.qmax_seen / n, (double)std::max(D.capQ[0], D.capQ[1]) / n, (double)c.c[C_BIG] / n,
+                    (double)D.capBig / n, (double)c.c[C_C] / n, (double)D.C.cap / n, (double)c.c[C_P] / n,
+                    (double)D.P[po].cap / n);
+        // A count read at an overflow only bounds the round's need from below
+        // (the round stopped early), so lists grow to twice the count.  The
+        // frontier and the level queues carry the same pairs level by level,
+        // so when either overflows both grow to the larger need.
         auto grow_pairs = [&](DBuf& b, size_t& cap, size_t need) {
             if (need > cap) {
-                size_t nc = std::max<size_t>(need + need / 4, cap * 2);
+                size_t nc = std::min<size_t>(std::max<size_t>(2 * need, cap * 2), kMaxListCap) / kRegions * kRegions;
                 b.ensure(nc * sizeof(PairRec));
                 cap = nc;
             }
         };
-        grow_pairs(D.F[fo], D.capF[fo], c.c[C_F]);
+        // level queues (kRegions equal regions; qmax_seen is kRegions times the
+        // largest region count seen): the split's counts are exact; an
+        // overflowing level's count may already be cleared, so then they double
+        size_t qneed = D.qmax_seen;
+        if (c.c[C_ERR] & 16u) qneed = std::max(qneed, std::max(D.capQ[0], D.capQ[1]) + 1);
+        size_t fneed = c.c[C_F];
+        if (fneed > D.capF[fo] || qneed > std::min(D.capQ[0], D.capQ[1])) fneed = qneed = std::max(fneed, qneed);
+        grow_pairs(D.F[fo], D.capF[fo], fneed);
         if (c.c[C_FAR] > D.capFF[ffo]) {  // keeps the far pairs retained from earlier rounds
-            size_t nc = std::max<size_t>((size_t)c.c[C_FAR] + c.c[C_FAR] / 4, D.capFF[ffo] * 2);
+            size_t nc = std::min<size_t>(std::max<size_t>(2 * (size_t)c.c[C_FAR], D.capFF[ffo] * 2), kMaxListCap);
             D.FF[ffo].ensure(nc * sizeof(PairRec), keep_far * sizeof(PairRec), s);
             D.capFF[ffo] = nc;
         }
-        // level queues: the split's count is exact (qmax_seen); an overflowing
-        // level's count may already be cleared, so then they double
-        size_t qneed = D.qmax_seen;
-        if (c.c[C_ERR] & 16u) qneed = std::max(qneed, std::max(D.capQ[0], D.capQ[1]) + 1);
         for (int i = 0; i < 2; ++i) grow_pairs(D.Q[i], D.capQ[i], qneed);
         if (c.c[C_BIG] > D.capBig) {
             size_t nc = std::max<size_t>((size_t)c.c[C_BIG] * 5 / 4, D.capBig * 2);
@@ -691,8 +721,11 @@ struct Solver {
         initcap(D.capF[1], D.F[1], sc(hdb ? 4 : 2));
         initcap(D.capFF[0], D.FF[0], sc(hdb ? 8 : 4));
         initcap(D.capFF[1], D.FF[1], sc(hdb ? 8 : 4));
-        initcap(D.capQ[0], D.Q[0], sc(2));
-        initcap(D.capQ[1], D.Q[1], sc(2));
+        // a thin-level chain keeps its queue in one region: room for a level
+        // of up to small_max pairs and its children
+        const size_t qmin = (size_t)(std::min(g_capacity_scale, 1.0) * kRegions * (2 * (double)g_small_max + 2048));
+        initcap(D.capQ[0], D.Q[0], (std::max(sc(2), qmin) + kRegions - 1) / kRegions * kRegions);
+        initcap(D.capQ[1], D.Q[1], (std::max(sc(2), qmin) + kRegions - 1) / kRegions * kRegions);
         if (D.capBig < sc(0.125)) {
             D.capBig = sc(0.125);
             D.big.ensure(D.capBig * 8);
@@ -725,7 +758,7 @@ struct Solver {
         int rounds = 0;
         u32 nout = 0;
         int stale_rounds = 0;
-        D.qring.ensure(kQRing * 4);
+        D.qring.ensure(kQRing * kSlotWords * 4);
         D.lstate.ensure(64);
         u32* ring = D.qring.as<u32>();
         while (true) {
@@ -752,7 +785,7 @@ struct Solver {
                 restart = false;
                 levels = 0;
                 D.qmax_seen = 0;
-                HIPCHK(hipMemsetAsync(ring, 0, kQRing * 4, s));
+                HIPCHK(hipMemsetAsync(ring, 0, kQRing * kSlotWords * 4, s));
                 // frontier and pool split
                 {
                     TIMED(GEOMST_K_SPLIT);
@@ -771,11 +804,10 @@ struct Solver {
                     LAUNCHCHK();
                 }
                 read_counters(D, s);
-                u32 nq = 0;
-                HIPCHK(hipMemcpyAsync(&nq, ring, 4, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
+                u32 nq = 0, nq_region = 0;
+                read_slot(ring, 0, nq, nq_region);
                 D.hcnt->c[C_Q] = nq;
-                D.qmax_seen = nq;
+                D.qmax_seen = (size_t)kRegions * nq_region;
                 if (D.hcnt->c[C_ERR] & 1u) {
                     restart = true;
                 } else {
@@ -790,8 +822,9 @@ struct Solver {
                                 TIMED(GEOMST_K_EXPAND);
                                 RoundArgs r = args(beta2, fo, 0, po);
                                 k_level_small<D_><<<1, kSmallBlock, 0, s>>>(
-                                    t, r, hdb, D.Q[0].as<PairRec>(), (u32)D.capQ[0], D.Q[1].as<PairRec>(),
-                                    (u32)D.capQ[1], lv & 1, ring, (u32)(lv % kQRing), g_small_max, D.lstate.as<u32>());
+                                    t, r, hdb, D.Q[0].as<PairRec>(), (u32)(D.capQ[0] / kRegions), D.Q[1].as<PairRec>(),
+                                    (u32)(D.capQ[1] / kRegions), lv & 1, ring, (u32)(lv % kQRing), g_small_max,
+                                    D.lstate.as<u32>());
                                 LAUNCHCHK();
                             }
                             u32 st2[2];
@@ -804,22 +837,22 @@ struct Solver {
                             }
                             nq = st2[0];
                             lv = (int)st2[1];
-                            D.qmax_seen = std::max<size_t>(D.qmax_seen, nq);
+                            D.qmax_seen = std::max<size_t>(D.qmax_seen, (size_t)kRegions * nq);  // all in region 0
                             continue;
                         }
                         for (int j = 0; j < kLevelBatch; ++j, ++lv, ++levels) {
                             TIMED(GEOMST_K_EXPAND);
                             RoundArgs r = args(beta2, fo, (lv + 1) & 1, po);
                             k_level<D_><<<LevelShape<D_>::grid, LevelShape<D_>::block, 0, s>>>(t, r, hdb, D.Q[lv & 1].as<PairRec>(),
-                                                                 (u32)D.capQ[lv & 1], ring + (lv % kQRing),
-                                                                 ring + ((lv + 1) % kQRing),
-                                                                 ring + ((lv + 2) % kQRing));
+                                                                 (u32)(D.capQ[lv & 1] / kRegions),
+                                                                 ring + (lv % kQRing) * kSlotWords,
+                                                                 ring + ((lv + 1) % kQRing) * kSlotWords,
+                                                                 ring + ((lv + 2) % kQRing) * kSlotWords);
                             LAUNCHCHK();
                         }
                         read_counters(D, s);
-                        HIPCHK(hipMemcpyAsync(&nq, ring + (lv % kQRing), 4, hipMemcpyDeviceToHost, s));
-                        HIPCHK(hipStreamSynchronize(s));
-                        D.qmax_seen = std::max<size_t>(D.qmax_seen, nq);
+                        read_slot(ring, lv % kQRing, nq, nq_region);
+                        D.qmax_seen = std::max<size_t>(D.qmax_seen, (size_t)kRegions * nq_region);
                         if (D.hcnt->c[C_ERR] & 1u) {
                             restart = true;
                             break;

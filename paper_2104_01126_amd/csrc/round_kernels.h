@@ -198,15 +198,21 @@ __device__ __forceinline__ void flag_overflow(Counters* cnt) { atomicOr(&cnt->c[
 __device__ __forceinline__ void flag_overflow_q(Counters* cnt) { atomicOr(&cnt->c[C_ERR], 1u | 16u); }
 
 // ------------------------------------------------------ block-level appends
-// Up to six output lists per block step.  Each thread passes how many
-// entries it adds to each list (at most 2 each); one atomic per non-empty
-// list per block reserves the space, and each thread gets its slot offsets
-// back.  All threads of the block must call it.
-constexpr int kLists = 6;
-struct BlockAlloc {
-    u64 wsum[2][16];
-    u32 base[kLists];
+// L output lists per block step.  Each thread passes how many entries it adds
+// to each list; the counts travel packed B bits apiece in 64-bit words
+// through one wave scan per word, and one atomic per non-empty list per block
+// reserves the space; each thread gets its slot offsets back.  A block's
+// total per list must stay below 2^B.  All threads of the block must call it.
+template <int L, int B>
+struct BlockAllocN {
+    static constexpr int kPer = 64 / B;
+    static constexpr int kWords = (L + kPer - 1) / kPer;
+    u64 wsum[kWords][16];
+    u32 base[L];
 };
+
+constexpr int kLists = 6;
+using BlockAlloc = BlockAllocN<kLists, 16>;
 
 __device__ __forceinline__ u64 wave_incl_scan_u64(u64 v) {
 #pragma unroll
@@ -217,38 +223,88 @@ __device__ __forceinline__ u64 wave_incl_scan_u64(u64 v) {
     return v;
 }
 
-// counts: lists 0-2 and 3-5 packed 16 bits apiece in two words
-__device__ __forceinline__ void block_alloc(BlockAlloc& S, const u32 (&cnt)[kLists], u32* const* counters,
-                                            u32 (&off)[kLists]) {
+template <int L, int B>
+__device__ __forceinline__ void block_alloc(BlockAllocN<L, B>& S, const u32 (&cnt)[L], u32* const* counters,
+                                            u32 (&off)[L]) {
+    constexpr int P = BlockAllocN<L, B>::kPer, W = BlockAllocN<L, B>::kWords;
+    constexpr u64 M = (1ull << B) - 1;
     const int w = threadIdx.x / kWave;
-    u64 p0 = (u64)cnt[0] | ((u64)cnt[1] << 16) | ((u64)cnt[2] << 32);
-    u64 p1 = (u64)cnt[3] | ((u64)cnt[4] << 16) | ((u64)cnt[5] << 32);
-    u64 i0 = wave_incl_scan_u64(p0), i1 = wave_incl_scan_u64(p1);
+    u64 p[W], inc[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) p[k] = 0;
+#pragma unroll
+    for (int l = 0; l < L; ++l) p[l / P] |= (u64)cnt[l] << (B * (l % P));
+#pragma unroll
+    for (int k = 0; k < W; ++k) inc[k] = wave_incl_scan_u64(p[k]);
     if (lane_id() == kWave - 1) {
-        S.wsum[0][w] = i0;
-        S.wsum[1][w] = i1;
+#pragma unroll
+        for (int k = 0; k < W; ++k) S.wsum[k][w] = inc[k];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        u64 r0 = 0, r1 = 0;
+        u64 r[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) r[k] = 0;
         for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
-            u64 x0 = S.wsum[0][i], x1 = S.wsum[1][i];
-            S.wsum[0][i] = r0;
-            S.wsum[1][i] = r1;
-            r0 += x0;
-            r1 += x1;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                u64 x = S.wsum[k][i];
+                S.wsum[k][i] = r[k];
+                r[k] += x;
+            }
         }
-        for (int l = 0; l < kLists; ++l) {
-            u32 c = (u32)(((l < 3 ? r0 : r1) >> (16 * (l % 3))) & 0xffff);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            u32 c = (u32)((r[l / P] >> (B * (l % P))) & M);
             S.base[l] = (c && counters[l]) ? atomicAdd(counters[l], c) : 0u;
         }
     }
     __syncthreads();
-    u64 e0 = i0 - p0 + S.wsum[0][w], e1 = i1 - p1 + S.wsum[1][w];
+    u64 e[W];
 #pragma unroll
-    for (int l = 0; l < kLists; ++l)
-        off[l] = S.base[l] + (u32)(((l < 3 ? e0 : e1) >> (16 * (l % 3))) & 0xffff);
+    for (int k = 0; k < W; ++k) e[k] = inc[k] - p[k] + S.wsum[k][w];
+#pragma unroll
+    for (int l = 0; l < L; ++l) off[l] = S.base[l] + (u32)((e[l / P] >> (B * (l % P))) & M);
     __syncthreads();
+}
+
+// ------------------------------------------------------ level-queue regions
+// A level queue is cut into kRegions equal regions, one per XCD: workgroup
+// b of a level launch runs on XCD b % 8 (the dispatcher deals workgroups to
+// the XCDs in turn), reads a slice of the queue that is mostly its own
+// region and appends the child pairs it makes to its own region.  A pair's
+// descendants thus stay on one XCD, and the records of the subtree they
+// touch stay in that XCD's L2.  The frontier split seeds the regions by tree
+// position of a pair's first node (internal node i spans sorted position i,
+// leaf n-1+i is position i), so a region starts out as one slab of the
+// Morton curve.  Each region's counter has a 128-byte line of its own; the
+// counters of one level form a slot of the kQRing-slot ring.
+constexpr int kRegions = 8;
+constexpr int kRegionStride = 32;  // u32 words between region counters
+constexpr int kSlotWords = kRegions * kRegionStride;
+
+__device__ __forceinline__ int node_region(u32 node, int n) {
+    const u32 pos = node < (u32)(n - 1) ? node : node - (u32)(n - 1);
+    return (int)(((u64)pos * kRegions) / (u64)n);
+}
+
+// Slot counts (clamped to the region capacity) as prefix sums pre[0..8].
+__device__ __forceinline__ void region_prefix(const u32* slot, u32 cap, u32 (&pre)[kRegions + 1]) {
+    pre[0] = 0;
+#pragma unroll
+    for (int x = 0; x < kRegions; ++x) pre[x + 1] = pre[x] + min(slot[x * kRegionStride], cap);
+}
+
+// Position in the queue buffer of entry v of the regions laid end to end.
+__device__ __forceinline__ u32 region_index(const u32 (&pre)[kRegions + 1], u32 cap, u32 v) {
+    u32 base = 0, start = 0;
+#pragma unroll
+    for (int x = 1; x < kRegions; ++x)
+        if (v >= pre[x]) {
+            base = (u32)x * cap;
+            start = pre[x];
+        }
+    return base + (v - start);
 }
 
 // Block-wide minimum of a non-negative double, one atomic per block.
@@ -314,19 +370,42 @@ __global__ void __launch_bounds__(kBlock) k_min_positive_lb(const PairRec* f, u3
     block_atomic_min(v, &cnt->m[M_F], sh);
 }
 
-// Near-frontier split: queue the pairs whose lower bound is within beta,
-// keep the rest in the near list.  A pair's connectivity is checked when it
-// is expanded, so this pass only streams the records.
+// Near-frontier split: queue the pairs whose lower bound is within beta
+// (each in the region of its first node), keep the rest in the near list.  A
+// pair's connectivity is checked when it is expanded, so this pass only
+// streams the records.
+constexpr int kSplitLists = kRegions + 2;  // regions, near list, far list
+using SplitAlloc = BlockAllocN<kSplitLists, 12>;
+
+// appends item k to region `rg` of the queue: the region's next offset
+__device__ __forceinline__ u32 take_region_slot(u32 (&off)[kSplitLists], int rg) {
+    u32 slot = 0;
+#pragma unroll
+    for (int x = 0; x < kRegions; ++x)
+        if (rg == x) slot = off[x]++;
+    return slot;
+}
+
+__device__ __forceinline__ void put_queued(const RoundArgs& r, u32 slot, int rg, const PairRec& p) {
+    if (slot < r.cap_q) r.q[(size_t)rg * r.cap_q + slot] = p;
+    else flag_overflow(r.cnt);
+}
+
 __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs r, const PairRec* fin, u32 nfin,
-                                                           u32* qcount) {
-    __shared__ BlockAlloc S;
+                                                           u32* qslot) {
+    __shared__ SplitAlloc S;
     __shared__ double shm[4];
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
-    u32* ctr[kLists] = {qcount, &r.cnt->c[C_F], nullptr, nullptr, nullptr, nullptr};
+    u32* ctr[kSplitLists];
+#pragma unroll
+    for (int x = 0; x < kRegions; ++x) ctr[x] = qslot + x * kRegionStride;
+    ctr[kRegions] = &r.cnt->c[C_F];
+    ctr[kRegions + 1] = nullptr;
     double minf = inf;
     for (u32 b0 = blockIdx.x * kSplitTile; b0 < nfin; b0 += gridDim.x * kSplitTile) {
         PairRec p[kSplitItems];
-        u32 due = 0, wait = 0, nd = 0, nw = 0;
+        u32 due = 0, wait = 0, rgs = 0;
+        u32 cnt[kSplitLists] = {};
 #pragma unroll
         for (int k = 0; k < kSplitItems; ++k) {
             const u32 i = b0 + k * kBlock + threadIdx.x;
@@ -335,25 +414,29 @@ __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs
                 const bool d = p[k].lb2 <= r.beta2;
                 due |= (u32)d << k;
                 wait |= (u32)!d << k;
-                nd += d;
-                nw += !d;
-                if (!d) minf = fmin(minf, p[k].lb2);
+                if (d) {
+                    const int rg = node_region(p[k].a, t.n);
+                    rgs |= (u32)rg << (3 * k);
+#pragma unroll
+                    for (int x = 0; x < kRegions; ++x) cnt[x] += (rg == x);
+                } else {
+                    ++cnt[kRegions];
+                    minf = fmin(minf, p[k].lb2);
+                }
             }
         }
-        u32 cnt[kLists] = {nd, nw, 0, 0, 0, 0};
-        u32 off[kLists];
+        u32 off[kSplitLists];
         block_alloc(S, cnt, ctr, off);
 #pragma unroll
         for (int k = 0; k < kSplitItems; ++k) {
             if ((due >> k) & 1u) {
-                if (off[0] < r.cap_q) r.q[off[0]] = p[k];
-                else flag_overflow(r.cnt);
-                ++off[0];
+                const int rg = (int)((rgs >> (3 * k)) & 7u);
+                put_queued(r, take_region_slot(off, rg), rg, p[k]);
             }
             if ((wait >> k) & 1u) {
-                if (off[1] < r.cap_f) r.fout[off[1]] = p[k];
+                if (off[kRegions] < r.cap_f) r.fout[off[kRegions]] = p[k];
                 else flag_overflow(r.cnt);
-                ++off[1];
+                ++off[kRegions];
             }
         }
     }
@@ -365,16 +448,21 @@ __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs
 // to the near list and keep the rest far.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_split_far(TreeView t, RoundArgs r, const PairRec* fin, u32 nfin,
-                                                      u32* qcount) {
-    __shared__ BlockAlloc S;
+                                                      u32* qslot) {
+    __shared__ SplitAlloc S;
     __shared__ double shm[4];
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
-    u32* ctr[kLists] = {qcount, &r.cnt->c[C_F], &r.cnt->c[C_FAR], nullptr, nullptr, nullptr};
+    u32* ctr[kSplitLists];
+#pragma unroll
+    for (int x = 0; x < kRegions; ++x) ctr[x] = qslot + x * kRegionStride;
+    ctr[kRegions] = &r.cnt->c[C_F];
+    ctr[kRegions + 1] = &r.cnt->c[C_FAR];
     double minf = inf, minfar = inf;
     for (u32 b0 = blockIdx.x * kSplitTile; b0 < nfin; b0 += gridDim.x * kSplitTile) {
         PairRec p[kSplitItems];
         u32 cls = 0;  // 2 bits per item: 1 due, 2 near, 3 far, 0 dropped
-        u32 nd = 0, nn = 0, nf = 0;
+        u32 rgs = 0;
+        u32 cnt[kSplitLists] = {};
 #pragma unroll
         for (int k = 0; k < kSplitItems; ++k) {
             const u32 i = b0 + k * kBlock + threadIdx.x;
@@ -387,29 +475,32 @@ __global__ void __launch_bounds__(kBlock) k_split_far(TreeView t, RoundArgs r, c
                 if (near) minf = fmin(minf, p[k].lb2);
                 if (far) minfar = fmin(minfar, p[k].lb2);
                 cls |= (due ? 1u : near ? 2u : far ? 3u : 0u) << (2 * k);
-                nd += due;
-                nn += near;
-                nf += far;
+                if (due) {
+                    const int rg = node_region(p[k].a, t.n);
+                    rgs |= (u32)rg << (3 * k);
+#pragma unroll
+                    for (int x = 0; x < kRegions; ++x) cnt[x] += (rg == x);
+                }
+                cnt[kRegions] += near;
+                cnt[kRegions + 1] += far;
             }
         }
-        u32 cnt[kLists] = {nd, nn, nf, 0, 0, 0};
-        u32 off[kLists];
+        u32 off[kSplitLists];
         block_alloc(S, cnt, ctr, off);
 #pragma unroll
         for (int k = 0; k < kSplitItems; ++k) {
             const u32 c = (cls >> (2 * k)) & 3u;
             if (c == 1u) {
-                if (off[0] < r.cap_q) r.q[off[0]] = p[k];
-                else flag_overflow(r.cnt);
-                ++off[0];
+                const int rg = (int)((rgs >> (3 * k)) & 7u);
+                put_queued(r, take_region_slot(off, rg), rg, p[k]);
             } else if (c == 2u) {
-                if (off[1] < r.cap_f) r.fout[off[1]] = p[k];
+                if (off[kRegions] < r.cap_f) r.fout[off[kRegions]] = p[k];
                 else flag_overflow(r.cnt);
-                ++off[1];
+                ++off[kRegions];
             } else if (c == 3u) {
-                if (off[2] < r.cap_far) r.ffar[off[2]] = p[k];
+                if (off[kRegions + 1] < r.cap_far) r.ffar[off[kRegions + 1]] = p[k];
                 else flag_overflow(r.cnt);
-                ++off[2];
+                ++off[kRegions + 1];
             }
         }
     }
@@ -431,16 +522,14 @@ struct LevelAcc {
     unsigned long long visits, evals, solved;
 };
 
-// One block step of a level: the block's threads take pairs b0.. of qin
-// (count nq); child pairs due in this round go to qout through counter
-// ctr[4].  All threads of the block must call it.
+// One block step of a level: a thread with `have` takes pair qin[i]; child
+// pairs due in this round go to qout through counter ctr[5].  All threads of
+// the block must call it.
 template <int D>
-__device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r, int hdb, const PairRec* qin, u32 nq,
-                                           u32 b0, PairRec* qout, u32 cap_qout, u32* const* ctr, BlockAlloc& S,
-                                           LevelAcc& acc) {
+__device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r, int hdb, const PairRec* qin,
+                                           bool have, u32 i, PairRec* qout, u32 cap_qout, u32* const* ctr,
+                                           BlockAlloc& S, LevelAcc& acc) {
     const NodeRec<D>* N = nodes_of<D>(t);
-    u32 i = b0 + threadIdx.x;
-    bool have = i < nq;
     bool to_c = false, to_p = false, to_big = false, to_f = false;
     EdgeOut e;
     u32 a = 0, b = 0, oth = 0;
@@ -605,24 +694,40 @@ template <int D>
 struct LevelShape {
     static constexpr int block = D <= 5 ? 1024 : 512;
     static constexpr int grid = D <= 5 ? 256 : 512;
+    static_assert(grid % kRegions == 0, "every XCD gets the same number of workgroups");
 };
 
+// The queue is read as its regions laid end to end; XCD x's workgroups take
+// the x-th eighth of that sequence (its own region when the regions are
+// balanced, a neighbour's surplus otherwise) and append children to region x
+// of the output queue r.q (region capacity r.cap_q).
 template <int D>
 __global__ void __launch_bounds__(LevelShape<D>::block) __attribute__((amdgpu_waves_per_eu(LevelWaves<D>::value)))
-k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const u32* nq_p, u32* nq_next,
-        u32* nq_clear) {
+k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const u32* slot_in, u32* slot_next,
+        u32* slot_clear) {
     __shared__ BlockAlloc S;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *nq_clear = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kRegions) slot_clear[threadIdx.x * kRegionStride] = 0;
     // an overflowed previous level counts more pairs than it stored: read
     // only what the queue holds (the overflow flag makes the round restart)
     constexpr int NT = LevelShape<D>::block;
-    const u32 nq = min(*nq_p, cap_in);
-    if (blockIdx.x * NT >= nq) return;
-    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR], nq_next};
+    u32 pre[kRegions + 1];
+    region_prefix(slot_in, cap_in, pre);
+    const u32 nq = pre[kRegions];
+    const int x = (int)(blockIdx.x % kRegions);
+    const u32 j = blockIdx.x / kRegions, g = gridDim.x / kRegions;
+    const u32 lo = (u32)((u64)nq * x / kRegions), hi = (u32)((u64)nq * (x + 1) / kRegions);
+    if (lo + j * NT >= hi) return;
+    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR],
+                        slot_next + x * kRegionStride};
+    PairRec* qout = r.q + (size_t)x * r.cap_q;
     const double inf_ = __longlong_as_double(0x7ff0000000000000ll);
     LevelAcc acc = {inf_, inf_, inf_, 0, 0, 0};
-    for (u32 b0 = blockIdx.x * NT; b0 < nq; b0 += gridDim.x * NT)
-        level_step<D>(t, r, hdb, qin, nq, b0, r.q, r.cap_q, ctr, S, acc);
+    for (u32 v0 = lo + j * NT; v0 < hi; v0 += g * NT) {
+        const u32 v = v0 + threadIdx.x;
+        const bool have = v < hi;
+        const u32 i = have ? region_index(pre, cap_in, v) : 0u;
+        level_step<D>(t, r, hdb, qin, have, i, qout, r.cap_q, ctr, S, acc);
+    }
     level_flush<NT>(r, acc);
 }
 
@@ -630,32 +735,43 @@ k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const 
 // the next queue's counter lives in LDS, so a chain of thin levels costs no
 // kernel launches or host round trips.  Stops when the queue is empty or
 // grows beyond `small_max` (then the grid-wide level kernel takes over).
-// The queue ping-pongs between q[0] and q[1]; on exit ring[b] holds the
-// remaining count of the buffer b it ends in (other ring slots are zeroed),
-// and state = {remaining, b}.
+// The first level reads the regions of ring slot `slot_in` of buffer b_in;
+// later levels keep the whole queue in region 0, ping-ponging between q[0]
+// and q[1] (cap0, cap1: region capacities).  On exit ring slot b holds the
+// remaining count in its region 0 for the buffer b it ends in (every other
+// ring counter is zeroed), and state = {remaining, b}.
 constexpr int kSmallBlock = 1024;
 
 template <int D>
 __global__ void __launch_bounds__(kSmallBlock) k_level_small(TreeView t, RoundArgs r, int hdb, PairRec* q0, u32 cap0,
                                                              PairRec* q1, u32 cap1, int b_in, u32* ring,
-                                                             u32 ring_in, u32 small_max, u32* state) {
+                                                             u32 slot_in, u32 small_max, u32* state) {
     __shared__ BlockAlloc S;
     __shared__ u32 qn;
     const double inf_ = __longlong_as_double(0x7ff0000000000000ll);
     LevelAcc acc = {inf_, inf_, inf_, 0, 0, 0};
     int b = b_in;
-    u32 nq = min(ring[ring_in], b ? cap1 : cap0);
+    u32 pre[kRegions + 1];
+    region_prefix(ring + slot_in * kSlotWords, b ? cap1 : cap0, pre);
+    u32 nq = pre[kRegions];
+    bool first = true;
     while (nq > 0 && nq <= small_max) {
         if (threadIdx.x == 0) qn = 0;
         __syncthreads();
         u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR], &qn};
         const PairRec* qin = b ? q1 : q0;
         PairRec* qout = b ? q0 : q1;
-        u32 capo = b ? cap0 : cap1;
-        for (u32 b0 = 0; b0 < nq; b0 += kSmallBlock) level_step<D>(t, r, hdb, qin, nq, b0, qout, capo, ctr, S, acc);
+        const u32 capi = b ? cap1 : cap0, capo = b ? cap0 : cap1;
+        for (u32 b0 = 0; b0 < nq; b0 += kSmallBlock) {
+            const u32 v = b0 + threadIdx.x;
+            const bool have = v < nq;
+            const u32 i = (have && first) ? region_index(pre, capi, v) : v;
+            level_step<D>(t, r, hdb, qin, have, i, qout, capo, ctr, S, acc);
+        }
         __syncthreads();
         u32 nn = qn;
         b ^= 1;
+        first = false;
         if (nn > capo) {  // overflowed (flagged): stop, the round restarts
             nq = 0;
             break;
@@ -664,9 +780,8 @@ __global__ void __launch_bounds__(kSmallBlock) k_level_small(TreeView t, RoundAr
         __syncthreads();
     }
     level_flush<kSmallBlock>(r, acc);
+    if (threadIdx.x < kQRing * kRegions) ring[threadIdx.x * kRegionStride] = threadIdx.x == b * kRegions ? nq : 0u;
     if (threadIdx.x == 0) {
-        for (int k = 0; k < kQRing; ++k) ring[k] = 0;
-        ring[b] = nq;
         state[0] = nq;
         state[1] = (u32)b;
     }
