@@ -536,13 +536,21 @@ __device__ __forceinline__ double point_box_lb2(const double (&q)[D], const B* l
     return s;
 }
 
+// Five waves per SIMD where the registers allow (d <= 5, k <= 16).
+template <int D, int KMAX>
+struct KnnWaves {
+    static constexpr int value = (D <= 5 && KMAX <= 16) ? 5 : 1;
+};
+
 // Batched solves pass the instance of each sorted position and each
 // instance's (first position, size) and k: a lane only accepts points of its
 // own instance (the sorted positions of an instance are contiguous).
 template <int D, int KMAX>
-__global__ void __launch_bounds__(64) k_knn(TreeView t, int kk_all, const u32* pinst, const int2* irange,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KnnWaves<D, KMAX>::value))) k_knn(TreeView t, int kk_all, const u32* pinst, const int2* irange,
                                            const int* ik, double* cd2_out, u32* err) {
     __shared__ int stack[kKnnStack];
+    static_assert(kKnnLeaf <= kWave, "a leaf is staged one row per lane");
+    __shared__ double rows[(kWave + 2 * kKnnSeed) * D];  // staged candidate rows
     const int n = t.n;
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
     int p = blockIdx.x * kWave + lane_id();
@@ -572,8 +580,19 @@ __global__ void __launch_bounds__(64) k_knn(TreeView t, int kk_all, const u32* p
     const int w0 = blockIdx.x * kWave;
     const int pre_lo = max(max(w0 - kKnnSeed, 0), lo_r);
     const int pre_hi = min(min(w0 + kWave + kKnnSeed, n), hi_r);
-    for (int j = pre_lo; j < pre_hi; ++j) {
-        double dd = sqdist<D>(q, t.X + (size_t)j * D);
+    // the wave loads the candidate rows into LDS together (coalesced), then
+    // every lane reads them from there: one memory round trip per batch of
+    // rows instead of one per row
+    // rows (the window is the same for the whole wave; in a batched solve a
+    // lane skips the rows of other instances)
+    const int win_lo = max(w0 - kKnnSeed, 0), win_hi = min(w0 + kWave + kKnnSeed, n);
+    for (int r = lane_id(); r < win_hi - win_lo; r += kWave)
+#pragma unroll
+        for (int k = 0; k < D; ++k) rows[r * D + k] = t.X[(size_t)(win_lo + r) * D + k];
+    __syncthreads();
+    for (int j = win_lo; j < win_hi; ++j) {
+        if (j < pre_lo || j >= pre_hi) continue;
+        double dd = sqdist<D>(q, rows + (j - win_lo) * D);
         if (dd < kth) {
             topk_insert<KMAX>(top, dd);
             kth = top[KMAX - 1];
@@ -592,14 +611,19 @@ __global__ void __launch_bounds__(64) k_knn(TreeView t, int kk_all, const u32* p
         bool want = live && lb < kth && r.x < hi_r && r.x + r.y > lo_r;
         if (!__any(want)) continue;
         if (r.y <= kKnnLeaf) {
+            if (lane_id() < r.y)
+#pragma unroll
+                for (int k = 0; k < D; ++k) rows[lane_id() * D + k] = t.X[(size_t)(r.x + lane_id()) * D + k];
+            __syncthreads();
             for (int j = r.x; j < r.x + r.y; ++j) {
                 if (j >= pre_lo && j < pre_hi) continue;  // seeded already
-                double dd = sqdist<D>(q, t.X + (size_t)j * D);
+                double dd = sqdist<D>(q, rows + (j - r.x) * D);
                 if (dd < kth && j >= lo_r && j < hi_r) {
                     topk_insert<KMAX>(top, dd);
                     kth = top[KMAX - 1];
                 }
             }
+            __syncthreads();  // the rows are read before the next leaf is staged
         } else {
             if (sp + 2 > kKnnStack) {
                 if (lane_id() == 0) atomicOr(err, 4u);
