@@ -162,7 +162,8 @@ struct Device {
     // rounds
     DBuf F[2], Q[2], big, ntask, toff, parts, qring, lstate;
     size_t qmax_seen = 0;
-    size_t capF[2] = {0, 0}, capQ[2] = {0, 0}, capBig = 0;
+    size_t capF[2] = {0, 0}, capQ[2] = {0, 0}, capBig = 0, capTiny = 0;
+    DBuf tiny;  // small separated pairs of the current round
     DBuf FF[2];  // far frontier (see the round loop)
     size_t capFF[2] = {0, 0};
     EdgeBufs C, P[2], OUT;
@@ -595,6 +596,8 @@ struct Solver {
         r.cap_q = (u32)(D.capQ[qo] / kRegions);  // per region
         r.big = D.big.as<uint2>();
         r.cap_big = (u32)D.capBig;
+        r.tiny = D.tiny.as<uint4>();
+        r.cap_tiny = (u32)D.capTiny;
         r.c = D.C.list();
         r.cap_c = (u32)D.C.cap;
         r.pout = D.P[po].list();
@@ -625,11 +628,11 @@ struct Solver {
         if (g_trace)
             fprintf(stderr,
                     "[geomst] need/cap per point: F %.3f/%.3f far %.3f/%.3f queue %.3f/%.3f big %.4f/%.4f "
-                    "C %.3f/%.3f P %.3f/%.3f\n",
+                    "C %.3f/%.3f P %.3f/%.3f tiny %.3f/%.3f\n",
                     (double)c.c[C_F] / n, (double)D.capF[fo] / n, (double)c.c[C_FAR] / n, (double)D.capFF[ffo] / n,
                     (double)D.qmax_seen / n, (double)std::max(D.capQ[0], D.capQ[1]) / n, (double)c.c[C_BIG] / n,
                     (double)D.capBig / n, (double)c.c[C_C] / n, (double)D.C.cap / n, (double)c.c[C_P] / n,
-                    (double)D.P[po].cap / n);
+                    (double)D.P[po].cap / n, (double)c.c[C_TINY] / n, (double)D.capTiny / n);
         // A count read at an overflow only bounds the round's need from below
         // (the round stopped early), so lists grow to twice the count.  The
         // frontier and the level queues carry the same pairs level by level,
@@ -655,6 +658,11 @@ struct Solver {
             D.capFF[ffo] = nc;
         }
         for (int i = 0; i < 2; ++i) grow_pairs(D.Q[i], D.capQ[i], qneed);
+        if (c.c[C_TINY] > D.capTiny) {
+            size_t nc = std::min<size_t>(std::max<size_t>(2 * (size_t)c.c[C_TINY], D.capTiny * 2), kMaxListCap);
+            D.tiny.ensure(nc * sizeof(uint4));
+            D.capTiny = nc;
+        }
         if (c.c[C_BIG] > D.capBig) {
             size_t nc = std::max<size_t>((size_t)c.c[C_BIG] * 5 / 4, D.capBig * 2);
             D.big.ensure(nc * 8);
@@ -715,6 +723,7 @@ struct Solver {
                 D.P[i].cap = 0;
             }
             D.capBig = 0;
+            D.capTiny = 0;
             D.C.cap = 0;
         }
         initcap(D.capF[0], D.F[0], sc(hdb ? 4 : 2));
@@ -726,6 +735,10 @@ struct Solver {
         const size_t qmin = (size_t)(std::min(g_capacity_scale, 1.0) * kRegions * (2 * (double)g_small_max + 2048));
         initcap(D.capQ[0], D.Q[0], (std::max(sc(2), qmin) + kRegions - 1) / kRegions * kRegions);
         initcap(D.capQ[1], D.Q[1], (std::max(sc(2), qmin) + kRegions - 1) / kRegions * kRegions);
+        if (D.capTiny < sc(hdb ? 4 : 1)) {
+            D.capTiny = sc(hdb ? 4 : 1);
+            D.tiny.ensure(D.capTiny * sizeof(uint4));
+        }
         if (D.capBig < sc(0.125)) {
             D.capBig = sc(0.125);
             D.big.ensure(D.capBig * 8);
@@ -775,6 +788,7 @@ struct Solver {
             read_counters(D, s);
             check_errors(D);  // flags raised by the previous round's last kernels
             D.hcnt->c[C_FAR] = epoch ? 0u : nFF;  // far appends go after the retained pairs
+            D.hcnt->c[C_TINY] = 0;
             write_counters(D, *D.hcnt, s);
             const Counters round_start = *D.hcnt;
             int levels = 0;
@@ -864,7 +878,20 @@ struct Solver {
                     }
                 }
                 if (!restart) {
+                    // small separated pairs: brute-force BCCP, one pair per thread
+                    const u32 ntiny = std::min<u32>(D.hcnt->c[C_TINY], (u32)D.capTiny);
+                    if (ntiny) {
+                        TIMED(GEOMST_K_BCCP);
+                        RoundArgs r = args(beta2, fo, 0, po);
+                        k_tiny_bccp<D_><<<std::min(blocks(ntiny, kTinyTile), (unsigned)kGrid), kBlock, 0, s>>>(
+                            t, r, hdb, D.tiny.as<uint4>(), ntiny);
+                        LAUNCHCHK();
+                    }
                     nbig = D.hcnt->c[C_BIG];
+                    if (!nbig && ntiny) {
+                        read_counters(D, s);
+                        if (D.hcnt->c[C_ERR] & 1u) restart = true;
+                    }
                     if (nbig) {
                         D.ntask.ensure((size_t)nbig * 4);
                         D.toff.ensure((size_t)nbig * 4);
@@ -1384,7 +1411,7 @@ struct Request {
 // capacities and, for HDBSCAN*, core distances and node core-distance ranges.
 size_t request_footprint(int64_t n, int d, int min_pts) {
     size_t node = d <= 3 ? 64 : 128;
-    return (size_t)n * (640 + 2 * node + 16 * (size_t)d + (min_pts > 0 ? 320 : 0));
+    return (size_t)n * (656 + 2 * node + 16 * (size_t)d + (min_pts > 0 ? 368 : 0));
 }
 
 struct Server {

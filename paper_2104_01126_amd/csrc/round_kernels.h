@@ -33,6 +33,7 @@ enum CounterSlot {
     C_ALIVE,   // Boruvka: edges still undecided after this step
     C_ERR,     // device-side error flags
     C_FAR,     // far frontier out
+    C_TINY,    // small separated pairs for the inline BCCP kernel
     C_NUM
 };
 enum CounterSlot64 { C64_EVALS = 0, C64_VISITS, C64_BCCP, C64_BIGEVALS, C64_TASKS, C64_NUM };
@@ -70,6 +71,8 @@ struct RoundArgs {
     u32 cap_q;
     uint2* big;
     u32 cap_big;
+    uint4* tiny;  // {first A, first B, count A << 16 | count B, 0}
+    u32 cap_tiny;
     EdgeList c;
     u32 cap_c;
     EdgeList pout;
@@ -512,8 +515,8 @@ __global__ void __launch_bounds__(kBlock) k_split_far(TreeView t, RoundArgs r, c
 // One breadth-first level of the FindPair recursion (Alg. 1).  Each lane
 // takes one pair: a pair whose points are all in one component is dropped; a
 // pair whose weight lower bound exceeds beta is parked in the frontier; a
-// well-separated pair yields its BCCP edge (computed here when it has at most
-// kTinyEvals point pairs, else queued for the large-pair kernel); otherwise
+// well-separated pair is queued for its BCCP edge (for k_tiny_bccp when it has
+// at most kTinyEvals point pairs, else for the large-pair kernel); otherwise
 // the node with the larger bounding sphere is split, and each child pair goes
 // to the frontier (bound above beta) or to the next level.  Connectivity of a
 // child pair is checked when it is expanded.
@@ -530,8 +533,8 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
                                            bool have, u32 i, PairRec* qout, u32 cap_qout, u32* const* ctr,
                                            BlockAlloc& S, LevelAcc& acc) {
     const NodeRec<D>* N = nodes_of<D>(t);
-    bool to_c = false, to_p = false, to_big = false, to_f = false;
-    EdgeOut e;
+    bool to_tiny = false, to_big = false, to_f = false;
+    uint4 tp = make_uint4(0u, 0u, 0u, 0u);
     u32 a = 0, b = 0, oth = 0;
     int2 ch = make_int2(0, 0);
     double lb = 0.0;
@@ -554,17 +557,10 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
             } else if (well_separated<D>(A, B, hdb, ca, cb, r.sep, dA, dB)) {
                 u64 work = (u64)A.count * (u64)B.count;
                 if (work <= (u64)kTinyEvals) {
-                    e = point_edge<D>(t, hdb, (u32)A.first, (u32)B.first);
-                    for (int x = A.first; x < A.first + A.count; ++x)
-                        for (int y = B.first; y < B.first + B.count; ++y) {
-                            EdgeOut c = point_edge<D>(t, hdb, (u32)x, (u32)y);
-                            if (key_less(c.k, e.k)) e = c;
-                        }
-                    acc.evals += work;
-                    ++acc.solved;
-                    to_c = e.k.w2 <= r.beta2;
-                    to_p = !to_c;
-                    if (to_p) acc.minp = fmin(acc.minp, e.k.w2);
+                    // solved by k_tiny_bccp after the level loop, away from
+                    // this step's barriers
+                    to_tiny = true;
+                    tp = make_uint4((u32)A.first, (u32)B.first, ((u32)A.count << 16) | (u32)B.count, 0u);
                 } else {
                     to_big = true;
                 }
@@ -622,15 +618,11 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
             acc.minfar = fmin(acc.minfar, wp[k].lb2);
         }
     }
-    u32 cnt[kLists] = {(u32)to_c, (u32)to_p, (u32)to_big, nn, nf, nq2};
+    u32 cnt[kLists] = {(u32)to_tiny, 0u, (u32)to_big, nn, nf, nq2};
     u32 off[kLists];
     block_alloc(S, cnt, ctr, off);
-    if (to_c) {
-        if (off[0] < r.cap_c) put_edge(r.c, off[0], e);
-        else flag_overflow(r.cnt);
-    }
-    if (to_p) {
-        if (off[1] < r.cap_p) put_edge(r.pout, off[1], e);
+    if (to_tiny) {
+        if (off[0] < r.cap_tiny) r.tiny[off[0]] = tp;
         else flag_overflow(r.cnt);
     }
     if (to_big) {
@@ -717,7 +709,7 @@ k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const 
     const u32 j = blockIdx.x / kRegions, g = gridDim.x / kRegions;
     const u32 lo = (u32)((u64)nq * x / kRegions), hi = (u32)((u64)nq * (x + 1) / kRegions);
     if (lo + j * NT >= hi) return;
-    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR],
+    u32* ctr[kLists] = {&r.cnt->c[C_TINY], nullptr, &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR],
                         slot_next + x * kRegionStride};
     PairRec* qout = r.q + (size_t)x * r.cap_q;
     const double inf_ = __longlong_as_double(0x7ff0000000000000ll);
@@ -758,7 +750,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_level_small(TreeView t, RoundAr
     while (nq > 0 && nq <= small_max) {
         if (threadIdx.x == 0) qn = 0;
         __syncthreads();
-        u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR], &qn};
+        u32* ctr[kLists] = {&r.cnt->c[C_TINY], nullptr, &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR], &qn};
         const PairRec* qin = b ? q1 : q0;
         PairRec* qout = b ? q0 : q1;
         const u32 capi = b ? cap1 : cap0, capo = b ? cap0 : cap1;
@@ -784,6 +776,73 @@ __global__ void __launch_bounds__(kSmallBlock) k_level_small(TreeView t, RoundAr
     if (threadIdx.x == 0) {
         state[0] = nq;
         state[1] = (u32)b;
+    }
+}
+
+// ------------------------------------------------------------ small pairs
+// BCCP (or BCCP*) of the separated pairs with at most kTinyEvals point pairs,
+// queued by the level steps: one pair per thread, kTinyItems pairs per
+// thread per block step, by brute force over the point pairs.  The edge goes
+// to the committed list when its weight is within beta, else to the pool.
+constexpr int kTinyItems = 4;
+constexpr int kTinyTile = kTinyItems * kBlock;
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_tiny_bccp(TreeView t, RoundArgs r, int hdb, const uint4* tiny, u32 ntiny) {
+    __shared__ BlockAlloc S;
+    __shared__ double shm[kBlock / kWave];
+    __shared__ unsigned long long shs[kBlock / kWave];
+    u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], nullptr, nullptr, nullptr, nullptr};
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    double minp = inf;
+    unsigned long long evals = 0, solved = 0;
+    for (u32 b0 = blockIdx.x * kTinyTile; b0 < ntiny; b0 += gridDim.x * kTinyTile) {
+        EdgeOut e[kTinyItems];
+        u32 cls = 0, nc = 0, np = 0;
+#pragma unroll
+        for (int k = 0; k < kTinyItems; ++k) {
+            const u32 i = b0 + k * kBlock + threadIdx.x;
+            if (i < ntiny) {
+                const uint4 q = tiny[i];
+                const u32 ca = q.z >> 16, cb = q.z & 0xffffu;
+                e[k] = point_edge<D>(t, hdb, q.x, q.y);
+                for (u32 x = q.x; x < q.x + ca; ++x)
+                    for (u32 y = q.y; y < q.y + cb; ++y) {
+                        EdgeOut c = point_edge<D>(t, hdb, x, y);
+                        if (key_less(c.k, e[k].k)) e[k] = c;
+                    }
+                evals += (unsigned long long)ca * cb;
+                ++solved;
+                const bool in = e[k].k.w2 <= r.beta2;
+                cls |= (in ? 1u : 2u) << (2 * k);
+                nc += in;
+                np += !in;
+                if (!in) minp = fmin(minp, e[k].k.w2);
+            }
+        }
+        u32 cnt[kLists] = {nc, np, 0u, 0u, 0u, 0u};
+        u32 off[kLists];
+        block_alloc(S, cnt, ctr, off);
+#pragma unroll
+        for (int k = 0; k < kTinyItems; ++k) {
+            const u32 c = (cls >> (2 * k)) & 3u;
+            if (c == 1u) {
+                if (off[0] < r.cap_c) put_edge(r.c, off[0], e[k]);
+                else flag_overflow(r.cnt);
+                ++off[0];
+            } else if (c == 2u) {
+                if (off[1] < r.cap_p) put_edge(r.pout, off[1], e[k]);
+                else flag_overflow(r.cnt);
+                ++off[1];
+            }
+        }
+    }
+    block_atomic_min(minp, &r.cnt->m[M_P], shm);
+    const unsigned long long ev = block_sum_u64(evals, shs);
+    const unsigned long long so = block_sum_u64(solved, shs);
+    if (threadIdx.x == 0 && so) {
+        atomicAdd(&r.cnt->c64[C64_EVALS], ev);
+        atomicAdd(&r.cnt->c64[C64_BCCP], so);
     }
 }
 
