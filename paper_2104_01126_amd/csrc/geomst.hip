@@ -883,7 +883,7 @@ struct Solver {
                     if (ntiny) {
                         TIMED(GEOMST_K_BCCP);
                         RoundArgs r = args(beta2, fo, 0, po);
-                        k_tiny_bccp<D_><<<std::min(blocks(ntiny, kTinyTile), (unsigned)kGrid), kBlock, 0, s>>>(
+                        k_tiny_bccp<D_><<<std::min(blocks(ntiny, kTinyTile), (unsigned)kTinyGrid), kTinyBlock, 0, s>>>(
                             t, r, hdb, D.tiny.as<uint4>(), ntiny);
                         LAUNCHCHK();
                     }

@@ -160,6 +160,19 @@ struct EdgeOut {
     u32 i, j;  // sorted positions
 };
 
+// The weight and squared distance of point_edge alone (same operations).
+template <int D>
+__device__ __forceinline__ void point_w2(const TreeView& t, int hdb, u32 i, u32 j, double& w2, double& e2) {
+    e2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double x = t.X[(size_t)i * D + k] - t.X[(size_t)j * D + k];
+        e2 = e2 + x * x;
+    }
+    w2 = e2;
+    if (hdb) w2 = fmax(fmax(t.cd2[i], t.cd2[j]), e2);
+}
+
 template <int D>
 __device__ __forceinline__ EdgeOut point_edge(const TreeView& t, int hdb, u32 i, u32 j) {
     EdgeOut o;
@@ -784,14 +797,17 @@ __global__ void __launch_bounds__(kSmallBlock) k_level_small(TreeView t, RoundAr
 // queued by the level steps: one pair per thread, kTinyItems pairs per
 // thread per block step, by brute force over the point pairs.  The edge goes
 // to the committed list when its weight is within beta, else to the pool.
-constexpr int kTinyItems = 4;
-constexpr int kTinyTile = kTinyItems * kBlock;
+constexpr int kTinyBlock = 256;
+constexpr int kTinyItems = 2;
+constexpr int kTinyTile = kTinyItems * kTinyBlock;
+constexpr int kTinyGrid = 1024;
 
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_tiny_bccp(TreeView t, RoundArgs r, int hdb, const uint4* tiny, u32 ntiny) {
+__global__ void __launch_bounds__(kTinyBlock) k_tiny_bccp(TreeView t, RoundArgs r, int hdb, const uint4* tiny,
+                                                          u32 ntiny) {
     __shared__ BlockAlloc S;
-    __shared__ double shm[kBlock / kWave];
-    __shared__ unsigned long long shs[kBlock / kWave];
+    __shared__ double shm[kTinyBlock / kWave];
+    __shared__ unsigned long long shs[kTinyBlock / kWave];
     u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], nullptr, nullptr, nullptr, nullptr};
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
     double minp = inf;
@@ -801,16 +817,29 @@ __global__ void __launch_bounds__(kBlock) k_tiny_bccp(TreeView t, RoundArgs r, i
         u32 cls = 0, nc = 0, np = 0;
 #pragma unroll
         for (int k = 0; k < kTinyItems; ++k) {
-            const u32 i = b0 + k * kBlock + threadIdx.x;
+            const u32 i = b0 + k * kTinyBlock + threadIdx.x;
             if (i < ntiny) {
                 const uint4 q = tiny[i];
                 const u32 ca = q.z >> 16, cb = q.z & 0xffffu;
-                e[k] = point_edge<D>(t, hdb, q.x, q.y);
+                // minimum of (w2, e2); the identifiers are read only to break
+                // an exact tie of both, and once for the winner
+                double bw = inf, be = inf;
+                u32 bx = q.x, by = q.y;
                 for (u32 x = q.x; x < q.x + ca; ++x)
                     for (u32 y = q.y; y < q.y + cb; ++y) {
-                        EdgeOut c = point_edge<D>(t, hdb, x, y);
-                        if (key_less(c.k, e[k].k)) e[k] = c;
+                        double w2, e2;
+                        point_w2<D>(t, hdb, x, y, w2, e2);
+                        bool better = w2 < bw || (w2 == bw && e2 < be);
+                        if (w2 == bw && e2 == be)
+                            better = key_less(point_edge<D>(t, hdb, x, y).k, point_edge<D>(t, hdb, bx, by).k);
+                        if (better) {
+                            bw = w2;
+                            be = e2;
+                            bx = x;
+                            by = y;
+                        }
                     }
+                e[k] = point_edge<D>(t, hdb, bx, by);
                 evals += (unsigned long long)ca * cb;
                 ++solved;
                 const bool in = e[k].k.w2 <= r.beta2;
