@@ -307,33 +307,28 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
         HIPCHK(hipStreamSynchronize(s));
         return tie != 0;
     };
-    // after sorting by (w2, d2): does any neighbour pair tie on both?
-    auto tied2 = [&]() -> bool {
+    // after sorting by w2: order the runs of equal w2 by (d2, ids); false if
+    // a run is too long for that
+    auto fix_runs = [&]() -> bool {
         HIPCHK(hipMemsetAsync(tieflag, 0, 4, s));
-        k_flag_ties2<<<gg, kBlock, 0, s>>>(L, va, m, tieflag);
+        k_fix_runs<<<gg, kBlock, 0, s>>>(L, ka, va, m, tieflag);
         LAUNCHCHK();
-        u32 tie = 0;
-        HIPCHK(hipMemcpyAsync(&tie, tieflag, 4, hipMemcpyDeviceToHost, s));
+        u32 longrun = 0;
+        HIPCHK(hipMemcpyAsync(&longrun, tieflag, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        return tie != 0;
+        return longrun == 0;
     };
-    // fast path: order by w2 (EMST) or (w2, d2) (HDBSCAN*) and keep it when no
-    // two keys tie; otherwise the full order, least significant word first.
     // Batched output: the instance is the most significant word.
     auto finish = [&]() -> u32* {
         if (pinst) word(va, 3, false);
         return va;
     };
-    if (!hdb) {
-        if (!word(nullptr, 2, true)) return finish();
-        word(nullptr, 0, false);
-        word(va, 2, false);
-        return finish();
-    }
-    word(nullptr, 1, false);
-    if (!word(va, 2, true) || !tied2()) return finish();
+    // fast path: order by w2; done when no two keys tie, or when every run of
+    // equal w2 is short enough to be ordered in place by (d2, ids); otherwise
+    // the full order, least significant word first
+    if (!word(nullptr, 2, true) || fix_runs()) return finish();
     word(nullptr, 0, false);
-    word(va, 1, false);
+    if (hdb) word(va, 1, false);
     word(va, 2, false);
     return finish();
 }

@@ -1316,14 +1316,39 @@ __global__ void k_flag_ties(const u64* key, u32 m, u32* flag) {
     if (__any(tie) && lane_id() == 0) atomicOr(flag, 1u);
 }
 
-// Flags whether two neighbours of a permutation tie on both w2 and d2.
-__global__ void k_flag_ties2(const EdgeList L, const u32* perm, u32 m, u32* flag) {
-    bool tie = false;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x + 1; i < m; i += gridDim.x * blockDim.x) {
-        u32 a = perm[i - 1], b = perm[i];
-        tie |= L.w2[a] == L.w2[b] && L.e2[a] == L.e2[b];
+// After a sort by w2 (keys `key`, permutation `val`): order every run of
+// equal w2 by (d2, ids) in place, which completes the order K.  One thread
+// per run, insertion sort through the permutation; a run longer than kRunMax
+// is left alone and flagged (the caller then sorts by every word).
+constexpr u32 kRunMax = 64;
+
+__global__ void __launch_bounds__(kBlock) k_fix_runs(const EdgeList L, const u64* key, u32* val, u32 m,
+                                                     u32* longrun) {
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        const u64 k = key[i];
+        if (i > 0 && key[i - 1] == k) continue;  // not the first of its run
+        u32 j = i + 1;
+        while (j < m && j - i <= kRunMax && key[j] == k) ++j;
+        const u32 len = j - i;
+        if (len == 1) continue;
+        if (len > kRunMax) {
+            atomicOr(longrun, 1u);
+            continue;
+        }
+        for (u32 a = i + 1; a < j; ++a) {
+            const u32 v = val[a];
+            const u64 ve = dbits(L.e2[v]), vi = L.ids[v];
+            u32 b = a;
+            while (b > i) {
+                const u32 u = val[b - 1];
+                const u64 ue = dbits(L.e2[u]), ui = L.ids[u];
+                if (ue < ve || (ue == ve && ui < vi)) break;
+                val[b] = u;
+                --b;
+            }
+            val[b] = v;
+        }
     }
-    if (__any(tie) && lane_id() == 0) atomicOr(flag, 1u);
 }
 
 // Instance of every arena row (instances packed in order; binary search in
