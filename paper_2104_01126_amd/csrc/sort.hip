@@ -1,7 +1,8 @@
 // Generic device primitives: prefix sums and stable LSD radix sorts (gfx950).
 //
 // The radix sort is the classic three-step pass (per-tile digit histograms,
-// an exclusive scan of the digit-major histogram table, a stable scatter).
+// an exclusive scan of the digit-major histogram table, a stable scatter),
+// three launches per 8-bit digit.
 // Stability inside a tile comes from processing the tile in (iteration,
 // wave, lane) order, which is the element order, and ranking equal digits
 // inside a wave with ballots; the scatter stages the ranked tile in LDS and
@@ -102,6 +103,7 @@ struct PairKeys {
     const u64* key;
     __device__ __forceinline__ u32 digit(size_t e, int shift) const { return (u32)(key[e] >> shift) & 255u; }
 };
+// Per-tile digit counts into the digit-major table.
 template <class K>
 __global__ void __launch_bounds__(kThreads) k_radix_hist(K keys, size_t count, int shift, u32* hist, u32 nblocks) {
     __shared__ u32 h[256];
@@ -116,13 +118,41 @@ __global__ void __launch_bounds__(kThreads) k_radix_hist(K keys, size_t count, i
     hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// Block d scans row d of the table (digit d's per-tile counts) in place and
+// stores the digit's total; the scatter adds the totals of the smaller digits.
+// One launch and no atomics.
+__global__ void __launch_bounds__(kThreads) k_radix_rowscan(u32* hist, u32 nblocks, u32* totals) {
+    const u32 d = blockIdx.x;
+    u32 run = 0;
+    u32* row = hist + (size_t)d * nblocks;
+    for (u32 c0 = 0; c0 < nblocks; c0 += kTile) {
+        const u32 b = c0 + threadIdx.x * kItems;
+        u32 v[kItems];
+        u32 sum = 0;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            v[i] = b + i < nblocks ? row[b + i] : 0u;
+            sum += v[i];
+        }
+        u32 tot;
+        u32 off = run + block_excl_scan(sum, &tot);
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            if (b + i < nblocks) row[b + i] = off;
+            off += v[i];
+        }
+        run += tot;
+    }
+    if (threadIdx.x == 0) totals[d] = run;
+}
+
 // Key-value scatter through LDS: the tile is first ranked into digit order in
 // LDS (stable, as above), then written out so that consecutive threads write
 // consecutive slots of one digit's run: coalesced stores instead of one
 // scattered store per element.
 __global__ void __launch_bounds__(kThreads) k_radix_scatter_lds(const u64* ki, const u32* vi, u64* ko, u32* vo,
                                                                 size_t count, int shift, const u32* offs,
-                                                                u32 nblocks) {
+                                                                u32 nblocks, const u32* totals) {
     __shared__ u64 sk[kTile];
     __shared__ u32 sv[kTile];
     __shared__ u32 lstart[256], gbase[256], run[256];
@@ -152,9 +182,10 @@ __global__ void __launch_bounds__(kThreads) k_radix_scatter_lds(const u64* ki, c
     __syncthreads();
     u32 tot;
     const u32 ex = block_excl_scan(run[t], &tot);
+    const u32 dbase = block_excl_scan(totals[t], &tot);  // elements of the smaller digits
     lstart[t] = ex;
     run[t] = ex;
-    gbase[t] = offs[(size_t)t * nblocks + blockIdx.x];
+    gbase[t] = dbase + offs[(size_t)t * nblocks + blockIdx.x];
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
@@ -211,7 +242,7 @@ size_t scan_temp_bytes(size_t count) {
 size_t radix_temp_bytes(size_t count) {
     size_t nb = cdiv(count ? count : 1, kTile);
     size_t h = nb * 256;
-    return (cdiv(h, 64) * 64) * sizeof(u32) + scan_temp_bytes(h);
+    return (cdiv(h, 64) * 64 + 256) * sizeof(u32);
 }
 
 void scan_exclusive_u32(const u32* in, u32* out, size_t count, void* temp, hipStream_t s) {
@@ -226,17 +257,19 @@ int radix_sort_pairs(u64* key, u32* val, u64* key2, u32* val2, size_t count, int
     if (count <= 1 || bits <= 0) return 0;
     u32 nb = (u32)cdiv(count, kTile);
     u32* hist = (u32*)temp;
-    void* stemp = (char*)temp + cdiv((size_t)nb * 256, 64) * 64 * sizeof(u32);
+    u32* totals = hist + cdiv((size_t)nb * 256, 64) * 64;  // 256 digit totals
+    const int passes = (std::min(bits, 64) + 7) / 8;
     int flip = 0;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
         u64* ki = flip ? key2 : key;
         u32* vi = flip ? val2 : val;
         u64* ko = flip ? key : key2;
         u32* vo = flip ? val : val2;
         PairKeys K{ki};
         k_radix_hist<<<nb, kThreads, 0, s>>>(K, count, shift, hist, nb);
-        scan_exclusive_u32(hist, hist, (size_t)nb * 256, stemp, s);
-        k_radix_scatter_lds<<<nb, kThreads, 0, s>>>(ki, vi, ko, vo, count, shift, hist, nb);
+        k_radix_rowscan<<<256, kThreads, 0, s>>>(hist, nb, totals);
+        k_radix_scatter_lds<<<nb, kThreads, 0, s>>>(ki, vi, ko, vo, count, shift, hist, nb, totals);
         flip ^= 1;
     }
     return flip;
