@@ -168,7 +168,7 @@ struct Device {
     size_t capFF[2] = {0, 0};
     EdgeBufs C, P[2], OUT;
     // Kruskal
-    DBuf kid, ke2, kw2, perm[2], alive[2], ru, rv, nalive, minmax;
+    DBuf kid, ke2, kw2, perm[2], alive[2], apos[2], ru, rv, nalive, minmax;
     DBuf birange, bik, browinst;  // batched solves: instance table and row -> instance
     Prof profm;
     Prof* prof = nullptr;
@@ -951,14 +951,16 @@ struct Solver {
                 u32* perm = sort_edges(D, L, m, n, hdb, s);
                 D.alive[0].ensure((size_t)m * 4);
                 D.alive[1].ensure((size_t)m * 4);
+                D.apos[0].ensure((size_t)m * 8);
+                D.apos[1].ensure((size_t)m * 8);
                 D.ru.ensure((size_t)m * 4);
                 D.rv.ensure((size_t)m * 4);
                 D.nalive.ensure(8);
-                k_iota<<<blocks(m, 256), 256, 0, s>>>(D.alive[0].as<u32>(), m);
+                unsigned gk = std::min(blocks(m, kBlock), (unsigned)kGrid);
+                k_alive_init<<<gk, kBlock, 0, s>>>(perm, L, m, D.alive[0].as<u32>(), D.apos[0].as<u64>());
                 LAUNCHCHK();
                 k_set_u32<<<1, 1, 0, s>>>(D.nalive.as<u32>(), m);
                 LAUNCHCHK();
-                unsigned gk = std::min(blocks(m, kBlock), (unsigned)kGrid);
                 int ac = 0;
                 while (true) {
                     for (int j = 0; j < kBoruvkaBatch; ++j) {
@@ -966,14 +968,14 @@ struct Solver {
                         u32* na_in = D.nalive.as<u32>() + ac;
                         u32* na_out = D.nalive.as<u32>() + (ac ^ 1);
                         const u32 stamp = --bstamp;  // decreasing: this step's keys beat older ones
-                        k_bor_pick<<<gk, kBlock, 0, s>>>(D.alive[ac].as<u32>(), na_in, m, perm, L, D.uf.as<u32>(),
-                                                        D.best.as<u64>(), stamp, D.ru.as<u32>(), D.rv.as<u32>(),
-                                                        na_out, D.cnt.as<Counters>());
+                        k_bor_pick<<<gk, kBlock, 0, s>>>(D.alive[ac].as<u32>(), D.apos[ac].as<u64>(), na_in, m,
+                                                        D.uf.as<u32>(), D.best.as<u64>(), stamp, D.ru.as<u32>(),
+                                                        D.rv.as<u32>(), na_out, D.cnt.as<Counters>());
                         LAUNCHCHK();
-                        k_bor_hook<<<std::min(blocks(m, kHookTile), 256u), kHookBlock, 0, s>>>(D.alive[ac].as<u32>(), na_in, m, perm, L, D.uf.as<u32>(),
-                                                        D.best.as<u64>(), stamp, D.ru.as<u32>(), D.rv.as<u32>(),
-                                                        D.alive[ac ^ 1].as<u32>(), na_out, D.OUT.list(),
-                                                        (u32)D.OUT.cap, D.cnt.as<Counters>());
+                        k_bor_hook<<<std::min(blocks(m, kHookTile), 256u), kHookBlock, 0, s>>>(
+                            D.alive[ac].as<u32>(), D.apos[ac].as<u64>(), na_in, m, perm, L, D.uf.as<u32>(),
+                            D.best.as<u64>(), stamp, D.ru.as<u32>(), D.rv.as<u32>(), D.alive[ac ^ 1].as<u32>(),
+                            D.apos[ac ^ 1].as<u64>(), na_out, D.OUT.list(), (u32)D.OUT.cap, D.cnt.as<Counters>());
                         LAUNCHCHK();
                         ac ^= 1;
                     }

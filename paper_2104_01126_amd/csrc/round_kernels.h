@@ -1391,14 +1391,23 @@ __device__ __forceinline__ u32 uf_find(u32* parent, u32 x, Counters* cnt) {
 // best[c] holds (stamp << 32 | rank) of component c's lightest edge in the
 // step with that stamp; stamps decrease step by step, so a new step's keys
 // win over stale ones without clearing the array between steps.
-__global__ void k_bor_pick(const u32* alive, const u32* nalive_p, u32 cap, const u32* perm, const EdgeList L,
-                           u32* parent, u64* best, u32 stamp, u32* ru, u32* rv, u32* nalive_next, Counters* cnt) {
+// The alive list holds each undecided edge's rank and, alongside, its two
+// end positions (apos), so the step reads them without the permutation.
+__global__ void k_alive_init(const u32* perm, const EdgeList L, u32 m, u32* alive, u64* apos) {
+    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < m; s += gridDim.x * blockDim.x) {
+        alive[s] = s;
+        apos[s] = L.pos[perm[s]];
+    }
+}
+
+__global__ void k_bor_pick(const u32* alive, const u64* apos, const u32* nalive_p, u32 cap, u32* parent, u64* best,
+                           u32 stamp, u32* ru, u32* rv, u32* nalive_next, Counters* cnt) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *nalive_next = 0;  // the hook step appends after this kernel
     const u32 na = min(*nalive_p, cap);
     for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < na; s += gridDim.x * blockDim.x) {
     u32 rank = alive[s];
     const u64 key = ((u64)stamp << 32) | rank;
-    u64 pos = L.pos[perm[rank]];
+    u64 pos = apos[s];
     u32 a = uf_find(parent, (u32)(pos >> 32), cnt);
     u32 b = uf_find(parent, (u32)pos, cnt);
     if (a == b) {
@@ -1420,21 +1429,23 @@ constexpr int kHookBlock = 1024;
 constexpr int kHookItems = 4;
 constexpr int kHookTile = kHookBlock * kHookItems;
 
-__global__ void __launch_bounds__(kHookBlock) k_bor_hook(const u32* alive, const u32* nalive_p, u32 cap,
-                                                         const u32* perm, const EdgeList L, u32* parent,
+__global__ void __launch_bounds__(kHookBlock) k_bor_hook(const u32* alive, const u64* apos, const u32* nalive_p,
+                                                         u32 cap, const u32* perm, const EdgeList L, u32* parent,
                                                          const u64* best, u32 stamp, const u32* ru, const u32* rv,
-                                                         u32* alive_next, u32* nalive_next, EdgeList out,
-                                                         u32 cap_out, Counters* cnt) {
+                                                         u32* alive_next, u64* apos_next, u32* nalive_next,
+                                                         EdgeList out, u32 cap_out, Counters* cnt) {
     __shared__ BlockAlloc S;
     const u32 na = min(*nalive_p, cap);
     u32* ctr[kLists] = {&cnt->c[C_OUT], nalive_next, nullptr, nullptr, nullptr, nullptr};
     for (u32 b0 = blockIdx.x * kHookTile; b0 < na; b0 += gridDim.x * kHookTile) {
         u32 sel = 0, keep = 0, ns = 0, nk = 0;
         u32 rank[kHookItems];
+        u32 src[kHookItems];
 #pragma unroll
         for (int k = 0; k < kHookItems; ++k) {
             const u32 s = b0 + k * kHookBlock + threadIdx.x;
             rank[k] = 0;
+            src[k] = s;
             const u32 a = s < na ? ru[s] : kNone;
             if (a == kNone) continue;
             const u32 b = rv[s];
@@ -1469,7 +1480,10 @@ __global__ void __launch_bounds__(kHookBlock) k_bor_hook(const u32* alive, const
                 ++off[0];
             }
             if ((keep >> k) & 1u) {
-                if (off[1] < cap) alive_next[off[1]] = rank[k];
+                if (off[1] < cap) {
+                    alive_next[off[1]] = rank[k];
+                    apos_next[off[1]] = apos[src[k]];
+                }
                 ++off[1];
             }
         }
