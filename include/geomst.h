@@ -254,6 +254,10 @@ int geomst_get_stats(geomst_stats_t* out);
  *   "beta_growth"    factor applied to the weight threshold between rounds,
  *                    > 1; 0 restores the default (2 for EMST: the threshold
  *                    doubles each round; sqrt(2) for HDBSCAN*).
+ *   "beta_start_quantile"  [0, 1]: the first threshold is the low edge of the
+ *                    binary64 binade in which this fraction of the initial
+ *                    pairs' positive lower bounds is reached (default 0:
+ *                    the smallest positive bound).
  *   "list_capacity_scale"  (0,1]: scale of the initial capacities of the
  *                    internal pair and edge lists (default 1); small values make
  *                    the lists overflow, grow and restart rounds (a testing aid).

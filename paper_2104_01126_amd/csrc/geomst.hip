@@ -35,6 +35,7 @@ double g_beta_growth = 0.0;  // 0: 2 for EMST, sqrt(2) for HDBSCAN*
 double g_separation = 2.0;   // s of the sphere separation test
 int g_bccp_chunk = kBigBDefault;  // B points per large-pair BCCP task
 double g_capacity_scale = 1.0;
+double g_beta_start = 0.0;  // fraction of the initial pair bounds below the first threshold (0: the smallest)
 constexpr int kMaxKeyLevels = 6;  // Morton key words per point (see k_morton_level)
 constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
 u32 g_refresh_div = 1024;    // refresh node components once a round merged n / this many
@@ -151,6 +152,7 @@ struct Device {
     bool init = false;
     hipStream_t own = nullptr;
     Counters* hcnt = nullptr;  // pinned mirror
+    u32* hpin = nullptr;       // pinned words read back together with the counters
     DBuf cnt;
     // input staging (host API)
     DBuf pin, eout, wout, cdout;
@@ -160,7 +162,7 @@ struct Device {
     // union-find / component refresh
     DBuf uf, best, bnd, incl;
     // rounds
-    DBuf F[2], Q[2], big, ntask, toff, parts, qring, lstate;
+    DBuf F[2], Q[2], big, ntask, toff, parts, qring, lstate, lbhist;
     size_t qmax_seen = 0;
     size_t capF[2] = {0, 0}, capQ[2] = {0, 0}, capBig = 0, capTiny = 0;
     DBuf tiny;  // small separated pairs of the current round
@@ -175,6 +177,7 @@ struct Device {
     ~Device() {
         if (own) (void)hipStreamDestroy(own);
         if (hcnt) (void)hipHostFree(hcnt);
+        if (hpin) (void)hipHostFree(hpin);
     }
 };
 
@@ -211,12 +214,6 @@ struct TimedScope {
 };
 #define TIMED(fam) TimedScope timed_scope_(*D.prof, s, fam)
 
-void counters_reset_round(Device& D, hipStream_t s) {
-    // zero the per-round counters and set the minima to "none" (all ones)
-    HIPCHK(hipMemsetAsync(D.cnt.p, 0, sizeof(u32) * C_OUT, s));
-    HIPCHK(hipMemsetAsync((char*)D.cnt.p + offsetof(Counters, m), 0xff, sizeof(u64) * 4, s));
-}
-
 void read_counters(Device& D, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(D.hcnt, D.cnt.p, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -247,6 +244,7 @@ double bits_to_double(u64 b) {
 }
 
 const double kInf = __builtin_inf();
+constexpr int kPinWords = 1024;  // pinned read-back words per device (a ring slot is the largest use)
 
 int id_bits(int n) {
     u32 m = (u32)(n - 1);
@@ -600,15 +598,15 @@ struct Solver {
         return r;
     }
 
-    // Total and largest region count of level-queue ring slot `slot`.
+    // Total and largest region count of level-queue ring slot `slot`, read
+    // together with the counters (one host round trip for both).
     void read_slot(const u32* ring, int slot, u32& total, u32& largest) {
-        u32 h[kSlotWords];
-        HIPCHK(hipMemcpyAsync(h, ring + slot * kSlotWords, sizeof(h), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipMemcpyAsync(D.hpin, ring + slot * kSlotWords, kSlotWords * 4, hipMemcpyDeviceToHost, s));
+        read_counters(D, s);
         total = largest = 0;
         for (int x = 0; x < kRegions; ++x) {
-            total += h[x * kRegionStride];
-            largest = std::max(largest, h[x * kRegionStride]);
+            total += D.hpin[x * kRegionStride];
+            largest = std::max(largest, D.hpin[x * kRegionStride]);
         }
     }
 
@@ -751,15 +749,37 @@ struct Solver {
         int fc = 0, pc = 0, ffc = 0;
         k_init_frontier<D_><<<blocks(n - 1, 256), 256, 0, s>>>(t, hdb, pinst, D.FF[ffc].as<PairRec>());
         LAUNCHCHK();
+        D.lbhist.ensure(kExpBins * 4);
+        HIPCHK(hipMemsetAsync(D.lbhist.p, 0, kExpBins * 4, s));
         k_min_positive_lb<<<std::min(blocks(n - 1, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
-            D.FF[ffc].as<PairRec>(), (u32)(n - 1), D.cnt.as<Counters>());
+            D.FF[ffc].as<PairRec>(), (u32)(n - 1), D.cnt.as<Counters>(), D.lbhist.as<u32>());
         LAUNCHCHK();
+        std::vector<u32> lbh(kExpBins);
+        HIPCHK(hipMemcpyAsync(lbh.data(), D.lbhist.p, kExpBins * 4, hipMemcpyDeviceToHost, s));
         read_counters(D, s);
         u64 b0 = D.hcnt->m[M_F];
         double beta2 = (b0 == ~0ull) ? 0.0 : bits_to_double(b0);
+        const double far_first = beta2;
+        // The first threshold: the low edge of the binade in which the given
+        // fraction of the initial pairs' positive bounds is reached (never
+        // below the smallest bound).  Rounds below it would commit almost
+        // nothing; any start gives the same tree.
+        if (g_beta_start > 0.0 && beta2 > 0.0) {
+            u64 total = 0;
+            for (u32 c : lbh) total += c;
+            const double target = std::max(1.0, std::ceil(g_beta_start * (double)total));
+            u64 cum = 0;
+            for (int e = 0; e < kExpBins; ++e) {
+                cum += lbh[e];
+                if ((double)cum >= target) {
+                    beta2 = std::max(beta2, bits_to_double((u64)e << 52));
+                    break;
+                }
+            }
+        }
         u32 nF = 0, nFF = (u32)(n - 1), nP = 0;
         t_near = -1.0;  // the first round starts a band
-        double far_min = beta2;
+        double far_min = far_first;
         const double growth = g_beta_growth > 0.0 ? g_beta_growth : (hdb ? 1.4142135623730951 : 2.0);
         const double g2 = growth * growth;
         u64 committed = 0, maxf = nF, big_pairs = 0;
@@ -779,12 +799,16 @@ struct Solver {
             const bool epoch = beta2 > t_near;
             if (epoch) t_near = beta2 * g2 * g2 * g2;  // the band covers about three rounds
             ffo = epoch ? (ffc ^ 1) : ffc;
-            counters_reset_round(D, s);
-            read_counters(D, s);
-            check_errors(D);  // flags raised by the previous round's last kernels
-            D.hcnt->c[C_FAR] = epoch ? 0u : nFF;  // far appends go after the retained pairs
+            // per-round counters reset on the device (error flags raised by
+            // the previous round's last kernels stay for the next read), and
+            // mirrored in the host copy, which a restart writes back
+            const u32 far_keep = epoch ? 0u : nFF;  // far appends go after the retained pairs
+            k_round_reset<<<1, kWave, 0, s>>>(D.cnt.as<Counters>(), far_keep);
+            LAUNCHCHK();
+            for (int i = 0; i < C_OUT; ++i) D.hcnt->c[i] = 0;
+            for (int i = 0; i < M_NUM; ++i) D.hcnt->m[i] = ~0ull;
+            D.hcnt->c[C_FAR] = far_keep;
             D.hcnt->c[C_TINY] = 0;
-            write_counters(D, *D.hcnt, s);
             const Counters round_start = *D.hcnt;
             int levels = 0;
             u32 nbig = 0;
@@ -812,7 +836,6 @@ struct Solver {
                             t, r, D.FF[ffc].as<PairRec>(), nFF, ring);
                     LAUNCHCHK();
                 }
-                read_counters(D, s);
                 u32 nq = 0, nq_region = 0;
                 read_slot(ring, 0, nq, nq_region);
                 D.hcnt->c[C_Q] = nq;
@@ -836,16 +859,15 @@ struct Solver {
                                     D.lstate.as<u32>());
                                 LAUNCHCHK();
                             }
-                            u32 st2[2];
-                            HIPCHK(hipMemcpyAsync(st2, D.lstate.p, 8, hipMemcpyDeviceToHost, s));
+                            HIPCHK(hipMemcpyAsync(D.hpin, D.lstate.p, 8, hipMemcpyDeviceToHost, s));
                             read_counters(D, s);
                             ++levels;
                             if (D.hcnt->c[C_ERR] & 1u) {
                                 restart = true;
                                 break;
                             }
-                            nq = st2[0];
-                            lv = (int)st2[1];
+                            nq = D.hpin[0];
+                            lv = (int)D.hpin[1];
                             D.qmax_seen = std::max<size_t>(D.qmax_seen, (size_t)kRegions * nq);  // all in region 0
                             continue;
                         }
@@ -859,7 +881,6 @@ struct Solver {
                                                                  ring + ((lv + 2) % kQRing) * kSlotWords);
                             LAUNCHCHK();
                         }
-                        read_counters(D, s);
                         read_slot(ring, lv % kQRing, nq, nq_region);
                         D.qmax_seen = std::max<size_t>(D.qmax_seen, (size_t)kRegions * nq_region);
                         if (D.hcnt->c[C_ERR] & 1u) {
@@ -899,9 +920,11 @@ struct Solver {
                         scan_exclusive_u32(D.ntask.as<u32>(), D.toff.as<u32>(), nbig, D.stemp.p, s);
                         LAUNCHCHK();
                         u32 last_off = 0, last_cnt = 0;
-                        HIPCHK(hipMemcpyAsync(&last_off, D.toff.as<u32>() + nbig - 1, 4, hipMemcpyDeviceToHost, s));
-                        HIPCHK(hipMemcpyAsync(&last_cnt, D.ntask.as<u32>() + nbig - 1, 4, hipMemcpyDeviceToHost, s));
+                        HIPCHK(hipMemcpyAsync(D.hpin, D.toff.as<u32>() + nbig - 1, 4, hipMemcpyDeviceToHost, s));
+                        HIPCHK(hipMemcpyAsync(D.hpin + 1, D.ntask.as<u32>() + nbig - 1, 4, hipMemcpyDeviceToHost, s));
                         read_counters(D, s);  // synchronises
+                        last_off = D.hpin[0];
+                        last_cnt = D.hpin[1];
                         if (D.hcnt->c64[C64_TASKS] >= (1ull << 31)) {
                             g_err = "the separated pairs of one round need more than 2^31 BCCP tasks";
                             throw Fail{GEOMST_EINTERNAL};
@@ -938,6 +961,7 @@ struct Solver {
                         throw Fail{GEOMST_EINTERNAL};
                     }
                     if (g_trace) fprintf(stderr, "[geomst] round %d: list overflow, growing and restarting\n", rounds);
+                    if (D.hcnt->c[C_ERR] & (4u | 8u)) check_errors(D);  // not an overflow: report it
                     grow_lists(fo, po, epoch ? 0 : nFF);
                     write_counters(D, round_start, s);
                 }
@@ -980,8 +1004,9 @@ struct Solver {
                         ac ^= 1;
                     }
                     u32 left = 0;
-                    HIPCHK(hipMemcpyAsync(&left, D.nalive.as<u32>() + ac, 4, hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipMemcpyAsync(D.hpin, D.nalive.as<u32>() + ac, 4, hipMemcpyDeviceToHost, s));
                     read_counters(D, s);  // one sync for both
+                    left = D.hpin[0];
                     if (left == 0) break;
                 }
             }
@@ -1085,6 +1110,7 @@ void ensure_init(Device& D) {
     if (D.init) return;
     HIPCHK(hipStreamCreateWithFlags(&D.own, hipStreamNonBlocking));
     HIPCHK(hipHostMalloc((void**)&D.hcnt, sizeof(Counters), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&D.hpin, kPinWords * sizeof(u32), hipHostMallocDefault));
     D.cnt.ensure(sizeof(Counters));
     D.prof = &D.profm;
     D.init = true;
@@ -1847,6 +1873,11 @@ int geomst_set_option(const char* name, double value) {
     if (!strcmp(name, "separation")) {
         if (!(value >= 0.0) || !(value <= 16.0)) return GEOMST_EINVAL;
         g_separation = value;
+        return GEOMST_OK;
+    }
+    if (!strcmp(name, "beta_start_quantile")) {
+        if (!(value >= 0.0 && value <= 1.0)) return GEOMST_EINVAL;
+        g_beta_start = value;
         return GEOMST_OK;
     }
     if (!strcmp(name, "list_capacity_scale")) {

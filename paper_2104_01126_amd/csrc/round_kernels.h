@@ -377,12 +377,41 @@ __global__ void k_init_frontier(TreeView t, int hdb, const u32* pinst, PairRec* 
     f[i] = p;
 }
 
-// Smallest positive lower bound over a pair list (the first beta).
-__global__ void __launch_bounds__(kBlock) k_min_positive_lb(const PairRec* f, u32 nf, Counters* cnt) {
+// Start of a round: zero the per-round list counters, set the minima to
+// "none", keep `far_keep` retained far pairs.  The error flags and the
+// running totals are left alone.
+__global__ void k_round_reset(Counters* cnt, u32 far_keep) {
+    const int i = threadIdx.x;
+    if (i < C_OUT) cnt->c[i] = 0;
+    if (i == 0) {
+        cnt->c[C_FAR] = far_keep;
+        cnt->c[C_TINY] = 0;
+    }
+    if (i < M_NUM) cnt->m[i] = ~0ull;
+}
+
+// Smallest positive lower bound over a pair list, and how many of the
+// positive finite bounds fall in each binade (histogram over the binary64
+// exponent): the first beta is chosen from them.
+constexpr int kExpBins = 2048;
+
+__global__ void __launch_bounds__(kBlock) k_min_positive_lb(const PairRec* f, u32 nf, Counters* cnt, u32* hist) {
     __shared__ double sh[4];
-    double v = __longlong_as_double(0x7ff0000000000000ll);
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x)
-        if (f[i].lb2 > 0.0) v = fmin(v, f[i].lb2);  // +inf (cross-instance) never wins
+    __shared__ u32 h[kExpBins];
+    for (int b = threadIdx.x; b < kExpBins; b += kBlock) h[b] = 0;
+    __syncthreads();
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    double v = inf;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x) {
+        const double lb = f[i].lb2;
+        if (lb > 0.0 && lb < inf) {  // +inf (cross-instance) never counts
+            v = fmin(v, lb);
+            atomicAdd(&h[(u32)(dbits(lb) >> 52) & (kExpBins - 1)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kExpBins; b += kBlock)
+        if (h[b]) atomicAdd(&hist[b], h[b]);
     block_atomic_min(v, &cnt->m[M_F], sh);
 }
 

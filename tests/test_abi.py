@@ -74,6 +74,10 @@ def test_options(lib):
     assert lib.geomst_set_option(b"beta_growth", 0.0) == G.OK
     assert lib.geomst_set_option(b"list_capacity_scale", 0.0) == G.EINVAL
     assert lib.geomst_set_option(b"kernel_timing", 2.0) == G.EINVAL
+    assert lib.geomst_set_option(b"beta_start_quantile", 1.5) == G.EINVAL
+    assert lib.geomst_set_option(b"beta_start_quantile", -0.1) == G.EINVAL
+    assert lib.geomst_set_option(b"beta_start_quantile", 1.0 / 64) == G.OK
+    assert lib.geomst_set_option(b"beta_start_quantile", 0.0) == G.OK  # back to the default
 
 
 def _c_layout(exprs):

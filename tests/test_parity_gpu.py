@@ -180,7 +180,8 @@ def test_rejects_non_finite_input(G):
 
 
 def test_repeatable_and_schedule_independent(G):
-    """Same bytes on repeated calls and for any threshold growth factor."""
+    """Same bytes on repeated calls, for any threshold growth factor and any
+    first threshold."""
     p = W.mixture(8000, 3, seed=41, k=9, noise_frac=0.05)
     ref = run_emst(G, p)
     try:
@@ -193,8 +194,15 @@ def test_repeatable_and_schedule_independent(G):
         G.set_option("beta_growth", 4.0)
         h2 = run_hdb(G, p, 7)
         assert all(same(a, b) for a, b in zip(h1, h2))
+        G.set_option("beta_growth", 0)
+        # the first threshold: smallest bound, the default quantile, all pairs
+        for q in (0.0, 0.25, 1.0):
+            G.set_option("beta_start_quantile", q)
+            assert all(same(a, b) for a, b in zip(ref, run_emst(G, p))), q
+            assert all(same(a, b) for a, b in zip(h1, run_hdb(G, p, 7))), q
     finally:
         G.set_option("beta_growth", 0)
+        G.set_option("beta_start_quantile", 0.0)
 
 
 def test_list_overflow_restarts(G):
