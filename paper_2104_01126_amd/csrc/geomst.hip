@@ -244,7 +244,7 @@ double bits_to_double(u64 b) {
 }
 
 const double kInf = __builtin_inf();
-constexpr int kPinWords = 1024;  // pinned read-back words per device (a ring slot is the largest use)
+constexpr int kPinWords = 2048;  // pinned read-back words per device (the bound histogram is the largest use)
 
 int id_bits(int n) {
     u32 m = (u32)(n - 1);
@@ -285,7 +285,7 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
         HIPCHK(hipMemsetAsync(tieflag, 0, 4, s));
         k_gather_word<<<gg, kBlock, 0, s>>>(L, perm, m, kind, B, pinst, ka, va, mm);
         LAUNCHCHK();
-        u64 h[2];
+        u64* h = (u64*)D.hpin;  // pinned
         HIPCHK(hipMemcpyAsync(h, mm, 16, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         u64 diff = h[0] ^ h[1];
@@ -300,10 +300,9 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
         if (!check_ties) return false;
         k_flag_ties<<<gg, kBlock, 0, s>>>(ka, m, tieflag);
         LAUNCHCHK();
-        u32 tie = 0;
-        HIPCHK(hipMemcpyAsync(&tie, tieflag, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(D.hpin, tieflag, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        return tie != 0;
+        return D.hpin[0] != 0;
     };
     // after sorting by w2: order the runs of equal w2 by (d2, ids); false if
     // a run is too long for that
@@ -311,10 +310,9 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
         HIPCHK(hipMemsetAsync(tieflag, 0, 4, s));
         k_fix_runs<<<gg, kBlock, 0, s>>>(L, ka, va, m, tieflag);
         LAUNCHCHK();
-        u32 longrun = 0;
-        HIPCHK(hipMemcpyAsync(&longrun, tieflag, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(D.hpin, tieflag, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        return longrun == 0;
+        return D.hpin[0] == 0;
     };
     // Batched output: the instance is the most significant word.
     auto finish = [&]() -> u32* {
@@ -404,7 +402,7 @@ struct Solver {
             LAUNCHCHK();
             scan_inclusive_u32(D.gflag.as<u32>(), D.gincl.as<u32>(), n, D.stemp.p, s);
             LAUNCHCHK();
-            u32 hv[2] = {0, 0};
+            u32* hv = D.hpin;  // pinned
             HIPCHK(hipMemcpyAsync(hv, D.hflag.p, 4, hipMemcpyDeviceToHost, s));
             HIPCHK(hipMemcpyAsync(hv + 1, D.gincl.as<u32>() + n - 1, 4, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
@@ -416,10 +414,9 @@ struct Solver {
             k_group_box<D_><<<blocks(ngroups, 4), 256, 0, s>>>(P, vala, n, D.gstart.as<u32>(), ngroups,
                                                                 D.gbox.as<double>(), D.hflag.as<u32>() + 1);
             LAUNCHCHK();
-            u32 refinable = 0;
-            HIPCHK(hipMemcpyAsync(&refinable, D.hflag.as<u32>() + 1, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(D.hpin, D.hflag.as<u32>() + 1, 4, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            if (!refinable) break;  // the remaining equal keys belong to coincident points
+            if (!D.hpin[0]) break;  // the remaining equal keys belong to coincident points
             u64* kl = keys + (size_t)L * n;
             k_morton_level<D_><<<blocks(n, 256), 256, 0, s>>>(P, vala, n, D.gid.as<u32>(), D.gstart.as<u32>(),
                                                                ngroups, D.gbox.as<double>(), kl);
@@ -749,13 +746,16 @@ struct Solver {
         int fc = 0, pc = 0, ffc = 0;
         k_init_frontier<D_><<<blocks(n - 1, 256), 256, 0, s>>>(t, hdb, pinst, D.FF[ffc].as<PairRec>());
         LAUNCHCHK();
-        D.lbhist.ensure(kExpBins * 4);
-        HIPCHK(hipMemsetAsync(D.lbhist.p, 0, kExpBins * 4, s));
+        const bool want_hist = g_beta_start > 0.0;
+        if (want_hist) {
+            D.lbhist.ensure(kExpBins * 4);
+            HIPCHK(hipMemsetAsync(D.lbhist.p, 0, kExpBins * 4, s));
+        }
         k_min_positive_lb<<<std::min(blocks(n - 1, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
-            D.FF[ffc].as<PairRec>(), (u32)(n - 1), D.cnt.as<Counters>(), D.lbhist.as<u32>());
+            D.FF[ffc].as<PairRec>(), (u32)(n - 1), D.cnt.as<Counters>(), want_hist ? D.lbhist.as<u32>() : nullptr);
         LAUNCHCHK();
-        std::vector<u32> lbh(kExpBins);
-        HIPCHK(hipMemcpyAsync(lbh.data(), D.lbhist.p, kExpBins * 4, hipMemcpyDeviceToHost, s));
+        const u32* lbh = D.hpin;  // pinned
+        if (want_hist) HIPCHK(hipMemcpyAsync(D.hpin, D.lbhist.p, kExpBins * 4, hipMemcpyDeviceToHost, s));
         read_counters(D, s);
         u64 b0 = D.hcnt->m[M_F];
         double beta2 = (b0 == ~0ull) ? 0.0 : bits_to_double(b0);
@@ -766,7 +766,7 @@ struct Solver {
         // nothing; any start gives the same tree.
         if (g_beta_start > 0.0 && beta2 > 0.0) {
             u64 total = 0;
-            for (u32 c : lbh) total += c;
+            for (int e = 0; e < kExpBins; ++e) total += lbh[e];
             const double target = std::max(1.0, std::ceil(g_beta_start * (double)total));
             u64 cum = 0;
             for (int e = 0; e < kExpBins; ++e) {

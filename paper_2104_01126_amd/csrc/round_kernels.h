@@ -390,9 +390,9 @@ __global__ void k_round_reset(Counters* cnt, u32 far_keep) {
     if (i < M_NUM) cnt->m[i] = ~0ull;
 }
 
-// Smallest positive lower bound over a pair list, and how many of the
-// positive finite bounds fall in each binade (histogram over the binary64
-// exponent): the first beta is chosen from them.
+// Smallest positive lower bound over a pair list and, when `hist` is given,
+// how many of the positive finite bounds fall in each binade (histogram over
+// the binary64 exponent): the first beta is chosen from them.
 constexpr int kExpBins = 2048;
 
 __global__ void __launch_bounds__(kBlock) k_min_positive_lb(const PairRec* f, u32 nf, Counters* cnt, u32* hist) {
@@ -406,12 +406,13 @@ __global__ void __launch_bounds__(kBlock) k_min_positive_lb(const PairRec* f, u3
         const double lb = f[i].lb2;
         if (lb > 0.0 && lb < inf) {  // +inf (cross-instance) never counts
             v = fmin(v, lb);
-            atomicAdd(&h[(u32)(dbits(lb) >> 52) & (kExpBins - 1)], 1u);
+            if (hist) atomicAdd(&h[(u32)(dbits(lb) >> 52) & (kExpBins - 1)], 1u);
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < kExpBins; b += kBlock)
-        if (h[b]) atomicAdd(&hist[b], h[b]);
+    if (hist)
+        for (int b = threadIdx.x; b < kExpBins; b += kBlock)
+            if (h[b]) atomicAdd(&hist[b], h[b]);
     block_atomic_min(v, &cnt->m[M_F], sh);
 }
 
