@@ -308,7 +308,10 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
     // a run is too long for that
     auto fix_runs = [&]() -> bool {
         HIPCHK(hipMemsetAsync(tieflag, 0, 4, s));
-        k_fix_runs<<<gg, kBlock, 0, s>>>(L, ka, va, m, tieflag);
+        D.ke2.ensure((size_t)m * 8);
+        k_run_keys<<<gg, kBlock, 0, s>>>(L, ka, va, m, kb, D.ke2.as<u64>());
+        LAUNCHCHK();
+        k_fix_runs<<<gg, kBlock, 0, s>>>(ka, va, kb, D.ke2.as<u64>(), m, tieflag);
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(D.hpin, tieflag, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));

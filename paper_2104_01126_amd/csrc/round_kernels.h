@@ -1347,12 +1347,27 @@ __global__ void k_flag_ties(const u64* key, u32 m, u32* flag) {
 }
 
 // After a sort by w2 (keys `key`, permutation `val`): order every run of
-// equal w2 by (d2, ids) in place, which completes the order K.  One thread
-// per run, insertion sort through the permutation; a run longer than kRunMax
-// is left alone and flagged (the caller then sorts by every word).
+// equal w2 by (d2, ids) in place, which completes the order K.  First the
+// (d2, ids) of every element that belongs to a run are gathered into sorted
+// order (te, ti), all elements in parallel; then one thread per run
+// insertion-sorts the run's (te, ti, val) in those contiguous arrays.  A run
+// longer than kRunMax is left alone and flagged (the caller then sorts by
+// every word).
 constexpr u32 kRunMax = 64;
 
-__global__ void __launch_bounds__(kBlock) k_fix_runs(const EdgeList L, const u64* key, u32* val, u32 m,
+__global__ void __launch_bounds__(kBlock) k_run_keys(const EdgeList L, const u64* key, const u32* val, u32 m,
+                                                     u64* te, u64* ti) {
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        const u64 k = key[i];
+        if ((i > 0 && key[i - 1] == k) || (i + 1 < m && key[i + 1] == k)) {
+            const u32 v = val[i];
+            te[i] = dbits(L.e2[v]);
+            ti[i] = L.ids[v];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fix_runs(const u64* key, u32* val, u64* te, u64* ti, u32 m,
                                                      u32* longrun) {
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         const u64 k = key[i];
@@ -1367,15 +1382,18 @@ __global__ void __launch_bounds__(kBlock) k_fix_runs(const EdgeList L, const u64
         }
         for (u32 a = i + 1; a < j; ++a) {
             const u32 v = val[a];
-            const u64 ve = dbits(L.e2[v]), vi = L.ids[v];
+            const u64 ve = te[a], vi = ti[a];
             u32 b = a;
             while (b > i) {
-                const u32 u = val[b - 1];
-                const u64 ue = dbits(L.e2[u]), ui = L.ids[u];
+                const u64 ue = te[b - 1], ui = ti[b - 1];
                 if (ue < ve || (ue == ve && ui < vi)) break;
-                val[b] = u;
+                te[b] = ue;
+                ti[b] = ui;
+                val[b] = val[b - 1];
                 --b;
             }
+            te[b] = ve;
+            ti[b] = vi;
             val[b] = v;
         }
     }
