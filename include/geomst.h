@@ -146,7 +146,7 @@ int geomst_batch(geomst_instance_t* inst, int64_t count);
  * identical to solving it alone.
  *
  * Admission estimate per request (device bytes):
- *   n * (656 + 2 * node + 16 * d + (min_pts > 0 ? 368 : 0)),
+ *   n * (664 + 2 * node + 16 * d + (min_pts > 0 ? 368 : 0)),
  *   node = 64 for d <= 3, else 128.
  * Workspaces only grow, so the device memory held by a server is at most
  * about hbm_budget_bytes plus the workspaces' growth beyond the estimate.

@@ -160,7 +160,7 @@ struct Device {
     DBuf keysA, keysB, gflag, gincl, gid, gstart, gbox, hflag;
     DBuf part, bbox, key, val, key2, val2, stemp, X, orig, cd2, nodes, npar, flags, cdr, btop, nrange;
     // union-find / component refresh
-    DBuf uf, best, bnd, incl;
+    DBuf uf, best, bnd, incl, ncomp;
     // rounds
     DBuf F[2], Q[2], big, ntask, toff, parts, qring, lstate, lbhist;
     size_t qmax_seen = 0;
@@ -527,8 +527,9 @@ struct Solver {
         LAUNCHCHK();
         scan_inclusive_u32(D.bnd.as<u32>(), D.incl.as<u32>(), n, D.stemp.p, s);
         LAUNCHCHK();
-        k_node_comp<D_><<<blocks(2 * n - 1, 256), 256, 0, s>>>(D.nodes.as<NodeRec<D_>>(), D.nrange.as<int2>(),
-                                                               D.uf.as<u32>(), D.incl.as<u32>(), 2 * n - 1);
+        k_node_comp<D_><<<blocks(2 * n - 1, 256), 256, 0, s>>>(D.nodes.as<NodeRec<D_>>(), D.ncomp.as<int>(),
+                                                               D.nrange.as<int2>(), D.uf.as<u32>(),
+                                                               D.incl.as<u32>(), 2 * n - 1);
         LAUNCHCHK();
     }
 
@@ -686,6 +687,10 @@ struct Solver {
 
         // union-find and node components
         D.nrange.ensure((size_t)(2 * n - 1) * 8);
+        // compact label copy; a value no label takes, so the first refresh
+        // writes every record
+        D.ncomp.ensure((size_t)(2 * n - 1) * 4);
+        HIPCHK(hipMemsetAsync(D.ncomp.p, 0x80, (size_t)(2 * n - 1) * 4, s));
         k_node_ranges<D_><<<blocks(2 * n - 1, 256), 256, 0, s>>>(D.nodes.as<NodeRec<D_>>(), 2 * n - 1,
                                                                  D.nrange.as<int2>());
         LAUNCHCHK();
@@ -1437,7 +1442,7 @@ struct Request {
 // capacities and, for HDBSCAN*, core distances and node core-distance ranges.
 size_t request_footprint(int64_t n, int d, int min_pts) {
     size_t node = d <= 3 ? 64 : 128;
-    return (size_t)n * (656 + 2 * node + 16 * (size_t)d + (min_pts > 0 ? 368 : 0));
+    return (size_t)n * (664 + 2 * node + 16 * (size_t)d + (min_pts > 0 ? 368 : 0));
 }
 
 struct Server {

@@ -1563,14 +1563,21 @@ __global__ void k_boundaries(const u32* uf, int n, u32* bnd) {
 
 // (ranges: every node's (first, count), a compact copy of the records'
 // ranges, so that this pass reads 8 bytes per node instead of a record.)
+// The labels are compared against a compact copy (4 bytes per node) and the
+// record is written only when its label changed: most labels survive a
+// round, and reading each record's line would cost 64 bytes per node.
 template <int D>
-__global__ void k_node_comp(NodeRec<D>* nodes, const int2* ranges, const u32* uf, const u32* incl, int nn) {
+__global__ void k_node_comp(NodeRec<D>* nodes, int* labels, const int2* ranges, const u32* uf, const u32* incl,
+                            int nn) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nn) return;
     int2 r = ranges[v];
     int last = r.x + r.y - 1;
     const int c = (incl[last] == incl[r.x]) ? (int)uf[r.x] : -1;
-    if (nodes[v].comp != c) nodes[v].comp = c;  // most labels survive a round: skip their writes
+    if (labels[v] != c) {
+        labels[v] = c;
+        nodes[v].comp = c;
+    }
 }
 
 template <int D>

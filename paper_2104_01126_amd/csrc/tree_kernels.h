@@ -501,7 +501,7 @@ __global__ void __launch_bounds__(kBoundsTop) k_bounds_top(int n, const int* par
 // scanned by all lanes (each lane against every point of the node).  The
 // per-lane k smallest values are kept sorted in registers.
 constexpr int kKnnLeaf = 32;
-constexpr int kKnnSeed = 64;  // sorted neighbours on each side of a wave's queries scanned first
+constexpr int kKnnSeed = 32;  // sorted neighbours on each side of a wave's queries scanned first
 constexpr int kKnnStack = 192;
 
 template <int KMAX>

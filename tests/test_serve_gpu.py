@@ -43,7 +43,7 @@ def alone(G, x, mp):
 
 def footprint(n, d, mp):
     node = 64 if d <= 3 else 128
-    return n * (656 + 2 * node + 16 * d + (368 if mp else 0))
+    return n * (664 + 2 * node + 16 * d + (368 if mp else 0))
 
 
 def small_trace(seconds, n_hi):
