@@ -201,7 +201,9 @@ __global__ void k_key_flags(const u64* keys, int n, int L, u32* flag, u32* any_d
         flag[i] = f;
         dup = (f == 0);
     }
-    if (__any(dup) && lane_id() == 0) atomicOr(any_dup, 1u);
+    // a flag many waves raise: test before setting, so that once it is
+    // visible the waves skip the contended atomic
+    if (__any(dup) && lane_id() == 0 && *(volatile u32*)any_dup == 0u) atomicOr(any_dup, 1u);
 }
 
 // gid[i] = group of sorted position i (inclusive scan of flags minus one);
@@ -252,7 +254,7 @@ __global__ void k_group_box(const double* P, const u32* val, int n, const u32* s
             gbox[(size_t)g * 2 * D + k] = lo[k];
             gbox[(size_t)g * 2 * D + D + k] = hi[k];
         }
-        if (ext) atomicOr(refinable, 1u);
+        if (ext && *(volatile u32*)refinable == 0u) atomicOr(refinable, 1u);  // test before setting
     }
 }
 
