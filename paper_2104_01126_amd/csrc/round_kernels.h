@@ -716,19 +716,20 @@ __device__ __forceinline__ void level_flush(const RoundArgs& r, LevelAcc& acc) {
 // loads, so more resident waves help more than the few registers they cost.
 template <int D>
 struct LevelWaves {
-    static constexpr int value = D <= 5 ? 4 : 1;
+    static constexpr int value = D <= 5 ? 4 : 3;
 };
 
 // One breadth-first level over the whole grid.  Blocks beyond the queue
 // leave at once.  Blocks are large because every step appends to the shared
 // lists with one atomic per list, and those few counters are the contended
-// addresses of the expansion: fewer, larger steps mean fewer atomics.
-// 1024 threads (one block per CU at four waves per SIMD) where the level
-// step fits 128 registers (d <= 5), else 512.
+// addresses of the expansion: fewer, larger steps mean fewer atomics.  One
+// block per CU, as large as the registers allow: 1024 threads at four waves
+// per SIMD where the level step fits 128 registers (d <= 5), else 768 at
+// three (up to 168 registers).
 template <int D>
 struct LevelShape {
-    static constexpr int block = D <= 5 ? 1024 : 512;
-    static constexpr int grid = D <= 5 ? 256 : 512;
+    static constexpr int block = D <= 5 ? 1024 : 768;
+    static constexpr int grid = 256;
     static_assert(grid % kRegions == 0, "every XCD gets the same number of workgroups");
 };
 
