@@ -861,7 +861,7 @@ struct Solver {
                             {
                                 TIMED(GEOMST_K_EXPAND);
                                 RoundArgs r = args(beta2, fo, 0, po);
-                                k_level_small<D_><<<1, kSmallBlock, 0, s>>>(
+                                k_level_small<D_><<<1, SmallBlock<D_>::value, 0, s>>>(
                                     t, r, hdb, D.Q[0].as<PairRec>(), (u32)(D.capQ[0] / kRegions), D.Q[1].as<PairRec>(),
                                     (u32)(D.capQ[1] / kRegions), lv & 1, ring, (u32)(lv % kQRing), g_small_max,
                                     D.lstate.as<u32>());

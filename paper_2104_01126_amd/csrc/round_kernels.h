@@ -776,10 +776,15 @@ k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const 
 // and q[1] (cap0, cap1: region capacities).  On exit ring slot b holds the
 // remaining count in its region 0 for the buffer b it ends in (every other
 // ring counter is zeroed), and state = {remaining, b}.
-constexpr int kSmallBlock = 1024;
+// 1024 threads where the level step fits 128 registers without spilling
+// (d <= 4), else 768.
+template <int D>
+struct SmallBlock {
+    static constexpr int value = D <= 4 ? 1024 : 768;
+};
 
 template <int D>
-__global__ void __launch_bounds__(kSmallBlock) k_level_small(TreeView t, RoundArgs r, int hdb, PairRec* q0, u32 cap0,
+__global__ void __launch_bounds__(SmallBlock<D>::value) k_level_small(TreeView t, RoundArgs r, int hdb, PairRec* q0, u32 cap0,
                                                              PairRec* q1, u32 cap1, int b_in, u32* ring,
                                                              u32 slot_in, u32 small_max, u32* state) {
     __shared__ BlockAlloc S;
@@ -798,7 +803,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_level_small(TreeView t, RoundAr
         const PairRec* qin = b ? q1 : q0;
         PairRec* qout = b ? q0 : q1;
         const u32 capi = b ? cap1 : cap0, capo = b ? cap0 : cap1;
-        for (u32 b0 = 0; b0 < nq; b0 += kSmallBlock) {
+        for (u32 b0 = 0; b0 < nq; b0 += SmallBlock<D>::value) {
             const u32 v = b0 + threadIdx.x;
             const bool have = v < nq;
             const u32 i = (have && first) ? region_index(pre, capi, v) : v;
@@ -815,7 +820,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_level_small(TreeView t, RoundAr
         nq = nn;
         __syncthreads();
     }
-    level_flush<kSmallBlock>(r, acc);
+    level_flush<SmallBlock<D>::value>(r, acc);
     if (threadIdx.x < kQRing * kRegions) ring[threadIdx.x * kRegionStride] = threadIdx.x == b * kRegions ? nq : 0u;
     if (threadIdx.x == 0) {
         state[0] = nq;
