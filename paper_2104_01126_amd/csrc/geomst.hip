@@ -8,6 +8,7 @@
 #include <string.h>
 #include <chrono>
 #include <mutex>
+#include <new>
 #include <condition_variable>
 #include <deque>
 #include <thread>
@@ -628,12 +629,13 @@ struct Solver {
                     (double)D.capBig / n, (double)c.c[C_C] / n, (double)D.C.cap / n, (double)c.c[C_P] / n,
                     (double)D.P[po].cap / n, (double)c.c[C_TINY] / n, (double)D.capTiny / n);
         // A count read at an overflow only bounds the round's need from below
-        // (the round stopped early), so lists grow to twice the count.  The
-        // frontier and the level queues carry the same pairs level by level,
-        // so when either overflows both grow to the larger need.
+        // (the round stopped early); lists grow to 1.25 times the count, and
+        // at least double.  The frontier and the level queues carry the same
+        // pairs level by level, so when either overflows both grow to the
+        // larger need.
         auto grow_pairs = [&](DBuf& b, size_t& cap, size_t need) {
             if (need > cap) {
-                size_t nc = std::min<size_t>(std::max<size_t>(2 * need, cap * 2), kMaxListCap) / kRegions * kRegions;
+                size_t nc = std::min<size_t>(std::max<size_t>(need + need / 4, cap * 2), kMaxListCap) / kRegions * kRegions;
                 b.ensure(nc * sizeof(PairRec));
                 cap = nc;
             }
@@ -647,13 +649,13 @@ struct Solver {
         if (fneed > D.capF[fo] || qneed > std::min(D.capQ[0], D.capQ[1])) fneed = qneed = std::max(fneed, qneed);
         grow_pairs(D.F[fo], D.capF[fo], fneed);
         if (c.c[C_FAR] > D.capFF[ffo]) {  // keeps the far pairs retained from earlier rounds
-            size_t nc = std::min<size_t>(std::max<size_t>(2 * (size_t)c.c[C_FAR], D.capFF[ffo] * 2), kMaxListCap);
+            size_t nc = std::min<size_t>(std::max<size_t>((size_t)c.c[C_FAR] + c.c[C_FAR] / 4, D.capFF[ffo] * 2), kMaxListCap);
             D.FF[ffo].ensure(nc * sizeof(PairRec), keep_far * sizeof(PairRec), s);
             D.capFF[ffo] = nc;
         }
         for (int i = 0; i < 2; ++i) grow_pairs(D.Q[i], D.capQ[i], qneed);
         if (c.c[C_TINY] > D.capTiny) {
-            size_t nc = std::min<size_t>(std::max<size_t>(2 * (size_t)c.c[C_TINY], D.capTiny * 2), kMaxListCap);
+            size_t nc = std::min<size_t>(std::max<size_t>((size_t)c.c[C_TINY] + c.c[C_TINY] / 4, D.capTiny * 2), kMaxListCap);
             D.tiny.ensure(nc * sizeof(uint4));
             D.capTiny = nc;
         }
@@ -1438,11 +1440,16 @@ struct Request {
 
 // Device-memory estimate of one request inside a batch: staged points and
 // outputs, multi-level sort keys and temporaries, 2n node records, union-find
-// and component arrays, the pair lists and edge pools at their initial
-// capacities and, for HDBSCAN*, core distances and node core-distance ranges.
+// and component arrays, the edge pools at their initial capacities, for
+// HDBSCAN* core distances and node core-distance ranges, and the waiting and
+// queued pairs (16 bytes each) that the frontier, far and queue lists hold at
+// their peak.  The pair count per point grows steeply with d (measured peaks
+// on uniform inputs with growth headroom: about 1,600 at d = 7 against 50 at
+// d = 3).
 size_t request_footprint(int64_t n, int d, int min_pts) {
+    static const size_t kListPairs[8] = {0, 16, 24, 48, 100, 200, 600, 1600};
     size_t node = d <= 3 ? 64 : 128;
-    return (size_t)n * (664 + 2 * node + 16 * (size_t)d + (min_pts > 0 ? 368 : 0));
+    return (size_t)n * (664 + 2 * node + 16 * (size_t)d + (min_pts > 0 ? 368 : 0) + 16 * kListPairs[d]);
 }
 
 struct Server {
@@ -1484,25 +1491,42 @@ void run_batch(Server* S, Device& D, std::vector<Request*>& batch) {
             it[i] = grp[i]->item;
             N += it[i].n;
         }
-        int status = GEOMST_OK;
-        g_err.clear();
-        try {
-            ensure_init(D);
-            solve_host_items(D, it.data(), (int64_t)it.size());
-        } catch (const Fail& f) {
-            status = f.code;
-        } catch (const std::bad_alloc&) {
-            status = GEOMST_ENOMEM;
-        } catch (...) {
-            g_err = "unexpected exception in a server worker";
-            status = GEOMST_EINTERNAL;
+        auto solve = [&](HostItem* items, int64_t count) -> int {
+            g_err.clear();
+            try {
+                ensure_init(D);
+                solve_host_items(D, items, count);
+            } catch (const Fail& f) {
+                return f.code;
+            } catch (const std::bad_alloc&) {
+                return GEOMST_ENOMEM;
+            } catch (...) {
+                g_err = "unexpected exception in a server worker";
+                return GEOMST_EINTERNAL;
+            }
+            return GEOMST_OK;
+        };
+        std::vector<int> status(grp.size(), solve(it.data(), (int64_t)it.size()));
+        std::vector<std::string> err(grp.size(), g_err);
+        if (status[0] == GEOMST_ENOMEM) {
+            // The workspace outgrew the device (the admission estimate does
+            // not cover the pair lists of high-dimensional inputs): release
+            // it and solve the requests one at a time.
+            if (D.own) (void)hipStreamSynchronize(D.own);  // nothing of the failed solve may still run
+            D.~Device();
+            new (&D) Device();
+            for (size_t i = 0; i < grp.size(); ++i) {
+                status[i] = solve(&it[i], 1);
+                err[i] = g_err;
+            }
         }
         {
             std::lock_guard<std::mutex> lk(S->mu);
             auto now = Clock::now();
-            for (Request* r : grp) {
-                r->status = status;
-                if (status) r->err = g_err.empty() ? "batch failed" : g_err;
+            for (size_t i = 0; i < grp.size(); ++i) {
+                Request* r = grp[i];
+                r->status = status[i];
+                if (status[i]) r->err = err[i].empty() ? "batch failed" : err[i];
                 r->batch_requests = (int)grp.size();
                 r->batch_points = N;
                 r->done = true;
