@@ -146,8 +146,8 @@ int geomst_batch(geomst_instance_t* inst, int64_t count);
  * identical to solving it alone.
  *
  * Admission estimate per request (device bytes):
- *   n * (664 + 2 * node + 16 * d + (min_pts > 0 ? 368 : 0) + 16 * pairs[d]),
- *   node = 64 for d <= 3, else 128; pairs[d] = 16, 24, 48, 100, 200, 600,
+ *   n * (720 + 2 * node + 16 * d + (min_pts > 0 ? 640 : 0) + 16 * pairs[d]),
+ *   node = 64 for d <= 3, else 128; pairs[d] = 24, 24, 64, 100, 200, 600,
  *   1600 for d = 1..7 (waiting and queued pairs per point at their peak).
  * If a batch still runs out of device memory, the worker releases its
  * workspace and solves the batch's requests one at a time.

@@ -726,24 +726,29 @@ struct Solver {
             D.capTiny = 0;
             D.C.cap = 0;
         }
-        initcap(D.capF[0], D.F[0], sc(hdb ? 4 : 2));
-        initcap(D.capF[1], D.F[1], sc(hdb ? 4 : 2));
-        initcap(D.capFF[0], D.FF[0], sc(hdb ? 8 : 4));
-        initcap(D.capFF[1], D.FF[1], sc(hdb ? 8 : 4));
+        // frontier and queue: pairs per point they typically reach (they grow
+        // with d), so that a first solve seldom restarts rounds to grow them
+        static const double kInitPairs[8] = {0, 4, 4, 12, 16, 24, 48, 96};
+        const double fq = std::max(kInitPairs[D_], hdb ? 4.0 : 2.0);
+        initcap(D.capF[0], D.F[0], sc(fq));
+        initcap(D.capF[1], D.F[1], sc(fq));
+        static const double kInitFar[8] = {0, 4, 4, 4, 8, 16, 32, 64};
+        initcap(D.capFF[0], D.FF[0], sc(kInitFar[D_] * (hdb ? 2 : 1)));
+        initcap(D.capFF[1], D.FF[1], sc(kInitFar[D_] * (hdb ? 2 : 1)));
         // a thin-level chain keeps its queue in one region: room for a level
         // of up to small_max pairs and its children
         const size_t qmin = (size_t)(std::min(g_capacity_scale, 1.0) * kRegions * (2 * (double)g_small_max + 2048));
-        initcap(D.capQ[0], D.Q[0], (std::max(sc(2), qmin) + kRegions - 1) / kRegions * kRegions);
-        initcap(D.capQ[1], D.Q[1], (std::max(sc(2), qmin) + kRegions - 1) / kRegions * kRegions);
-        if (D.capTiny < sc(hdb ? 4 : 1)) {
-            D.capTiny = sc(hdb ? 4 : 1);
+        initcap(D.capQ[0], D.Q[0], (std::max(sc(fq), qmin) + kRegions - 1) / kRegions * kRegions);
+        initcap(D.capQ[1], D.Q[1], (std::max(sc(fq), qmin) + kRegions - 1) / kRegions * kRegions);
+        if (D.capTiny < sc(hdb ? 8 : 3)) {
+            D.capTiny = sc(hdb ? 8 : 3);
             D.tiny.ensure(D.capTiny * sizeof(uint4));
         }
         if (D.capBig < sc(0.125)) {
             D.capBig = sc(0.125);
             D.big.ensure(D.capBig * 8);
         }
-        D.C.ensure(sc(2), 0, s);
+        D.C.ensure(sc(hdb ? 6 : 3), 0, s);
         D.P[0].ensure(sc(1), 0, s);
         D.P[1].ensure(sc(1), 0, s);
         D.OUT.ensure((size_t)n + 64, 0, s);
@@ -1444,12 +1449,12 @@ struct Request {
 // HDBSCAN* core distances and node core-distance ranges, and the waiting and
 // queued pairs (16 bytes each) that the frontier, far and queue lists hold at
 // their peak.  The pair count per point grows steeply with d (measured peaks
-// on uniform inputs with growth headroom: about 1,600 at d = 7 against 50 at
+// on uniform inputs with growth headroom: about 1,600 at d = 7 against 64 at
 // d = 3).
 size_t request_footprint(int64_t n, int d, int min_pts) {
-    static const size_t kListPairs[8] = {0, 16, 24, 48, 100, 200, 600, 1600};
+    static const size_t kListPairs[8] = {0, 24, 24, 64, 100, 200, 600, 1600};
     size_t node = d <= 3 ? 64 : 128;
-    return (size_t)n * (664 + 2 * node + 16 * (size_t)d + (min_pts > 0 ? 368 : 0) + 16 * kListPairs[d]);
+    return (size_t)n * (720 + 2 * node + 16 * (size_t)d + (min_pts > 0 ? 640 : 0) + 16 * kListPairs[d]);
 }
 
 struct Server {

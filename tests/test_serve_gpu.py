@@ -43,8 +43,8 @@ def alone(G, x, mp):
 
 def footprint(n, d, mp):
     node = 64 if d <= 3 else 128
-    pairs = [0, 16, 24, 48, 100, 200, 600, 1600][d]
-    return n * (664 + 2 * node + 16 * d + (368 if mp else 0) + 16 * pairs)
+    pairs = [0, 24, 24, 64, 100, 200, 600, 1600][d]
+    return n * (720 + 2 * node + 16 * d + (640 if mp else 0) + 16 * pairs)
 
 
 def small_trace(seconds, n_hi):
