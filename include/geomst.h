@@ -244,7 +244,7 @@ typedef struct {
     double ms_core;           /* core distances (HDBSCAN*) */
     double ms_rounds;         /* all rounds */
     double ms_final;          /* output sort and write */
-    int64_t big_evals;        /* distance evaluations in the large-pair kernel */
+    int64_t big_evals;        /* distances the large-pair kernel evaluated (pruned blocks excluded) */
     int64_t sort_elems;       /* elements x 8-bit passes moved by the radix sorts */
     double kernel_ms[16];     /* device time per kernel family (kernel_timing on) */
     int64_t kernel_launches[16];

@@ -36,6 +36,14 @@ __device__ __forceinline__ u32 wave_append(u32* counter, bool pred) {
     return pred ? base + (u32)__popcll(mask & lanemask_lt()) : kNone;
 }
 
+// A value known to be equal in every active lane, moved to scalar registers.
+__device__ __forceinline__ double wave_uniform_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Wave-wide minimum of a u64 (all 64 lanes must be active).
 __device__ __forceinline__ u64 wave_min_u64(u64 v) {
 #pragma unroll

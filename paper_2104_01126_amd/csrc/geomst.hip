@@ -163,7 +163,7 @@ struct Device {
     // union-find / component refresh
     DBuf uf, best, bnd, incl, ncomp;
     // rounds
-    DBuf F[2], Q[2], big, ntask, toff, parts, qring, lstate, lbhist;
+    DBuf F[2], Q[2], big, ntask, toff, parts, ubest, tdone, qring, lstate, lbhist;
     size_t qmax_seen = 0;
     size_t capF[2] = {0, 0}, capQ[2] = {0, 0}, capBig = 0, capTiny = 0;
     DBuf tiny;  // small separated pairs of the current round
@@ -947,23 +947,29 @@ struct Solver {
                         u32 ntasks = last_off + last_cnt;
                         if (g_trace) trace_big_pairs(nbig, ntasks);
                         D.parts.ensure((size_t)ntasks * sizeof(PartKey));
+                        D.ubest.ensure((size_t)nbig * 8);
+                        D.tdone.ensure((size_t)ntasks * 4);
                         {
                             TIMED(GEOMST_K_BCCP);
+                            HIPCHK(hipMemsetAsync(D.ubest.p, 0xff, (size_t)nbig * 8, s));  // no weight yet
                             if (hdb)
                                 k_big_bccp<D_, 1><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
                                                                        D.parts.as<PartKey>(), D.cnt.as<Counters>(),
-                                                                       g_bccp_chunk);
+                                                                       g_bccp_chunk, D.ubest.as<u64>(), D.tdone.as<u32>());
                             else
                                 k_big_bccp<D_, 0><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
                                                                        D.parts.as<PartKey>(), D.cnt.as<Counters>(),
-                                                                       g_bccp_chunk);
+                                                                       g_bccp_chunk, D.ubest.as<u64>(), D.tdone.as<u32>());
                             LAUNCHCHK();
+                            // the per-pair best weights are dead after k_big_bccp: the
+                            // same array then holds each pair's evaluation count
                             k_big_reduce<<<blocks(nbig, kBlock / kWave), kBlock, 0, s>>>(
-                                nbig, D.toff.as<u32>(), D.ntask.as<u32>(), D.parts.as<PartKey>());
+                                nbig, D.toff.as<u32>(), D.ntask.as<u32>(), D.parts.as<PartKey>(), D.tdone.as<u32>(),
+                                D.ubest.as<unsigned long long>());
                             LAUNCHCHK();
                             RoundArgs r = args(beta2, fo, 0, po);
                             k_big_combine<<<std::min(blocks(nbig, kBlock), (unsigned)kGrid), kBlock, 0, s>>>(
-                                r, nbig, D.toff.as<u32>(), D.parts.as<PartKey>());
+                                r, nbig, D.toff.as<u32>(), D.parts.as<PartKey>(), D.ubest.as<unsigned long long>());
                             LAUNCHCHK();
                         }
                         read_counters(D, s);

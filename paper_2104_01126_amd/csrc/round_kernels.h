@@ -970,13 +970,21 @@ __global__ void __launch_bounds__(kBlock) k_big_ntasks(TreeView t, const uint2* 
     if (threadIdx.x == 0) {
         atomicAdd(&cnt->c64[C64_TASKS], sc);  // the host rejects totals beyond 2^31
         atomicAdd(&cnt->c64[C64_EVALS], sw);
-        atomicAdd(&cnt->c64[C64_BIGEVALS], sw);
     }
 }
 
+// Pruning: a 64-point B block is skipped when the bound between the task's
+// A points' box and the block's box exceeds the best weight seen so far, by
+// this task or (through `ubest`, the bit patterns of each pair's best weight,
+// all ones before the launch) by any task of the same pair.  The bound is the
+// squared box gap summed in the distances' operation order (and for BCCP* the
+// smallest core distances on either side), so it never exceeds a computed
+// weight of the block: a skipped block holds no pair at or below the pair's
+// final minimum.
 template <int D, int HDB>
 __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u32 nbig, const u32* toff,
-                                                  PartKey* part, Counters* cnt, int bchunk) {
+                                                  PartKey* part, Counters* cnt, int bchunk, u64* ubest,
+                                                  u32* tdone) {
     __shared__ double sbuf[2][64 * D];
     __shared__ double scd[2][64];
     const int lane = lane_id();
@@ -1020,6 +1028,7 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
             pk.ids = ((u64)best.k.lo << 32) | best.k.hi;
             pk.pos = ((u64)best.i << 32) | best.j;
             part[task] = pk;
+            tdone[task] = tot;
         }
         return;
     }
@@ -1046,34 +1055,88 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
     const int jb1 = min(jb0 + bchunk, rb.x + rb.y);
 #pragma unroll
     for (int r = 0; r < kBigAPL; ++r) blk[r] = jb0;
-    // stage the first block
-    if (lane < jb1 - jb0) {
+    // box (and smallest core distance) of the task's A points; a task with
+    // a single B block has nothing to prune and skips this
+    const bool multi = jb1 - jb0 > 64;
+    double alo[D], ahi[D], acm = inf;
 #pragma unroll
-        for (int k = 0; k < D; ++k) sbuf[0][lane * D + k] = t.X[(size_t)(jb0 + lane) * D + k];
-        if (HDB) scd[0][lane] = t.cd2[jb0 + lane];
+    for (int k = 0; k < D; ++k) {
+        alo[k] = inf;
+        ahi[k] = -inf;
     }
+    if (multi) {
+#pragma unroll
+        for (int r = 0; r < kBigAPL; ++r)
+            if (abase + r * 64 + lane < aend) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    alo[k] = fmin(alo[k], p[r][k]);
+                    ahi[k] = fmax(ahi[k], p[r][k]);
+                }
+                if (HDB) acm = fmin(acm, ca[r]);
+            }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            alo[k] = wave_uniform_f64(wave_min_f64(alo[k]));
+            ahi[k] = wave_uniform_f64(-wave_min_f64(-ahi[k]));
+        }
+        if (HDB) acm = wave_uniform_f64(wave_min_f64(acm));
+    }
+    // stage the first block
+    double bx[D] = {}, bcd = inf;
+    const bool h0 = lane < jb1 - jb0;
+    if (h0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            bx[k] = t.X[(size_t)(jb0 + lane) * D + k];
+            sbuf[0][lane * D + k] = bx[k];
+        }
+        if (HDB) {
+            bcd = t.cd2[jb0 + lane];
+            scd[0][lane] = bcd;
+        }
+    }
+    u64 ub = ubest[lo];
     // every load above has landed: keeps the compiler from placing waits for
     // them inside the inner loop, where they would also wait for the prefetch
     __builtin_amdgcn_s_waitcnt(0);
+    // bound between the A box and the staged block
+    auto block_bound = [&](const double (&x)[D], bool have, double cdb) -> double {
+        double g2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double lo_b = wave_min_f64(have ? x[k] : inf), hi_b = -wave_min_f64(have ? -x[k] : inf);
+            const double g = fmax(fmax(lo_b - ahi[k], alo[k] - hi_b), 0.0);
+            g2 = g2 + g * g;
+        }
+        if (HDB) g2 = fmax(g2, fmax(acm, wave_min_f64(have ? cdb : inf)));
+        return wave_uniform_f64(g2);
+    };
+    double blb = multi ? block_bound(bx, h0, bcd) : 0.0;
+    double mt = inf;  // this task's best weight so far
+    const u32 na_task = (u32)min(kBigA, aend - abase);
+    u32 done = 0;     // distances evaluated
     __syncthreads();
     int buf = 0;
     for (int js = jb0; js < jb1; js += 64, buf ^= 1) {
         const int cntb = min(64, jb1 - js);
-        // prefetch the next block into registers
+        // prefetch the next block (and the pair's best weight) into registers
         const int jn = js + 64;
         const bool hn = jn < jb1 && lane < jb1 - jn;
-        double nx[D], ncd = 0.0;
+        double nx[D] = {}, ncd = inf;
         if (hn) {
 #pragma unroll
             for (int k = 0; k < D; ++k) nx[k] = t.X[(size_t)(jn + lane) * D + k];
             if (HDB) ncd = t.cd2[jn + lane];
         }
+        const u64 ubn = ubest[lo];
+        const bool skip = blb > fmin(mt, __longlong_as_double((long long)ub));
         double bm[kBigAPL];
 #pragma unroll
         for (int r = 0; r < kBigAPL; ++r) bm[r] = inf;
         const double* sb = sbuf[buf];
 #pragma unroll 4
-        for (int j = 0; j < cntb; ++j) {
+        for (int j = 0; j < (skip ? 0 : cntb); ++j) {
             double q[D];
 #pragma unroll
             for (int k = 0; k < D; ++k) q[k] = sb[j * D + k];
@@ -1099,15 +1162,30 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
                 bm[r] = fmin(bm[r], d2[r]);
             }
         }
+        if (!skip) {
+            done += (u32)cntb * na_task;
+            double mm = inf;
 #pragma unroll
-        for (int r = 0; r < kBigAPL; ++r) {
-            double w = HDB ? fmax(ca[r], bm[r]) : bm[r];
-            if (w < m[r]) {
-                m[r] = w;
-                blk[r] = js;
-                tie[r] = false;
-            } else if (w == m[r]) {
-                tie[r] = true;
+            for (int r = 0; r < kBigAPL; ++r) {
+                double w = HDB ? fmax(ca[r], bm[r]) : bm[r];
+                if (w < m[r]) {
+                    m[r] = w;
+                    blk[r] = js;
+                    tie[r] = false;
+                } else if (w == m[r]) {
+                    tie[r] = true;
+                }
+                if (abase + r * 64 + lane < aend) mm = fmin(mm, m[r]);
+            }
+            mm = wave_uniform_f64(wave_min_f64(mm));
+            if (mm < mt) {
+                mt = mm;
+                // shared only by tasks with several blocks (whose later blocks
+                // can use it) and only when it beats the last bound read:
+                // pairs cut into many one-block tasks would otherwise queue
+                // an atomic per task on one address
+                if (multi && dbits(mt) < ub && lane == 0)
+                    atomicMin((unsigned long long*)&ubest[lo], (unsigned long long)dbits(mt));
             }
         }
         if (hn) {
@@ -1115,6 +1193,8 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
             for (int k = 0; k < D; ++k) sbuf[buf ^ 1][lane * D + k] = nx[k];
             if (HDB) scd[buf ^ 1][lane] = ncd;
         }
+        if (jn < jb1) blb = block_bound(nx, hn, ncd);
+        ub = ubn;
         __syncthreads();
     }
     double mm = inf;
@@ -1162,6 +1242,7 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
         pk.ids = ((u64)best.k.lo << 32) | best.k.hi;
         pk.pos = ((u64)best.i << 32) | best.j;
         part[task] = pk;
+        tdone[task] = done;
     }
 }
 
@@ -1171,20 +1252,29 @@ __device__ __forceinline__ bool part_less(const PartKey& x, const PartKey& b) {
 
 // Per pair, the minimum of its task keys, written into the pair's first
 // task slot; one wave per pair.
-__global__ void __launch_bounds__(kBlock) k_big_reduce(u32 nbig, const u32* toff, const u32* ntask, PartKey* part) {
+__global__ void __launch_bounds__(kBlock) k_big_reduce(u32 nbig, const u32* toff, const u32* ntask, PartKey* part,
+                                                        const u32* tdone, unsigned long long* pdone) {
     const int lane = lane_id();
     const u32 i = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (i >= nbig) return;
     const u32 o = toff[i], c = ntask[i];
-    if (c == 1) return;
+    if (c == 1) {
+        if (lane == 0) pdone[i] = tdone[o];
+        return;
+    }
     PartKey b;
     b.w2 = b.e2 = __longlong_as_double(0x7ff0000000000000ll);
     b.ids = ~0ull;
     b.pos = 0;
+    unsigned long long dn = 0;
     for (u32 k = (u32)lane; k < c; k += kWave) {
         PartKey x = part[o + k];
         if (part_less(x, b)) b = x;
+        dn += tdone[o + k];
     }
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) dn += __shfl_xor(dn, s);
+    if (lane == 0) pdone[i] = dn;
 #pragma unroll
     for (int s = 32; s > 0; s >>= 1) {
         PartKey x;
@@ -1200,9 +1290,11 @@ __global__ void __launch_bounds__(kBlock) k_big_reduce(u32 nbig, const u32* toff
 // Commits or defers each large pair's BCCP edge (its key is in the pair's
 // first task slot after k_big_reduce).
 __global__ void __launch_bounds__(kBlock) k_big_combine(RoundArgs r, u32 nbig, const u32* toff,
-                                                        const PartKey* part) {
+                                                        const PartKey* part, const unsigned long long* pdone) {
     __shared__ BlockAlloc S;
     __shared__ double shm[4];
+    __shared__ unsigned long long shs[kBlock / kWave];
+    unsigned long long dn = 0;
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
     u32* ctr[kLists] = {&r.cnt->c[C_C], &r.cnt->c[C_P], nullptr, nullptr, nullptr, nullptr};
     double minp = inf;
@@ -1214,7 +1306,10 @@ __global__ void __launch_bounds__(kBlock) k_big_combine(RoundArgs r, u32 nbig, c
         b.e2 = inf;
         b.ids = ~0ull;
         b.pos = 0;
-        if (have) b = part[toff[i]];
+        if (have) {
+            b = part[toff[i]];
+            dn += pdone[i];
+        }
         bool to_c = have && b.w2 <= r.beta2;
         bool to_p = have && !to_c;
         if (to_p) minp = fmin(minp, b.w2);
@@ -1231,6 +1326,8 @@ __global__ void __launch_bounds__(kBlock) k_big_combine(RoundArgs r, u32 nbig, c
         }
     }
     block_atomic_min(minp, &r.cnt->m[M_P], shm);
+    dn = block_sum_u64(dn, shs);
+    if (threadIdx.x == 0 && dn) atomicAdd(&r.cnt->c64[C64_BIGEVALS], dn);  // distances the tasks evaluated
 }
 
 // ------------------------------------------------------------ pool split
