@@ -49,6 +49,13 @@ struct Fail {
     int code;
 };
 
+// The device counters block: the Counters record followed by the few words
+// the host reads back with it, so that one copy serves each host check.
+constexpr size_t kAuxLstate = (sizeof(Counters) + 63) / 64 * 64;   // one-workgroup level state (2 words)
+constexpr size_t kAuxNalive = kAuxLstate + 64;                     // Boruvka alive counts (2 words)
+constexpr size_t kAuxRing = (kAuxNalive + 64 + 255) / 256 * 256;   // level-queue count ring
+constexpr size_t kCntBytes = kAuxRing + (size_t)kQRing * kSlotWords * 4;
+
 #define HIPCHK(x)                                                                             \
     do {                                                                                      \
         hipError_t e_ = (x);                                                                  \
@@ -152,7 +159,7 @@ struct Device {
     std::mutex mu;
     bool init = false;
     hipStream_t own = nullptr;
-    Counters* hcnt = nullptr;  // pinned mirror
+    Counters* hcnt = nullptr;  // pinned mirror of the counters block (kCntBytes)
     u32* hpin = nullptr;       // pinned words read back together with the counters
     DBuf cnt;
     // input staging (host API)
@@ -163,7 +170,7 @@ struct Device {
     // union-find / component refresh
     DBuf uf, best, bnd, incl, ncomp;
     // rounds
-    DBuf F[2], Q[2], big, ntask, toff, parts, ubest, tdone, qring, lstate, lbhist;
+    DBuf F[2], Q[2], big, ntask, toff, parts, ubest, tdone, lbhist;
     size_t qmax_seen = 0;
     size_t capF[2] = {0, 0}, capQ[2] = {0, 0}, capBig = 0, capTiny = 0;
     DBuf tiny;  // small separated pairs of the current round
@@ -171,7 +178,7 @@ struct Device {
     size_t capFF[2] = {0, 0};
     EdgeBufs C, P[2], OUT;
     // Kruskal
-    DBuf kid, ke2, kw2, perm[2], alive[2], apos[2], ru, rv, nalive, minmax;
+    DBuf kid, ke2, kw2, perm[2], alive[2], apos[2], ru, rv, minmax;
     DBuf birange, bik, browinst;  // batched solves: instance table and row -> instance
     Prof profm;
     Prof* prof = nullptr;
@@ -215,10 +222,34 @@ struct TimedScope {
 };
 #define TIMED(fam) TimedScope timed_scope_(*D.prof, s, fam)
 
-void read_counters(Device& D, hipStream_t s) {
-    HIPCHK(hipMemcpyAsync(D.hcnt, D.cnt.p, sizeof(Counters), hipMemcpyDeviceToHost, s));
+// Timing of back-to-back launches of one family: one event between
+// consecutive launches closes the previous sample and opens the next, so a
+// batch of k launches records k + 1 events instead of 2k.
+struct TimedChain {
+    Prof& P;
+    hipStream_t s;
+    int fam;
+    bool on;
+    size_t last = 0;
+    TimedChain(Prof& p, hipStream_t st, int f) : P(p), s(st), fam(f), on(p.on && ((p.mask >> f) & 1u)) {
+        if (on) last = P.rec(s);
+    }
+    void tick() {
+        if (!on) return;
+        const size_t e = P.rec(s);  // events are numbered in record order
+        P.pend.push_back({fam, last});
+        last = e;
+    }
+};
+
+// Reads the first `bytes` of the counters block into its pinned mirror.
+void read_counters(Device& D, hipStream_t s, size_t bytes = sizeof(Counters)) {
+    HIPCHK(hipMemcpyAsync(D.hcnt, D.cnt.p, bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
 }
+
+u32* aux_dev(Device& D, size_t off) { return (u32*)((char*)D.cnt.p + off); }
+const u32* aux_host(const Device& D, size_t off) { return (const u32*)((const char*)D.hcnt + off); }
 
 // Queues a copy of c to the device counters.  The pinned mirror is the copy
 // source, so the host leaves it alone until the next read_counters.
@@ -602,13 +633,14 @@ struct Solver {
 
     // Total and largest region count of level-queue ring slot `slot`, read
     // together with the counters (one host round trip for both).
-    void read_slot(const u32* ring, int slot, u32& total, u32& largest) {
-        HIPCHK(hipMemcpyAsync(D.hpin, ring + slot * kSlotWords, kSlotWords * 4, hipMemcpyDeviceToHost, s));
-        read_counters(D, s);
+    void read_slot(int slot, u32& total, u32& largest) {
+        const size_t off = kAuxRing + (size_t)slot * kSlotWords * 4;
+        read_counters(D, s, off + kSlotWords * 4);
+        const u32* h = aux_host(D, off);
         total = largest = 0;
         for (int x = 0; x < kRegions; ++x) {
-            total += D.hpin[x * kRegionStride];
-            largest = std::max(largest, D.hpin[x * kRegionStride]);
+            total += h[x * kRegionStride];
+            largest = std::max(largest, h[x * kRegionStride]);
         }
     }
 
@@ -801,9 +833,7 @@ struct Solver {
         int rounds = 0;
         u32 nout = 0;
         int stale_rounds = 0;
-        D.qring.ensure(kQRing * kSlotWords * 4);
-        D.lstate.ensure(64);
-        u32* ring = D.qring.as<u32>();
+        u32* ring = aux_dev(D, kAuxRing);
         while (true) {
             ++rounds;
             if (rounds > 100000) {
@@ -818,7 +848,7 @@ struct Solver {
             // the previous round's last kernels stay for the next read), and
             // mirrored in the host copy, which a restart writes back
             const u32 far_keep = epoch ? 0u : nFF;  // far appends go after the retained pairs
-            k_round_reset<<<1, kWave, 0, s>>>(D.cnt.as<Counters>(), far_keep);
+            k_round_reset<<<1, kWave, 0, s>>>(D.cnt.as<Counters>(), far_keep, ring);
             LAUNCHCHK();
             for (int i = 0; i < C_OUT; ++i) D.hcnt->c[i] = 0;
             for (int i = 0; i < M_NUM; ++i) D.hcnt->m[i] = ~0ull;
@@ -833,7 +863,7 @@ struct Solver {
                 restart = false;
                 levels = 0;
                 D.qmax_seen = 0;
-                HIPCHK(hipMemsetAsync(ring, 0, kQRing * kSlotWords * 4, s));
+                if (restarts) HIPCHK(hipMemsetAsync(ring, 0, kQRing * kSlotWords * 4, s));  // else k_round_reset
                 // frontier and pool split
                 {
                     TIMED(GEOMST_K_SPLIT);
@@ -852,7 +882,7 @@ struct Solver {
                     LAUNCHCHK();
                 }
                 u32 nq = 0, nq_region = 0;
-                read_slot(ring, 0, nq, nq_region);
+                read_slot(0, nq, nq_region);
                 D.hcnt->c[C_Q] = nq;
                 D.qmax_seen = (size_t)kRegions * nq_region;
                 if (D.hcnt->c[C_ERR] & 1u) {
@@ -871,23 +901,22 @@ struct Solver {
                                 k_level_small<D_><<<1, SmallBlock<D_>::value, 0, s>>>(
                                     t, r, hdb, D.Q[0].as<PairRec>(), (u32)(D.capQ[0] / kRegions), D.Q[1].as<PairRec>(),
                                     (u32)(D.capQ[1] / kRegions), lv & 1, ring, (u32)(lv % kQRing), g_small_max,
-                                    D.lstate.as<u32>());
+                                    aux_dev(D, kAuxLstate));
                                 LAUNCHCHK();
                             }
-                            HIPCHK(hipMemcpyAsync(D.hpin, D.lstate.p, 8, hipMemcpyDeviceToHost, s));
-                            read_counters(D, s);
+                            read_counters(D, s, kAuxLstate + 8);
                             ++levels;
                             if (D.hcnt->c[C_ERR] & 1u) {
                                 restart = true;
                                 break;
                             }
-                            nq = D.hpin[0];
-                            lv = (int)D.hpin[1];
+                            nq = aux_host(D, kAuxLstate)[0];
+                            lv = (int)aux_host(D, kAuxLstate)[1];
                             D.qmax_seen = std::max<size_t>(D.qmax_seen, (size_t)kRegions * nq);  // all in region 0
                             continue;
                         }
+                        TimedChain chain(*D.prof, s, GEOMST_K_EXPAND);
                         for (int j = 0; j < kLevelBatch; ++j, ++lv, ++levels) {
-                            TIMED(GEOMST_K_EXPAND);
                             RoundArgs r = args(beta2, fo, (lv + 1) & 1, po);
                             k_level<D_><<<LevelShape<D_>::grid, LevelShape<D_>::block, 0, s>>>(t, r, hdb, D.Q[lv & 1].as<PairRec>(),
                                                                  (u32)(D.capQ[lv & 1] / kRegions),
@@ -895,8 +924,9 @@ struct Solver {
                                                                  ring + ((lv + 1) % kQRing) * kSlotWords,
                                                                  ring + ((lv + 2) % kQRing) * kSlotWords);
                             LAUNCHCHK();
+                            chain.tick();
                         }
-                        read_slot(ring, lv % kQRing, nq, nq_region);
+                        read_slot(lv % kQRing, nq, nq_region);
                         D.qmax_seen = std::max<size_t>(D.qmax_seen, (size_t)kRegions * nq_region);
                         if (D.hcnt->c[C_ERR] & 1u) {
                             restart = true;
@@ -1000,18 +1030,18 @@ struct Solver {
                 D.apos[1].ensure((size_t)m * 8);
                 D.ru.ensure((size_t)m * 4);
                 D.rv.ensure((size_t)m * 4);
-                D.nalive.ensure(8);
+                u32* nalive = aux_dev(D, kAuxNalive);
                 unsigned gk = std::min(blocks(m, kBlock), (unsigned)kGrid);
                 k_alive_init<<<gk, kBlock, 0, s>>>(perm, L, m, D.alive[0].as<u32>(), D.apos[0].as<u64>());
                 LAUNCHCHK();
-                k_set_u32<<<1, 1, 0, s>>>(D.nalive.as<u32>(), m);
+                k_set_u32<<<1, 1, 0, s>>>(nalive, m);
                 LAUNCHCHK();
                 int ac = 0;
                 while (true) {
                     for (int j = 0; j < kBoruvkaBatch; ++j) {
                         TIMED(GEOMST_K_KRUSKAL);
-                        u32* na_in = D.nalive.as<u32>() + ac;
-                        u32* na_out = D.nalive.as<u32>() + (ac ^ 1);
+                        u32* na_in = nalive + ac;
+                        u32* na_out = nalive + (ac ^ 1);
                         const u32 stamp = --bstamp;  // decreasing: this step's keys beat older ones
                         k_bor_pick<<<gk, kBlock, 0, s>>>(D.alive[ac].as<u32>(), D.apos[ac].as<u64>(), na_in, m,
                                                         D.uf.as<u32>(), D.best.as<u64>(), stamp, D.ru.as<u32>(),
@@ -1025,9 +1055,8 @@ struct Solver {
                         ac ^= 1;
                     }
                     u32 left = 0;
-                    HIPCHK(hipMemcpyAsync(D.hpin, D.nalive.as<u32>() + ac, 4, hipMemcpyDeviceToHost, s));
-                    read_counters(D, s);  // one sync for both
-                    left = D.hpin[0];
+                    read_counters(D, s, kAuxNalive + 8);  // the counters and the alive count
+                    left = aux_host(D, kAuxNalive)[ac];
                     if (left == 0) break;
                 }
             }
@@ -1130,9 +1159,9 @@ Device& device_ctx(int* dev_out) {
 void ensure_init(Device& D) {
     if (D.init) return;
     HIPCHK(hipStreamCreateWithFlags(&D.own, hipStreamNonBlocking));
-    HIPCHK(hipHostMalloc((void**)&D.hcnt, sizeof(Counters), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&D.hcnt, kCntBytes, hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&D.hpin, kPinWords * sizeof(u32), hipHostMallocDefault));
-    D.cnt.ensure(sizeof(Counters));
+    D.cnt.ensure(kCntBytes);
     D.prof = &D.profm;
     D.init = true;
 }

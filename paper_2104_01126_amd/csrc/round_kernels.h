@@ -380,7 +380,7 @@ __global__ void k_init_frontier(TreeView t, int hdb, const u32* pinst, PairRec* 
 // Start of a round: zero the per-round list counters, set the minima to
 // "none", keep `far_keep` retained far pairs.  The error flags and the
 // running totals are left alone.
-__global__ void k_round_reset(Counters* cnt, u32 far_keep) {
+__global__ void k_round_reset(Counters* cnt, u32 far_keep, u32* ring) {
     const int i = threadIdx.x;
     if (i < C_OUT) cnt->c[i] = 0;
     if (i == 0) {
@@ -388,6 +388,7 @@ __global__ void k_round_reset(Counters* cnt, u32 far_keep) {
         cnt->c[C_TINY] = 0;
     }
     if (i < M_NUM) cnt->m[i] = ~0ull;
+    for (int w = i; w < kQRing * kSlotWords; w += blockDim.x) ring[w] = 0;  // level-queue counts
 }
 
 // Smallest positive lower bound over a pair list and, when `hist` is given,
@@ -1555,27 +1556,50 @@ __global__ void k_bor_pick(const u32* alive, const u64* apos, const u32* nalive_
                            u32 stamp, u32* ru, u32* rv, u32* nalive_next, Counters* cnt) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *nalive_next = 0;  // the hook step appends after this kernel
     const u32 na = min(*nalive_p, cap);
-    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < na; s += gridDim.x * blockDim.x) {
-    u32 rank = alive[s];
-    const u64 key = ((u64)stamp << 32) | rank;
-    u64 pos = apos[s];
-    u32 a = uf_find(parent, (u32)(pos >> 32), cnt);
-    u32 b = uf_find(parent, (u32)pos, cnt);
-    if (a == b) {
-        ru[s] = kNone;
-        continue;
-    }
-    ru[s] = a;
-    rv[s] = b;
-    // read first: most candidates already lose to a smaller rank
-    if (key < best[a]) atomicMin((unsigned long long*)&best[a], (unsigned long long)key);
-    if (key < best[b]) atomicMin((unsigned long long*)&best[b], (unsigned long long)key);
+    const int lane = lane_id();
+    // the loop bound is uniform over the block, so every lane reaches the
+    // shuffle below
+    for (u32 s0 = blockIdx.x * blockDim.x; s0 < na; s0 += gridDim.x * blockDim.x) {
+        const u32 s = s0 + threadIdx.x;
+        u32 a = kNone, b = kNone;
+        u64 key = ~0ull;
+        if (s < na) {
+            const u32 rank = alive[s];
+            const u64 pos = apos[s];
+            a = uf_find(parent, (u32)(pos >> 32), cnt);
+            b = uf_find(parent, (u32)pos, cnt);
+            if (a == b) {
+                ru[s] = kNone;
+                a = b = kNone;
+            } else {
+                ru[s] = a;
+                rv[s] = b;
+                key = ((u64)stamp << 32) | rank;
+            }
+        }
+        // The alive list runs in rank order (within each hook block's
+        // output), and runs of consecutive edges often share a component
+        // (ties of core distances; a few large components late in the
+        // tree).  An end whose component the previous lane's lighter edge
+        // also touches needs no update: that edge, or a still lighter one
+        // before it, reaches the component's minimum.  The lightest edge of
+        // a component is never skipped, so the minima are unchanged.
+        const u32 pa = __shfl_up(a, 1), pb = __shfl_up(b, 1);
+        const u64 pk = __shfl_up(key, 1);
+        if (a == kNone) continue;
+        const bool prev = lane > 0 && pk < key;
+        // read first: most candidates already lose to a smaller rank
+        if (!(prev && (pa == a || pb == a)) && key < best[a])
+            atomicMin((unsigned long long*)&best[a], (unsigned long long)key);
+        if (!(prev && (pa == b || pb == b)) && key < best[b])
+            atomicMin((unsigned long long*)&best[b], (unsigned long long)key);
     }
 }
 
 // Hook step: each component's lightest edge (its rank is in best) joins it
-// to the other end's component.  Four edges per thread and 1024-thread
-// blocks: one append per list per 4096 edges.
+// to the other end's component.  Four consecutive edges per thread and
+// 1024-thread blocks: one append per list per 4096 edges, and the kept edges
+// of a block stay in their input order.
 constexpr int kHookBlock = 1024;
 constexpr int kHookItems = 4;
 constexpr int kHookTile = kHookBlock * kHookItems;
@@ -1594,7 +1618,7 @@ __global__ void __launch_bounds__(kHookBlock) k_bor_hook(const u32* alive, const
         u32 src[kHookItems];
 #pragma unroll
         for (int k = 0; k < kHookItems; ++k) {
-            const u32 s = b0 + k * kHookBlock + threadIdx.x;
+            const u32 s = b0 + threadIdx.x * kHookItems + k;
             rank[k] = 0;
             src[k] = s;
             const u32 a = s < na ? ru[s] : kNone;
