@@ -312,9 +312,8 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
     u32* tieflag = D.minmax.as<u32>() + 8;
     // one word: gather through the current permutation (in place), then sort
     auto word = [&](const u32* perm, int kind, bool check_ties) -> bool {
-        HIPCHK(hipMemsetAsync(mm, 0xff, 8, s));
-        HIPCHK(hipMemsetAsync(mm + 1, 0, 8, s));
-        HIPCHK(hipMemsetAsync(tieflag, 0, 4, s));
+        k_sort_init<<<1, kWave, 0, s>>>(mm, tieflag);
+        LAUNCHCHK();
         k_gather_word<<<gg, kBlock, 0, s>>>(L, perm, m, kind, B, pinst, ka, va, mm);
         LAUNCHCHK();
         u64* h = (u64*)D.hpin;  // pinned
@@ -339,21 +338,28 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
     // after sorting by w2: order the runs of equal w2 by (d2, ids); false if
     // a run is too long for that
     auto fix_runs = [&]() -> bool {
-        HIPCHK(hipMemsetAsync(tieflag, 0, 4, s));
-        D.ke2.ensure((size_t)m * 8);
+        D.ke2.ensure((size_t)m * 8);  // tieflag[1] (long runs) was cleared with the w2 word
         k_run_keys<<<gg, kBlock, 0, s>>>(L, ka, va, m, kb, D.ke2.as<u64>());
         LAUNCHCHK();
-        k_fix_runs<<<gg, kBlock, 0, s>>>(ka, va, kb, D.ke2.as<u64>(), m, tieflag);
+        k_fix_runs<<<gg, kBlock, 0, s>>>(ka, va, kb, D.ke2.as<u64>(), m, vb, tieflag + 1);
         LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(D.hpin, tieflag, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(D.hpin, tieflag + 1, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        return D.hpin[0] == 0;
+        if (D.hpin[0] != 0) return false;
+        std::swap(va, vb);
+        return true;
     };
     // Batched output: the instance is the most significant word.
     auto finish = [&]() -> u32* {
         if (pinst) word(va, 3, false);
         return va;
     };
+    // a short list: the whole order in one workgroup, no host round trip
+    if (!pinst && m <= (u32)kSmallSort) {
+        k_sort_small<<<1, kSmallSortBlock, 0, s>>>(L, m, va);
+        LAUNCHCHK();
+        return va;
+    }
     // fast path: order by w2; done when no two keys tie, or when every run of
     // equal w2 is short enough to be ordered in place by (d2, ids); otherwise
     // the full order, least significant word first

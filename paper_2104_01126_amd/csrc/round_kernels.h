@@ -1442,6 +1442,17 @@ __global__ void __launch_bounds__(kBlock) k_gather_word(const EdgeList L, const 
     }
 }
 
+// Clears the per-word state of the edge sort: the key word's running min and
+// max, the tie flag and the long-run flag.
+__global__ void k_sort_init(u64* minmax, u32* flags) {
+    if (threadIdx.x == 0) {
+        minmax[0] = ~0ull;
+        minmax[1] = 0;
+        flags[0] = 0;
+        flags[1] = 0;
+    }
+}
+
 // Flags whether two neighbours of a sorted key array are equal.
 __global__ void k_flag_ties(const u64* key, u32 m, u32* flag) {
     bool tie = false;
@@ -1451,13 +1462,14 @@ __global__ void k_flag_ties(const u64* key, u32 m, u32* flag) {
 }
 
 // After a sort by w2 (keys `key`, permutation `val`): order every run of
-// equal w2 by (d2, ids) in place, which completes the order K.  First the
-// (d2, ids) of every element that belongs to a run are gathered into sorted
-// order (te, ti), all elements in parallel; then one thread per run
-// insertion-sorts the run's (te, ti, val) in those contiguous arrays.  A run
-// longer than kRunMax is left alone and flagged (the caller then sorts by
-// every word).
-constexpr u32 kRunMax = 64;
+// equal w2 by (d2, ids), which completes the order K.  First the (d2, ids)
+// of every element that belongs to a run are gathered into sorted order
+// (te, ti), all elements in parallel; then every element of a run counts the
+// run's members that precede it in (d2, ids) and writes its edge to that
+// rank in `out` (elements outside runs are copied).  The members of a run sit
+// side by side, so the lanes of a run read the same words together.  A run
+// longer than kRunMax is flagged (the caller then sorts by every word).
+constexpr u32 kRunMax = 256;
 
 __global__ void __launch_bounds__(kBlock) k_run_keys(const EdgeList L, const u64* key, const u32* val, u32 m,
                                                      u64* te, u64* ti) {
@@ -1471,36 +1483,78 @@ __global__ void __launch_bounds__(kBlock) k_run_keys(const EdgeList L, const u64
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_fix_runs(const u64* key, u32* val, u64* te, u64* ti, u32 m,
-                                                     u32* longrun) {
+__global__ void __launch_bounds__(kBlock) k_fix_runs(const u64* key, const u32* val, const u64* te, const u64* ti,
+                                                     u32 m, u32* out, u32* longrun) {
+    bool too_long = false;
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         const u64 k = key[i];
-        if (i > 0 && key[i - 1] == k) continue;  // not the first of its run
-        u32 j = i + 1;
-        while (j < m && j - i <= kRunMax && key[j] == k) ++j;
-        const u32 len = j - i;
-        if (len == 1) continue;
-        if (len > kRunMax) {
-            atomicOr(longrun, 1u);
+        const bool left = i > 0 && key[i - 1] == k, right = i + 1 < m && key[i + 1] == k;
+        if (!left && !right) {
+            out[i] = val[i];
             continue;
         }
-        for (u32 a = i + 1; a < j; ++a) {
-            const u32 v = val[a];
-            const u64 ve = te[a], vi = ti[a];
-            u32 b = a;
-            while (b > i) {
-                const u64 ue = te[b - 1], ui = ti[b - 1];
-                if (ue < ve || (ue == ve && ui < vi)) break;
-                te[b] = ue;
-                ti[b] = ui;
-                val[b] = val[b - 1];
-                --b;
+        u32 s = i, e = i + 1;
+        while (s > 0 && i - s < kRunMax && key[s - 1] == k) --s;
+        while (e < m && e - i < kRunMax && key[e] == k) ++e;
+        if (e - s > kRunMax || (s > 0 && key[s - 1] == k) || (e < m && key[e] == k)) {
+            too_long = true;
+            continue;
+        }
+        const u64 ve = te[i], vi = ti[i];
+        u32 r = 0;
+        for (u32 j = s; j < e; ++j) {
+            const u64 ue = te[j], uj = ti[j];
+            r += (ue < ve || (ue == ve && (uj < vi || (uj == vi && j < i)))) ? 1u : 0u;
+        }
+        out[s + r] = val[i];
+    }
+    if (__any(too_long) && lane_id() == 0) atomicOr(longrun, 1u);
+}
+
+// The whole order K for a short list in one workgroup: a bitonic sort of
+// (w2 bits, d2 bits, ids, index) in LDS, padded to a power of two with keys
+// above every edge's.  Writes the permutation (sorted rank -> edge).
+constexpr int kSmallSort = 2048;
+constexpr int kSmallSortBlock = 1024;
+
+__global__ void __launch_bounds__(kSmallSortBlock) k_sort_small(const EdgeList L, u32 m, u32* perm) {
+    __shared__ u64 kw[kSmallSort], ke[kSmallSort], ki[kSmallSort];
+    __shared__ u32 kv[kSmallSort];
+    u32 N = 2;
+    while (N < m) N <<= 1;
+    for (u32 i = threadIdx.x; i < N; i += blockDim.x) {
+        const bool real = i < m;
+        kw[i] = real ? dbits(L.w2[i]) : ~0ull;
+        ke[i] = real ? dbits(L.e2[i]) : ~0ull;
+        ki[i] = real ? L.ids[i] : ~0ull;
+        kv[i] = i;
+    }
+    __syncthreads();
+    for (u32 k = 2; k <= N; k <<= 1) {
+        for (u32 j = k >> 1; j > 0; j >>= 1) {
+            for (u32 t = threadIdx.x; t < N / 2; t += blockDim.x) {
+                const u32 a = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // bit j of a is clear
+                const u32 b = a + j;
+                const bool up = (a & k) == 0;
+                const u64 wa = kw[a], wb = kw[b], ea = ke[a], eb = ke[b], ia = ki[a], ib = ki[b];
+                const bool b_less =
+                    wb < wa || (wb == wa && (eb < ea || (eb == ea && (ib < ia || (ib == ia && kv[b] < kv[a])))));
+                if (b_less == up) {
+                    kw[a] = wb;
+                    kw[b] = wa;
+                    ke[a] = eb;
+                    ke[b] = ea;
+                    ki[a] = ib;
+                    ki[b] = ia;
+                    const u32 v = kv[a];
+                    kv[a] = kv[b];
+                    kv[b] = v;
+                }
             }
-            te[b] = ve;
-            ti[b] = vi;
-            val[b] = v;
+            __syncthreads();
         }
     }
+    for (u32 i = threadIdx.x; i < m; i += blockDim.x) perm[i] = kv[i];
 }
 
 // Instance of every arena row (instances packed in order; binary search in
