@@ -43,6 +43,7 @@ u32 g_refresh_div = 1024;    // refresh node components once a round merged n / 
 u32 g_small_switch = 2048;  // queues up to this size go to the one-workgroup level kernel
 u32 g_small_max = 4096;     // ... which keeps going while a level stays this small
 constexpr int kBoruvkaBatch = 4;  // Boruvka steps launched between host checks
+constexpr u32 kSparseDiv = 64;  // beta grows faster while the tree has fewer than n / this many edges
 const bool g_trace = getenv("GEOMST_TRACE") != nullptr;
 
 struct Fail {
@@ -1106,7 +1107,15 @@ struct Solver {
                 g_err = "no pairs left before the tree was complete";
                 throw Fail{GEOMST_EINTERNAL};
             }
-            beta2 = std::max(beta2 * g2, nxt);
+            // While the tree is nearly empty (the first rounds: the smallest
+            // pair bounds lie far below the bulk of the tree's weights) a
+            // round costs its fixed work for few edges, so the threshold then
+            // grows by g^2 at once.  Later rounds that merge little (the gaps
+            // between clusters) keep the plain growth: there, larger steps
+            // put more inter-cluster pairs into one round, before their
+            // components are known.  Any schedule gives the same tree.
+            const bool sparse = (u64)nout * kSparseDiv < (u64)n;
+            beta2 = std::max(beta2 * (sparse ? g2 * g2 : g2), nxt);
         }
         if (nout != target_edges) {
             g_err = "wrong number of tree edges";
