@@ -116,6 +116,40 @@ def test_emst_structured(G, case):
     check_emst_exact(G, np.ascontiguousarray(p), case)
 
 
+def equal_weight_blocks(blocks, side, seed):
+    """`blocks` square lattices of side x side points, block b with spacing
+    1 + b/64 (exact in binary64, and so are all squared distances), placed
+    1000 apart: each block's 2 * side * (side - 1) nearest-neighbour edges
+    share one squared weight, a run of equal w2 of that length."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    for b in range(blocks):
+        s = 1.0 + b / 64.0
+        i, j = np.meshgrid(np.arange(side), np.arange(side), indexing="ij")
+        pts.append(np.stack([1000.0 * b + s * i.ravel(), s * j.ravel()], axis=1))
+    p = np.concatenate(pts)
+    return p[rng.permutation(len(p))]
+
+
+@pytest.mark.parametrize("case", ["runs180", "runs60", "small_grid", "small_dups"])
+def test_edge_sort_paths(G, case):
+    """Equal-weight runs of every length class the edge sort treats apart:
+    up to 64 and up to 256 members (ranked in place after the w2 pass), a
+    whole list of at most 2,048 edges (one-workgroup sort), and ties of both
+    kinds inside such short lists."""
+    if case == "runs180":
+        p = equal_weight_blocks(12, 10, seed=31)      # runs of 180 equal w2
+    elif case == "runs60":
+        p = equal_weight_blocks(20, 6, seed=32)       # runs of 60 equal w2
+    elif case == "small_grid":
+        p = W.grid(20, 2, seed=33)                    # 400 points, all ties
+    else:
+        p = W.with_duplicates(1500, 3, seed=34, n_unique=200)
+    check_emst_exact(G, p, case)
+    if case in ("runs180", "small_dups"):
+        check_hdb_exact(G, p, 4, case)
+
+
 @pytest.mark.parametrize("mp", [1, 2, 3, 5, 10, 16, 33, 64])
 def test_hdbscan_minpts(G, mp):
     p = W.mixture(4000 + 11, 3, seed=mp, k=10, sig_lo=0.003, sig_hi=0.05, noise_frac=0.1)
