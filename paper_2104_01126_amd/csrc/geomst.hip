@@ -402,7 +402,7 @@ struct Solver {
         LAUNCHCHK();
         k_bbox_partial<D_><<<nbb, 256, 0, s>>>(P, n, D.part.as<double>());
         LAUNCHCHK();
-        k_bbox_final<D_><<<1, 64, 0, s>>>(D.part.as<double>(), (int)nbb, D.bbox.as<double>());
+        k_bbox_final<D_><<<1, kBboxFinal, 0, s>>>(D.part.as<double>(), (int)nbb, D.bbox.as<double>());
         LAUNCHCHK();
         D.key.ensure((size_t)n * 8);
         D.key2.ensure((size_t)n * 8);

@@ -124,16 +124,45 @@ __global__ void __launch_bounds__(256) k_bbox_partial(const double* P, int n, do
     }
 }
 
+// Combines the per-block boxes: every lane folds a strided share of them
+// (independent loads, not one dependent chain per coordinate), then the
+// waves and the block reduce.
+constexpr int kBboxFinal = 256;
+
 template <int D>
-__global__ void k_bbox_final(const double* partial, int nb, double* bbox) {
-    int k = threadIdx.x;
-    if (k >= 2 * D) return;
-    double v = partial[k];
-    for (int b = 1; b < nb; ++b) {
-        double x = partial[(size_t)b * 2 * D + k];
-        v = (k < D) ? fmin(v, x) : fmax(v, x);
+__global__ void __launch_bounds__(kBboxFinal) k_bbox_final(const double* partial, int nb, double* bbox) {
+    __shared__ double red[2 * D][kBboxFinal / kWave];
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    double lo[D], hi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        lo[k] = inf;
+        hi[k] = -inf;
     }
-    bbox[k] = v;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            lo[k] = fmin(lo[k], partial[(size_t)b * 2 * D + k]);
+            hi[k] = fmax(hi[k], partial[(size_t)b * 2 * D + D + k]);
+        }
+    }
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        lo[k] = wave_min_f64(lo[k]);
+        hi[k] = -wave_min_f64(-hi[k]);
+        if (lane_id() == 0) {
+            red[k][w] = lo[k];
+            red[D + k][w] = hi[k];
+        }
+    }
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k < 2 * D) {
+        double v = red[k][0];
+        for (int i = 1; i < kBboxFinal / kWave; ++i) v = (k < D) ? fmin(v, red[k][i]) : fmax(v, red[k][i]);
+        bbox[k] = v;
+    }
 }
 
 // ------------------------------------------------------------ Morton code
@@ -376,9 +405,22 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
     __shared__ u32 lflag[kBoundsBlock];
     __shared__ double slo[kBoundsBlock][D], shi[kBoundsBlock][D];
     __shared__ double2 scd[kBoundsBlock];
+    __shared__ int sfirst[kBoundsBlock], scount[kBoundsBlock], ssplit[kBoundsBlock], sparent[kBoundsBlock];
     const int base = blockIdx.x * kBoundsBlock;
     const int end = min(base + kBoundsBlock, n);  // leaves [base, end)
     lflag[threadIdx.x] = 0;
+    // Internal node v covers sorted position v, so only nodes base..end-1
+    // can lie inside the block: their ranges, splits and parents are loaded
+    // once, side by side, and the climbs below read them from LDS.
+    {
+        const int v = base + threadIdx.x;
+        if (v < end && v < n - 1) {
+            sfirst[threadIdx.x] = nodes[v].first;
+            scount[threadIdx.x] = nodes[v].count;
+            ssplit[threadIdx.x] = nodes[v].split;
+            sparent[threadIdx.x] = parent[v];
+        }
+    }
     __syncthreads();
     int p = base + threadIdx.x;
     if (p >= n) return;
@@ -400,8 +442,9 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
     int v = parent[leaf];
     while (v >= 0) {
         NodeRec<D>& V = nodes[v];
-        int f = V.first, c = V.count;
-        if (!(f >= base && f + c <= end)) {
+        const bool local = v >= base && v < end;  // else v's range holds a position outside the block
+        const int f = local ? sfirst[v - base] : 0, c = local ? scount[v - base] : 0;
+        if (!local || !(f >= base && f + c <= end)) {
             // spanning node: hand the climb over to phase 2
             const u32 sb = (u32)base / kBoundsSpan;
             __threadfence();
@@ -412,7 +455,7 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
         __threadfence_block();
         if (atomicAdd(&lflag[v - base], 1u) == 0) return;
         __threadfence_block();
-        int2 ch = node_kids(n, f, c, V.split);
+        int2 ch = node_kids(n, f, c, ssplit[v - base]);
         double lo[D], hi[D];
         double2 cd = make_double2(0.0, 0.0);
 #pragma unroll
@@ -442,7 +485,7 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
         }
         if (geometry) write_box<D>(V, lo, hi);
         child = v;
-        v = parent[v];
+        v = sparent[v - base];
     }
 }
 
