@@ -674,16 +674,26 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KnnWave
                 if (lane_id() == 0) atomicOr(err, 4u);
                 continue;
             }
-            int2 c = node_kids(n, N[v].first, N[v].count, N[v].split);
-            // visit first the child nearer to lane 0's query
+            const int g = N[v].split;
+            int2 c = node_kids(n, r.x, r.y, g);
+            // A child goes on the stack only if some lane may still want it
+            // (its range [first, g] or [g + 1, last] meets the lane's
+            // instance and its bound is below the lane's k-th distance): the
+            // k-th distances only shrink, so a child no lane wants now is
+            // never wanted later, and skipping it saves a dependent load.
+            // The child nearer to lane 0's query is visited first.
             double la = point_box_lb2<D>(q, N[c.x].lo, N[c.x].hi);
             double lr = point_box_lb2<D>(q, N[c.y].lo, N[c.y].hi);
+            const bool wa = __any(live && la < kth && r.x < hi_r && g + 1 > lo_r);
+            const bool wb = __any(live && lr < kth && g + 1 < hi_r && r.x + r.y > lo_r);
             bool leftfirst = __shfl(la <= lr ? 1 : 0, 0) != 0;
+            const int first = leftfirst ? c.y : c.x, second = leftfirst ? c.x : c.y;
+            const bool wfirst = leftfirst ? wb : wa, wsecond = leftfirst ? wa : wb;
             if (lane_id() == 0) {
-                stack[sp] = leftfirst ? c.y : c.x;
-                stack[sp + 1] = leftfirst ? c.x : c.y;
+                if (wfirst) stack[sp] = first;
+                if (wsecond) stack[sp + (wfirst ? 1 : 0)] = second;
             }
-            sp += 2;
+            sp += (wfirst ? 1 : 0) + (wsecond ? 1 : 0);
             __syncthreads();
         }
     }
