@@ -573,8 +573,8 @@ struct LevelAcc {
 // pairs due in this round go to qout through counter ctr[5].  All threads of
 // the block must call it.
 template <int D>
-__device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r, int hdb, const PairRec* qin,
-                                           bool have, u32 i, PairRec* qout, u32 cap_qout, u32* const* ctr,
+__device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r, int hdb, bool have,
+                                           const PairRec& pr, PairRec* qout, u32 cap_qout, u32* const* ctr,
                                            BlockAlloc& S, LevelAcc& acc) {
     const NodeRec<D>* N = nodes_of<D>(t);
     bool to_tiny = false, to_big = false, to_f = false;
@@ -585,7 +585,6 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
     double lbc[2] = {0.0, 0.0};
     bool cf[2] = {false, false}, cq[2] = {false, false};
     if (have) {
-        PairRec pr = qin[i];
         a = pr.a;
         b = pr.b;
         ++acc.visits;
@@ -762,8 +761,9 @@ k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const 
     for (u32 v0 = lo + j * NT; v0 < hi; v0 += g * NT) {
         const u32 v = v0 + threadIdx.x;
         const bool have = v < hi;
-        const u32 i = have ? region_index(pre, cap_in, v) : 0u;
-        level_step<D>(t, r, hdb, qin, have, i, qout, r.cap_q, ctr, S, acc);
+        PairRec pr = {0u, 0u, 0.0};
+        if (have) pr = qin[region_index(pre, cap_in, v)];
+        level_step<D>(t, r, hdb, have, pr, qout, r.cap_q, ctr, S, acc);
     }
     level_flush<NT>(r, acc);
 }
@@ -808,7 +808,9 @@ __global__ void __launch_bounds__(SmallBlock<D>::value) k_level_small(TreeView t
             const u32 v = b0 + threadIdx.x;
             const bool have = v < nq;
             const u32 i = (have && first) ? region_index(pre, capi, v) : v;
-            level_step<D>(t, r, hdb, qin, have, i, qout, capo, ctr, S, acc);
+            PairRec pr = {0u, 0u, 0.0};
+            if (have) pr = qin[i];
+            level_step<D>(t, r, hdb, have, pr, qout, capo, ctr, S, acc);
         }
         __syncthreads();
         u32 nn = qn;
