@@ -1386,17 +1386,6 @@ __global__ void __launch_bounds__(kBlock) k_split_pool(RoundArgs r, EdgeList pin
 }
 
 // ------------------------------------------------------------ Kruskal
-// Sort keys: ids packed tight as (lo << B) | hi, then e2 and w2 bit patterns
-// (non-negative doubles order like their bits).
-__global__ void k_sortkeys(const EdgeList L, u32 m, int B, u64* kid, u64* ke2, u64* kw2, u32* perm) {
-    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    u64 ids = L.ids[i];
-    kid[i] = ((ids >> 32) << B) | (ids & 0xffffffffull);
-    if (ke2) ke2[i] = dbits(L.e2[i]);
-    kw2[i] = dbits(L.w2[i]);
-    perm[i] = i;
-}
 
 // One key word of the edge order, gathered through the current permutation
 // (identity when perm is null; perm may alias val): 0 = ids packed as
