@@ -1114,8 +1114,14 @@ struct Solver {
             // between clusters) keep the plain growth: there, larger steps
             // put more inter-cluster pairs into one round, before their
             // components are known.  Any schedule gives the same tree.
+            // For EMST, a round that found no edge at all (nothing committed,
+            // pooled or queued as a large pair, before the first edge) grows
+            // it by g^4: on the same grid of thresholds, it skips rounds that
+            // would only split pairs.  (For HDBSCAN* the larger first round
+            // this leads to cost more than the rounds it saves.)
             const bool sparse = (u64)nout * kSparseDiv < (u64)n;
-            beta2 = std::max(beta2 * (sparse ? g2 * g2 : g2), nxt);
+            const bool empty = !hdb && nout == 0 && m == 0 && nP == 0 && nbig == 0;
+            beta2 = std::max(beta2 * (empty ? g2 * g2 * g2 * g2 : sparse ? g2 * g2 : g2), nxt);
         }
         if (nout != target_edges) {
             g_err = "wrong number of tree edges";
