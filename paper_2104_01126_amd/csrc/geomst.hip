@@ -1055,7 +1055,7 @@ struct Solver {
                                                         D.rv.as<u32>(), na_out, D.cnt.as<Counters>());
                         LAUNCHCHK();
                         k_bor_hook<<<std::min(blocks(m, kHookTile), 256u), kHookBlock, 0, s>>>(
-                            D.alive[ac].as<u32>(), D.apos[ac].as<u64>(), na_in, m, perm, L, D.uf.as<u32>(),
+                            D.alive[ac].as<u32>(), na_in, m, perm, L, D.uf.as<u32>(),
                             D.best.as<u64>(), stamp, D.ru.as<u32>(), D.rv.as<u32>(), D.alive[ac ^ 1].as<u32>(),
                             D.apos[ac ^ 1].as<u64>(), na_out, D.OUT.list(), (u32)D.OUT.cap, D.cnt.as<Counters>());
                         LAUNCHCHK();

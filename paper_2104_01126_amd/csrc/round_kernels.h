@@ -1588,8 +1588,10 @@ __device__ __forceinline__ u32 uf_find(u32* parent, u32 x, Counters* cnt) {
 // best[c] holds (stamp << 32 | rank) of component c's lightest edge in the
 // step with that stamp; stamps decrease step by step, so a new step's keys
 // win over stale ones without clearing the array between steps.
-// The alive list holds each undecided edge's rank and, alongside, its two
-// end positions (apos), so the step reads them without the permutation.
+// The alive list holds each undecided edge's rank and, alongside, a vertex
+// of each end's component (apos): the end positions at first, the roots
+// found by the last step once the edge has been kept, so a step reads no
+// permutation and its finds start close to the roots.
 __global__ void k_alive_init(const u32* perm, const EdgeList L, u32 m, u32* alive, u64* apos) {
     for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < m; s += gridDim.x * blockDim.x) {
         alive[s] = s;
@@ -1649,7 +1651,7 @@ constexpr int kHookBlock = 1024;
 constexpr int kHookItems = 4;
 constexpr int kHookTile = kHookBlock * kHookItems;
 
-__global__ void __launch_bounds__(kHookBlock) k_bor_hook(const u32* alive, const u64* apos, const u32* nalive_p,
+__global__ void __launch_bounds__(kHookBlock) k_bor_hook(const u32* alive, const u32* nalive_p,
                                                          u32 cap, const u32* perm, const EdgeList L, u32* parent,
                                                          const u64* best, u32 stamp, const u32* ru, const u32* rv,
                                                          u32* alive_next, u64* apos_next, u32* nalive_next,
@@ -1660,15 +1662,16 @@ __global__ void __launch_bounds__(kHookBlock) k_bor_hook(const u32* alive, const
     for (u32 b0 = blockIdx.x * kHookTile; b0 < na; b0 += gridDim.x * kHookTile) {
         u32 sel = 0, keep = 0, ns = 0, nk = 0;
         u32 rank[kHookItems];
-        u32 src[kHookItems];
+        u64 roots[kHookItems];
 #pragma unroll
         for (int k = 0; k < kHookItems; ++k) {
             const u32 s = b0 + threadIdx.x * kHookItems + k;
             rank[k] = 0;
-            src[k] = s;
+            roots[k] = 0;
             const u32 a = s < na ? ru[s] : kNone;
             if (a == kNone) continue;
             const u32 b = rv[s];
+            roots[k] = ((u64)a << 32) | b;
             rank[k] = alive[s];
             const u64 key = ((u64)stamp << 32) | rank[k];
             const bool pa = best[a] == key, pb = best[b] == key;
@@ -1701,8 +1704,10 @@ __global__ void __launch_bounds__(kHookBlock) k_bor_hook(const u32* alive, const
             }
             if ((keep >> k) & 1u) {
                 if (off[1] < cap) {
+                    // the ends' roots of this step: a later step's finds
+                    // start there instead of at the end points
                     alive_next[off[1]] = rank[k];
-                    apos_next[off[1]] = apos[src[k]];
+                    apos_next[off[1]] = roots[k];
                 }
                 ++off[1];
             }
