@@ -261,6 +261,12 @@ int geomst_get_stats(geomst_stats_t* out);
  *                    binary64 binade in which this fraction of the initial
  *                    pairs' positive lower bounds is reached (default 0:
  *                    the smallest positive bound).
+ *   "beta_schedule"  0 = default: the threshold grows by g per round, by g^2
+ *                    while the tree holds fewer than n/64 edges, and (EMST)
+ *                    by g^4 after a round that found no edge before the
+ *                    first one; 1 = plain: beta <- max(g * beta, smallest
+ *                    waiting bound) every round, starting at the smallest
+ *                    positive pair bound (doubling for EMST).
  *   "list_capacity_scale"  (0,1]: scale of the initial capacities of the
  *                    internal pair and edge lists (default 1); small values make
  *                    the lists overflow, grow and restart rounds (a testing aid).

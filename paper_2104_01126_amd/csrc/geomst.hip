@@ -37,6 +37,7 @@ double g_separation = 2.0;   // s of the sphere separation test
 int g_bccp_chunk = kBigBDefault;  // B points per large-pair BCCP task
 double g_capacity_scale = 1.0;
 double g_beta_start = 0.0;  // fraction of the initial pair bounds below the first threshold (0: the smallest)
+int g_beta_plain = 0;        // 1: the threshold grows by exactly g every round (no early-round acceleration)
 constexpr int kMaxKeyLevels = 6;  // Morton key words per point (see k_morton_level)
 constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
 u32 g_refresh_div = 1024;    // refresh node components once a round merged n / this many
@@ -1119,8 +1120,8 @@ struct Solver {
             // it by g^4: on the same grid of thresholds, it skips rounds that
             // would only split pairs.  (For HDBSCAN* the larger first round
             // this leads to cost more than the rounds it saves.)
-            const bool sparse = (u64)nout * kSparseDiv < (u64)n;
-            const bool empty = !hdb && nout == 0 && m == 0 && nP == 0 && nbig == 0;
+            const bool sparse = !g_beta_plain && (u64)nout * kSparseDiv < (u64)n;
+            const bool empty = !g_beta_plain && !hdb && nout == 0 && m == 0 && nP == 0 && nbig == 0;
             beta2 = std::max(beta2 * (empty ? g2 * g2 * g2 * g2 : sparse ? g2 * g2 : g2), nxt);
         }
         if (nout != target_edges) {
@@ -1971,6 +1972,11 @@ int geomst_set_option(const char* name, double value) {
     if (!strcmp(name, "beta_start_quantile")) {
         if (!(value >= 0.0 && value <= 1.0)) return GEOMST_EINVAL;
         g_beta_start = value;
+        return GEOMST_OK;
+    }
+    if (!strcmp(name, "beta_schedule")) {
+        if (value != 0.0 && value != 1.0) return GEOMST_EINVAL;
+        g_beta_plain = value != 0.0;
         return GEOMST_OK;
     }
     if (!strcmp(name, "list_capacity_scale")) {

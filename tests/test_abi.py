@@ -78,6 +78,9 @@ def test_options(lib):
     assert lib.geomst_set_option(b"beta_start_quantile", -0.1) == G.EINVAL
     assert lib.geomst_set_option(b"beta_start_quantile", 1.0 / 64) == G.OK
     assert lib.geomst_set_option(b"beta_start_quantile", 0.0) == G.OK  # back to the default
+    assert lib.geomst_set_option(b"beta_schedule", 2.0) == G.EINVAL
+    assert lib.geomst_set_option(b"beta_schedule", 1.0) == G.OK
+    assert lib.geomst_set_option(b"beta_schedule", 0.0) == G.OK
 
 
 def _c_layout(exprs):

@@ -9,7 +9,10 @@ weights of every returned edge, core distances of sampled points, and the cut
 property on sampled cuts (each tree edge is the lightest edge leaving the
 small side of the cut it makes).
 """
+import hashlib
+import json
 import math
+import os
 import sys
 
 import numpy as np
@@ -52,6 +55,23 @@ def run_hdb(G, p, mp):
 
 def same(a, b):
     return a.shape == b.shape and np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def digest_file(name):
+    """Checker digests written by tests/golden/make_digests.py (None if that
+    workload's file has not been generated)."""
+    path = os.path.join(GOLDEN, f"digest_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
 def check_emst_exact(G, p, tag):
@@ -214,8 +234,8 @@ def test_rejects_non_finite_input(G):
 
 
 def test_repeatable_and_schedule_independent(G):
-    """Same bytes on repeated calls, for any threshold growth factor and any
-    first threshold."""
+    """Same bytes on repeated calls, for any threshold growth factor, any
+    first threshold and the plain doubling schedule."""
     p = W.mixture(8000, 3, seed=41, k=9, noise_frac=0.05)
     ref = run_emst(G, p)
     try:
@@ -234,9 +254,34 @@ def test_repeatable_and_schedule_independent(G):
             G.set_option("beta_start_quantile", q)
             assert all(same(a, b) for a, b in zip(ref, run_emst(G, p))), q
             assert all(same(a, b) for a, b in zip(h1, run_hdb(G, p, 7))), q
+        G.set_option("beta_start_quantile", 0.0)
+        G.set_option("beta_schedule", 1)  # plain: beta doubles every round
+        assert all(same(a, b) for a, b in zip(ref, run_emst(G, p)))
+        assert all(same(a, b) for a, b in zip(h1, run_hdb(G, p, 7)))
     finally:
         G.set_option("beta_growth", 0)
         G.set_option("beta_start_quantile", 0.0)
+        G.set_option("beta_schedule", 0)
+
+
+@pytest.mark.parametrize("chunk", [64, 128])
+def test_large_pair_chunks_exact(G, chunk):
+    """Tight, far-apart clusters give separated pairs of thousands of points
+    on each side; with B chunks of 64 or 128 points every such pair is cut
+    into many tasks along B (tasks with a nonzero B offset that share the
+    pair's best weight), and the result must still be the checker's."""
+    p3 = W.mixture(20_000, 3, seed=61, k=4, sig_lo=0.001, sig_hi=0.01, noise_frac=0.0)
+    p5 = W.mixture(20_000, 5, seed=62, k=4, sig_lo=0.001, sig_hi=0.01, noise_frac=0.01)
+    try:
+        G.set_option("bccp_chunk", chunk)
+        check_emst_exact(G, p3, f"clusters3 chunk={chunk}")
+        st = G.stats()
+        assert st.big_pairs > 0 and st.big_evals > 0, "no large-pair tasks were run"
+        check_hdb_exact(G, p5, 10, f"clusters5 chunk={chunk}")
+        st = G.stats()
+        assert st.big_pairs > 0 and st.big_evals > 0, "no large-pair tasks were run"
+    finally:
+        G.set_option("bccp_chunk", 0)
 
 
 def test_list_overflow_restarts(G):
@@ -314,6 +359,13 @@ def test_emst_1m_full_size(G):
         side[v] = 1
         lo, hi, _, _ = oracle.lightest_cut_edge(p, side)
         assert (lo, hi) in tree
+    # the whole output, byte for byte, against the checker's dense Prim run
+    g = digest_file("emst_1m")
+    if g is None:
+        pytest.skip("tests/golden/digest_emst_1m.json has not been generated")
+    assert g["n"] == n
+    assert sha(e) == g["edges"], "edge list differs from the checker's"
+    assert sha(w2) == g["w2"], "squared weights differ from the checker's"
 
 
 def test_hdbscan_2m_full_size(G):
@@ -340,3 +392,21 @@ def test_hdbscan_2m_full_size(G):
     key = np.lexsort((e[:, 1], e[:, 0], e2all, w2))
     assert np.array_equal(key, np.arange(n - 1)), "edges not sorted by the key"
     tree_order(n, e)
+    # the whole output, byte for byte, against the checker's run (core
+    # distances by exhaustive scan, then dense Prim)
+    g = digest_file("hdbscan_2m")
+    if g is None:
+        pytest.skip("tests/golden/digest_hdbscan_2m.json has not been generated")
+    assert g["n"] == n and g["min_pts"] == 10
+    assert sha(cd2) == g["cd2"], "core distances differ from the checker's"
+    assert sha(e) == g["edges"], "edge list differs from the checker's"
+    assert sha(w2) == g["w2"], "squared weights differ from the checker's"
+    # cut property on sampled cuts; cd2 is now byte-identical to the
+    # checker's own core distances
+    sampled_cut_checks(p, e, w2, cd2=cd2, max_side=100, count=12, seed=4)
+    tree = {tuple(x) for x in e.tolist()}
+    for v in rng.choice(n, 100, replace=False):
+        side = np.zeros(n, np.uint8)
+        side[v] = 1
+        lo, hi, _, _ = oracle.lightest_cut_edge(p, side, cd2=cd2)
+        assert (lo, hi) in tree

@@ -80,6 +80,36 @@ def test_mix_identical_to_alone(G):
         assert np.array_equal(e, eo) and same(w, wo), r
 
 
+def test_trace_prefix_against_checker(G):
+    """The first 0.05 s of the serving stream itself (n log-uniform in
+    [1e3, 1e6], d = 2..7, EMST and HDBSCAN* with minPts 5/10/16), submitted
+    at once: every result is byte-identical to the same request solved
+    alone, and every request with n <= 20,000 also to the checker."""
+    trace = W.serving_trace(duration_s=0.05)
+    say("serving trace prefix", len(trace), "requests", sum(r.n for r in trace), "points")
+    pts = [W.serving_points(r) for r in trace]
+    with G.Server(workers=2) as S:
+        tickets = [S.submit(x, r.min_pts) for x, r in zip(pts, trace)]
+        got = [S.wait(t) for t in tickets]
+    checked = 0
+    for r, x, (e, w, cd, info) in zip(trace, pts, got):
+        assert info["status"] == 0, r
+        e0, w0, cd0 = alone(G, x, r.min_pts)
+        assert same(e, e0) and same(w, w0), r
+        if r.min_pts:
+            assert same(cd, cd0), r
+        if r.n <= 20000:
+            say("checker", r.index, r.n, r.d, r.min_pts)
+            if r.min_pts:
+                _, cdo, eo, _, _, wo = oracle.hdbscan(x, r.min_pts)
+                assert same(cd, cdo), r
+            else:
+                eo, _, wo = oracle.emst(x)
+            assert np.array_equal(e, eo) and same(w, wo), r
+            checked += 1
+    assert checked >= 20
+
+
 def test_concurrent_submitters(G):
     trace = small_trace(0.03, 5000)
     pts = [W.serving_points(r) for r in trace]
