@@ -88,6 +88,32 @@ int geomst_hdbscan_dev(const double* d_points, int64_t n, int32_t d, int32_t min
                        void* stream);
 
 /*
+ * No-allocation variant of geomst_emst_dev, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, result and stream
+ * semantics as geomst_emst_dev; the caller still passes the inputs and
+ * outputs.  Every internal buffer is carved from one fixed device array of
+ * GEOMST_NOALLOC_SCRATCH_MIB MiB that the library holds on each device it
+ * runs on until the process ends; counter read-backs go to static host
+ * memory.  The call allocates nothing (no hipMalloc, hipFree, hipHostMalloc,
+ * event or stream creation) and keeps no state between calls: the array keeps
+ * the last call's contents and every call clears what it needs.
+ *   - n > GEOMST_NOALLOC_MAX_POINTS: GEOMST_EINVAL before any device work.
+ *   - a solve whose internal pair or edge lists outgrow the array (possible
+ *     for large, high-dimensional or tightly clustered inputs):
+ *     GEOMST_ENOMEM, with the array size in geomst_last_error().
+ *   - calls on one device share its array: they are serialised by a lock and
+ *     each returns only after its stream has finished, so two calls never use
+ *     the array at once; a caller must not run two such calls' kernels
+ *     concurrently by other means.  Kernel timing ("kernel_timing") is not
+ *     recorded for this call.
+ */
+#define GEOMST_NOALLOC_MAX_POINTS 65536
+#define GEOMST_NOALLOC_SCRATCH_MIB 512
+int geomst_emst_dev_noalloc(const double* d_points, int64_t n, int32_t d, int64_t* d_edges, double* d_weights,
+                            double* d_weights_sq, void* stream);
+
+/*
  * Batched solve: `count` independent instances in one device arena, solved
  * together as a forest (one tree build and one set of round launches for all
  * of them; pairs never cross instances).  Results are exactly those of solving

@@ -71,20 +71,37 @@ constexpr size_t kCntBytes = kAuxRing + (size_t)kQRing * kSlotWords * 4;
 
 inline unsigned blocks(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
+// A fixed device region carved by bumping an offset (the no-allocation entry
+// point's scratch).  While a solve on this thread has one installed, every
+// buffer a solve grows comes from it instead of hipMalloc; a buffer that is
+// the region's last carve grows in place, others move up and abandon their
+// old range until the region is reset for the next call.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, top = 0;
+    void* last = nullptr;
+};
+thread_local Arena* g_arena = nullptr;
+
 // Grow-only device buffer.
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool fixed = false;  // carved from an Arena: never freed
     DBuf() = default;
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
     ~DBuf() {
-        if (p) (void)hipFree(p);
+        if (p && !fixed) (void)hipFree(p);
     }
     void ensure(size_t need, size_t keep = 0, hipStream_t s = 0) {
         if (need <= bytes) return;
         size_t nb = std::max(need, bytes + bytes / 2);
         nb = (nb + 255) & ~(size_t)255;
+        if (g_arena) {
+            carve(*g_arena, nb, keep, s);
+            return;
+        }
         void* q = nullptr;
         // queued kernels of this solve may still use p (solves leave no work
         // queued behind them, so this solve's stream is the only one to wait for)
@@ -101,6 +118,32 @@ struct DBuf {
     template <class T>
     T* as() const {
         return (T*)p;
+    }
+    void carve(Arena& A, size_t nb, size_t keep, hipStream_t s) {
+        if (p && !fixed) {
+            g_err = "internal: a heap buffer met the fixed scratch";
+            throw Fail{GEOMST_EINTERNAL};
+        }
+        if (p && p == A.last && (size_t)((char*)p - A.base) + nb <= A.cap) {
+            A.top = (size_t)((char*)p - A.base) + nb;  // the last carve grows in place
+            bytes = nb;
+            return;
+        }
+        if (A.top + nb > A.cap) {
+            g_err = "the solve needs more than the " + std::to_string(A.cap >> 20) +
+                    " MiB of fixed device scratch of the no-allocation entry point";
+            throw Fail{GEOMST_ENOMEM};
+        }
+        void* q = A.base + A.top;
+        if (keep && p) {
+            HIPCHK(hipMemcpyAsync(q, p, std::min(keep, bytes), hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        A.top += nb;
+        A.last = q;
+        p = q;
+        bytes = nb;
+        fixed = true;
     }
 };
 
@@ -184,6 +227,8 @@ struct Device {
     DBuf birange, bik, browinst;  // batched solves: instance table and row -> instance
     Prof profm;
     Prof* prof = nullptr;
+    bool noalloc = false;     // buffers come from the fixed scratch; no event timing
+    double list_scale = 1.0;  // scale of the initial pair and edge list capacities
     ~Device() {
         if (own) (void)hipStreamDestroy(own);
         if (hcnt) (void)hipHostFree(hcnt);
@@ -755,7 +800,7 @@ struct Solver {
             }
         };
         auto sc = [&](double per_point) {
-            return std::max<size_t>(64, (size_t)(g_capacity_scale * (per_point * n + 4096)));
+            return std::max<size_t>(64, (size_t)(g_capacity_scale * D.list_scale * (per_point * n + 4096)));
         };
         if (g_capacity_scale != 1.0) {  // testing aid: start from the given capacities
             for (int i = 0; i < 2; ++i) {
@@ -1220,7 +1265,7 @@ void solve_dev(Device& D, hipStream_t s, const double* P, int n, int d, int minp
     g_stats.n = n;
     g_stats.d = d;
     g_stats.min_pts = minpts;
-    D.prof->begin(g_kernel_timing & g_kernel_timing_families);
+    D.prof->begin(D.noalloc ? 0u : (g_kernel_timing & g_kernel_timing_families));
     auto t0 = std::chrono::steady_clock::now();
     if (n == 1) {
         // one point: no edges; its core distance is 0 (minPts = 1)
@@ -1479,6 +1524,99 @@ int run_host(const double* P, int64_t n, int32_t d, int32_t minpts, int64_t* edg
     return GEOMST_OK;
 }
 
+// ------------------------------------------------- no-allocation entry point
+// geomst_emst_dev_noalloc runs the same solve as geomst_emst_dev with every
+// device buffer carved from the fixed array `scratch` (below) and the counter
+// read-backs in static host memory, so it calls no hipMalloc, hipHostMalloc,
+// hipEventCreate or hipStreamCreate.  Per device: the array's device address
+// (taken once with that device current), a lock that serialises the calls,
+// and storage for a workspace that is rebuilt empty at every call.
+constexpr size_t kNoAllocBytes = (size_t)GEOMST_NOALLOC_SCRATCH_MIB << 20;
+
+struct NoAllocSlot {
+    std::mutex mu;
+    char* ptr = nullptr;  // device address of `scratch` on this device
+    bool live = false;    // store holds a constructed workspace
+    alignas(Device) unsigned char store[sizeof(Device)];
+    alignas(256) unsigned char hcnt[kCntBytes];
+    u32 hpin[kPinWords];
+};
+NoAllocSlot g_noalloc[16];
+
+struct ArenaScope {
+    explicit ArenaScope(Arena* a) { g_arena = a; }
+    ~ArenaScope() { g_arena = nullptr; }
+};
+
+}  // namespace
+}  // namespace geomst
+
+// The no-allocation entry point's scratch (one copy per device, resident
+// while the library is loaded).  Host code never passes this name to a
+// kernel: it only stands in for the symbol; the device address comes from
+// hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[geomst::kNoAllocBytes];
+
+namespace geomst {
+namespace {
+
+int run_dev_noalloc(const double* P, int64_t n, int32_t d, long long* edges, double* w, double* w2, void* stream) {
+    g_err.clear();
+    int rc = validate(P, n, d, 0, edges);
+    if (rc) return rc;
+    if (n > GEOMST_NOALLOC_MAX_POINTS) {
+        g_err = "n exceeds GEOMST_NOALLOC_MAX_POINTS (" + std::to_string(GEOMST_NOALLOC_MAX_POINTS) +
+                ") for the no-allocation entry point";
+        return GEOMST_EINVAL;
+    }
+    try {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        if (dev < 0 || dev >= 16) {
+            g_err = "device index out of range";
+            throw Fail{GEOMST_EDEVICE};
+        }
+        NoAllocSlot& S = g_noalloc[dev];
+        std::lock_guard<std::mutex> lk(S.mu);
+        if (!S.ptr) {
+            void* a = nullptr;
+            HIPCHK(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+            if (!a) {
+                g_err = "hipGetSymbolAddress returned no address for the scratch array";
+                throw Fail{GEOMST_EDEVICE};
+            }
+            S.ptr = (char*)a;
+        }
+        if (S.live) {
+            Device* old = (Device*)S.store;
+            old->hcnt = nullptr;  // static host memory, not pinned: nothing to free
+            old->hpin = nullptr;
+            old->~Device();
+            S.live = false;
+        }
+        Device& D = *new (S.store) Device();
+        S.live = true;
+        D.hcnt = (Counters*)S.hcnt;
+        D.hpin = S.hpin;
+        D.noalloc = true;
+        D.list_scale = 0.25;
+        D.prof = &D.profm;
+        Arena A;
+        A.base = S.ptr;
+        A.cap = kNoAllocBytes;
+        ArenaScope scope(&A);
+        D.cnt.ensure(kCntBytes);
+        D.init = true;
+        solve_dev(D, (hipStream_t)stream, P, (int)n, d, 0, edges, w, w2, nullptr, nullptr);
+    } catch (const Fail& f) {
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return GEOMST_ENOMEM;
+    }
+    return GEOMST_OK;
+}
+
 // ------------------------------------------------------------ serving
 // Continuous batching: requests queue up with their arrival time; each worker
 // thread owns a workspace and a stream, takes what is queued at the front (up
@@ -1668,6 +1806,11 @@ int geomst_hdbscan(const double* points, int64_t n, int32_t d, int32_t min_pts, 
 int geomst_emst_dev(const double* d_points, int64_t n, int32_t d, int64_t* d_edges, double* d_weights,
                     double* d_weights_sq, void* stream) {
     return run_dev(d_points, n, d, 0, (long long*)d_edges, d_weights, d_weights_sq, nullptr, nullptr, stream);
+}
+
+int geomst_emst_dev_noalloc(const double* d_points, int64_t n, int32_t d, int64_t* d_edges, double* d_weights,
+                            double* d_weights_sq, void* stream) {
+    return run_dev_noalloc(d_points, n, d, (long long*)d_edges, d_weights, d_weights_sq, stream);
 }
 
 int geomst_hdbscan_dev(const double* d_points, int64_t n, int32_t d, int32_t min_pts, double* d_core_dist,

@@ -89,6 +89,8 @@ def load(path: str = LIB_PATH):
     lib.geomst_hdbscan.argtypes = [P, i64, i32, i32, P, P, P]
     lib.geomst_emst_dev.argtypes = [P, i64, i32, P, P, P, P]
     lib.geomst_hdbscan_dev.argtypes = [P, i64, i32, i32, P, P, P, P, P, P]
+    lib.geomst_emst_dev_noalloc.argtypes = [P, i64, i32, P, P, P, P]
+    lib.geomst_emst_dev_noalloc.restype = ctypes.c_int
     lib.geomst_batch_dev.argtypes = [P, i32, ctypes.POINTER(BatchItem), i64, P, P, P, P, P, P]
     lib.geomst_batch.argtypes = [ctypes.POINTER(Instance), i64]
     lib.geomst_batch_dev.restype = ctypes.c_int
@@ -209,6 +211,34 @@ def emst(points, want_sq: bool = False):
     w = np.zeros(m)
     _check(lib.geomst_emst(p.ctypes.data, n, d, e.ctypes.data, w.ctypes.data))
     return e, w
+
+
+def header_constant(name: str, header: str = HEADER) -> int:
+    """Integer value of a #define in include/geomst.h."""
+    m = re.search(r"#define\s+" + re.escape(name) + r"\s+(-?\d+)", open(header).read())
+    if not m:
+        raise KeyError(name)
+    return int(m.group(1))
+
+
+def emst_noalloc(points, want_sq: bool = False):
+    """EMST through geomst_emst_dev_noalloc (fixed device scratch, no
+    allocation inside the call): CUDA tensor in -> CUDA tensors out, like
+    ``emst``.  The output tensors are allocated here, by the caller."""
+    import torch
+    if not _is_cuda_tensor(points):
+        raise ValueError("emst_noalloc takes a float64 CUDA tensor")
+    p = points.contiguous()
+    if p.dtype != torch.float64 or p.dim() != 2:
+        raise ValueError("points must be a float64 [n, d] tensor")
+    n, d = p.shape
+    m = max(n - 1, 0)
+    e = torch.empty((m, 2), dtype=torch.int64, device=p.device)
+    w = torch.empty(m, dtype=torch.float64, device=p.device)
+    w2 = torch.empty(m, dtype=torch.float64, device=p.device) if want_sq else None
+    _check(load().geomst_emst_dev_noalloc(p.data_ptr(), n, d, e.data_ptr(), w.data_ptr(),
+                                          w2.data_ptr() if w2 is not None else None, _stream_ptr()))
+    return (e, w, w2) if want_sq else (e, w)
 
 
 def hdbscan(points, min_pts: int, want_sq: bool = False):

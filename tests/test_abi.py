@@ -62,6 +62,10 @@ def test_rejects_bad_arguments_without_device(lib):
     assert lib.geomst_hdbscan(p.ctypes.data, 4, 3, 5, cd.ctypes.data, e.ctypes.data, None) == G.EINVAL
     assert lib.geomst_hdbscan(p.ctypes.data, 4, 3, 65, cd.ctypes.data, e.ctypes.data, None) == G.EINVAL
     assert lib.geomst_emst_dev(None, 4, 3, None, None, None, None) == G.EINVAL
+    assert lib.geomst_emst_dev_noalloc(None, 4, 3, None, None, None, None) == G.EINVAL
+    nmax = G.header_constant("GEOMST_NOALLOC_MAX_POINTS")
+    assert lib.geomst_emst_dev_noalloc(p.ctypes.data, nmax + 1, 3, e.ctypes.data, None, None, None) == G.EINVAL
+    assert "GEOMST_NOALLOC_MAX_POINTS" in G.last_error()
     with pytest.raises(G.GeomstError):
         G.emst(np.zeros((4, 9)))
 
