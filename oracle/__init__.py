@@ -50,8 +50,9 @@ def _load():
         lib.oracle_core_dist2.argtypes = [P, i64, i32, i32, P, i64, P]
         lib.oracle_edge_keys.argtypes = [P, i64, i32, P, P, P, i64, P, P]
         lib.oracle_lightest_cut_edge.argtypes = [P, i64, i32, P, P, P, P, P, P]
+        lib.oracle_dendrogram.argtypes = [P, P, i64, i64, P, P, P, P]
         for f in (lib.oracle_emst, lib.oracle_hdbscan, lib.oracle_core_dist2,
-                  lib.oracle_edge_keys, lib.oracle_lightest_cut_edge):
+                  lib.oracle_edge_keys, lib.oracle_lightest_cut_edge, lib.oracle_dendrogram):
             f.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -143,3 +144,22 @@ def lightest_cut_edge(points, in_s, cd2=None):
                                             ctypes.byref(hi), ctypes.byref(w2), ctypes.byref(e2)),
            "oracle_lightest_cut_edge")
     return lo.value, hi.value, w2.value, e2.value
+
+
+def dendrogram(edges, weights, start: int = 0):
+    """Ordered dendrogram and reachability plot of a spanning tree whose edges
+    are given in their total order (Sec. 2.1; Sec. 4.1):
+    -> (children int64[n-1][2], size int64[n-1], order int64[n], reach float64[n]).
+    Internal node n+k is edge k (height weights[k]); its left child holds the
+    endpoint nearer to ``start``; order/reach are Prim's visiting order from
+    ``start`` on the tree and the weight of the edge that reached each point."""
+    e = np.ascontiguousarray(edges, dtype=np.int64).reshape(-1, 2)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    n = len(e) + 1
+    ch = np.zeros((n - 1, 2), np.int64)
+    sz = np.zeros(n - 1, np.int64)
+    order = np.zeros(n, np.int64)
+    reach = np.zeros(n)
+    _check(_load().oracle_dendrogram(_ptr(e), _ptr(w), n, int(start), _ptr(ch), _ptr(sz), _ptr(order),
+                                     _ptr(reach)), "oracle_dendrogram")
+    return ch, sz, order, reach

@@ -313,3 +313,169 @@ int oracle_lightest_cut_edge(const double *P, int64_t n, int32_t d, const double
 }
 
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------ dendrogram and plot */
+
+/*
+ * Ordered dendrogram and reachability plot of a weighted spanning tree
+ * (paper Sec. 2.1, "dendrogram" and "reachability plot"; Sec. 4.1, ordered
+ * dendrogram of a start vertex s).
+ *
+ * Input: the n-1 tree edges in the order that is their total order (the MST
+ * calls return them sorted by K, so edge k is the k-th lightest), weights[k]
+ * the height of edge k, and the start vertex s.
+ *
+ * Dendrogram (the sequential bottom-up definition of Sec. 4): every point
+ * starts as its own cluster (leaf node i, 0 <= i < n); edges are taken in
+ * order, and edge k merges the clusters of its two endpoints into internal
+ * node n + k, whose height is weights[k] and whose size is the number of
+ * points below it.  Ordered: of the two clusters merged by edge (u, v), the
+ * one holding the endpoint nearer to s in the tree (fewer tree edges from s,
+ * the "vertex distance") is the left child.
+ *
+ * Reachability plot: the order in which Prim's algorithm run on the tree
+ * from s visits the points, always taking the lightest edge (lowest index)
+ * leaving the visited set, and for each visited point the weight of the edge
+ * that reached it (s gets +infinity).
+ *
+ * children[k] = {left, right} node ids of internal node n + k; size[k] its
+ * point count; order[i] the i-th point of the plot; reach[i] its height.
+ * Returns OR_EINVAL if the edges are not a spanning tree of 0..n-1.
+ */
+static int64_t uf_find(int64_t *par, int64_t x)
+{
+    while (par[x] != x) {
+        par[x] = par[par[x]];
+        x = par[x];
+    }
+    return x;
+}
+
+/* binary min-heap of edge indices */
+static void heap_push(int64_t *h, int64_t *len, int64_t v)
+{
+    int64_t i = (*len)++;
+    h[i] = v;
+    while (i > 0 && h[(i - 1) / 2] > h[i]) {
+        int64_t p = (i - 1) / 2, t = h[p];
+        h[p] = h[i];
+        h[i] = t;
+        i = p;
+    }
+}
+
+static int64_t heap_pop(int64_t *h, int64_t *len)
+{
+    int64_t top = h[0];
+    h[0] = h[--(*len)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < *len && h[l] < h[m]) m = l;
+        if (r < *len && h[r] < h[m]) m = r;
+        if (m == i) break;
+        int64_t t = h[m];
+        h[m] = h[i];
+        h[i] = t;
+        i = m;
+    }
+    return top;
+}
+
+int oracle_dendrogram(const int64_t *edges, const double *weights, int64_t n, int64_t s,
+                      int64_t *children, int64_t *size, int64_t *order, double *reach)
+{
+    if (n < 1 || s < 0 || s >= n || !order || !reach) return OR_EINVAL;
+    if (n > 1 && (!edges || !weights || !children || !size)) return OR_EINVAL;
+    int64_t m = n - 1;
+    for (int64_t k = 0; k < 2 * m; ++k)
+        if (edges[k] < 0 || edges[k] >= n) return OR_EINVAL;
+    int64_t *deg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *adj = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * m + 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t *dist = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *par = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *top = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *heap = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * m + 1));
+    unsigned char *seen = (unsigned char *)calloc((size_t)n, 1);
+    int rc = OR_OK;
+    if (!deg || !adj || !fill || !dist || !queue || !par || !top || !cnt || !heap || !seen) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    /* adjacency lists: edge indices incident to each vertex */
+    for (int64_t k = 0; k < m; ++k) {
+        deg[edges[2 * k] + 1]++;
+        deg[edges[2 * k + 1] + 1]++;
+    }
+    for (int64_t v = 0; v < n; ++v) deg[v + 1] += deg[v];
+    for (int64_t v = 0; v <= n; ++v) fill[v] = deg[v];
+    for (int64_t k = 0; k < m; ++k) {
+        adj[fill[edges[2 * k]]++] = k;
+        adj[fill[edges[2 * k + 1]]++] = k;
+    }
+    /* vertex distances from s by breadth-first search over the tree */
+    for (int64_t v = 0; v < n; ++v) dist[v] = -1;
+    int64_t qh = 0, qt = 0;
+    dist[s] = 0;
+    queue[qt++] = s;
+    while (qh < qt) {
+        int64_t x = queue[qh++];
+        for (int64_t j = deg[x]; j < deg[x + 1]; ++j) {
+            int64_t k = adj[j];
+            int64_t y = edges[2 * k] == x ? edges[2 * k + 1] : edges[2 * k];
+            if (dist[y] < 0) {
+                dist[y] = dist[x] + 1;
+                queue[qt++] = y;
+            }
+        }
+    }
+    if (qt != n) { /* not connected, hence (with n-1 edges) not a tree */
+        rc = OR_EINVAL;
+        goto done;
+    }
+    /* bottom-up merges in edge order (Kruskal's order) */
+    for (int64_t v = 0; v < n; ++v) {
+        par[v] = v;
+        top[v] = v;
+        cnt[v] = 1;
+    }
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t u = edges[2 * k], v = edges[2 * k + 1];
+        int64_t ru = uf_find(par, u), rv = uf_find(par, v);
+        if (ru == rv) { /* a cycle */
+            rc = OR_EINVAL;
+            goto done;
+        }
+        int u_left = dist[u] < dist[v];
+        children[2 * k] = u_left ? top[ru] : top[rv];
+        children[2 * k + 1] = u_left ? top[rv] : top[ru];
+        size[k] = cnt[ru] + cnt[rv];
+        par[rv] = ru;
+        cnt[ru] += cnt[rv];
+        top[ru] = n + k;
+    }
+    /* Prim on the tree from s: lowest-index edge leaving the visited set */
+    int64_t hl = 0, no = 0;
+    seen[s] = 1;
+    order[no] = s;
+    reach[no++] = INFINITY;
+    for (int64_t j = deg[s]; j < deg[s + 1]; ++j) heap_push(heap, &hl, adj[j]);
+    while (hl > 0) {
+        int64_t k = heap_pop(heap, &hl);
+        int64_t u = edges[2 * k], v = edges[2 * k + 1];
+        int64_t y = seen[u] ? v : u;
+        if (seen[y]) continue;
+        seen[y] = 1;
+        order[no] = y;
+        reach[no++] = weights[k];
+        for (int64_t j = deg[y]; j < deg[y + 1]; ++j)
+            if (adj[j] != k) heap_push(heap, &hl, adj[j]);
+    }
+done:
+    free(deg); free(adj); free(fill); free(dist); free(queue); free(par); free(top); free(cnt);
+    free(heap); free(seen);
+    return rc;
+}
