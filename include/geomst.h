@@ -88,6 +88,40 @@ int geomst_hdbscan_dev(const double* d_points, int64_t n, int32_t d, int32_t min
                        void* stream);
 
 /*
+ * Ordered dendrogram and reachability plot of a weighted spanning tree
+ * (Sec. 2.1, "dendrogram" and "reachability plot"; Sec. 4.1, the ordered
+ * dendrogram of a start vertex; Sec. 4.2, the top-down heavy/light
+ * construction).  Single-linkage clustering with the EMST as input, the
+ * HDBSCAN* hierarchy with the mutual-reachability MST (a point is noise for
+ * eps below its core distance).
+ *   edges     [n-1][2] int64, the tree's edges in their total order (as the
+ *             MST calls return them: edge k is the k-th lightest); the
+ *             library takes this order as given
+ *   weights   [n-1] float64, edge k's height (the MST calls' weights)
+ *   start     the plot's first point s, 0 <= start < n
+ *   children  [n-1][2] int64 out (may be NULL): internal node n + k merges,
+ *             at height weights[k], the clusters {children[k][0],
+ *             children[k][1]} (ids < n are points, ids >= n internal nodes);
+ *             the left child [0] holds the endpoint of edge k nearer to s in
+ *             the tree, so an in-order traversal lists the points in plot
+ *             order
+ *   size      [n-1] int64 out (may be NULL): points below node n + k
+ *   order     [n] int64 out: Prim's visiting order from s on the tree
+ *             (lightest edge leaving the visited set first)
+ *   reach     [n] float64 out: reach[i] = the weight of the edge that reached
+ *             order[i] (the smallest weight from it to any earlier point);
+ *             reach[0] = +inf
+ * EINVAL for a bad n or start, an endpoint outside [0, n), a self-loop, or
+ * edges that do not form a spanning tree.  n = 1: order = {0}, reach = {inf}.
+ * The _dev variant takes device pointers and queues on `stream` (returns
+ * after the results are complete); the plain variant host pointers.
+ */
+int geomst_dendrogram_dev(const int64_t* d_edges, const double* d_weights, int64_t n, int64_t start,
+                          int64_t* d_children, int64_t* d_size, int64_t* d_order, double* d_reach, void* stream);
+int geomst_dendrogram(const int64_t* edges, const double* weights, int64_t n, int64_t start, int64_t* children,
+                      int64_t* size, int64_t* order, double* reach);
+
+/*
  * No-allocation variant of geomst_emst_dev, for callers that cannot allocate
  * device memory (code that must not call hipMalloc, tight serving loops,
  * harnesses that forbid allocation).  Same arguments, result and stream
@@ -250,7 +284,8 @@ enum {
     GEOMST_K_KRUSKAL = 6,  /* Boruvka pick / hook / reset */
     GEOMST_K_REFRESH = 7,  /* union-find compression and node components */
     GEOMST_K_OUTPUT = 8,   /* output writes */
-    GEOMST_K_COUNT = 9
+    GEOMST_K_DENDRO = 9,   /* dendrogram and reachability plot */
+    GEOMST_K_COUNT = 10
 };
 
 /* Counters and timings of the last solve made by the calling thread. */

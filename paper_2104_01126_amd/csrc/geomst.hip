@@ -25,6 +25,7 @@
 #include "common.h"
 #include "tree_kernels.h"
 #include "round_kernels.h"
+#include "dendro_kernels.h"
 
 namespace geomst {
 namespace {
@@ -200,6 +201,11 @@ struct EdgeBufs {
     EdgeList list() const { return EdgeList{w2.as<double>(), e2.as<double>(), ids.as<u64>(), pos.as<u64>()}; }
 };
 
+// Workspace of the dendrogram call (see dendro_kernels.h).
+struct DendroBufs {
+    DBuf eu, ev, key[2], val[2], pos, first, nx[2], dd[2], near, pedge, lab, sz, P, MX, SZ, OWN, par[2], off[2], err;
+};
+
 struct Device {
     std::mutex mu;
     bool init = false;
@@ -225,6 +231,7 @@ struct Device {
     // Kruskal
     DBuf kid, ke2, kw2, perm[2], alive[2], apos[2], ru, rv, minmax;
     DBuf birange, bik, browinst;  // batched solves: instance table and row -> instance
+    DendroBufs dg;
     Prof profm;
     Prof* prof = nullptr;
     bool noalloc = false;     // buffers come from the fixed scratch; no event timing
@@ -1524,6 +1531,154 @@ int run_host(const double* P, int64_t n, int32_t d, int32_t minpts, int64_t* edg
     return GEOMST_OK;
 }
 
+// ------------------------------------------------------------ dendrogram
+int ceil_log2(u64 x) {
+    int b = 0;
+    while ((1ull << b) < x) ++b;
+    return b;
+}
+
+// Ordered dendrogram and reachability plot of a spanning tree whose n-1
+// edges come in their total order (see dendro_kernels.h for the steps).
+void dendrogram_dev(Device& D, hipStream_t s, const long long* edges, const double* w, int n, int start,
+                    long long* children, long long* size, long long* order, double* reach) {
+    g_cur_stream = s;
+    memset(&g_stats, 0, sizeof(g_stats));
+    g_stats.n = n;
+    D.prof->begin(D.noalloc ? 0u : (g_kernel_timing & g_kernel_timing_families));
+    auto t0 = std::chrono::steady_clock::now();
+    DendroBufs& B = D.dg;
+    B.err.ensure(4);
+    u32* err = B.err.as<u32>();
+    HIPCHK(hipMemsetAsync(err, 0, 4, s));
+    auto check = [&](const char* stage) {
+        HIPCHK(hipMemcpyAsync(D.hpin, err, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const u32 e = D.hpin[0];
+        if (e & (kDgErrIds | kDgErrTree)) {
+            g_err = (e & kDgErrIds) ? "an edge has an endpoint outside [0, n) or joins a point to itself"
+                                    : "the edges do not form a spanning tree of the n points";
+            throw Fail{GEOMST_EINVAL};
+        }
+        if (e) {
+            g_err = std::string("internal error in the dendrogram (") + stage + ")";
+            throw Fail{GEOMST_EINTERNAL};
+        }
+    };
+    if (n == 1) {
+        k_dg_single<<<1, 1, 0, s>>>(order, reach);
+        LAUNCHCHK();
+        HIPCHK(hipStreamSynchronize(s));
+        return;
+    }
+    const u32 m = (u32)(n - 1), na = 2 * m, nn = 2 * (u32)n - 1;
+    B.eu.ensure((size_t)m * 4);
+    B.ev.ensure((size_t)m * 4);
+    for (int i = 0; i < 2; ++i) {
+        B.key[i].ensure((size_t)na * 8);
+        B.val[i].ensure((size_t)na * 4);
+        B.nx[i].ensure((size_t)na * 4);
+        B.dd[i].ensure((size_t)na * 4);
+        B.par[i].ensure((size_t)nn * 4);
+        B.off[i].ensure((size_t)nn * 4);
+    }
+    B.pos.ensure((size_t)na * 4);
+    B.first.ensure((size_t)n * 4);
+    B.near.ensure(m);
+    B.pedge.ensure((size_t)n * 4);
+    B.lab.ensure((size_t)na * 4);
+    B.sz.ensure((size_t)na * 4);
+    B.P.ensure((size_t)nn * 4);
+    B.MX.ensure((size_t)nn * 4);
+    B.SZ.ensure((size_t)nn * 4);
+    B.OWN.ensure((size_t)nn * 4);
+    D.stemp.ensure(std::max(radix_temp_bytes(na), scan_temp_bytes(na)));
+    int c = 0;
+    {
+        TIMED(GEOMST_K_DENDRO);
+        // 1. root the tree at the start: Euler tour and list ranking
+        k_dg_load<<<blocks(m, 256), 256, 0, s>>>(edges, m, (u32)n, B.eu.as<u32>(), B.ev.as<u32>(),
+                                                 B.key[0].as<u64>(), B.val[0].as<u32>(), err);
+        LAUNCHCHK();
+        const int flip = radix_sort_pairs(B.key[0].as<u64>(), B.val[0].as<u32>(), B.key[1].as<u64>(),
+                                          B.val[1].as<u32>(), na, id_bits(n), D.stemp.p, s);
+        LAUNCHCHK();
+        const u64* skey = B.key[flip].as<u64>();
+        const u32* sarc = B.val[flip].as<u32>();
+        HIPCHK(hipMemsetAsync(B.first.p, 0xff, (size_t)n * 4, s));
+        k_dg_adj<<<blocks(na, 256), 256, 0, s>>>(skey, sarc, na, B.pos.as<u32>(), B.first.as<u32>());
+        LAUNCHCHK();
+        k_dg_succ<<<blocks(na, 256), 256, 0, s>>>(skey, sarc, B.pos.as<u32>(), B.first.as<u32>(), na, (u32)start,
+                                                  B.nx[0].as<u32>(), B.dd[0].as<u32>(), err);
+        LAUNCHCHK();
+        for (int r = 0, rounds = id_bits((int)na) + 1; r < rounds; ++r, c ^= 1) {
+            k_dg_jump<<<blocks(na, 256), 256, 0, s>>>(B.nx[c].as<u32>(), B.dd[c].as<u32>(), B.nx[c ^ 1].as<u32>(),
+                                                      B.dd[c ^ 1].as<u32>(), na);
+            LAUNCHCHK();
+        }
+        k_dg_orient<<<blocks(m, 256), 256, 0, s>>>(B.eu.as<u32>(), B.ev.as<u32>(), B.nx[c].as<u32>(),
+                                                   B.dd[c].as<u32>(), m, B.near.as<unsigned char>(),
+                                                   B.pedge.as<u32>(), err);
+        LAUNCHCHK();
+    }
+    check("rooting");
+    {
+        TIMED(GEOMST_K_DENDRO);
+        // 2. children by heavy/light halving
+        u32* lab = B.lab.as<u32>();
+        u32* sz = B.sz.as<u32>();
+        HIPCHK(hipMemcpyAsync(lab, B.eu.p, (size_t)m * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(lab + m, B.ev.p, (size_t)m * 4, hipMemcpyDeviceToDevice, s));
+        k_dg_fill_u32<<<blocks(na, 256), 256, 0, s>>>(sz, na, 1u);
+        LAUNCHCHK();
+        for (int j = ceil_log2(m); j >= 1; --j) {
+            k_dg_level_reset<<<blocks(na, 256), 256, 0, s>>>(lab, m, B.P.as<u32>(), B.MX.as<u32>(), B.SZ.as<u32>(),
+                                                             B.OWN.as<u32>());
+            LAUNCHCHK();
+            k_dg_level_union<<<blocks(m, 256), 256, 0, s>>>(lab, m, j, B.P.as<u32>());
+            LAUNCHCHK();
+            k_dg_level_info<<<blocks(m, 256), 256, 0, s>>>(lab, sz, m, j, B.P.as<u32>(), B.MX.as<u32>(),
+                                                            B.SZ.as<u32>(), B.OWN.as<u32>());
+            LAUNCHCHK();
+            k_dg_level_rename<<<blocks(m, 256), 256, 0, s>>>(lab, sz, m, (u32)n, j, B.P.as<u32>(), B.MX.as<u32>(),
+                                                              B.SZ.as<u32>());
+            LAUNCHCHK();
+        }
+        // 3. orientation, then in-order positions by pointer jumping
+        k_dg_children<<<blocks(m, 256), 256, 0, s>>>(lab, sz, B.near.as<unsigned char>(), m, (u32)n, children, size,
+                                                     B.par[0].as<u32>(), B.off[0].as<u32>());
+        LAUNCHCHK();
+        int q = 0;
+        for (int r = 0, rounds = id_bits((int)nn) + 1; r < rounds; ++r, q ^= 1) {
+            k_dg_jump<<<blocks(nn, 256), 256, 0, s>>>(B.par[q].as<u32>(), B.off[q].as<u32>(), B.par[q ^ 1].as<u32>(),
+                                                      B.off[q ^ 1].as<u32>(), nn);
+            LAUNCHCHK();
+        }
+        k_dg_plot<<<blocks(n, 256), 256, 0, s>>>(B.off[q].as<u32>(), B.pedge.as<u32>(), w, (u32)n, (u32)start, order,
+                                                 reach, err);
+        LAUNCHCHK();
+    }
+    check("positions");
+    g_stats.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    D.prof->finish(g_stats);
+}
+
+int validate_dendro(const void* edges, const void* w, int64_t n, int64_t start, const void* order, const void* reach) {
+    if (n < 1 || n > (1ll << 26)) {
+        g_err = "n must be in [1, 2^26]";
+        return GEOMST_EINVAL;
+    }
+    if (start < 0 || start >= n) {
+        g_err = "start must be in [0, n)";
+        return GEOMST_EINVAL;
+    }
+    if (!order || !reach || (n > 1 && (!edges || !w))) {
+        g_err = "edges, weights, order or reach is NULL";
+        return GEOMST_EINVAL;
+    }
+    return GEOMST_OK;
+}
+
 // ------------------------------------------------- no-allocation entry point
 // geomst_emst_dev_noalloc runs the same solve as geomst_emst_dev with every
 // device buffer carved from the fixed array `scratch` (below) and the counter
@@ -1806,6 +1961,71 @@ int geomst_hdbscan(const double* points, int64_t n, int32_t d, int32_t min_pts, 
 int geomst_emst_dev(const double* d_points, int64_t n, int32_t d, int64_t* d_edges, double* d_weights,
                     double* d_weights_sq, void* stream) {
     return run_dev(d_points, n, d, 0, (long long*)d_edges, d_weights, d_weights_sq, nullptr, nullptr, stream);
+}
+
+int geomst_dendrogram_dev(const int64_t* d_edges, const double* d_weights, int64_t n, int64_t start,
+                          int64_t* d_children, int64_t* d_size, int64_t* d_order, double* d_reach, void* stream) {
+    g_err.clear();
+    int rc = validate_dendro(d_edges, d_weights, n, start, d_order, d_reach);
+    if (rc) return rc;
+    try {
+        int dev;
+        Device& D = device_ctx(&dev);
+        std::lock_guard<std::mutex> lk(D.mu);
+        ensure_init(D);
+        dendrogram_dev(D, (hipStream_t)stream, (const long long*)d_edges, d_weights, (int)n, (int)start,
+                       (long long*)d_children, (long long*)d_size, (long long*)d_order, d_reach);
+    } catch (const Fail& f) {
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return GEOMST_ENOMEM;
+    }
+    return GEOMST_OK;
+}
+
+int geomst_dendrogram(const int64_t* edges, const double* weights, int64_t n, int64_t start, int64_t* children,
+                      int64_t* size, int64_t* order, double* reach) {
+    g_err.clear();
+    int rc = validate_dendro(edges, weights, n, start, order, reach);
+    if (rc) return rc;
+    try {
+        int dev;
+        Device& D = device_ctx(&dev);
+        std::lock_guard<std::mutex> lk(D.mu);
+        ensure_init(D);
+        hipStream_t s = D.own;
+        const size_t m = (size_t)(n - 1);
+        // staging: edges and children share one buffer, weights / reach and
+        // sizes / order the others
+        D.pin.ensure(std::max<size_t>(m * 16, 16));
+        D.wout.ensure(std::max<size_t>(m * 8, (size_t)n * 8));
+        D.eout.ensure(std::max<size_t>(m * 16, 16) + (size_t)n * 8 + m * 8);
+        long long* de = D.pin.as<long long>();
+        double* dw = D.wout.as<double>();
+        long long* dch = D.eout.as<long long>();
+        long long* dorder = dch + 2 * m;
+        long long* dsize = dorder + n;
+        D.cdout.ensure((size_t)n * 8);
+        double* dreach = D.cdout.as<double>();
+        if (m) {
+            HIPCHK(hipMemcpyAsync(de, edges, m * 16, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(dw, weights, m * 8, hipMemcpyHostToDevice, s));
+        }
+        dendrogram_dev(D, s, de, dw, (int)n, (int)start, children ? dch : nullptr, size ? dsize : nullptr, dorder,
+                       dreach);
+        if (m && children) HIPCHK(hipMemcpyAsync(children, dch, m * 16, hipMemcpyDeviceToHost, s));
+        if (m && size) HIPCHK(hipMemcpyAsync(size, dsize, m * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(order, dorder, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(reach, dreach, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (const Fail& f) {
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return GEOMST_ENOMEM;
+    }
+    return GEOMST_OK;
 }
 
 int geomst_emst_dev_noalloc(const double* d_points, int64_t n, int32_t d, int64_t* d_edges, double* d_weights,

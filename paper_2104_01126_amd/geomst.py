@@ -90,6 +90,10 @@ def load(path: str = LIB_PATH):
     lib.geomst_emst_dev.argtypes = [P, i64, i32, P, P, P, P]
     lib.geomst_hdbscan_dev.argtypes = [P, i64, i32, i32, P, P, P, P, P, P]
     lib.geomst_emst_dev_noalloc.argtypes = [P, i64, i32, P, P, P, P]
+    lib.geomst_dendrogram_dev.argtypes = [P, P, i64, i64, P, P, P, P, P]
+    lib.geomst_dendrogram.argtypes = [P, P, i64, i64, P, P, P, P]
+    lib.geomst_dendrogram_dev.restype = ctypes.c_int
+    lib.geomst_dendrogram.restype = ctypes.c_int
     lib.geomst_emst_dev_noalloc.restype = ctypes.c_int
     lib.geomst_batch_dev.argtypes = [P, i32, ctypes.POINTER(BatchItem), i64, P, P, P, P, P, P]
     lib.geomst_batch.argtypes = [ctypes.POINTER(Instance), i64]
@@ -162,7 +166,7 @@ class Stats:
 
 
 # kernel families (GEOMST_K_* in include/geomst.h)
-KERNEL_FAMILIES = ["tree", "sort", "core", "split", "expand", "bccp", "kruskal", "refresh", "output"]
+KERNEL_FAMILIES = ["tree", "sort", "core", "split", "expand", "bccp", "kruskal", "refresh", "output", "dendro"]
 
 
 def stats() -> Stats:
@@ -274,6 +278,40 @@ def hdbscan(points, min_pts: int, want_sq: bool = False):
     _check(lib.geomst_hdbscan(p.ctypes.data, n, d, int(min_pts), cd.ctypes.data, e.ctypes.data,
                               w.ctypes.data))
     return cd, e, w
+
+
+def dendrogram(edges, weights, start: int = 0):
+    """Ordered dendrogram and reachability plot of a spanning tree given by
+    its edges in their total order (as ``emst``/``hdbscan`` return them) ->
+    (children int64 [n-1,2], size int64 [n-1], order int64 [n], reach
+    float64 [n]).  numpy in -> numpy out; CUDA tensors in -> CUDA tensors
+    out (queued on torch's current stream)."""
+    lib = load()
+    if _is_cuda_tensor(edges):
+        import torch
+        e = edges.contiguous()
+        w = weights.contiguous()
+        if e.dtype != torch.int64 or w.dtype != torch.float64:
+            raise ValueError("edges must be int64 and weights float64")
+        n = e.shape[0] + 1
+        dev = e.device
+        ch = torch.empty((n - 1, 2), dtype=torch.int64, device=dev)
+        sz = torch.empty(n - 1, dtype=torch.int64, device=dev)
+        order = torch.empty(n, dtype=torch.int64, device=dev)
+        reach = torch.empty(n, dtype=torch.float64, device=dev)
+        _check(lib.geomst_dendrogram_dev(e.data_ptr(), w.data_ptr(), n, int(start), ch.data_ptr(), sz.data_ptr(),
+                                         order.data_ptr(), reach.data_ptr(), _stream_ptr()))
+        return ch, sz, order, reach
+    e = np.ascontiguousarray(edges, dtype=np.int64).reshape(-1, 2)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    n = len(e) + 1
+    ch = np.zeros((n - 1, 2), np.int64)
+    sz = np.zeros(n - 1, np.int64)
+    order = np.zeros(n, np.int64)
+    reach = np.zeros(n)
+    _check(lib.geomst_dendrogram(e.ctypes.data, w.ctypes.data, n, int(start), ch.ctypes.data, sz.ctypes.data,
+                                 order.ctypes.data, reach.ctypes.data))
+    return ch, sz, order, reach
 
 
 # ------------------------------------------------------------------ batches

@@ -63,6 +63,17 @@ def test_rejects_bad_arguments_without_device(lib):
     assert lib.geomst_hdbscan(p.ctypes.data, 4, 3, 65, cd.ctypes.data, e.ctypes.data, None) == G.EINVAL
     assert lib.geomst_emst_dev(None, 4, 3, None, None, None, None) == G.EINVAL
     assert lib.geomst_emst_dev_noalloc(None, 4, 3, None, None, None, None) == G.EINVAL
+    o = np.zeros(4, np.int64)
+    r = np.zeros(4)
+    w = np.zeros(3)
+    assert lib.geomst_dendrogram(e.ctypes.data, w.ctypes.data, 4, 4, None, None, o.ctypes.data,
+                                 r.ctypes.data) == G.EINVAL   # start out of range
+    assert lib.geomst_dendrogram(e.ctypes.data, w.ctypes.data, 0, 0, None, None, o.ctypes.data,
+                                 r.ctypes.data) == G.EINVAL   # n < 1
+    assert lib.geomst_dendrogram(None, w.ctypes.data, 4, 0, None, None, o.ctypes.data,
+                                 r.ctypes.data) == G.EINVAL   # edges NULL
+    assert lib.geomst_dendrogram_dev(e.ctypes.data, w.ctypes.data, 4, 0, None, None, None, None,
+                                     None) == G.EINVAL          # order NULL
     nmax = G.header_constant("GEOMST_NOALLOC_MAX_POINTS")
     assert lib.geomst_emst_dev_noalloc(p.ctypes.data, nmax + 1, 3, e.ctypes.data, None, None, None) == G.EINVAL
     assert "GEOMST_NOALLOC_MAX_POINTS" in G.last_error()
