@@ -2,12 +2,22 @@
 """Throughput benchmark of the GPU EMST / HDBSCAN* path on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload emst_1m]
-                [--no-cpu-baseline]
+                [--no-cpu-baseline] [--no-extras] [--serve-seconds S]
 
 A step is one complete solve (tree build, [core distances,] every
 filtered-Kruskal round, output sort and write) of one synthetic workload whose
 points are already resident in HBM.  Prints ONE JSON line on stdout; progress
 goes to stderr.
+
+The default run times the 1M-point EMST as the headline (`value`, `roofline`,
+`cpu_baseline`) and adds, in the same line, the rest of the metric:
+`extras.c1_plain_beta` (the same workload with the threshold doubling every
+round), `extras.c1_host_api` (host arrays in and out, PCIe copies included),
+`extras.c0` (2,000 points), `extras.c2` (2M-point HDBSCAN*, with BCCP
+distance evaluations per second as a fraction of FP64 peak and the ordered
+dendrogram), `extras.c3` (4,096 instances batched vs one call each) and
+`extras.c4` (a prefix of the serving stream, served vs one request per
+launch, p50/p99 latency); each of c0-c2 is the median of its timed solves.
 """
 import argparse
 import json
@@ -192,7 +202,7 @@ def bench_batch(a, G, torch, np):
     print(json.dumps(out), flush=True)
 
 
-def replay(G, trace, pts, server_kw, label):
+def replay(G, trace, pts, server_kw, label, dump=None):
     """Open-loop replay of a request trace against a server: a submitter
     thread submits each request at its arrival time; latency = completion -
     scheduled arrival (submission lag included)."""
@@ -224,6 +234,11 @@ def replay(G, trace, pts, server_kw, label):
             time.sleep(0.0005)
         e, w, cd, info = S.wait(tickets[i])
         lat[i] = lag[i] * 1000.0 + info["latency_ms"]
+        if dump is not None:
+            r = trace[i]
+            dump.append({"i": r.index, "n": r.n, "d": r.d, "min_pts": r.min_pts, "mixture": r.mixture,
+                         "service_ms": round(info["service_ms"], 3), "queue_ms": round(info["queue_ms"], 3),
+                         "batch_requests": info["batch_requests"], "batch_points": info["batch_points"]})
         done_at = max(done_at, trace[i].arrival_s + lat[i] / 1000.0)
         if (i + 1) % 100 == 0:
             st = S.stats()
@@ -238,7 +253,8 @@ def replay(G, trace, pts, server_kw, label):
             "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
             "mean_ms": round(float(lat.mean()), 2), "makespan_s": round(span, 3),
             "batches_incl_warmup": st["batches"], "max_batch_requests": st["max_batch_requests"],
-            "peak_reserved_gb": round(st["peak_reserved_bytes"] / 1e9, 2), "max_queue_seen": qdepth}
+            "peak_reserved_gb": round(st["peak_reserved_bytes"] / 1e9, 2), "max_queue_seen": qdepth,
+            "enomem_batches": st["enomem_batches"], "workspace_gb": round(st["workspace_bytes"] / 1e9, 2)}
 
 
 def bench_serve(a, G):
@@ -251,11 +267,26 @@ def bench_serve(a, G):
     log(f"serving: {len(trace)} requests in the first {a.serve_seconds} s of the stream, "
         f"{sum(r.n for r in trace) / 1e6:.1f} M points; generating")
     pts = [W.serving_points(r) for r in trace]
-    served = replay(G, trace, pts, dict(hbm_budget_bytes=200_000_000_000, workers=a.serve_workers), "served")
-    log("served:", served)
-    plain = replay(G, trace, pts, dict(hbm_budget_bytes=200_000_000_000, workers=1, max_batch_requests=1),
-                   "plain")
-    log("plain:", plain)
+    served = plain = None
+    dump = [] if a.serve_dump else None
+    if a.serve_mode in ("both", "served"):
+        served = replay(G, trace, pts, dict(hbm_budget_bytes=200_000_000_000, workers=a.serve_workers,
+                                            small_max_points=a.serve_small_max), "served",
+                        dump if a.serve_mode == "served" else None)
+        log("served:", served)
+    if a.serve_mode in ("both", "plain"):
+        plain = replay(G, trace, pts, dict(hbm_budget_bytes=200_000_000_000, workers=1, max_batch_requests=1),
+                       "plain", dump if a.serve_mode == "plain" else None)
+        log("plain:", plain)
+    if dump is not None:
+        with open(a.serve_dump, "w") as fh:
+            for rec in dump:
+                fh.write(json.dumps(rec) + "\n")
+    if served is None or plain is None:
+        one = served or plain
+        print(json.dumps({"metric": METRIC, "value": one["points_per_s"], "unit": "points/s", "n_gpus": 1,
+                          "mode": a.serve_mode, "requests": len(trace), "result": one}), flush=True)
+        return
     out = {
         "metric": METRIC, "value": served["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": 1,
         "warmup": 1, "ms_per_step": round(served["makespan_s"] * 1000, 1), "higher_is_better": True,
@@ -268,6 +299,200 @@ def bench_serve(a, G):
     print(json.dumps(out), flush=True)
 
 
+def timed_solves(G, torch, x, mp, steps, warmup, label):
+    """Per-solve wall times (ms) of `steps` solves after `warmup` ones."""
+    for _ in range(warmup):
+        solve(G, x, mp)
+    torch.cuda.synchronize()
+    ts = []
+    for i in range(steps):
+        t = time.perf_counter()
+        solve(G, x, mp)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1000.0)
+    log(f"{label}: median {sorted(ts)[len(ts) // 2]:.2f} ms over {steps} solves")
+    return ts
+
+
+def median(v):
+    v = sorted(v)
+    return v[len(v) // 2] if len(v) % 2 else 0.5 * (v[len(v) // 2 - 1] + v[len(v) // 2])
+
+
+def bccp_fraction(st, d, hdb):
+    """BCCP distance evaluations of one solve (all BCCP kernels: small pairs,
+    wave-per-pair and tiled large pairs, pruned blocks excluded) over the
+    BCCP family's device time, as FP64 flops against the vector peak."""
+    ms = st.kernel_ms[5]
+    flops = 3 * d - 1 + (2 if hdb else 0)
+    if ms <= 0:
+        return None
+    evals_s = st.bccp_evals_done / (ms / 1000.0)
+    tf = evals_s * flops / 1e12
+    big = st.big_evals * flops / 1e12 / (ms / 1000.0)
+    return {"bccp_evals": st.bccp_evals_done, "bccp_device_ms": round(ms, 4),
+            "bccp_evals_per_s": round(evals_s, 1), "flops_per_eval": flops,
+            "bccp_tflops": round(tf, 4), "bccp_frac_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 5),
+            "large_pair_evals": st.big_evals, "large_pair_share_of_evals": round(st.big_evals / max(1, st.bccp_evals_done), 4),
+            "large_pair_tflops_over_family_time": round(big, 4)}
+
+
+def extra_plain(G, torch, np, name, steps, warmup, dendrogram=False):
+    from paper_2104_01126_amd import workloads as W
+    wl = WORKLOADS[name]
+    log(f"{name}: generating")
+    pts = {"emst_small": W.emst_small, "emst_1m": W.emst_1m, "hdbscan_2m": W.hdbscan_2m}[name]()
+    n, d = pts.shape
+    mp = wl["min_pts"]
+    x = torch.from_numpy(pts).to("cuda:0")
+    ts = timed_solves(G, torch, x, mp, steps, warmup, name)
+    st = G.stats()
+    G.set_option("kernel_timing", 1)
+    solve(G, x, mp)
+    torch.cuda.synchronize()
+    stk = G.stats()
+    G.set_option("kernel_timing", 0)
+    fams = G.KERNEL_FAMILIES
+    rec = {"workload": wl["desc"], "n": n, "d": d, "min_pts": mp or None,
+           "median_ms": round(median(ts), 3), "points_per_s": round(n / (median(ts) / 1000.0), 1),
+           "solves": steps, "min_ms": round(min(ts), 3), "max_ms": round(max(ts), 3),
+           "kernel_ms_breakdown": {fams[i]: round(float(stk.kernel_ms[i]), 4) for i in range(len(fams))},
+           "counts": {k: getattr(st, k) for k in ("rounds", "pair_visits", "bccp_pairs", "bccp_evals",
+                                                  "bccp_evals_done", "big_evals", "committed_edges")}}
+    rec["bccp"] = bccp_fraction(stk, d, bool(mp))
+    if dendrogram:
+        if mp:
+            cd, e, w = G.hdbscan(x, mp)
+        else:
+            e, w = G.emst(x)
+        for _ in range(2):
+            G.dendrogram(e, w, 0)
+        torch.cuda.synchronize()
+        dts = []
+        for _ in range(5):
+            t = time.perf_counter()
+            G.dendrogram(e, w, 0)
+            torch.cuda.synchronize()
+            dts.append((time.perf_counter() - t) * 1000.0)
+        rec["dendrogram_median_ms"] = round(median(dts), 3)
+        rec["with_dendrogram_points_per_s"] = round(n / ((median(ts) + median(dts)) / 1000.0), 1)
+        log(f"{name}: ordered dendrogram + reachability plot median {median(dts):.2f} ms")
+    del x
+    torch.cuda.empty_cache()
+    return rec
+
+
+def extra_c1_variants(G, torch, np, x, n, steps):
+    """c1 under plain beta doubling, and through the host-array API."""
+    out = {}
+    G.set_option("beta_schedule", 1)
+    try:
+        ts = timed_solves(G, torch, x, 0, steps, 2, "c1 plain beta doubling")
+        st = G.stats()
+    finally:
+        G.set_option("beta_schedule", 0)
+    out["c1_plain_beta"] = {"schedule": "beta doubles every round from the smallest pair bound",
+                            "median_ms": round(median(ts), 3), "points_per_s": round(n / (median(ts) / 1000.0), 1),
+                            "rounds": st.rounds, "pair_visits": st.pair_visits}
+    ts = timed_solves(G, torch, x, 0, steps, 1, "c1 default schedule, no events")
+    out["c1_no_events"] = {"median_ms": round(median(ts), 3), "points_per_s": round(n / (median(ts) / 1000.0), 1)}
+    host = x.cpu().numpy()
+    G.emst(host)
+    hs = []
+    for _ in range(steps):
+        t = time.perf_counter()
+        G.emst(host)
+        hs.append((time.perf_counter() - t) * 1000.0)
+    out["c1_host_api"] = {"median_ms": round(median(hs), 3), "points_per_s": round(n / (median(hs) / 1000.0), 1),
+                          "note": "host arrays in and out (H2D points, D2H edges and weights included)"}
+    log(f"c1 host api: median {median(hs):.2f} ms")
+    return out
+
+
+def extra_batch(G, torch, np, steps):
+    from paper_2104_01126_amd import workloads as W
+    log("c3 batch_4096: generating")
+    inst = W.batch_4096()
+    arena, items, stride = G.pack(inst, 0)
+    N = arena.shape[0]
+    x = torch.from_numpy(arena).to("cuda:0")
+    singles = [torch.from_numpy(np.ascontiguousarray(p)).to("cuda:0") for p in inst]
+    G.batch_dev(x, items, stride)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        t = time.perf_counter()
+        G.batch_dev(x, items, stride)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1000.0)
+    log(f"c3 batched: median {median(ts):.1f} ms")
+    G.emst(singles[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, s_ in enumerate(singles):
+        G.emst(s_)
+        if (i + 1) % 1024 == 0:
+            log(f"c3 plain: {i + 1}/{len(singles)} calls")
+    torch.cuda.synchronize()
+    dplain = time.perf_counter() - t0
+    rec = {"workload": WORKLOADS["batch_4096"]["desc"], "instances": len(inst), "total_points": N,
+           "batched_median_ms": round(median(ts), 2), "batched_points_per_s": round(N / (median(ts) / 1000.0), 1),
+           "batched_instances_per_s": round(len(inst) / (median(ts) / 1000.0), 1),
+           "plain_seconds": round(dplain, 3), "plain_points_per_s": round(N / dplain, 1),
+           "batched_vs_plain": round(dplain / (median(ts) / 1000.0), 2)}
+    del x, singles
+    torch.cuda.empty_cache()
+    return rec
+
+
+def extra_serve(G, seconds, workers):
+    from paper_2104_01126_amd import workloads as W
+    trace = W.serving_trace(duration_s=seconds)
+    log(f"c4 serving: {len(trace)} requests in the first {seconds} s of the stream, "
+        f"{sum(r.n for r in trace) / 1e6:.1f} M points; generating")
+    pts = [W.serving_points(r) for r in trace]
+    served = replay(G, trace, pts, dict(hbm_budget_bytes=200_000_000_000, workers=workers), "served")
+    log("served:", served)
+    plain = replay(G, trace, pts, dict(hbm_budget_bytes=200_000_000_000, workers=1, max_batch_requests=1),
+                   "plain")
+    log("plain:", plain)
+    return {"workload": WORKLOADS["serve_poisson"]["desc"], "trace_seconds": seconds, "requests": len(trace),
+            "points": sum(r.n for r in trace), "workers": workers, "served": served, "plain": plain,
+            "served_vs_plain_solves": round(served["solves_per_s"] / plain["solves_per_s"], 2),
+            "served_vs_plain_points": round(served["points_per_s"] / plain["points_per_s"], 2)}
+
+
+def oracle_single_thread():
+    """The checker on one thread (its own process, OMP_NUM_THREADS=1): the
+    2,000-point workload and the first 30,000 points of the 1M workload."""
+    import subprocess
+    code = ("import time, sys; sys.path.insert(0, %r)\n"
+            "import oracle\nfrom paper_2104_01126_amd import workloads as W\n"
+            "oracle.build(force=False)\n"
+            "p = W.emst_small(); t = time.perf_counter(); oracle.emst(p); a = time.perf_counter() - t\n"
+            "q = W.emst_1m()[:30000]; t = time.perf_counter(); oracle.emst(q); b = time.perf_counter() - t\n"
+            "print(a, b, oracle.num_threads())\n") % ROOT
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
+    a, b, th = r.stdout.split()
+    return {"c0_seconds": round(float(a), 4), "c0_points_per_s": round(2000 / float(a), 1),
+            "c1_first_30000_seconds": round(float(b), 3), "c1_first_30000_points_per_s": round(30000 / float(b), 1),
+            "threads": int(th)}
+
+
+def oracle_full_size_record():
+    """Full-size checker runs behind the parity digests (tests/golden/): run
+    on the build host, not on this machine; context for the GPU rates."""
+    out = {}
+    for name in ("emst_small", "emst_1m", "hdbscan_2m", "batch_4096"):
+        path = os.path.join(ROOT, "tests", "golden", f"digest_{name}.json")
+        if os.path.exists(path):
+            g = json.load(open(path))
+            out[name] = {"oracle_seconds": g["oracle_seconds"], "threads": g["oracle_threads"],
+                         "host": "build host (not the GPU box)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,9 +500,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="emst_1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=0.25,
-                    help="serve_poisson: length of the replayed prefix of the 60 s request stream")
-    ap.add_argument("--serve-workers", type=int, default=2)
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
+                    help="length of the replayed prefix of the 60 s request stream (serving)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload only (no c0/c2/c3/c4 sub-records)")
+    ap.add_argument("--serve-workers", type=int, default=0, help="server workers (0: the library default)")
+    ap.add_argument("--serve-small-max", type=int, default=0,
+                    help="server small-lane size limit (0: the library default; 1: no small lane)")
+    ap.add_argument("--serve-dump", default=None, help="serve_poisson: write per-request timings (JSON lines)")
+    ap.add_argument("--serve-mode", default="both", choices=["both", "served", "plain"],
+                    help="serve_poisson: replay against the server, the plain path, or both")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy three times (reference for PMC byte counters)")
     a = ap.parse_args()
@@ -405,6 +637,19 @@ def main():
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.workload, pts, mp)
+    if a.workload == "emst_1m" and not a.no_extras:
+        ex = {}
+        ex.update(extra_c1_variants(G, torch, np, x, n, 5))
+        del x
+        torch.cuda.empty_cache()
+        ex["c0"] = extra_plain(G, torch, np, "emst_small", 11, 3)
+        ex["c2"] = extra_plain(G, torch, np, "hdbscan_2m", 5, 2, dendrogram=True)
+        ex["c3"] = extra_batch(G, torch, np, 5)
+        ex["c4"] = extra_serve(G, a.serve_seconds, a.serve_workers)
+        if not a.no_cpu_baseline:
+            ex["oracle_single_thread"] = oracle_single_thread()
+        ex["oracle_full_size"] = oracle_full_size_record()
+        out["extras"] = ex
     print(json.dumps(out), flush=True)
 
 

@@ -196,23 +196,32 @@ int geomst_batch(geomst_instance_t* inst, int64_t count);
 /*
  * Serving: a request loop with continuous batching over independent EMST and
  * HDBSCAN* solves (each request is the problem of Sec. 2.1 on its own points).
- * Worker threads each own a device workspace and a stream; an idle worker
- * takes the requests queued at the front, in arrival order, up to its share
- * of the device-memory budget (hbm_budget_bytes / workers, by the estimate
- * below) and the batch limits, and solves them like geomst_batch, one forest
- * per group of equal d and kind (EMST or HDBSCAN*).  Requests that arrive
- * while batches run form the next batch; the batches of different workers
- * overlap on the device.  Each result is the unique tree of its own points,
- * identical to solving it alone.
+ * Worker threads each own a device workspace and a stream.  Requests go to
+ * one of two lanes by size: small ones (n <= small_max_points) are taken from
+ * the lane's front, in arrival order, up to the worker's share of the
+ * device-memory budget (hbm_budget_bytes / workers, by the estimate below)
+ * and the batch limits, and solved like geomst_batch, one forest per group of
+ * equal d; large ones, and every HDBSCAN* request (forests that mix minPts
+ * values and densities ran slower than their members alone), are solved one
+ * per worker at a time.  With several workers, worker 0 serves the small lane first and
+ * the others the large lane, each taking from the other lane when its own is
+ * empty; a single worker takes requests in arrival order.  Requests that
+ * arrive while batches run are admitted as workers free up; the batches of
+ * different workers overlap on the device.  Each result is the unique tree of
+ * its own points, identical to solving it alone.
  *
  * Admission estimate per request (device bytes):
  *   n * (720 + 2 * node + 16 * d + (min_pts > 0 ? 640 : 0) + 16 * pairs[d]),
  *   node = 64 for d <= 3, else 128; pairs[d] = 24, 24, 64, 100, 200, 600,
  *   1600 for d = 1..7 (waiting and queued pairs per point at their peak).
- * If a batch still runs out of device memory, the worker releases its
- * workspace and solves the batch's requests one at a time.
- * Workspaces only grow, so the device memory held by a server is at most
- * about hbm_budget_bytes plus the workspaces' growth beyond the estimate.
+ * A worker's workspace may hold at most hbm_budget_bytes / workers device
+ * bytes (counted as its buffers grow, before they are allocated).  A batch
+ * that would outgrow that share (the estimate can undercount the pair lists
+ * of clustered or high-dimensional inputs), or that meets a device
+ * allocation failure, makes the worker release its workspace and solve the
+ * batch's requests one at a time (counted in enomem_batches).  Workspaces
+ * only grow, up to their share, so the device memory a server's workspaces
+ * hold never exceeds hbm_budget_bytes.
  */
 typedef struct geomst_server geomst_server_t;
 
@@ -220,9 +229,9 @@ typedef struct {
     uint64_t hbm_budget_bytes;  /* 0 = 200 GB */
     int32_t workers;            /* concurrent batches, 1..16; 0 = 2 */
     int32_t device;             /* HIP device index; -1 = the caller's current */
-    int32_t max_batch_requests; /* 0 = 4096 */
-    int32_t reserved;           /* must be 0 */
-    int64_t max_batch_points;   /* 0 = 2^24; at most 2^26 */
+    int32_t max_batch_requests; /* small-lane batches; 0 = 4096 */
+    int32_t small_max_points;   /* requests with n <= this are "small"; 0 = 32768 */
+    int64_t max_batch_points;   /* small-lane batch points; 0 = 2^20; at most 2^26 */
 } geomst_server_cfg_t;
 
 /* Timings of one request, filled by geomst_wait (milliseconds). */
@@ -241,6 +250,8 @@ typedef struct {
     int64_t reserved_bytes;      /* estimate held by the running batches */
     int64_t peak_reserved_bytes;
     int64_t max_batch_requests, max_batch_points;
+    int64_t enomem_batches;      /* batches that outgrew a worker's share and were re-solved one request at a time */
+    int64_t workspace_bytes;     /* device bytes the workers' workspaces hold now */
 } geomst_server_stats_t;
 
 /* Creates a server; cfg may be NULL for the defaults.  EINVAL on bad fields,
@@ -309,6 +320,7 @@ typedef struct {
     int64_t sort_elems;       /* elements x 8-bit passes moved by the radix sorts */
     double kernel_ms[16];     /* device time per kernel family (kernel_timing on) */
     int64_t kernel_launches[16];
+    int64_t bccp_evals_done;  /* distances the BCCP kernels evaluated (bccp_evals minus pruned blocks) */
 } geomst_stats_t;
 
 int geomst_get_stats(geomst_stats_t* out);
@@ -328,6 +340,10 @@ int geomst_get_stats(geomst_stats_t* out);
  *                    first one; 1 = plain: beta <- max(g * beta, smallest
  *                    waiting bound) every round, starting at the smallest
  *                    positive pair bound (doubling for EMST).
+ *   "server_share_scale"  (0,1]: a server worker's batch may grow its
+ *                    workspace to this fraction of its budget share (default 1;
+ *                    small values force the one-request-at-a-time fallback, a
+ *                    testing aid).
  *   "list_capacity_scale"  (0,1]: scale of the initial capacities of the
  *                    internal pair and edge lists (default 1); small values make
  *                    the lists overflow, grow and restart rounds (a testing aid).

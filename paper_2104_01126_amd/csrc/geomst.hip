@@ -8,6 +8,7 @@
 #include <string.h>
 #include <chrono>
 #include <mutex>
+#include <atomic>
 #include <new>
 #include <condition_variable>
 #include <deque>
@@ -39,6 +40,7 @@ int g_bccp_chunk = kBigBDefault;  // B points per large-pair BCCP task
 double g_capacity_scale = 1.0;
 double g_beta_start = 0.0;  // fraction of the initial pair bounds below the first threshold (0: the smallest)
 int g_beta_plain = 0;        // 1: the threshold grows by exactly g every round (no early-round acceleration)
+double g_share_scale = 1.0;  // server workers: scale of the workspace share a batch may grow to (testing aid)
 constexpr int kMaxKeyLevels = 6;  // Morton key words per point (see k_morton_level)
 constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
 u32 g_refresh_div = 1024;    // refresh node components once a round merged n / this many
@@ -84,6 +86,15 @@ struct Arena {
 };
 thread_local Arena* g_arena = nullptr;
 
+// Device-memory accounting of the workspace a solve on this thread grows
+// (set by the server's workers): growth beyond `limit` bytes fails with
+// ENOMEM before any allocation is made.
+struct WsBudget {
+    std::atomic<size_t> held{0};
+    size_t limit = ~(size_t)0;
+};
+thread_local WsBudget* g_ws_budget = nullptr;
+
 // Grow-only device buffer.
 struct DBuf {
     void* p = nullptr;
@@ -103,6 +114,12 @@ struct DBuf {
             carve(*g_arena, nb, keep, s);
             return;
         }
+        if (g_ws_budget) {
+            if (g_ws_budget->held - bytes + nb > g_ws_budget->limit) {
+                g_err = "the worker's workspace would exceed its share of the device-memory budget";
+                throw Fail{GEOMST_ENOMEM};
+            }
+        }
         void* q = nullptr;
         // queued kernels of this solve may still use p (solves leave no work
         // queued behind them, so this solve's stream is the only one to wait for)
@@ -113,6 +130,7 @@ struct DBuf {
             HIPCHK(hipStreamSynchronize(s));
         }
         if (p) HIPCHK(hipFree(p));
+        if (g_ws_budget) g_ws_budget->held = g_ws_budget->held - bytes + nb;
         p = q;
         bytes = nb;
     }
@@ -235,6 +253,7 @@ struct Device {
     Prof profm;
     Prof* prof = nullptr;
     bool noalloc = false;     // buffers come from the fixed scratch; no event timing
+    WsBudget budget;          // bytes held by this workspace's buffers (server workers)
     double list_scale = 1.0;  // scale of the initial pair and edge list capacities
     ~Device() {
         if (own) (void)hipStreamDestroy(own);
@@ -1215,6 +1234,8 @@ struct Solver {
         st.ms_rounds = ms(t2, t3);
         st.ms_final = ms(t3, t4);
         st.big_evals = (int64_t)D.hcnt->c64[C64_BIGEVALS];
+        st.bccp_evals_done =
+            (int64_t)(D.hcnt->c64[C64_EVALS] - D.hcnt->c64[C64_BIGWORK] + D.hcnt->c64[C64_BIGEVALS]);
         D.prof->finish(st);
     }
 };
@@ -1786,6 +1807,7 @@ struct Request {
     HostItem item{};
     size_t footprint = 0;
     int status = GEOMST_OK;
+    int lane = 0;
     std::string err;  // the worker's error message when status != OK
     bool started = false, done = false;
     Clock::time_point t_arrive, t_start, t_done;
@@ -1814,7 +1836,8 @@ struct Server {
     int64_t max_pts = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<Request*> queue;
+    std::deque<Request*> lane[2];  // 0: small requests (batched), 1: large requests (one at a time)
+    int64_t small_max = 0;         // requests with n <= this go to the small lane
     std::unordered_map<uint64_t, Request*> all;
     std::vector<std::thread> workers;
     std::vector<std::unique_ptr<Device>> ws;
@@ -1846,8 +1869,13 @@ void run_batch(Server* S, Device& D, std::vector<Request*>& batch) {
             it[i] = grp[i]->item;
             N += it[i].n;
         }
-        auto solve = [&](HostItem* items, int64_t count) -> int {
+        auto solve = [&](HostItem* items, int64_t count, size_t limit) -> int {
             g_err.clear();
+            D.budget.limit = limit;
+            g_ws_budget = &D.budget;
+            struct Reset {
+                ~Reset() { g_ws_budget = nullptr; }
+            } reset;
             try {
                 ensure_init(D);
                 solve_host_items(D, items, count);
@@ -1861,7 +1889,8 @@ void run_batch(Server* S, Device& D, std::vector<Request*>& batch) {
             }
             return GEOMST_OK;
         };
-        std::vector<int> status(grp.size(), solve(it.data(), (int64_t)it.size()));
+        std::vector<int> status(grp.size(),
+                                solve(it.data(), (int64_t)it.size(), (size_t)((double)S->cap_per_worker * g_share_scale)));
         std::vector<std::string> err(grp.size(), g_err);
         if (status[0] == GEOMST_ENOMEM) {
             // The workspace outgrew the device (the admission estimate does
@@ -1870,8 +1899,17 @@ void run_batch(Server* S, Device& D, std::vector<Request*>& batch) {
             if (D.own) (void)hipStreamSynchronize(D.own);  // nothing of the failed solve may still run
             D.~Device();
             new (&D) Device();
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->st.enomem_batches += 1;
+            }
             for (size_t i = 0; i < grp.size(); ++i) {
-                status[i] = solve(&it[i], 1);
+                // one request may use the whole budget less what the other
+                // workers hold now
+                size_t others = 0;
+                for (auto& w : S->ws)
+                    if (w.get() != &D) others += w->budget.held.load(std::memory_order_relaxed);
+                status[i] = solve(&it[i], 1, S->budget > others ? S->budget - others : 0);
                 err[i] = g_err;
             }
         }
@@ -1894,24 +1932,40 @@ void run_batch(Server* S, Device& D, std::vector<Request*>& batch) {
     }
 }
 
+// Size-class lanes: small requests are solved as forests (one launch
+// sequence for many instances, which is what pays for them), large ones one
+// at a time, since a forest is only as fast as its slowest member and large
+// instances already fill the device.  With several workers, worker 0 prefers
+// the small lane and the others the large lane; each takes from the other
+// lane when its own is empty, so no worker idles while requests wait.  A
+// single worker takes the requests in arrival order.
 void worker_loop(Server* S, int wi) {
     (void)hipSetDevice(S->device);
     Device& D = *S->ws[wi];
+    const bool single = S->ws.size() == 1;
+    const int pref = wi == 0 ? 0 : 1;
     while (true) {
         std::vector<Request*> batch;
         size_t fp = 0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+            S->cv_work.wait(lk, [&] { return S->stop || !S->lane[0].empty() || !S->lane[1].empty(); });
             if (S->stop) break;
+            int ln;
+            if (S->lane[0].empty()) ln = 1;
+            else if (S->lane[1].empty()) ln = 0;
+            else if (single) ln = S->lane[0].front()->ticket < S->lane[1].front()->ticket ? 0 : 1;
+            else ln = pref;
+            std::deque<Request*>& q = S->lane[ln];
+            const int max_req = ln == 0 ? S->max_req : 1;
             int64_t pts = 0;
             auto now = Clock::now();
-            while (!S->queue.empty()) {
-                Request* r = S->queue.front();
-                bool fits = fp + r->footprint <= S->cap_per_worker && (int)batch.size() < S->max_req &&
+            while (!q.empty()) {
+                Request* r = q.front();
+                bool fits = fp + r->footprint <= S->cap_per_worker && (int)batch.size() < max_req &&
                             pts + r->item.n <= S->max_pts;
                 if (!batch.empty() && !fits) break;  // the first request always fits (checked at submit)
-                S->queue.pop_front();
+                q.pop_front();
                 r->started = true;
                 r->t_start = now;
                 batch.push_back(r);
@@ -2120,7 +2174,7 @@ int geomst_server_create(const geomst_server_cfg_t* cfg, geomst_server_t** out) 
     *out = nullptr;
     geomst_server_cfg_t c{};
     if (cfg) c = *cfg;
-    if (c.workers < 0 || c.workers > 16 || c.max_batch_requests < 0 || c.reserved != 0 || c.max_batch_points < 0 ||
+    if (c.workers < 0 || c.workers > 16 || c.max_batch_requests < 0 || c.small_max_points < 0 || c.max_batch_points < 0 ||
         c.max_batch_points > (1ll << 26) || c.device < -1 || c.device >= 16) {
         g_err = "bad server configuration";
         return GEOMST_EINVAL;
@@ -2139,10 +2193,11 @@ int geomst_server_create(const geomst_server_cfg_t* cfg, geomst_server_t** out) 
         std::unique_ptr<geomst_server> S(new geomst_server());
         S->device = dev;
         int w = c.workers ? c.workers : 2;
+        S->small_max = c.small_max_points ? c.small_max_points : 32768;
         S->budget = c.hbm_budget_bytes ? (size_t)c.hbm_budget_bytes : (size_t)200e9;
         S->cap_per_worker = S->budget / (size_t)w;
         S->max_req = c.max_batch_requests ? c.max_batch_requests : 4096;
-        S->max_pts = c.max_batch_points ? c.max_batch_points : (1ll << 24);
+        S->max_pts = c.max_batch_points ? c.max_batch_points : (1ll << 20);
         for (int i = 0; i < w; ++i) S->ws.emplace_back(new Device());
         for (int i = 0; i < w; ++i) S->workers.emplace_back(worker_loop, S.get(), i);
         *out = S.release();
@@ -2168,7 +2223,7 @@ int geomst_submit(geomst_server_t* srv, geomst_instance_t* req, uint64_t* ticket
         return rc;
     }
     size_t fp = request_footprint(it.n, it.d, it.min_pts);
-    if (fp > srv->cap_per_worker || it.n > srv->max_pts) {
+    if (fp > srv->cap_per_worker || (it.n <= srv->small_max && it.n > srv->max_pts)) {
         g_err = "request exceeds a worker's share of the memory budget or the batch point limit";
         req->status = GEOMST_ENOMEM;
         return GEOMST_ENOMEM;
@@ -2189,7 +2244,11 @@ int geomst_submit(geomst_server_t* srv, geomst_instance_t* req, uint64_t* ticket
             r->ticket = srv->next_ticket++;
             *ticket = r->ticket;
             srv->all[r->ticket] = r.get();
-            srv->queue.push_back(r.get());
+            // forests pay for small EMST requests; HDBSCAN* forests that mix
+            // minPts values and densities ran slower than their members
+            // solved one by one, so HDBSCAN* requests take the large lane
+            r->lane = (it.n <= srv->small_max && it.min_pts == 0) ? 0 : 1;
+            srv->lane[r->lane].push_back(r.get());
             srv->st.submitted += 1;
             srv->st.queued += 1;
             r.release();
@@ -2262,7 +2321,8 @@ int geomst_cancel(geomst_server_t* srv, uint64_t ticket) {
     }
     Request* r = f->second;
     if (!r->started) {
-        srv->queue.erase(std::find(srv->queue.begin(), srv->queue.end(), r));
+        auto& q = srv->lane[r->lane];
+        q.erase(std::find(q.begin(), q.end(), r));
         srv->st.queued -= 1;
     }
     srv->all.erase(f);
@@ -2276,6 +2336,8 @@ int geomst_server_stats(geomst_server_t* srv, geomst_server_stats_t* out) {
     if (!srv || !out) return GEOMST_EINVAL;
     std::lock_guard<std::mutex> lk(srv->mu);
     *out = srv->st;
+    out->workspace_bytes = 0;
+    for (auto& w : srv->ws) out->workspace_bytes += (int64_t)w->budget.held.load(std::memory_order_relaxed);
     return GEOMST_OK;
 }
 
@@ -2284,7 +2346,8 @@ void geomst_server_destroy(geomst_server_t* srv) {
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->stop = true;
-        srv->queue.clear();
+        srv->lane[0].clear();
+        srv->lane[1].clear();
     }
     srv->cv_work.notify_all();
     for (auto& t : srv->workers) t.join();
@@ -2335,6 +2398,11 @@ int geomst_set_option(const char* name, double value) {
     if (!strcmp(name, "beta_start_quantile")) {
         if (!(value >= 0.0 && value <= 1.0)) return GEOMST_EINVAL;
         g_beta_start = value;
+        return GEOMST_OK;
+    }
+    if (!strcmp(name, "server_share_scale")) {
+        if (!(value > 0.0) || !(value <= 1.0)) return GEOMST_EINVAL;
+        g_share_scale = value;
         return GEOMST_OK;
     }
     if (!strcmp(name, "beta_schedule")) {

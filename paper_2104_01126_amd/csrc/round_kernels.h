@@ -36,7 +36,10 @@ enum CounterSlot {
     C_TINY,    // small separated pairs for the inline BCCP kernel
     C_NUM
 };
-enum CounterSlot64 { C64_EVALS = 0, C64_VISITS, C64_BCCP, C64_BIGEVALS, C64_TASKS, C64_NUM };
+// C64_EVALS counts |A||B| of every separated pair; C64_BIGWORK the part of it
+// handed to the large-pair kernel, of which C64_BIGEVALS were evaluated (the
+// rest was pruned by block bounds).
+enum CounterSlot64 { C64_EVALS = 0, C64_VISITS, C64_BCCP, C64_BIGEVALS, C64_TASKS, C64_BIGWORK, C64_NUM };
 enum MinSlot { M_F = 0, M_P, M_FAR, M_NUM };
 
 struct Counters {
@@ -973,6 +976,7 @@ __global__ void __launch_bounds__(kBlock) k_big_ntasks(TreeView t, const uint2* 
     if (threadIdx.x == 0) {
         atomicAdd(&cnt->c64[C64_TASKS], sc);  // the host rejects totals beyond 2^31
         atomicAdd(&cnt->c64[C64_EVALS], sw);
+        atomicAdd(&cnt->c64[C64_BIGWORK], sw);
     }
 }
 

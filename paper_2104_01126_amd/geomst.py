@@ -42,6 +42,7 @@ class _Stats(ctypes.Structure):
         ("ms_core", ctypes.c_double), ("ms_rounds", ctypes.c_double), ("ms_final", ctypes.c_double),
         ("big_evals", ctypes.c_int64), ("sort_elems", ctypes.c_int64),
         ("kernel_ms", ctypes.c_double * 16), ("kernel_launches", ctypes.c_int64 * 16),
+        ("bccp_evals_done", ctypes.c_int64),
     ]
 
 
@@ -58,7 +59,7 @@ class Instance(ctypes.Structure):
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("workers", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("max_batch_requests", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_batch_requests", ctypes.c_int32), ("small_max_points", ctypes.c_int32),
                 ("max_batch_points", ctypes.c_int64)]
 
 
@@ -70,7 +71,7 @@ class RequestInfo(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "queued", "running", "completed", "batches",
                                               "reserved_bytes", "peak_reserved_bytes", "max_batch_requests",
-                                              "max_batch_points")]
+                                              "max_batch_points", "enomem_batches", "workspace_bytes")]
 
 
 _lib = None
@@ -163,6 +164,7 @@ class Stats:
     sort_elems: int
     kernel_ms: list
     kernel_launches: list
+    bccp_evals_done: int
 
 
 # kernel families (GEOMST_K_* in include/geomst.h)
@@ -403,10 +405,11 @@ class Server:
     request's batch is done.  The output arrays are allocated here and kept
     alive until the ticket is released."""
 
-    def __init__(self, hbm_budget_bytes=0, workers=0, device=-1, max_batch_requests=0, max_batch_points=0):
+    def __init__(self, hbm_budget_bytes=0, workers=0, device=-1, max_batch_requests=0, max_batch_points=0,
+                 small_max_points=0):
         lib = load()
-        cfg = ServerCfg(int(hbm_budget_bytes), int(workers), int(device), int(max_batch_requests), 0,
-                        int(max_batch_points))
+        cfg = ServerCfg(int(hbm_budget_bytes), int(workers), int(device), int(max_batch_requests),
+                        int(small_max_points), int(max_batch_points))
         h = ctypes.c_void_p()
         _check(lib.geomst_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -139,7 +139,7 @@ def test_server_struct_layouts():
 
 def test_server_validation_without_device(lib):
     h = ctypes.c_void_p()
-    bad = [G.ServerCfg(0, 17, -1, 0, 0, 0), G.ServerCfg(0, 2, -1, 0, 1, 0), G.ServerCfg(0, 2, -1, 0, 0, (1 << 26) + 1),
+    bad = [G.ServerCfg(0, 17, -1, 0, 0, 0), G.ServerCfg(0, 2, -1, 0, -1, 0), G.ServerCfg(0, 2, -1, 0, 0, (1 << 26) + 1),
            G.ServerCfg(0, 2, -2, 0, 0, 0), G.ServerCfg(0, -1, -1, 0, 0, 0)]
     for cfg in bad:
         assert lib.geomst_server_create(ctypes.byref(cfg), ctypes.byref(h)) == G.EINVAL

@@ -199,6 +199,32 @@ def test_admission_budget(G):
         assert same(e, e0) and same(w, w0)
 
 
+def test_enomem_fallback_identity(G):
+    """A worker whose batch outgrows its workspace share releases the
+    workspace and solves the batch's requests one at a time: forced here by
+    shrinking the share a batch may use; every result must still be the
+    same bytes as the request solved alone, and the fallback is counted."""
+    trace = small_trace(0.02, 4000)
+    pts = [W.serving_points(r) for r in trace]
+    say("enomem fallback", len(trace))
+    try:
+        G.set_option("server_share_scale", 1e-4)
+        with G.Server(workers=2) as S:
+            tickets = [S.submit(x, r.min_pts) for x, r in zip(pts, trace)]
+            got = [S.wait(t) for t in tickets]
+            st = S.stats()
+    finally:
+        G.set_option("server_share_scale", 1.0)
+    assert st["enomem_batches"] >= 1, st
+    assert st["workspace_bytes"] > 0
+    for r, x, (e, w, cd, info) in zip(trace, pts, got):
+        assert info["status"] == 0, r
+        e0, w0, cd0 = alone(G, x, r.min_pts)
+        assert same(e, e0) and same(w, w0), r
+        if r.min_pts:
+            assert same(cd, cd0), r
+
+
 def test_destroy_with_queued_requests(G):
     x = [W.uniform(20000, 4, seed=500 + i) for i in range(12)]
     say("destroy with queue")
