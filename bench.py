@@ -337,7 +337,7 @@ def bccp_fraction(st, d, hdb):
             "large_pair_tflops_over_family_time": round(big, 4)}
 
 
-def extra_plain(G, torch, np, name, steps, warmup, dendrogram=False):
+def extra_plain(G, torch, np, name, steps, warmup, dendrogram=False, variants=False):
     from paper_2104_01126_amd import workloads as W
     wl = WORKLOADS[name]
     log(f"{name}: generating")
@@ -360,6 +360,44 @@ def extra_plain(G, torch, np, name, steps, warmup, dendrogram=False):
            "counts": {k: getattr(st, k) for k in ("rounds", "pair_visits", "bccp_pairs", "bccp_evals",
                                                   "bccp_evals_done", "big_evals", "committed_edges")}}
     rec["bccp"] = bccp_fraction(stk, d, bool(mp))
+    if mp and variants:
+        # HDBSCAN*-GanTao (geometric separation only, Sec. 3.2.1) beside the
+        # default separation (Sec. 3.2.2), and the paper's minPts range
+        G.set_option("separation_mode", 1)
+        try:
+            tg = timed_solves(G, torch, x, mp, 3, 1, f"{name} geometric-only separation")
+            sg = G.stats()
+        finally:
+            G.set_option("separation_mode", 0)
+        rec["gantao"] = {"median_ms": round(median(tg), 3), "points_per_s": round(n / (median(tg) / 1000.0), 1),
+                         "bccp_pairs": sg.bccp_pairs, "pair_visits": sg.pair_visits,
+                         "pairs_vs_default": round(sg.bccp_pairs / max(1, st.bccp_pairs), 3)}
+        # WSPD sizes (Naive: every well-separated pair materialised) on the
+        # first 200,000 points of the recipe, with and without mutual
+        # unreachability
+        from paper_2104_01126_amd import workloads as W
+        xs = torch.from_numpy(W.hdbscan_2m(200_000)).to("cuda:0")
+        wspd = {}
+        for sep in (0, 1):
+            G.set_option("schedule", 1)
+            G.set_option("separation_mode", sep)
+            try:
+                solve(G, xs, mp)
+                torch.cuda.synchronize()
+                wspd["geometric_only" if sep else "geometric_or_mutually_unreachable"] = G.stats().bccp_pairs
+            finally:
+                G.set_option("schedule", 0)
+                G.set_option("separation_mode", 0)
+        wspd["ratio"] = round(wspd["geometric_only"] / max(1, wspd["geometric_or_mutually_unreachable"]), 4)
+        rec["wspd_pairs_first_200k"] = wspd
+        del xs
+        sweep = {}
+        for k in (10, 20, 30, 40, 50):
+            tk = timed_solves(G, torch, x, k, 3, 1, f"{name} minPts={k}")
+            sk = G.stats()
+            sweep[str(k)] = {"median_ms": round(median(tk), 3), "points_per_s": round(n / (median(tk) / 1000.0), 1),
+                             "bccp_pairs": sk.bccp_pairs}
+        rec["minpts_sweep"] = sweep
     if dendrogram:
         if mp:
             cd, e, w = G.hdbscan(x, mp)
@@ -394,6 +432,19 @@ def extra_c1_variants(G, torch, np, x, n, steps):
     out["c1_plain_beta"] = {"schedule": "beta doubles every round from the smallest pair bound",
                             "median_ms": round(median(ts), 3), "points_per_s": round(n / (median(ts) / 1000.0), 1),
                             "rounds": st.rounds, "pair_visits": st.pair_visits}
+    # the paper's own schedules (Naive; GFK, Alg. 2; MemoGFK, Alg. 3) as
+    # ablations beside the default weight-threshold schedule
+    sch = {}
+    for code, nm in ((3, "memogfk"), (2, "gfk"), (1, "naive")):
+        G.set_option("schedule", code)
+        try:
+            tsch = timed_solves(G, torch, x, 0, 3, 1, f"c1 schedule {nm}")
+            ss = G.stats()
+        finally:
+            G.set_option("schedule", 0)
+        sch[nm] = {"median_ms": round(median(tsch), 3), "rounds": ss.rounds, "bccp_pairs": ss.bccp_pairs,
+                   "bccp_evals": ss.bccp_evals_done, "pair_visits": ss.pair_visits}
+    out["c1_paper_schedules"] = sch
     ts = timed_solves(G, torch, x, 0, steps, 1, "c1 default schedule, no events")
     out["c1_no_events"] = {"median_ms": round(median(ts), 3), "points_per_s": round(n / (median(ts) / 1000.0), 1)}
     host = x.cpu().numpy()
@@ -643,7 +694,7 @@ def main():
         del x
         torch.cuda.empty_cache()
         ex["c0"] = extra_plain(G, torch, np, "emst_small", 11, 3)
-        ex["c2"] = extra_plain(G, torch, np, "hdbscan_2m", 5, 2, dendrogram=True)
+        ex["c2"] = extra_plain(G, torch, np, "hdbscan_2m", 5, 2, dendrogram=True, variants=True)
         ex["c3"] = extra_batch(G, torch, np, 5)
         ex["c4"] = extra_serve(G, a.serve_seconds, a.serve_workers)
         if not a.no_cpu_baseline:

@@ -353,6 +353,22 @@ int geomst_get_stats(geomst_stats_t* out);
  *   "kernel_timing_families"  bit mask of GEOMST_K_* families to time while
  *                    "kernel_timing" is on (fewer events, less overhead);
  *                    0 = all (default).
+ *   "schedule"       round schedule of the filtered Kruskal: 0 = weight
+ *                    thresholds (default, see "beta_schedule"); 1 = Naive:
+ *                    one round that materialises every well-separated pair
+ *                    and its BCCP (Sec. 5, EMST-Naive); 2 = GFK (Alg. 2):
+ *                    cardinality beta = 2, 4, 8, ..., each round computes
+ *                    the BCCP of every unconnected pair with |A| + |B| <= beta
+ *                    and commits the edges up to rho_hi, the smallest bound of
+ *                    the larger unconnected pairs (heavier edges wait in the
+ *                    BCCP cache); 3 = MemoGFK (Alg. 3): the same thresholds
+ *                    (GetRho by a pruned traversal each round), retrieving
+ *                    only the pairs with bounds up to rho_hi.  Single-
+ *                    instance calls only (batches use 0).  Same tree.
+ *   "separation_mode"  HDBSCAN* well-separation: 0 = geometrically separated
+ *                    or mutually unreachable (Sec. 3.2.2, default); 1 =
+ *                    geometrically separated only (the HDBSCAN*-GanTao
+ *                    variant, Sec. 3.2.1: more pairs, same tree).
  *   "separation"     the constant s of the sphere separation test (Sec. 2.3),
  *                    in [0, 16]; default 2.
  *   "bccp_chunk"     B points per large-pair BCCP task, a multiple of 64 in

@@ -36,6 +36,11 @@ thread_local hipStream_t g_cur_stream = nullptr;  // stream of the solve running
 thread_local geomst_stats_t g_stats;
 double g_beta_growth = 0.0;  // 0: 2 for EMST, sqrt(2) for HDBSCAN*
 double g_separation = 2.0;   // s of the sphere separation test
+int g_sep_mode = 0;          // 0: geometric or mutually unreachable (Sec. 3.2.2); 1: geometric only
+// Round schedule: 0 distance thresholds (default); 1 Naive (one round, all
+// pairs); 2 GFK (Alg. 2: cardinality beta, BCCPs of every pair up to beta);
+// 3 MemoGFK (Alg. 3: cardinality beta, pairs retrieved up to rho_hi).
+int g_sched = 0;
 int g_bccp_chunk = kBigBDefault;  // B points per large-pair BCCP task
 double g_capacity_scale = 1.0;
 double g_beta_start = 0.0;  // fraction of the initial pair bounds below the first threshold (0: the smallest)
@@ -243,6 +248,7 @@ struct Device {
     size_t qmax_seen = 0;
     size_t capF[2] = {0, 0}, capQ[2] = {0, 0}, capBig = 0, capTiny = 0;
     DBuf tiny;  // small separated pairs of the current round
+    DBuf rq[2], rho, rhocnt;  // GetRho traversal of the cardinality schedules
     DBuf FF[2];  // far frontier (see the round loop)
     size_t capFF[2] = {0, 0};
     EdgeBufs C, P[2], OUT;
@@ -644,6 +650,55 @@ struct Solver {
         LAUNCHCHK();
     }
 
+    u32 gfk_card = 0;     // GFK schedule: this round's cardinality beta (0 otherwise)
+
+    // GetRho (Alg. 3; rho_hi of Alg. 2): the smallest weight lower bound of
+    // the well-separated pairs below the waiting pairs (near list F[fc] and
+    // far list FF[ffc]) with |A| + |B| > beta_card that are not connected,
+    // by a pruned breadth-first traversal; +inf when there is none.
+    double get_rho(u32 beta_card, int fc, u32 nF, int ffc, u32 nFF) {
+        if ((u64)nF + nFF == 0) return kInf;
+        TIMED(GEOMST_K_EXPAND);
+        D.rho.ensure(8);
+        D.rhocnt.ensure(4);
+        u64* rho = D.rho.as<u64>();
+        u32* cnt = D.rhocnt.as<u32>();
+        k_set_u64<<<1, 1, 0, s>>>(rho, 0x7ff0000000000000ull);
+        LAUNCHCHK();
+        HIPCHK(hipMemsetAsync(cnt, 0, 4, s));
+        size_t nin = (size_t)nF + nFF;
+        D.rq[0].ensure(2 * nin * sizeof(PairRec));
+        const int mutual = g_sep_mode == 0;
+        const PairRec* lists[2] = {D.F[fc].as<PairRec>(), D.FF[ffc].as<PairRec>()};
+        const u32 counts[2] = {nF, nFF};
+        for (int l = 0; l < 2; ++l) {
+            if (!counts[l]) continue;
+            k_rho_level<D_><<<blocks(counts[l], kBlock), kBlock, 0, s>>>(t, hdb, mutual, g_separation, lists[l],
+                                                                         counts[l], D.rq[0].as<PairRec>(), cnt,
+                                                                         beta_card, rho);
+            LAUNCHCHK();
+        }
+        int c = 0;
+        while (true) {
+            HIPCHK(hipMemcpyAsync(D.hpin, cnt, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            nin = D.hpin[0];
+            if (!nin) break;
+            D.rq[c ^ 1].ensure(2 * nin * sizeof(PairRec));
+            HIPCHK(hipMemsetAsync(cnt, 0, 4, s));
+            k_rho_level<D_><<<blocks(nin, kBlock), kBlock, 0, s>>>(t, hdb, mutual, g_separation,
+                                                                   D.rq[c].as<PairRec>(), (u32)nin,
+                                                                   D.rq[c ^ 1].as<PairRec>(), cnt, beta_card, rho);
+            LAUNCHCHK();
+            c ^= 1;
+        }
+        HIPCHK(hipMemcpyAsync(D.hpin, rho, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        u64 b;
+        memcpy(&b, D.hpin, 8);
+        return bits_to_double(b);
+    }
+
     double t_near = 0.0;  // edge of the near frontier band
     u32 bstamp = 0;       // Boruvka step stamp (decreases by one per step)
     int ffo = 0;          // far list receiving appends this round
@@ -691,6 +746,8 @@ struct Solver {
         r.cnt = D.cnt.as<Counters>();
         r.beta2 = beta2;
         r.sep = g_separation;
+        r.mutual = g_sep_mode == 0;
+        r.beta_card = gfk_card;
         r.t_near = t_near;
         r.ffar = D.FF[ffo].as<PairRec>();
         r.cap_far = (u32)D.capFF[ffo];
@@ -903,6 +960,11 @@ struct Solver {
                 }
             }
         }
+        // Naive: one round over every pair.  Cardinality schedules (single
+        // instance): each round's threshold is GetRho of its beta.
+        const int sched = pinst ? 0 : g_sched;
+        if (sched == 1) beta2 = kInf;
+        u32 beta_card = 2;
         u32 nF = 0, nFF = (u32)(n - 1), nP = 0;
         t_near = -1.0;  // the first round starts a band
         double far_min = far_first;
@@ -920,6 +982,16 @@ struct Solver {
                 throw Fail{GEOMST_EINTERNAL};
             }
             int fo = fc ^ 1, po = pc ^ 1;
+            if (sched >= 2) {
+                // GetRho on current components: rho_hi of this round's
+                // cardinality beta (an empty weight range only advances beta)
+                if (stale_rounds) {
+                    refresh_components();
+                    stale_rounds = 0;
+                }
+                beta2 = std::max(beta2, get_rho(beta_card, fc, nF, ffc, nFF));
+                gfk_card = sched == 2 ? beta_card : 0;
+            }
             const bool epoch = beta2 > t_near;
             if (epoch) t_near = beta2 * g2 * g2 * g2;  // the band covers about three rounds
             ffo = epoch ? (ffc ^ 1) : ffc;
@@ -948,7 +1020,7 @@ struct Solver {
                     TIMED(GEOMST_K_SPLIT);
                     RoundArgs r = args(beta2, fo, 0, po);
                     if (nF)
-                        k_split_frontier<<<std::min(blocks(nF, kSplitTile), (unsigned)kGrid), kBlock, 0, s>>>(
+                        k_split_frontier<D_><<<std::min(blocks(nF, kSplitTile), (unsigned)kGrid), kBlock, 0, s>>>(
                             t, r, D.F[fc].as<PairRec>(), nF, ring);
                     LAUNCHCHK();
                     if (nP)
@@ -1191,6 +1263,10 @@ struct Solver {
             // it by g^4: on the same grid of thresholds, it skips rounds that
             // would only split pairs.  (For HDBSCAN* the larger first round
             // this leads to cost more than the rounds it saves.)
+            if (sched >= 2) {  // Alg. 2 / Alg. 3: beta doubles
+                beta_card = beta_card >= 0x80000000u ? 0xffffffffu : beta_card * 2;
+                continue;
+            }
             const bool sparse = !g_beta_plain && (u64)nout * kSparseDiv < (u64)n;
             const bool empty = !g_beta_plain && !hdb && nout == 0 && m == 0 && nP == 0 && nbig == 0;
             beta2 = std::max(beta2 * (empty ? g2 * g2 * g2 * g2 : sparse ? g2 * g2 : g2), nxt);
@@ -2388,6 +2464,16 @@ int geomst_set_option(const char* name, double value) {
         if (value == 0.0) value = kBigBDefault;
         if (!(value >= 64.0) || !(value <= 65536.0) || value != (double)(64 * (int)(value / 64.0))) return GEOMST_EINVAL;
         g_bccp_chunk = (int)value;
+        return GEOMST_OK;
+    }
+    if (!strcmp(name, "schedule")) {
+        if (value != 0.0 && value != 1.0 && value != 2.0 && value != 3.0) return GEOMST_EINVAL;
+        g_sched = (int)value;
+        return GEOMST_OK;
+    }
+    if (!strcmp(name, "separation_mode")) {
+        if (value != 0.0 && value != 1.0) return GEOMST_EINVAL;
+        g_sep_mode = (int)value;
         return GEOMST_OK;
     }
     if (!strcmp(name, "separation")) {

@@ -64,6 +64,8 @@ struct RoundArgs {
     Counters* cnt;
     double beta2;
     double sep;      // separation constant s of the sphere test
+    int mutual;      // HDBSCAN*: mutual unreachability also separates (0: geometric test only)
+    u32 beta_card;   // GFK schedule: pairs with |A| + |B| <= this are due whatever their bound (0: off)
     double t_near;   // waiting pairs with bounds up to this go to the near list
     PairRec* ffar;   // far list (appended)
     u32 cap_far;
@@ -124,16 +126,28 @@ __device__ __forceinline__ bool connected(const TreeView& t, u32 a, u32 b) {
     return ca >= 0 && ca == N[b].comp;
 }
 
+// GFK schedule (Alg. 2): a pair of cardinality at most beta_card has its BCCP
+// computed in this round whatever its bound (edges above the threshold wait
+// in the pool, the BCCP cache).
+template <int D>
+__device__ __forceinline__ bool card_due(const TreeView& t, u32 beta_card, u32 a, u32 b) {
+    if (!beta_card) return false;
+    const NodeRec<D>* N = nodes_of<D>(t);
+    return (u64)N[a].count + (u64)N[b].count <= (u64)beta_card;
+}
+
 // Well-separation test.  Geometric (Sec. 2.3, s = 2, in the form of
 // Sec. 3.2.2): the gap between the bounding spheres is at least the larger
-// sphere diameter.  For HDBSCAN* also mutual unreachability (Sec. 3.2.2):
-// max(gap, cdmin A, cdmin B) >= max(diam A, diam B, cdmax A, cdmax B).
+// sphere diameter.  For HDBSCAN* (mutual != 0) also mutual unreachability
+// (Sec. 3.2.2): max(gap, cdmin A, cdmin B) >= max(diam A, diam B, cdmax A,
+// cdmax B).  With mutual == 0 an HDBSCAN* solve uses the geometric test
+// alone, as the HDBSCAN*-GanTao variant does (Sec. 3.2.1).
 // Both are taken together with a strict guard on computed values (largest
 // intra-node distance bound below the inter-node bound) which makes the
 // BCCP edge of each pair contain the tree's edge exactly; a pair of two
 // single points is always separated.
 template <int D>
-__device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRec<D>& B, int hdb, double2 ca,
+__device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRec<D>& B, int mutual, double2 ca,
                                                double2 cb, double s, double dA, double dB) {
     if (A.count == 1 && B.count == 1) return true;
     double L = box_lb2<D>(A, B);
@@ -148,11 +162,15 @@ __device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRe
     }
     double need = ra + rb + s * fmax(ra, rb);
     bool geo = (fmax(dA, dB) < L) && (c2 >= need * need);
-    if (geo || !hdb) return geo;
+    if (geo || !mutual) return geo;
     double gap = fmax(sqrt(c2) - ra - rb, 0.0);
     double lhs_s = fmax(fmax(dA, dB), fmax(ca.y, cb.y));
     double rhs_s = fmax(gap * gap, fmax(ca.x, cb.x));
-    double lhs = fmax(fmax(dA, dB), fmax(ca.y, cb.y));
+    // The strict guard bounds the weight of a pair of distinct points inside
+    // one node, max(diam^2, cdmax), below the pair's bound; a single-point
+    // node has no such pair, so its own core distance does not enter.
+    double la = A.count > 1 ? fmax(dA, ca.y) : -1.0, lb_ = B.count > 1 ? fmax(dB, cb.y) : -1.0;
+    double lhs = fmax(la, lb_);
     double rhs = fmax(L, fmax(ca.x, cb.x));
     return (rhs_s >= lhs_s) && (lhs < rhs);
 }
@@ -441,6 +459,7 @@ __device__ __forceinline__ void put_queued(const RoundArgs& r, u32 slot, int rg,
     else flag_overflow(r.cnt);
 }
 
+template <int D>
 __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs r, const PairRec* fin, u32 nfin,
                                                            u32* qslot) {
     __shared__ SplitAlloc S;
@@ -461,7 +480,7 @@ __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs
             const u32 i = b0 + k * kBlock + threadIdx.x;
             if (i < nfin) {
                 p[k] = fin[i];
-                const bool d = p[k].lb2 <= r.beta2;
+                const bool d = p[k].lb2 <= r.beta2 || card_due<D>(t, r.beta_card, p[k].a, p[k].b);
                 due |= (u32)d << k;
                 wait |= (u32)!d << k;
                 if (d) {
@@ -519,7 +538,7 @@ __global__ void __launch_bounds__(kBlock) k_split_far(TreeView t, RoundArgs r, c
             if (i < nfin) {
                 p[k] = fin[i];
                 const bool keep = p[k].lb2 < inf && !connected<D>(t, p[k].a, p[k].b);
-                const bool due = keep && p[k].lb2 <= r.beta2;
+                const bool due = keep && (p[k].lb2 <= r.beta2 || card_due<D>(t, r.beta_card, p[k].a, p[k].b));
                 const bool near = keep && !due && p[k].lb2 <= r.t_near;
                 const bool far = keep && !due && !near;
                 if (near) minf = fmin(minf, p[k].lb2);
@@ -598,9 +617,9 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
             double2 ca = hdb ? t.cdr[a] : z, cb = hdb ? t.cdr[b] : z;
             lb = pair_wlb2<D>(A, B, hdb, ca, cb);
             const double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
-            if (lb > r.beta2) {
+            if (lb > r.beta2 && !card_due<D>(t, r.beta_card, a, b)) {
                 to_f = true;
-            } else if (well_separated<D>(A, B, hdb, ca, cb, r.sep, dA, dB)) {
+            } else if (well_separated<D>(A, B, hdb && r.mutual, ca, cb, r.sep, dA, dB)) {
                 u64 work = (u64)A.count * (u64)B.count;
                 if (work <= (u64)kTinyEvals) {
                     // solved by k_tiny_bccp after the level loop, away from
@@ -630,8 +649,10 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     if (kc[c] >= 0 && kc[c] == kother) continue;
-                    if (lbc[c] > r.beta2) cf[c] = true;
-                    else cq[c] = true;
+                    if (lbc[c] > r.beta2 && !card_due<D>(t, r.beta_card, c == 0 ? (u32)ch.x : (u32)ch.y, oth))
+                        cf[c] = true;
+                    else
+                        cq[c] = true;
                 }
             }
         }
@@ -835,6 +856,65 @@ __global__ void __launch_bounds__(SmallBlock<D>::value) k_level_small(TreeView t
 }
 
 // ------------------------------------------------------------ small pairs
+// ------------------------------------------------------------ GetRho
+// Threshold of the cardinality schedules (Alg. 3 GetRho; rho_hi of Alg. 2):
+// the smallest weight lower bound over the well-separated pairs that descend
+// from the waiting pairs, have |A| + |B| > beta_card and are not connected.
+// One breadth-first level, one pair per lane: a pair is dropped when its
+// nodes are connected, when |A| + |B| <= beta_card (every descendant is at
+// most as large) or when its bound is not below the current rho (no
+// descendant can lower it); a separated pair lowers rho; otherwise the node
+// with the larger sphere is split and the child pairs that pass the same
+// tests go to the next level (at most two per input, so `out` holds 2 nin).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_rho_level(TreeView t, int hdb, int mutual, double sep, const PairRec* in,
+                                                      u32 nin, PairRec* out, u32* nout, u32 beta_card, u64* rho) {
+    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    const NodeRec<D>* N = nodes_of<D>(t);
+    const double2 z = make_double2(0.0, 0.0);
+    bool push0 = false, push1 = false;
+    PairRec c0, c1;
+    if (i < nin) {
+        const PairRec p = in[i];
+        const NodeRec<D> A = N[p.a], B = N[p.b];
+        const double cur = bitsd(__hip_atomic_load(rho, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const bool conn = A.comp >= 0 && A.comp == B.comp;
+        const double2 ca = hdb ? t.cdr[p.a] : z, cb = hdb ? t.cdr[p.b] : z;
+        const double lb = pair_wlb2<D>(A, B, hdb, ca, cb);
+        if (!conn && (u64)A.count + (u64)B.count > (u64)beta_card && lb < cur) {
+            const double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
+            if (well_separated<D>(A, B, hdb && mutual, ca, cb, sep, dA, dB)) {
+                atomicMin((unsigned long long*)rho, (unsigned long long)dbits(lb));
+            } else {
+                const bool split_a = (B.count == 1) || (A.count > 1 && (dA > dB || (dA == dB && A.count >= B.count)));
+                const NodeRec<D>& X = split_a ? A : B;
+                const NodeRec<D>& O = split_a ? B : A;
+                const u32 oth = split_a ? p.b : p.a;
+                const double2 co = split_a ? cb : ca;
+                const int2 ch = node_kids(t.n, X.first, X.count, X.split);
+                const NodeRec<D> C0 = N[ch.x], C1 = N[ch.y];
+                const double2 k0 = hdb ? t.cdr[ch.x] : z, k1 = hdb ? t.cdr[ch.y] : z;
+                c0.a = (u32)ch.x;
+                c0.b = oth;
+                c0.lb2 = pair_wlb2<D>(C0, O, hdb, k0, co);
+                c1.a = (u32)ch.y;
+                c1.b = oth;
+                c1.lb2 = pair_wlb2<D>(C1, O, hdb, k1, co);
+                push0 = !(C0.comp >= 0 && C0.comp == O.comp) && (u64)C0.count + (u64)O.count > (u64)beta_card &&
+                        c0.lb2 < cur;
+                push1 = !(C1.comp >= 0 && C1.comp == O.comp) && (u64)C1.count + (u64)O.count > (u64)beta_card &&
+                        c1.lb2 < cur;
+            }
+        }
+    }
+    const u32 s0 = wave_append(nout, push0);
+    if (push0) out[s0] = c0;
+    const u32 s1 = wave_append(nout, push1);
+    if (push1) out[s1] = c1;
+}
+
+__global__ void k_set_u64(u64* p, u64 v) { *p = v; }
+
 // BCCP (or BCCP*) of the separated pairs with at most kTinyEvals point pairs,
 // queued by the level steps: one pair per thread, kTinyItems pairs per
 // thread per block step, by brute force over the point pairs.  The edge goes

@@ -93,6 +93,11 @@ def test_options(lib):
     assert lib.geomst_set_option(b"beta_start_quantile", -0.1) == G.EINVAL
     assert lib.geomst_set_option(b"beta_start_quantile", 1.0 / 64) == G.OK
     assert lib.geomst_set_option(b"beta_start_quantile", 0.0) == G.OK  # back to the default
+    assert lib.geomst_set_option(b"schedule", 4.0) == G.EINVAL
+    assert lib.geomst_set_option(b"schedule", 0.0) == G.OK
+    assert lib.geomst_set_option(b"separation_mode", 2.0) == G.EINVAL
+    assert lib.geomst_set_option(b"separation_mode", 0.0) == G.OK
+    assert lib.geomst_set_option(b"server_share_scale", 0.0) == G.EINVAL
     assert lib.geomst_set_option(b"beta_schedule", 2.0) == G.EINVAL
     assert lib.geomst_set_option(b"beta_schedule", 1.0) == G.OK
     assert lib.geomst_set_option(b"beta_schedule", 0.0) == G.OK

@@ -264,6 +264,69 @@ def test_repeatable_and_schedule_independent(G):
         G.set_option("beta_schedule", 0)
 
 
+@pytest.mark.parametrize("case", ["mixture3", "mixture5", "uniform7", "dups2"])
+def test_gantao_geometric_separation(G, case):
+    """HDBSCAN*-GanTao (Sec. 3.2.1): only geometrically separated pairs; the
+    tree must be the checker's.  (How many BCCPs each mode computes depends
+    on connectivity pruning across rounds, so the counts are reported by the
+    benchmark, not compared here.)"""
+    if case == "mixture3":
+        p = W.mixture(8000, 3, seed=71, k=9, noise_frac=0.05)
+    elif case == "mixture5":
+        p = W.hdbscan_2m(12_000)
+    elif case == "uniform7":
+        p = W.uniform(3000, 7, seed=72)
+    else:
+        p = W.with_duplicates(4000, 2, seed=73, n_unique=600)
+    for mp in (4, 10, 33):
+        try:
+            G.set_option("separation_mode", 1)
+            check_hdb_exact(G, p, mp, f"{case} geometric-only mp={mp}")
+        finally:
+            G.set_option("separation_mode", 0)
+
+
+@pytest.mark.parametrize("sched", [1, 2, 3])
+def test_paper_schedules_exact(G, sched):
+    """The paper's own round schedules (Naive; GFK, Alg. 2; MemoGFK, Alg. 3)
+    give the checker's tree: EMST and HDBSCAN*, uniform and clustered,
+    with both separation rules for HDBSCAN*."""
+    cases = [("uniform3", W.uniform(6000, 3, seed=81), 0), ("mixture2", W.mixture(5000, 2, seed=82, k=6), 0),
+             ("uniform6", W.uniform(2500, 6, seed=83), 0), ("mixture5", W.hdbscan_2m(8000), 10),
+             ("dups3", W.with_duplicates(3000, 3, seed=84, n_unique=400), 5)]
+    try:
+        G.set_option("schedule", sched)
+        for tag, p, mp in cases:
+            if mp:
+                check_hdb_exact(G, p, mp, f"{tag} schedule={sched}")
+                G.set_option("separation_mode", 1)
+                try:
+                    check_hdb_exact(G, p, mp, f"{tag} schedule={sched} geometric-only")
+                finally:
+                    G.set_option("separation_mode", 0)
+            else:
+                check_emst_exact(G, p, f"{tag} schedule={sched}")
+            if sched == 1:
+                assert G.stats().rounds == 1
+    finally:
+        G.set_option("schedule", 0)
+
+
+@pytest.mark.parametrize("mp", [10, 20, 30, 40, 50])
+def test_minpts_sweep_exact(G, mp):
+    """The paper's minPts range 10..50 (Sec. 5) on 20,000 points of the 5-D
+    mixture recipe, both separation modes."""
+    p = W.hdbscan_2m(20_000)
+    check_hdb_exact(G, p, mp, f"hdbscan_2m recipe n=20000 mp={mp}")
+    try:
+        G.set_option("separation_mode", 1)
+        out = run_hdb(G, p, mp)
+    finally:
+        G.set_option("separation_mode", 0)
+    ref = run_hdb(G, p, mp)
+    assert all(same(a, b) for a, b in zip(out, ref))
+
+
 @pytest.mark.parametrize("chunk", [64, 128])
 def test_large_pair_chunks_exact(G, chunk):
     """Tight, far-apart clusters give separated pairs of thousands of points
