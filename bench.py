@@ -477,6 +477,42 @@ def extra_batch(G, torch, np, steps):
         torch.cuda.synchronize()
         ts.append((time.perf_counter() - t) * 1000.0)
     log(f"c3 batched: median {median(ts):.1f} ms")
+    # device time of one batched solve (HIP events around every kernel
+    # family) against its wall time: the share a captured graph could at
+    # most remove from host launches and round trips
+    G.set_option("kernel_timing", 1)
+    t = time.perf_counter()
+    G.batch_dev(x, items, stride)
+    torch.cuda.synchronize()
+    wall_ev = (time.perf_counter() - t) * 1000.0
+    stk = G.stats()
+    G.set_option("kernel_timing", 0)
+    dev_ms = float(sum(stk.kernel_ms))
+    launches = int(sum(stk.kernel_launches))
+    # the project's tuner's cache, when present: tuned against default
+    tuned = None
+    cache = os.path.join(ROOT, "paper_2104_01126_amd", "tuning_cache.jsonl")
+    if os.path.exists(cache):
+        import hashlib
+        ref = G.batch_dev(x, items, stride, want_sq=True)
+        hd = hashlib.sha256(ref["edges"].cpu().numpy().tobytes() + ref["weights_sq"].cpu().numpy().tobytes()).hexdigest()
+        G.load_tuning(cache)
+        try:
+            out = G.batch_dev(x, items, stride, want_sq=True)
+            ht = hashlib.sha256(out["edges"].cpu().numpy().tobytes() + out["weights_sq"].cpu().numpy().tobytes()).hexdigest()
+            applied = G.stats().tuning_applied
+            tt = []
+            for _ in range(steps):
+                t = time.perf_counter()
+                G.batch_dev(x, items, stride)
+                torch.cuda.synchronize()
+                tt.append((time.perf_counter() - t) * 1000.0)
+        finally:
+            G.load_tuning(None)
+        tuned = {"cache": "paper_2104_01126_amd/tuning_cache.jsonl", "applied": bool(applied),
+                 "median_ms": round(median(tt), 2), "tuned_vs_default": round(median(ts) / median(tt), 3),
+                 "same_bytes": hd == ht}
+        log(f"c3 batched, tuned: median {median(tt):.1f} ms (same bytes: {hd == ht})")
     G.emst(singles[0])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -490,7 +526,9 @@ def extra_batch(G, torch, np, steps):
            "batched_median_ms": round(median(ts), 2), "batched_points_per_s": round(N / (median(ts) / 1000.0), 1),
            "batched_instances_per_s": round(len(inst) / (median(ts) / 1000.0), 1),
            "plain_seconds": round(dplain, 3), "plain_points_per_s": round(N / dplain, 1),
-           "batched_vs_plain": round(dplain / (median(ts) / 1000.0), 2)}
+           "batched_vs_plain": round(dplain / (median(ts) / 1000.0), 2),
+           "device_ms_one_solve": round(dev_ms, 2), "wall_ms_with_events": round(wall_ev, 2),
+           "launch_groups_timed": launches, "tuned": tuned}
     del x, singles
     torch.cuda.empty_cache()
     return rec

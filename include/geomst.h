@@ -232,6 +232,7 @@ typedef struct {
     int32_t max_batch_requests; /* small-lane batches; 0 = 4096 */
     int32_t small_max_points;   /* requests with n <= this are "small"; 0 = 32768 */
     int64_t max_batch_points;   /* small-lane batch points; 0 = 2^20; at most 2^26 */
+    const char* tuning_cache;   /* tuning cache to load (geomst_load_tuning), or NULL */
 } geomst_server_cfg_t;
 
 /* Timings of one request, filled by geomst_wait (milliseconds). */
@@ -321,6 +322,7 @@ typedef struct {
     double kernel_ms[16];     /* device time per kernel family (kernel_timing on) */
     int64_t kernel_launches[16];
     int64_t bccp_evals_done;  /* distances the BCCP kernels evaluated (bccp_evals minus pruned blocks) */
+    int64_t tuning_applied;   /* 1 if a loaded tuning-cache entry set this solve's knobs */
 } geomst_stats_t;
 
 int geomst_get_stats(geomst_stats_t* out);
@@ -380,10 +382,27 @@ int geomst_get_stats(geomst_stats_t* out);
  *                    the first many pairs run in one workgroup, which keeps
  *                    going while levels stay at most the second size
  *                    (defaults 2048 and 4096).
- * Options are process-wide; set them while no solve is running.
+ * Options are process-wide; every solve reads them once when it starts
+ * (under a lock), so a change never reaches a solve already running.
  * Returns GEOMST_EINVAL for an unknown name or a bad value.
  */
 int geomst_set_option(const char* name, double value);
+
+/*
+ * Tuning cache (written by the project's tuner, paper_2104_01126_amd/tune.py):
+ * a text file of flat JSON objects, one per line, e.g.
+ *   {"kind": "emst", "d": 3, "nlog2": 25, "bccp_chunk": 1024,
+ *    "small_level_switch": 2048, "small_level_max": 4096, "beta_growth": 2.0}
+ * ("kind" emst or hdbscan, "d" the dimension or batch stride, "nlog2" =
+ * floor(log2 of the solve's total points); knobs as for geomst_set_option:
+ * bccp_chunk, small_level_switch, small_level_max, refresh_divisor,
+ * beta_growth, beta_start_quantile; other keys are ignored).  A solve takes
+ * the entry of its kind and d with the nearest nlog2 (within 2) for every
+ * knob still at its built-in default.  The knobs never change the result.
+ * path NULL clears the table.  ENOENT if the file cannot be opened, EINVAL
+ * (table unchanged) for a malformed line.
+ */
+int geomst_load_tuning(const char* path);
 
 /* Thread-local description of the last error (empty string if none). */
 const char* geomst_last_error(void);

@@ -55,6 +55,71 @@ constexpr int kBoruvkaBatch = 4;  // Boruvka steps launched between host checks
 constexpr u32 kSparseDiv = 64;  // beta grows faster while the tree has fewer than n / this many edges
 const bool g_trace = getenv("GEOMST_TRACE") != nullptr;
 
+// Options of one solve: the process-wide values (geomst_set_option) read
+// once under a lock when the solve starts, so a change made meanwhile never
+// reaches a running solve; knobs still at their built-in defaults take the
+// loaded tuning table's value for the solve's (kind, d, log2 n) instead.
+struct Opts {
+    double beta_growth, separation, capacity_scale, beta_start;
+    int bccp_chunk, beta_plain, sep_mode, sched;
+    u32 refresh_div, small_switch, small_max;
+    bool tuned = false;
+};
+
+struct TuneEntry {
+    int kind, d, nlog2;  // kind 0 EMST, 1 HDBSCAN*
+    int bccp_chunk = 0;
+    u32 small_switch = 0, small_max = 0, refresh_div = 0;
+    double beta_growth = 0.0, beta_start = -1.0;
+};
+
+std::mutex g_opt_mu;
+std::vector<TuneEntry> g_tuning;
+
+int log2_floor(int64_t x) {
+    int b = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+Opts snapshot_options(int kind, int d, int64_t n) {
+    std::lock_guard<std::mutex> lk(g_opt_mu);
+    Opts o;
+    o.beta_growth = g_beta_growth;
+    o.separation = g_separation;
+    o.capacity_scale = g_capacity_scale;
+    o.beta_start = g_beta_start;
+    o.bccp_chunk = g_bccp_chunk;
+    o.beta_plain = g_beta_plain;
+    o.sep_mode = g_sep_mode;
+    o.sched = g_sched;
+    o.refresh_div = g_refresh_div;
+    o.small_switch = g_small_switch;
+    o.small_max = g_small_max;
+    // the entry of the same kind and d whose log2 n is nearest (within 2)
+    const TuneEntry* best = nullptr;
+    const int nl = log2_floor(n);
+    for (const TuneEntry& e : g_tuning) {
+        if (e.kind != kind || e.d != d || std::abs(e.nlog2 - nl) > 2) continue;
+        if (!best || std::abs(e.nlog2 - nl) < std::abs(best->nlog2 - nl)) best = &e;
+    }
+    if (best) {
+        if (best->bccp_chunk && o.bccp_chunk == kBigBDefault) o.bccp_chunk = best->bccp_chunk;
+        if (best->small_switch && o.small_switch == 2048 && o.small_max == 4096) {
+            o.small_switch = best->small_switch;
+            o.small_max = std::max(best->small_max, best->small_switch);
+        }
+        if (best->refresh_div && o.refresh_div == 1024) o.refresh_div = best->refresh_div;
+        if (best->beta_growth > 0.0 && o.beta_growth == 0.0) o.beta_growth = best->beta_growth;
+        if (best->beta_start >= 0.0 && o.beta_start == 0.0) o.beta_start = best->beta_start;
+        o.tuned = true;
+    }
+    return o;
+}
+
 struct Fail {
     int code;
 };
@@ -466,8 +531,10 @@ struct Solver {
     const int* ik = nullptr;      // k-NN k per instance
     u32 target_edges = 0;         // edges of the whole forest
 
-    Solver(Device& dev, hipStream_t stream, int n_, int mp, geomst_stats_t& stats)
-        : D(dev), s(stream), n(n_), minpts(mp), hdb(mp > 0), st(stats), target_edges((u32)(n_ - 1)) {}
+    Opts o;                       // this solve's options (snapshot)
+
+    Solver(Device& dev, hipStream_t stream, int n_, int mp, geomst_stats_t& stats, const Opts& opts)
+        : D(dev), s(stream), n(n_), minpts(mp), hdb(mp > 0), st(stats), target_edges((u32)(n_ - 1)), o(opts) {}
 
     void build_tree(const double* P) {
         int nn = 2 * n - 1;
@@ -668,12 +735,12 @@ struct Solver {
         HIPCHK(hipMemsetAsync(cnt, 0, 4, s));
         size_t nin = (size_t)nF + nFF;
         D.rq[0].ensure(2 * nin * sizeof(PairRec));
-        const int mutual = g_sep_mode == 0;
+        const int mutual = o.sep_mode == 0;
         const PairRec* lists[2] = {D.F[fc].as<PairRec>(), D.FF[ffc].as<PairRec>()};
         const u32 counts[2] = {nF, nFF};
         for (int l = 0; l < 2; ++l) {
             if (!counts[l]) continue;
-            k_rho_level<D_><<<blocks(counts[l], kBlock), kBlock, 0, s>>>(t, hdb, mutual, g_separation, lists[l],
+            k_rho_level<D_><<<blocks(counts[l], kBlock), kBlock, 0, s>>>(t, hdb, mutual, o.separation, lists[l],
                                                                          counts[l], D.rq[0].as<PairRec>(), cnt,
                                                                          beta_card, rho);
             LAUNCHCHK();
@@ -686,7 +753,7 @@ struct Solver {
             if (!nin) break;
             D.rq[c ^ 1].ensure(2 * nin * sizeof(PairRec));
             HIPCHK(hipMemsetAsync(cnt, 0, 4, s));
-            k_rho_level<D_><<<blocks(nin, kBlock), kBlock, 0, s>>>(t, hdb, mutual, g_separation,
+            k_rho_level<D_><<<blocks(nin, kBlock), kBlock, 0, s>>>(t, hdb, mutual, o.separation,
                                                                    D.rq[c].as<PairRec>(), (u32)nin,
                                                                    D.rq[c ^ 1].as<PairRec>(), cnt, beta_card, rho);
             LAUNCHCHK();
@@ -726,7 +793,7 @@ struct Solver {
             }
             ++nlarge;
             big_ev += w;
-            double ta = std::ceil(a / kBigA), tbn = std::ceil(b / g_bccp_chunk);
+            double ta = std::ceil(a / kBigA), tbn = std::ceil(b / o.bccp_chunk);
             slots += ta * kBigA * (tbn > 1 ? b : b);  // lanes x B points each task row covers
             int h = b < 64 ? 0 : b < 256 ? 1 : b < 1024 ? 2 : b < 4096 ? 3 : b < 16384 ? 4 : b < 65536 ? 5 : 6;
             ++hist[h];
@@ -745,8 +812,8 @@ struct Solver {
         RoundArgs r;
         r.cnt = D.cnt.as<Counters>();
         r.beta2 = beta2;
-        r.sep = g_separation;
-        r.mutual = g_sep_mode == 0;
+        r.sep = o.separation;
+        r.mutual = o.sep_mode == 0;
         r.beta_card = gfk_card;
         r.t_near = t_near;
         r.ffar = D.FF[ffo].as<PairRec>();
@@ -883,9 +950,9 @@ struct Solver {
             }
         };
         auto sc = [&](double per_point) {
-            return std::max<size_t>(64, (size_t)(g_capacity_scale * D.list_scale * (per_point * n + 4096)));
+            return std::max<size_t>(64, (size_t)(o.capacity_scale * D.list_scale * (per_point * n + 4096)));
         };
-        if (g_capacity_scale != 1.0) {  // testing aid: start from the given capacities
+        if (o.capacity_scale != 1.0) {  // testing aid: start from the given capacities
             for (int i = 0; i < 2; ++i) {
                 D.capF[i] = D.capQ[i] = D.capFF[i] = 0;
                 D.P[i].cap = 0;
@@ -905,7 +972,7 @@ struct Solver {
         initcap(D.capFF[1], D.FF[1], sc(kInitFar[D_] * (hdb ? 2 : 1)));
         // a thin-level chain keeps its queue in one region: room for a level
         // of up to small_max pairs and its children
-        const size_t qmin = (size_t)(std::min(g_capacity_scale, 1.0) * kRegions * (2 * (double)g_small_max + 2048));
+        const size_t qmin = (size_t)(std::min(o.capacity_scale, 1.0) * kRegions * (2 * (double)o.small_max + 2048));
         initcap(D.capQ[0], D.Q[0], (std::max(sc(fq), qmin) + kRegions - 1) / kRegions * kRegions);
         initcap(D.capQ[1], D.Q[1], (std::max(sc(fq), qmin) + kRegions - 1) / kRegions * kRegions);
         if (D.capTiny < sc(hdb ? 8 : 3)) {
@@ -929,7 +996,7 @@ struct Solver {
         int fc = 0, pc = 0, ffc = 0;
         k_init_frontier<D_><<<blocks(n - 1, 256), 256, 0, s>>>(t, hdb, pinst, D.FF[ffc].as<PairRec>());
         LAUNCHCHK();
-        const bool want_hist = g_beta_start > 0.0;
+        const bool want_hist = o.beta_start > 0.0;
         if (want_hist) {
             D.lbhist.ensure(kExpBins * 4);
             HIPCHK(hipMemsetAsync(D.lbhist.p, 0, kExpBins * 4, s));
@@ -947,10 +1014,10 @@ struct Solver {
         // fraction of the initial pairs' positive bounds is reached (never
         // below the smallest bound).  Rounds below it would commit almost
         // nothing; any start gives the same tree.
-        if (g_beta_start > 0.0 && beta2 > 0.0) {
+        if (o.beta_start > 0.0 && beta2 > 0.0) {
             u64 total = 0;
             for (int e = 0; e < kExpBins; ++e) total += lbh[e];
-            const double target = std::max(1.0, std::ceil(g_beta_start * (double)total));
+            const double target = std::max(1.0, std::ceil(o.beta_start * (double)total));
             u64 cum = 0;
             for (int e = 0; e < kExpBins; ++e) {
                 cum += lbh[e];
@@ -962,13 +1029,13 @@ struct Solver {
         }
         // Naive: one round over every pair.  Cardinality schedules (single
         // instance): each round's threshold is GetRho of its beta.
-        const int sched = pinst ? 0 : g_sched;
+        const int sched = pinst ? 0 : o.sched;
         if (sched == 1) beta2 = kInf;
         u32 beta_card = 2;
         u32 nF = 0, nFF = (u32)(n - 1), nP = 0;
         t_near = -1.0;  // the first round starts a band
         double far_min = far_first;
-        const double growth = g_beta_growth > 0.0 ? g_beta_growth : (hdb ? 1.4142135623730951 : 2.0);
+        const double growth = o.beta_growth > 0.0 ? o.beta_growth : (hdb ? 1.4142135623730951 : 2.0);
         const double g2 = growth * growth;
         u64 committed = 0, maxf = nF, big_pairs = 0;
         int rounds = 0;
@@ -1045,13 +1112,13 @@ struct Solver {
                     // ring[lv % 4] its count.
                     int lv = 0;
                     while (nq > 0) {
-                        if (nq <= g_small_switch) {
+                        if (nq <= o.small_switch) {
                             {
                                 TIMED(GEOMST_K_EXPAND);
                                 RoundArgs r = args(beta2, fo, 0, po);
                                 k_level_small<D_><<<1, SmallBlock<D_>::value, 0, s>>>(
                                     t, r, hdb, D.Q[0].as<PairRec>(), (u32)(D.capQ[0] / kRegions), D.Q[1].as<PairRec>(),
-                                    (u32)(D.capQ[1] / kRegions), lv & 1, ring, (u32)(lv % kQRing), g_small_max,
+                                    (u32)(D.capQ[1] / kRegions), lv & 1, ring, (u32)(lv % kQRing), o.small_max,
                                     aux_dev(D, kAuxLstate));
                                 LAUNCHCHK();
                             }
@@ -1110,7 +1177,7 @@ struct Solver {
                         D.stemp.ensure(std::max(scan_temp_bytes(nbig), radix_temp_bytes(n)));
                         HIPCHK(hipMemsetAsync(&D.cnt.as<Counters>()->c64[C64_TASKS], 0, 8, s));
                         k_big_ntasks<D_><<<blocks(nbig, 256), 256, 0, s>>>(t, D.big.as<uint2>(), nbig,
-                                                                            D.ntask.as<u32>(), g_bccp_chunk,
+                                                                            D.ntask.as<u32>(), o.bccp_chunk,
                                                                             D.cnt.as<Counters>());
                         LAUNCHCHK();
                         scan_exclusive_u32(D.ntask.as<u32>(), D.toff.as<u32>(), nbig, D.stemp.p, s);
@@ -1136,11 +1203,11 @@ struct Solver {
                             if (hdb)
                                 k_big_bccp<D_, 1><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
                                                                        D.parts.as<PartKey>(), D.cnt.as<Counters>(),
-                                                                       g_bccp_chunk, D.ubest.as<u64>(), D.tdone.as<u32>());
+                                                                       o.bccp_chunk, D.ubest.as<u64>(), D.tdone.as<u32>());
                             else
                                 k_big_bccp<D_, 0><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
                                                                        D.parts.as<PartKey>(), D.cnt.as<Counters>(),
-                                                                       g_bccp_chunk, D.ubest.as<u64>(), D.tdone.as<u32>());
+                                                                       o.bccp_chunk, D.ubest.as<u64>(), D.tdone.as<u32>());
                             LAUNCHCHK();
                             // the per-pair best weights are dead after k_big_bccp: the
                             // same array then holds each pair's evaluation count
@@ -1220,7 +1287,7 @@ struct Solver {
             const Counters& c = *D.hcnt;
             check_errors(D);
             u32 merged = c.c[C_OUT] - nout;
-            if ((u64)merged * g_refresh_div >= (u64)n || stale_rounds >= 3 || c.c[C_OUT] >= target_edges) {
+            if ((u64)merged * o.refresh_div >= (u64)n || stale_rounds >= 3 || c.c[C_OUT] >= target_edges) {
                 refresh_components();
                 stale_rounds = 0;
             } else {
@@ -1267,8 +1334,8 @@ struct Solver {
                 beta_card = beta_card >= 0x80000000u ? 0xffffffffu : beta_card * 2;
                 continue;
             }
-            const bool sparse = !g_beta_plain && (u64)nout * kSparseDiv < (u64)n;
-            const bool empty = !g_beta_plain && !hdb && nout == 0 && m == 0 && nP == 0 && nbig == 0;
+            const bool sparse = !o.beta_plain && (u64)nout * kSparseDiv < (u64)n;
+            const bool empty = !o.beta_plain && !hdb && nout == 0 && m == 0 && nP == 0 && nbig == 0;
             beta2 = std::max(beta2 * (empty ? g2 * g2 * g2 * g2 : sparse ? g2 * g2 : g2), nxt);
         }
         if (nout != target_edges) {
@@ -1386,10 +1453,12 @@ void solve_dev(Device& D, hipStream_t s, const double* P, int n, int d, int minp
         HIPCHK(hipStreamSynchronize(s));
         return;
     }
+    const Opts opts = snapshot_options(minpts > 0 ? 1 : 0, d, n);
+    g_stats.tuning_applied = opts.tuned ? 1 : 0;
     switch (d) {
 #define CASE(K)                                                   \
     case K: {                                                     \
-        Solver<K> sv(D, s, n, minpts, g_stats);                   \
+        Solver<K> sv(D, s, n, minpts, g_stats, opts);             \
         sv.run(P, edges, w, w2, cd, cd2);                         \
         break;                                                    \
     }
@@ -1446,10 +1515,12 @@ void solve_batch_dev(Device& D, hipStream_t s, const double* P, int stride, cons
         HIPCHK(hipStreamSynchronize(s));
         return;
     }
+    const Opts opts = snapshot_options(hdb ? 1 : 0, stride, N);
+    g_stats.tuning_applied = opts.tuned ? 1 : 0;
     switch (stride) {
 #define CASE(K)                                                   \
     case K: {                                                     \
-        Solver<K> sv(D, s, (int)N, hdb ? maxk : 0, g_stats);      \
+        Solver<K> sv(D, s, (int)N, hdb ? maxk : 0, g_stats, opts); \
         sv.ninst = (int)count;                                    \
         sv.pinst = D.browinst.as<u32>();                          \
         sv.irange = D.birange.as<int2>();                         \
@@ -1626,6 +1697,84 @@ int run_host(const double* P, int64_t n, int32_t d, int32_t minpts, int64_t* edg
         return GEOMST_ENOMEM;
     }
     return GEOMST_OK;
+}
+
+// One line of a tuning cache: a flat JSON object such as
+// {"kind": "emst", "d": 3, "nlog2": 25, "bccp_chunk": 1024,
+//  "small_level_switch": 2048, "small_level_max": 4096, "beta_growth": 2.0,
+//  "refresh_divisor": 1024, "beta_start_quantile": 0.0}
+// (other keys the tuner records, e.g. measured times, are ignored).  Blank
+// lines and lines starting with '#' are skipped.  Returns false on a
+// malformed line or an out-of-range value.
+bool parse_tune_line(const char* line, std::vector<TuneEntry>& out) {
+    std::string t(line);
+    size_t a = t.find_first_not_of(" \t\r\n");
+    if (a == std::string::npos || t[a] == '#') return true;
+    size_t b = t.find_last_not_of(" \t\r\n");
+    if (t[a] != '{' || t[b] != '}') return false;
+    std::string body = t.substr(a + 1, b - a - 1);
+    TuneEntry e{};
+    e.kind = -1;
+    e.d = 0;
+    e.nlog2 = -1;
+    size_t p = 0;
+    while (p < body.size()) {
+        size_t q1 = body.find('"', p);
+        if (q1 == std::string::npos) break;
+        size_t q2 = body.find('"', q1 + 1);
+        size_t colon = q2 == std::string::npos ? q2 : body.find(':', q2);
+        if (colon == std::string::npos) return false;
+        std::string key = body.substr(q1 + 1, q2 - q1 - 1);
+        size_t v0 = body.find_first_not_of(" \t", colon + 1);
+        if (v0 == std::string::npos) return false;
+        size_t v1;
+        std::string val;
+        if (body[v0] == '"') {
+            v1 = body.find('"', v0 + 1);
+            if (v1 == std::string::npos) return false;
+            val = body.substr(v0 + 1, v1 - v0 - 1);
+            ++v1;
+        } else {
+            v1 = body.find(',', v0);
+            if (v1 == std::string::npos) v1 = body.size();
+            val = body.substr(v0, v1 - v0);
+        }
+        char* endp = nullptr;
+        const double x = strtod(val.c_str(), &endp);
+        const bool num = endp && endp != val.c_str();
+        if (key == "kind") {
+            if (val == "emst") e.kind = 0;
+            else if (val == "hdbscan") e.kind = 1;
+            else return false;
+        } else if (key == "d") {
+            if (!num || x < 1 || x > kMaxDim || x != (int)x) return false;
+            e.d = (int)x;
+        } else if (key == "nlog2") {
+            if (!num || x < 0 || x > 26 || x != (int)x) return false;
+            e.nlog2 = (int)x;
+        } else if (key == "bccp_chunk") {
+            if (!num || x < 64 || x > 65536 || x != 64.0 * (int)(x / 64.0)) return false;
+            e.bccp_chunk = (int)x;
+        } else if (key == "small_level_switch" || key == "small_level_max") {
+            if (!num || x < 0 || x > 1048576 || x != (u32)x) return false;
+            (key == "small_level_switch" ? e.small_switch : e.small_max) = (u32)x;
+        } else if (key == "refresh_divisor") {
+            if (!num || x < 1 || x > 1048576 || x != (u32)x) return false;
+            e.refresh_div = (u32)x;
+        } else if (key == "beta_growth") {
+            if (!num || !(x > 1.0) || !(x < 1e6)) return false;
+            e.beta_growth = x;
+        } else if (key == "beta_start_quantile") {
+            if (!num || !(x >= 0.0) || !(x <= 1.0)) return false;
+            e.beta_start = x;
+        }
+        p = body.find(',', v1);
+        if (p == std::string::npos) break;
+        ++p;
+    }
+    if (e.kind < 0 || e.d < 1 || e.nlog2 < 0) return false;
+    out.push_back(e);
+    return true;
 }
 
 // ------------------------------------------------------------ dendrogram
@@ -2270,6 +2419,10 @@ int geomst_server_create(const geomst_server_cfg_t* cfg, geomst_server_t** out) 
         S->device = dev;
         int w = c.workers ? c.workers : 2;
         S->small_max = c.small_max_points ? c.small_max_points : 32768;
+        if (c.tuning_cache) {
+            int trc = geomst_load_tuning(c.tuning_cache);
+            if (trc) return trc;
+        }
         S->budget = c.hbm_budget_bytes ? (size_t)c.hbm_budget_bytes : (size_t)200e9;
         S->cap_per_worker = S->budget / (size_t)w;
         S->max_req = c.max_batch_requests ? c.max_batch_requests : 4096;
@@ -2444,6 +2597,7 @@ int geomst_get_stats(geomst_stats_t* out) {
 
 int geomst_set_option(const char* name, double value) {
     if (!name) return GEOMST_EINVAL;
+    std::lock_guard<std::mutex> lk(g_opt_mu);
     if (!strcmp(name, "beta_growth")) {
         if (value != 0.0 && (!(value > 1.0) || !(value < 1e6))) return GEOMST_EINVAL;
         g_beta_growth = value;
@@ -2513,6 +2667,36 @@ int geomst_set_option(const char* name, double value) {
         return GEOMST_OK;
     }
     return GEOMST_EINVAL;
+}
+
+int geomst_load_tuning(const char* path) {
+    g_err.clear();
+    if (!path) {
+        std::lock_guard<std::mutex> lk(g_opt_mu);
+        g_tuning.clear();
+        return GEOMST_OK;
+    }
+    FILE* fh = fopen(path, "r");
+    if (!fh) {
+        g_err = std::string("cannot open tuning cache ") + path;
+        return GEOMST_ENOENT;
+    }
+    std::vector<TuneEntry> table;
+    char line[4096];
+    int lineno = 0;
+    int rc = GEOMST_OK;
+    while (rc == GEOMST_OK && fgets(line, sizeof line, fh)) {
+        ++lineno;
+        if (!parse_tune_line(line, table)) {
+            g_err = std::string("tuning cache ") + path + ": bad entry on line " + std::to_string(lineno);
+            rc = GEOMST_EINVAL;
+        }
+    }
+    fclose(fh);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_opt_mu);
+    g_tuning.swap(table);
+    return GEOMST_OK;
 }
 
 const char* geomst_last_error(void) { return g_err.c_str(); }

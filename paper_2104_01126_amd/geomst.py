@@ -42,7 +42,7 @@ class _Stats(ctypes.Structure):
         ("ms_core", ctypes.c_double), ("ms_rounds", ctypes.c_double), ("ms_final", ctypes.c_double),
         ("big_evals", ctypes.c_int64), ("sort_elems", ctypes.c_int64),
         ("kernel_ms", ctypes.c_double * 16), ("kernel_launches", ctypes.c_int64 * 16),
-        ("bccp_evals_done", ctypes.c_int64),
+        ("bccp_evals_done", ctypes.c_int64), ("tuning_applied", ctypes.c_int64),
     ]
 
 
@@ -60,7 +60,7 @@ class Instance(ctypes.Structure):
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("workers", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("max_batch_requests", ctypes.c_int32), ("small_max_points", ctypes.c_int32),
-                ("max_batch_points", ctypes.c_int64)]
+                ("max_batch_points", ctypes.c_int64), ("tuning_cache", ctypes.c_char_p)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -93,6 +93,8 @@ def load(path: str = LIB_PATH):
     lib.geomst_emst_dev_noalloc.argtypes = [P, i64, i32, P, P, P, P]
     lib.geomst_dendrogram_dev.argtypes = [P, P, i64, i64, P, P, P, P, P]
     lib.geomst_dendrogram.argtypes = [P, P, i64, i64, P, P, P, P]
+    lib.geomst_load_tuning.argtypes = [ctypes.c_char_p]
+    lib.geomst_load_tuning.restype = ctypes.c_int
     lib.geomst_dendrogram_dev.restype = ctypes.c_int
     lib.geomst_dendrogram.restype = ctypes.c_int
     lib.geomst_emst_dev_noalloc.restype = ctypes.c_int
@@ -143,6 +145,11 @@ def set_option(name: str, value: float):
     _check(load().geomst_set_option(name.encode(), float(value)))
 
 
+def load_tuning(path):
+    """Load a tuning cache (JSON lines written by tune.py); None clears it."""
+    _check(load().geomst_load_tuning(None if path is None else os.fsencode(path)))
+
+
 @dataclass
 class Stats:
     n: int
@@ -165,6 +172,7 @@ class Stats:
     kernel_ms: list
     kernel_launches: list
     bccp_evals_done: int
+    tuning_applied: int
 
 
 # kernel families (GEOMST_K_* in include/geomst.h)
@@ -406,10 +414,11 @@ class Server:
     alive until the ticket is released."""
 
     def __init__(self, hbm_budget_bytes=0, workers=0, device=-1, max_batch_requests=0, max_batch_points=0,
-                 small_max_points=0):
+                 small_max_points=0, tuning_cache=None):
         lib = load()
         cfg = ServerCfg(int(hbm_budget_bytes), int(workers), int(device), int(max_batch_requests),
-                        int(small_max_points), int(max_batch_points))
+                        int(small_max_points), int(max_batch_points),
+                        None if tuning_cache is None else os.fsencode(tuning_cache))
         h = ctypes.c_void_p()
         _check(lib.geomst_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -186,3 +186,28 @@ def test_pack_layout():
     assert stride == 3 and arena.shape == (6, 3)
     assert np.array_equal(arena[:3, :2], a) and np.all(arena[:3, 2] == 0.0) and np.array_equal(arena[3:], b)
     assert (items[1].offset, items[1].n, items[1].d, items[1].min_pts) == (3, 3, 3, 2)
+
+
+def test_tuning_cache_parsing(lib, tmp_path):
+    """The tuning cache loader (host only): a valid file loads, a malformed
+    or out-of-range line is rejected and leaves the table unchanged, a
+    missing file is ENOENT, NULL clears the table."""
+    good = tmp_path / "tune.jsonl"
+    good.write_text('# tuner output\n'
+                    '{"kind": "emst", "d": 3, "nlog2": 25, "bccp_chunk": 1024, "small_level_switch": 1024, '
+                    '"small_level_max": 2048, "beta_growth": 3.0, "ms": 170.2}\n'
+                    '\n'
+                    '{"kind": "hdbscan", "d": 5, "nlog2": 21, "refresh_divisor": 512, "beta_start_quantile": 0.0}\n')
+    assert lib.geomst_load_tuning(str(good).encode()) == G.OK
+    for bad in ['{"kind": "emst", "d": 3}',                                        # no nlog2
+                '{"kind": "kmeans", "d": 3, "nlog2": 10}',                         # bad kind
+                '{"kind": "emst", "d": 3, "nlog2": 10, "bccp_chunk": 100}',        # not a multiple of 64
+                '{"kind": "emst", "d": 9, "nlog2": 10}',                           # d out of range
+                '{"kind": "emst", "d": 3, "nlog2": 10, "beta_growth": 1.0}',       # growth must exceed 1
+                '"kind": "emst"']:                                                 # not an object
+        p = tmp_path / "bad.jsonl"
+        p.write_text(bad + "\n")
+        assert lib.geomst_load_tuning(str(p).encode()) == G.EINVAL, bad
+        assert "line 1" in G.last_error()
+    assert lib.geomst_load_tuning(str(tmp_path / "missing.jsonl").encode()) == G.ENOENT
+    assert lib.geomst_load_tuning(None) == G.OK

@@ -105,6 +105,39 @@ def test_batch_host_api(G):
         assert np.array_equal(e, eo) and same(w, wo)
 
 
+def test_tuning_cache_keeps_bytes(G, tmp_path):
+    """A tuning cache with unusual knob values (small BCCP tiles, small level
+    buckets, fast threshold growth) applies to matching solves and changes
+    no byte of any result."""
+    inst = mixed_instances(5, 60, 4000)
+    mps = [0] * len(inst)
+    ref = run_batch(G, inst, mps)
+    stride = max(x.shape[1] for x in inst)
+    N = sum(len(x) for x in inst)
+    nl = int(np.floor(np.log2(N)))
+    p = W.mixture(20000, 3, seed=91, k=5, noise_frac=0.02)
+    e0, w0 = G.emst(p)
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text(
+        f'{{"kind": "emst", "d": {stride}, "nlog2": {nl}, "bccp_chunk": 64, "small_level_switch": 512, '
+        f'"small_level_max": 1024, "beta_growth": 4.0}}\n'
+        '{"kind": "emst", "d": 3, "nlog2": 14, "bccp_chunk": 128, "small_level_switch": 256, '
+        '"small_level_max": 512, "beta_growth": 1.5, "refresh_divisor": 64}\n')
+    try:
+        G.load_tuning(str(cache))
+        got = run_batch(G, inst, mps)
+        assert G.stats().tuning_applied == 1
+        e1, w1 = G.emst(p)
+        assert G.stats().tuning_applied == 1
+    finally:
+        G.load_tuning(None)
+    for a, b in zip(ref, got):
+        assert all(same(a[k], b[k]) for k in a)
+    assert same(e0, e1) and same(w0, w1)
+    G.emst(p)
+    assert G.stats().tuning_applied == 0
+
+
 def test_batch_all_single_points(G):
     inst = [np.array([[float(i), 0.0]]) for i in range(7)]
     res = run_batch(G, inst, [0] * 7)
