@@ -70,8 +70,10 @@ def unit_model(fam, st, d, hdb=False):
     bound).  Bytes are the data the method itself must move, flops the
     arithmetic it must do; neither counts re-reads or bookkeeping."""
     if fam == "bccp":
-        # large-pair BCCP: (3d-1) flops per distance (d sub, d mul, d-1 add),
+        # small-pair BCCP: (3d-1) flops per distance (d sub, d mul, d-1 add),
         # two more for the BCCP* maxima
+        return (st.bccp_evals_done - st.big_evals) * (3 * d - 1 + (2 if hdb else 0)), "TFLOP/s", "alu"
+    if fam == "bccp_large":
         return st.big_evals * (3 * d - 1 + (2 if hdb else 0)), "TFLOP/s", "alu"
     if fam == "expand":
         # per examined node pair: its 16-byte record and the two nodes' box
@@ -87,7 +89,8 @@ def unit_model(fam, st, d, hdb=False):
     return None, None, None
 
 
-FAMILY_KERNEL = {"expand": "k_level", "bccp": "k_big_bccp", "sort": "k_radix", "kruskal": "k_bor"}
+FAMILY_KERNEL = {"expand": "k_level", "bccp": "k_tiny_bccp", "bccp_large": "k_big_bccp", "sort": "k_radix",
+                 "kruskal": "k_bor"}
 # the library's "expand" timing brackets k_level and k_level_small launches
 
 
@@ -320,21 +323,26 @@ def median(v):
 
 
 def bccp_fraction(st, d, hdb):
-    """BCCP distance evaluations of one solve (all BCCP kernels: small pairs,
-    wave-per-pair and tiled large pairs, pruned blocks excluded) over the
-    BCCP family's device time, as FP64 flops against the vector peak."""
-    ms = st.kernel_ms[5]
+    """BCCP distance evaluations of one solve (pruned blocks excluded) over
+    the device time of the BCCP kernels, as FP64 flops against the vector
+    peak: all BCCP kernels together, the small-pair kernel (up to 16 point
+    pairs, one pair per thread) and the medium/large-pair kernels apart."""
+    ms_s, ms_l = st.kernel_ms[5], st.kernel_ms[10]
     flops = 3 * d - 1 + (2 if hdb else 0)
-    if ms <= 0:
+    if ms_s + ms_l <= 0:
         return None
-    evals_s = st.bccp_evals_done / (ms / 1000.0)
-    tf = evals_s * flops / 1e12
-    big = st.big_evals * flops / 1e12 / (ms / 1000.0)
-    return {"bccp_evals": st.bccp_evals_done, "bccp_device_ms": round(ms, 4),
-            "bccp_evals_per_s": round(evals_s, 1), "flops_per_eval": flops,
-            "bccp_tflops": round(tf, 4), "bccp_frac_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 5),
-            "large_pair_evals": st.big_evals, "large_pair_share_of_evals": round(st.big_evals / max(1, st.bccp_evals_done), 4),
-            "large_pair_tflops_over_family_time": round(big, 4)}
+
+    def part(evals, ms):
+        if ms <= 0:
+            return {"evals": evals, "device_ms": 0.0}
+        eps = evals / (ms / 1000.0)
+        return {"evals": evals, "device_ms": round(ms, 4), "evals_per_s": round(eps, 1),
+                "tflops": round(eps * flops / 1e12, 4), "frac_fp64_peak": round(eps * flops / 1e12 / FP64_PEAK_TFLOPS, 5)}
+    allp = part(st.bccp_evals_done, ms_s + ms_l)
+    return {"flops_per_eval": flops, "all": allp,
+            "small_pairs": part(st.bccp_evals_done - st.big_evals, ms_s),
+            "large_pairs": part(st.big_evals, ms_l),
+            "bccp_evals_per_s": allp.get("evals_per_s"), "bccp_frac_fp64_peak": allp.get("frac_fp64_peak")}
 
 
 def extra_plain(G, torch, np, name, steps, warmup, dendrogram=False, variants=False):
@@ -660,7 +668,7 @@ def main():
         kl += np.array(st.kernel_launches)
         if agg is None:
             agg = {k: 0 for k in ("pair_visits", "bccp_evals", "big_evals", "sort_elems", "committed_edges",
-                                  "bccp_pairs", "rounds")}
+                                  "bccp_pairs", "rounds", "bccp_evals_done")}
         for k in agg:
             agg[k] += getattr(st, k)
     torch.cuda.synchronize()
@@ -679,7 +687,7 @@ def main():
     per_fam = {fams[i]: round(float(br[i]), 4) for i in range(len(fams))}
     log("device ms by kernel family (untimed breakdown solve):", per_fam)
     evals_per_s = agg["bccp_evals"] / dt
-    big_ms = br[fams.index("bccp")]
+    big_ms = br[fams.index("bccp_large")]
     flops_per_eval = 3 * d - 1 + (2 if mp else 0)
     bccp_tflops = (st0.big_evals * flops_per_eval / (big_ms / 1000.0) / 1e12) if big_ms > 0 else 0.0
     # dominant kernel family and its roofline, from the timed steps
@@ -720,6 +728,7 @@ def main():
         "bccp_evals_per_s": round(evals_per_s, 1),
         "bccp_large_pair_tflops": round(bccp_tflops, 4),
         "bccp_large_pair_frac_fp64_peak": round(bccp_tflops / FP64_PEAK_TFLOPS, 5),
+        "bccp": bccp_fraction(st0, d, bool(mp)),
         "roofline": roof,
         "kernel_ms_breakdown": per_fam,
         "counts_per_step": {k: v // a.steps for k, v in agg.items()},

@@ -292,12 +292,13 @@ enum {
     GEOMST_K_CORE = 2,     /* k-NN core distances */
     GEOMST_K_SPLIT = 3,    /* frontier and pool splits */
     GEOMST_K_EXPAND = 4,   /* pair expansion (FindPair) with inline small BCCPs */
-    GEOMST_K_BCCP = 5,     /* large-pair BCCP tiles and their combine */
+    GEOMST_K_BCCP = 5,     /* small-pair BCCP (up to 16 point pairs, one pair per thread) */
     GEOMST_K_KRUSKAL = 6,  /* Boruvka pick / hook / reset */
     GEOMST_K_REFRESH = 7,  /* union-find compression and node components */
     GEOMST_K_OUTPUT = 8,   /* output writes */
     GEOMST_K_DENDRO = 9,   /* dendrogram and reachability plot */
-    GEOMST_K_COUNT = 10
+    GEOMST_K_BCCP_LARGE = 10, /* medium and large pairs: block boxes, tasks, tiles and their combine */
+    GEOMST_K_COUNT = 11
 };
 
 /* Counters and timings of the last solve made by the calling thread. */

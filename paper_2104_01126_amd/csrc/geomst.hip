@@ -314,6 +314,7 @@ struct Device {
     size_t capF[2] = {0, 0}, capQ[2] = {0, 0}, capBig = 0, capTiny = 0;
     DBuf tiny;  // small separated pairs of the current round
     DBuf rq[2], rho, rhocnt;  // GetRho traversal of the cardinality schedules
+    DBuf bb64;                // boxes of the aligned 64-point blocks (large-pair BCCP pruning)
     DBuf FF[2];  // far frontier (see the round loop)
     size_t capFF[2] = {0, 0};
     EdgeBufs C, P[2], OUT;
@@ -922,6 +923,14 @@ struct Solver {
         }
         auto t2 = clk::now();
 
+        // boxes of the aligned 64-point blocks for the large-pair BCCP
+        {
+            TIMED(GEOMST_K_BCCP_LARGE);
+            const u32 nb64 = (u32)((n + 63) / 64);
+            D.bb64.ensure((size_t)nb64 * (2 * D_ + 1) * 8);
+            k_block_boxes<D_><<<blocks(nb64, kBlock), kBlock, 0, s>>>(t, hdb, D.bb64.as<double>());
+            LAUNCHCHK();
+        }
         // union-find and node components
         D.nrange.ensure((size_t)(2 * n - 1) * 8);
         // compact label copy; a value no label takes, so the first refresh
@@ -1198,16 +1207,18 @@ struct Solver {
                         D.ubest.ensure((size_t)nbig * 8);
                         D.tdone.ensure((size_t)ntasks * 4);
                         {
-                            TIMED(GEOMST_K_BCCP);
+                            TIMED(GEOMST_K_BCCP_LARGE);
                             HIPCHK(hipMemsetAsync(D.ubest.p, 0xff, (size_t)nbig * 8, s));  // no weight yet
                             if (hdb)
                                 k_big_bccp<D_, 1><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
                                                                        D.parts.as<PartKey>(), D.cnt.as<Counters>(),
-                                                                       o.bccp_chunk, D.ubest.as<u64>(), D.tdone.as<u32>());
+                                                                       o.bccp_chunk, D.ubest.as<u64>(), D.tdone.as<u32>(),
+                                                                       D.bb64.as<double>());
                             else
                                 k_big_bccp<D_, 0><<<ntasks, 64, 0, s>>>(t, D.big.as<uint2>(), nbig, D.toff.as<u32>(),
                                                                        D.parts.as<PartKey>(), D.cnt.as<Counters>(),
-                                                                       o.bccp_chunk, D.ubest.as<u64>(), D.tdone.as<u32>());
+                                                                       o.bccp_chunk, D.ubest.as<u64>(), D.tdone.as<u32>(),
+                                                                       D.bb64.as<double>());
                             LAUNCHCHK();
                             // the per-pair best weights are dead after k_big_bccp: the
                             // same array then holds each pair's evaluation count

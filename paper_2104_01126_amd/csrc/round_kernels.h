@@ -1017,6 +1017,7 @@ constexpr int kBigAPL = 4;
 constexpr int kBigA = 64 * kBigAPL;
 constexpr int kBigBDefault = 2048;
 constexpr int kMidMax = 4096;  // pairs up to this many point pairs: one wave, flattened products
+constexpr int kThinA = 4096;   // thin pairs (smaller side <= 64 points): A points per task
 
 struct PartKey {
     double w2, e2;
@@ -1048,7 +1049,9 @@ __global__ void __launch_bounds__(kBlock) k_big_ntasks(TreeView t, const uint2* 
         int2 ra, rb;
         big_orient<D>(t, big[i], ra, rb);
         work = (u64)ra.y * (u64)rb.y;
-        c = work <= (u64)kMidMax ? 1ull : (u64)((ra.y + kBigA - 1) / kBigA) * (u64)((rb.y + bchunk - 1) / bchunk);
+        c = work <= (u64)kMidMax ? 1ull
+            : rb.y <= 64         ? (u64)((ra.y + kThinA - 1) / kThinA)
+                                 : (u64)((ra.y + kBigA - 1) / kBigA) * (u64)((rb.y + bchunk - 1) / bchunk);
         ntask[i] = c < (1ull << 31) ? (u32)c : 1u;
     }
     const unsigned long long sc = block_sum_u64(c, sh);
@@ -1058,6 +1061,43 @@ __global__ void __launch_bounds__(kBlock) k_big_ntasks(TreeView t, const uint2* 
         atomicAdd(&cnt->c64[C64_EVALS], sw);
         atomicAdd(&cnt->c64[C64_BIGWORK], sw);
     }
+}
+
+// Box of every aligned 64-point block of sorted positions [64 i, 64 i + 64):
+// bb[i * (2D + 1) + k] = min coordinate k, [.. + D + k] = max, [.. + 2D] =
+// smallest squared core distance (0 for EMST).  Computed once per solve; a
+// large-pair task bounds a B block by the boxes of the (at most two) aligned
+// blocks that cover it, so a block it skips costs two box reads and no point
+// loads.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_block_boxes(TreeView t, int hdb, double* bb) {
+    const u32 b = blockIdx.x * blockDim.x + threadIdx.x;
+    const u32 nb = (u32)((t.n + 63) / 64);
+    if (b >= nb) return;
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    double lo[D], hi[D], cm = inf;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        lo[k] = inf;
+        hi[k] = -inf;
+    }
+    const u32 j0 = b * 64, j1 = min(j0 + 64, (u32)t.n);
+    for (u32 j = j0; j < j1; ++j) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double x = t.X[(size_t)j * D + k];
+            lo[k] = fmin(lo[k], x);
+            hi[k] = fmax(hi[k], x);
+        }
+        if (hdb) cm = fmin(cm, t.cd2[j]);
+    }
+    double* o = bb + (size_t)b * (2 * D + 1);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        o[k] = lo[k];
+        o[D + k] = hi[k];
+    }
+    o[2 * D] = hdb ? cm : 0.0;
 }
 
 // Pruning: a 64-point B block is skipped when the bound between the task's
@@ -1071,9 +1111,10 @@ __global__ void __launch_bounds__(kBlock) k_big_ntasks(TreeView t, const uint2* 
 template <int D, int HDB>
 __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u32 nbig, const u32* toff,
                                                   PartKey* part, Counters* cnt, int bchunk, u64* ubest,
-                                                  u32* tdone) {
+                                                  u32* tdone, const double* bb) {
     __shared__ double sbuf[2][64 * D];
     __shared__ double scd[2][64];
+    __shared__ u32 sorig[64];
     const int lane = lane_id();
     const u32 task = blockIdx.x;
     // pair owning this task: last i with toff[i] <= task
@@ -1086,15 +1127,52 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
     int2 ra, rb;
     big_orient<D>(t, big[lo], ra, rb);
     if ((u64)ra.y * (u64)rb.y <= (u64)kMidMax) {
-        // medium pair: the lanes stride over the flattened A x B products
-        // with the exact key compare
+        // medium pair: |B|^2 <= |A||B| <= kMidMax, so B (the smaller node)
+        // fits one 64-row LDS tile.  Each lane takes A points in turn and
+        // runs over the staged B rows comparing (w2, e2); the ids are read
+        // (from the staged copy) only to break an exact tie of both.
         const u32 nb = (u32)rb.y, tot = (u32)ra.y * nb;
+        if (lane < (int)nb) {
+            const u32 j = (u32)rb.x + (u32)lane;
+#pragma unroll
+            for (int k = 0; k < D; ++k) sbuf[0][lane * D + k] = t.X[(size_t)j * D + k];
+            scd[0][lane] = HDB ? t.cd2[j] : 0.0;
+            sorig[lane] = t.orig[j];
+        }
+        __syncthreads();
         EdgeOut best;
         best.k = key_none();
         best.i = best.j = kNone;
-        for (u32 idx = (u32)lane; idx < tot; idx += kWave) {
-            u32 ia = idx / nb;
-            EdgeOut c = point_edge<D>(t, HDB, (u32)ra.x + ia, (u32)rb.x + (idx - ia * nb));
+        for (u32 ia = (u32)lane; ia < (u32)ra.y; ia += kWave) {
+            const u32 i = (u32)ra.x + ia;
+            double a[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) a[k] = t.X[(size_t)i * D + k];
+            const double cda = HDB ? t.cd2[i] : 0.0;
+            const u32 oa = t.orig[i];
+            double bw = __longlong_as_double(0x7ff0000000000000ll), be = bw;
+            u32 bj = 0;
+            for (u32 jb = 0; jb < nb; ++jb) {
+                double e2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double x = a[k] - sbuf[0][jb * D + k];
+                    e2 = e2 + x * x;
+                }
+                const double w2 = HDB ? fmax(fmax(cda, scd[0][jb]), e2) : e2;
+                bool better = w2 < bw || (w2 == bw && e2 < be);
+                if (w2 == bw && e2 == be) {
+                    const u32 ob = sorig[jb], oc = sorig[bj];
+                    const u32 lo1 = min(oa, ob), hi1 = max(oa, ob), lo0 = min(oa, oc), hi0 = max(oa, oc);
+                    better = lo1 < lo0 || (lo1 == lo0 && hi1 < hi0);
+                }
+                if (better) {
+                    bw = w2;
+                    be = e2;
+                    bj = jb;
+                }
+            }
+            EdgeOut c = point_edge<D>(t, HDB, i, (u32)rb.x + bj);
             if (key_less(c.k, best.k)) best = c;
         }
 #pragma unroll
@@ -1116,6 +1194,201 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
             pk.pos = ((u64)best.i << 32) | best.j;
             part[task] = pk;
             tdone[task] = tot;
+        }
+        return;
+    }
+    if (rb.y <= 64) {
+        // Thin pair: B (at most 64 points) staged in LDS with its ids, the
+        // task's A range (up to kThinA points) streamed in aligned 64-point
+        // blocks, one A point per lane against every B row.  The block whose
+        // box is nearest to B's box is evaluated first; every other block is
+        // skipped when its bound (from the precomputed block boxes) exceeds
+        // the best weight of this task or of the pair (shared through ubest).
+        const double inf = __longlong_as_double(0x7ff0000000000000ll);
+        const u32 nb = (u32)rb.y;
+        const int a0 = ra.x + (int)(task - toff[lo]) * kThinA, a1 = min(a0 + kThinA, ra.x + ra.y);
+        double blo[D], bhi[D], bcm = inf;
+        if (lane < (int)nb) {
+            const u32 j = (u32)rb.x + (u32)lane;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double x = t.X[(size_t)j * D + k];
+                sbuf[0][lane * D + k] = x;
+                blo[k] = x;
+                bhi[k] = x;
+            }
+            const double c = HDB ? t.cd2[j] : 0.0;
+            scd[0][lane] = c;
+            bcm = c;
+            sorig[lane] = t.orig[j];
+        } else {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                blo[k] = inf;
+                bhi[k] = -inf;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            blo[k] = wave_uniform_f64(wave_min_f64(blo[k]));
+            bhi[k] = wave_uniform_f64(-wave_min_f64(-bhi[k]));
+        }
+        if (HDB) bcm = wave_uniform_f64(wave_min_f64(bcm));
+        __syncthreads();
+        auto thin_bound = [&](u32 bi) -> double {
+            const double* o = bb + (size_t)bi * (2 * D + 1);
+            double g2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double g = fmax(fmax(o[k] - bhi[k], blo[k] - o[D + k]), 0.0);
+                g2 = g2 + g * g;
+            }
+            if (HDB) g2 = fmax(g2, fmax(bcm, o[2 * D]));
+            return g2;
+        };
+        EdgeOut best;
+        best.k = key_none();
+        best.i = best.j = kNone;
+        u32 done = 0;
+        // one 64-point block: lane l takes A point 64 bi + l (inside [a0, a1))
+        auto eval_point = [&](int i, const double (&a)[D], double cda, u32 oa) -> double {
+            double bw = inf, be = inf;
+            u32 bj = 0;
+            for (u32 jb = 0; jb < nb; ++jb) {
+                double e2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double x = a[k] - sbuf[0][jb * D + k];
+                    e2 = e2 + x * x;
+                }
+                const double w2 = HDB ? fmax(fmax(cda, scd[0][jb]), e2) : e2;
+                bool better = w2 < bw || (w2 == bw && e2 < be);
+                if (w2 == bw && e2 == be) {
+                    const u32 ob = sorig[jb], oc = sorig[bj];
+                    const u32 lo1 = min(oa, ob), hi1 = max(oa, ob), lo0 = min(oa, oc), hi0 = max(oa, oc);
+                    better = lo1 < lo0 || (lo1 == lo0 && hi1 < hi0);
+                }
+                if (better) {
+                    bw = w2;
+                    be = e2;
+                    bj = jb;
+                }
+            }
+            // the point's best key, from the values just computed (the same
+            // operations as point_edge)
+            EdgeOut c;
+            const u32 ob = sorig[bj];
+            c.k.w2 = bw;
+            c.k.e2 = be;
+            c.k.lo = min(oa, ob);
+            c.k.hi = max(oa, ob);
+            c.i = (u32)i;
+            c.j = (u32)rb.x + bj;
+            if (key_less(c.k, best.k)) best = c;
+            return bw;
+        };
+        // up to four blocks at once: every lane issues its four A-point loads
+        // before any distance, so the load latencies overlap
+        auto eval_blocks = [&](const u32 (&bis)[4], int nbk) -> double {
+            double a[4][D], cda[4];
+            u32 oa[4];
+            bool in[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = (int)(bis[q] * 64u) + lane;
+                in[q] = q < nbk && i >= a0 && i < a1;
+                const int ic = in[q] ? i : a0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) a[q][k] = t.X[(size_t)ic * D + k];
+                cda[q] = HDB ? t.cd2[ic] : 0.0;
+                oa[q] = t.orig[ic];
+            }
+            double wl = inf;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (in[q]) wl = fmin(wl, eval_point((int)(bis[q] * 64u) + lane, a[q], cda[q], oa[q]));
+                if (q < nbk) done += (u32)(min(a1, (int)(bis[q] * 64u) + 64) - max(a0, (int)(bis[q] * 64u))) * nb;
+            }
+            return wave_uniform_f64(wave_min_f64(wl));
+        };
+        // A task covers at most kThinA / 64 + 1 = 65 aligned blocks: lane l
+        // holds the bounds of blocks ib0 + l and ib0 + 64 + l in registers
+        static_assert(kThinA <= 64 * 64, "two blocks per lane");
+        const u32 ib0 = (u32)a0 >> 6, ib1 = (u32)(a1 - 1) >> 6;
+        const u32 bl0 = ib0 + (u32)lane, bl1 = ib0 + 64u + (u32)lane;
+        const double g0 = bl0 <= ib1 ? thin_bound(bl0) : inf, g1 = bl1 <= ib1 ? thin_bound(bl1) : inf;
+        // nearest block first (smallest bound; ties to the lower block)
+        double lbm = g0;
+        u32 lbi = bl0;
+        if (g1 < lbm) {
+            lbm = g1;
+            lbi = bl1;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double g = __shfl_xor(lbm, o);
+            const u32 b2 = __shfl_xor(lbi, o);
+            if (g < lbm || (g == lbm && b2 < lbi)) {
+                lbm = g;
+                lbi = b2;
+            }
+        }
+        const u32 first_bi = (u32)__builtin_amdgcn_readfirstlane((int)lbi);
+        const u32 fb[4] = {first_bi, first_bi, first_bi, first_bi};
+        double mt = eval_blocks(fb, 1);
+        u64 ub = ubest[lo];
+        if (dbits(mt) < ub && lane == 0) atomicMin((unsigned long long*)&ubest[lo], (unsigned long long)dbits(mt));
+        // then the blocks still within the best weight, in order; the masks
+        // are re-taken against the best after every block
+        u64 left0 = __ballot(bl0 <= ib1 && bl0 != first_bi), left1 = __ballot(bl1 <= ib1 && bl1 != first_bi);
+        while (true) {
+            const double lim = fmin(mt, __longlong_as_double((long long)ub));
+            left0 &= __ballot(!(g0 > lim));
+            left1 &= __ballot(!(g1 > lim));
+            if (!left0 && !left1) break;
+            u32 bis[4] = {0, 0, 0, 0};
+            int nbk = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (left0) {
+                    const int l = __ffsll((long long)left0) - 1;
+                    left0 &= left0 - 1;
+                    bis[q] = ib0 + (u32)l;
+                    ++nbk;
+                } else if (left1) {
+                    const int l = __ffsll((long long)left1) - 1;
+                    left1 &= left1 - 1;
+                    bis[q] = ib0 + 64u + (u32)l;
+                    ++nbk;
+                }
+            }
+            const double w = eval_blocks(bis, nbk);
+            if (w < mt) {
+                mt = w;
+                if (dbits(mt) < ub && lane == 0)
+                    atomicMin((unsigned long long*)&ubest[lo], (unsigned long long)dbits(mt));
+            }
+            ub = ubest[lo];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            EdgeOut w;
+            w.k.w2 = __shfl_xor(best.k.w2, o);
+            w.k.e2 = __shfl_xor(best.k.e2, o);
+            w.k.lo = __shfl_xor(best.k.lo, o);
+            w.k.hi = __shfl_xor(best.k.hi, o);
+            w.i = __shfl_xor(best.i, o);
+            w.j = __shfl_xor(best.j, o);
+            if (key_less(w.k, best.k)) best = w;
+        }
+        if (lane == 0) {
+            PartKey pk;
+            pk.w2 = best.k.w2;
+            pk.e2 = best.k.e2;
+            pk.ids = ((u64)best.k.lo << 32) | best.k.hi;
+            pk.pos = ((u64)best.i << 32) | best.j;
+            part[task] = pk;
+            tdone[task] = done;
         }
         return;
     }
@@ -1169,37 +1442,38 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
         }
         if (HDB) acm = wave_uniform_f64(wave_min_f64(acm));
     }
-    // stage the first block
-    double bx[D] = {}, bcd = inf;
-    const bool h0 = lane < jb1 - jb0;
-    if (h0) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            bx[k] = t.X[(size_t)(jb0 + lane) * D + k];
-            sbuf[0][lane * D + k] = bx[k];
-        }
-        if (HDB) {
-            bcd = t.cd2[jb0 + lane];
-            scd[0][lane] = bcd;
-        }
-    }
-    u64 ub = ubest[lo];
-    // every load above has landed: keeps the compiler from placing waits for
-    // them inside the inner loop, where they would also wait for the prefetch
-    __builtin_amdgcn_s_waitcnt(0);
-    // bound between the A box and the staged block
-    auto block_bound = [&](const double (&x)[D], bool have, double cdb) -> double {
+    // bound between the A box and the B block [js, js + cnt): the smaller
+    // of the bounds to the aligned blocks covering it (a bound to a union is
+    // the smaller bound); every lane computes the same value from the same
+    // box words
+    auto box_bound = [&](u32 bi) -> double {
+        const double* o = bb + (size_t)bi * (2 * D + 1);
         double g2 = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const double lo_b = wave_min_f64(have ? x[k] : inf), hi_b = -wave_min_f64(have ? -x[k] : inf);
-            const double g = fmax(fmax(lo_b - ahi[k], alo[k] - hi_b), 0.0);
+            const double g = fmax(fmax(o[k] - ahi[k], alo[k] - o[D + k]), 0.0);
             g2 = g2 + g * g;
         }
-        if (HDB) g2 = fmax(g2, fmax(acm, wave_min_f64(have ? cdb : inf)));
-        return wave_uniform_f64(g2);
+        if (HDB) g2 = fmax(g2, fmax(acm, o[2 * D]));
+        return g2;
     };
-    double blb = multi ? block_bound(bx, h0, bcd) : 0.0;
+    auto block_bound = [&](int js, int cnt) -> double {
+        const u32 b0 = (u32)js >> 6, b1 = (u32)(js + cnt - 1) >> 6;
+        const double x = box_bound(b0);
+        return b1 != b0 ? fmin(x, box_bound(b1)) : x;
+    };
+    u64 ub = ubest[lo];
+    double blb = multi ? block_bound(jb0, min(64, jb1 - jb0)) : 0.0;
+    // stage the first block unless it is already known to be pruned
+    const bool h0 = lane < jb1 - jb0 && !(blb > __longlong_as_double((long long)ub));
+    if (h0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) sbuf[0][lane * D + k] = t.X[(size_t)(jb0 + lane) * D + k];
+        if (HDB) scd[0][lane] = t.cd2[jb0 + lane];
+    }
+    // every load above has landed: keeps the compiler from placing waits for
+    // them inside the inner loop, where they would also wait for the prefetch
+    __builtin_amdgcn_s_waitcnt(0);
     double mt = inf;  // this task's best weight so far
     const u32 na_task = (u32)min(kBigA, aend - abase);
     u32 done = 0;     // distances evaluated
@@ -1207,9 +1481,12 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
     int buf = 0;
     for (int js = jb0; js < jb1; js += 64, buf ^= 1) {
         const int cntb = min(64, jb1 - js);
-        // prefetch the next block (and the pair's best weight) into registers
+        // prefetch the next block (and the pair's best weight) into
+        // registers, unless its bound already exceeds the best weight known
+        // (the best only decreases, so it would be skipped anyway)
         const int jn = js + 64;
-        const bool hn = jn < jb1 && lane < jb1 - jn;
+        const double nblb = (multi && jn < jb1) ? block_bound(jn, min(64, jb1 - jn)) : 0.0;
+        const bool hn = jn < jb1 && lane < jb1 - jn && !(nblb > fmin(mt, __longlong_as_double((long long)ub)));
         double nx[D] = {}, ncd = inf;
         if (hn) {
 #pragma unroll
@@ -1280,7 +1557,7 @@ __global__ void __launch_bounds__(64) k_big_bccp(TreeView t, const uint2* big, u
             for (int k = 0; k < D; ++k) sbuf[buf ^ 1][lane * D + k] = nx[k];
             if (HDB) scd[buf ^ 1][lane] = ncd;
         }
-        if (jn < jb1) blb = block_bound(nx, hn, ncd);
+        blb = nblb;
         ub = ubn;
         __syncthreads();
     }

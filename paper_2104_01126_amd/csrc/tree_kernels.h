@@ -547,7 +547,13 @@ __global__ void __launch_bounds__(kBoundsTop) k_bounds_top(int n, const int* par
 // per-lane k smallest values are kept sorted in registers.
 constexpr int kKnnLeaf = 32;
 constexpr int kKnnSeed = 32;  // sorted neighbours on each side of a wave's queries scanned first
-constexpr int kKnnStack = 192;
+// The walk's stack holds at most (tree depth + 1) nodes: each pop pushes at
+// most two children.  A root-to-leaf path of the radix tree splits on a
+// distinct bit of (key words, position) at every node, so the depth is at
+// most 6 * 63 key bits + 26 position bits = 404 and 512 entries never
+// overflow (the check below stays as a guard).  LDS per wave: 2 KB stack +
+// (64 + 2 * 32) staged rows of 8d bytes.
+constexpr int kKnnStack = 512;
 
 template <int KMAX>
 __device__ __forceinline__ void topk_insert(double (&top)[KMAX], double v) {

@@ -176,7 +176,8 @@ class Stats:
 
 
 # kernel families (GEOMST_K_* in include/geomst.h)
-KERNEL_FAMILIES = ["tree", "sort", "core", "split", "expand", "bccp", "kruskal", "refresh", "output", "dendro"]
+KERNEL_FAMILIES = ["tree", "sort", "core", "split", "expand", "bccp", "kruskal", "refresh", "output", "dendro",
+                   "bccp_large"]
 
 
 def stats() -> Stats:

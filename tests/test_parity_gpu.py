@@ -170,6 +170,23 @@ def test_edge_sort_paths(G, case):
         check_hdb_exact(G, p, 4, case)
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_deep_tree_exponential_spacing(G, d):
+    """Points whose first coordinate is 2^i (i < 340): every refinement word of
+    the Morton keys resolves only a few of them, so the radix tree is a deep
+    chain (deeper than 192 nodes); the k-NN walk and the decomposition must
+    still give the checker's trees."""
+    rng = np.random.default_rng(50 + d)
+    i = rng.permutation(340)
+    p = np.zeros((340, d))
+    p[:, 0] = np.ldexp(1.0, i)
+    if d > 1:
+        p[:, 1:] = rng.random((340, d - 1))
+    for mp in (3, 10):
+        check_hdb_exact(G, p, mp, f"exponential d={d} mp={mp}")
+    check_emst_exact(G, p, f"exponential d={d}")
+
+
 @pytest.mark.parametrize("mp", [1, 2, 3, 5, 10, 16, 33, 64])
 def test_hdbscan_minpts(G, mp):
     p = W.mixture(4000 + 11, 3, seed=mp, k=10, sig_lo=0.003, sig_hi=0.05, noise_frac=0.1)
