@@ -599,6 +599,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="length of the replayed prefix of the 60 s request stream (serving)")
+    ap.add_argument("--with-dendrogram", action="store_true",
+                    help="single workloads: also time the ordered dendrogram of the solved tree (3 calls)")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline workload only (no c0/c2/c3/c4 sub-records)")
     ap.add_argument("--serve-workers", type=int, default=0, help="server workers (0: the library default)")
@@ -733,6 +735,21 @@ def main():
         "kernel_ms_breakdown": per_fam,
         "counts_per_step": {k: v // a.steps for k, v in agg.items()},
     }
+    if a.with_dendrogram:
+        if mp:
+            cd_, e_, w_ = G.hdbscan(x, mp)
+        else:
+            e_, w_ = G.emst(x)
+        G.dendrogram(e_, w_, 0)
+        torch.cuda.synchronize()
+        dts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            G.dendrogram(e_, w_, 0)
+            torch.cuda.synchronize()
+            dts.append((time.perf_counter() - t) * 1000.0)
+        out["dendrogram_median_ms"] = round(median(dts), 3)
+        log(f"dendrogram: median {median(dts):.2f} ms")
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.workload, pts, mp)
     if a.workload == "emst_1m" and not a.no_extras:

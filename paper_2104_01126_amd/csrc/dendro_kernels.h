@@ -176,15 +176,51 @@ __global__ void k_dg_level_union(const u32* lab, u32 m, int j, u32* P) {
 
 // Per light component: its heaviest edge (the new cluster's root) and its
 // point count (each member cluster's count added once, by the first lane to
-// claim its name).
+// claim its name).  In the first levels a block's light half forms a few
+// huge components, and one atomic per edge on their roots would serialise:
+// lanes whose root equals the first remaining lane's root combine their
+// values in the wave first (two such rounds), the others update directly.
+__device__ __forceinline__ u32 wave_max_u32(u32 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (u32)__shfl_xor((int)v, o));
+    return v;
+}
+__device__ __forceinline__ u32 wave_sum_u32(u32 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += (u32)__shfl_xor((int)v, o);
+    return v;
+}
+
 __global__ void k_dg_level_info(const u32* lab, const u32* sz, u32 m, int j, u32* P, u32* MX, u32* SZ, u32* OWN) {
     const u32 k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m || !dg_light(k, j)) return;
-    const u32 a = lab[k], b = lab[m + k];
-    const u32 r = dg_find(P, a);
-    atomicMax(&MX[r], k + 1);
-    if (atomicCAS(&OWN[a], 0u, 1u) == 0u) atomicAdd(&SZ[r], sz[k]);
-    if (atomicCAS(&OWN[b], 0u, 1u) == 0u) atomicAdd(&SZ[r], sz[m + k]);
+    const bool act = k < m && dg_light(k, j);
+    u32 r = 0, add = 0;
+    if (act) {
+        const u32 a = lab[k], b = lab[m + k];
+        r = dg_find(P, a);
+        if (atomicCAS(&OWN[a], 0u, 1u) == 0u) add += sz[k];
+        if (atomicCAS(&OWN[b], 0u, 1u) == 0u) add += sz[m + k];
+    }
+    bool mine = act;  // this lane's values are still to be applied
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+        const u64 left = __ballot(mine);
+        if (!left) break;
+        const int leader = __ffsll((long long)left) - 1;
+        const u32 rl = (u32)__shfl((int)r, leader);
+        const bool same = mine && r == rl;
+        const u32 mx = wave_max_u32(same ? k + 1 : 0u);
+        const u32 sm = wave_sum_u32(same ? add : 0u);
+        if (lane_id() == leader) {
+            atomicMax(&MX[rl], mx);
+            if (sm) atomicAdd(&SZ[rl], sm);
+        }
+        if (same) mine = false;
+    }
+    if (mine) {
+        atomicMax(&MX[r], k + 1);
+        if (add) atomicAdd(&SZ[r], add);
+    }
 }
 
 // Heavy edges of blocks that have a light half: rename each endpoint cluster
