@@ -51,8 +51,11 @@ def _load():
         lib.oracle_edge_keys.argtypes = [P, i64, i32, P, P, P, i64, P, P]
         lib.oracle_lightest_cut_edge.argtypes = [P, i64, i32, P, P, P, P, P, P]
         lib.oracle_dendrogram.argtypes = [P, P, i64, i64, P, P, P, P]
+        lib.oracle_optics_approx.argtypes = [P, i64, i32, i32, ctypes.c_double, P, P, P, P, P]
+        lib.oracle_optics_wspd.argtypes = [P, i64, i32, ctypes.c_double, P, P, i64, P]
         for f in (lib.oracle_emst, lib.oracle_hdbscan, lib.oracle_core_dist2,
-                  lib.oracle_edge_keys, lib.oracle_lightest_cut_edge, lib.oracle_dendrogram):
+                  lib.oracle_edge_keys, lib.oracle_lightest_cut_edge, lib.oracle_dendrogram,
+                  lib.oracle_optics_approx, lib.oracle_optics_wspd):
             f.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -163,3 +166,35 @@ def dendrogram(edges, weights, start: int = 0):
     _check(_load().oracle_dendrogram(_ptr(e), _ptr(w), n, int(start), _ptr(ch), _ptr(sz), _ptr(order),
                                      _ptr(reach)), "oracle_dendrogram")
     return ch, sz, order, reach
+
+
+def optics_approx(points, min_pts: int, rho: float):
+    """Approximate OPTICS MST (OPTICS-GanTaoApprox, paper Appendix) on the
+    spatial-median k-d tree of quantisation cells; readings T1-M in
+    ``oracle.c``.  -> (cd2, edges int64[n-1][2] sorted by K, w2, e2,
+    stats = (well-separated pairs, evaluated point pairs, examined pairs))."""
+    p = _pts(points)
+    n, d = p.shape
+    m = max(n - 1, 0)
+    cd2 = np.zeros(n)
+    e = np.zeros((m, 2), np.int64)
+    w2, e2 = np.zeros(m), np.zeros(m)
+    st = np.zeros(3, np.int64)
+    _check(_load().oracle_optics_approx(_ptr(p), n, d, int(min_pts), float(rho), _ptr(cd2), _ptr(e), _ptr(w2),
+                                        _ptr(e2), _ptr(st)), "oracle_optics_approx")
+    return cd2, e, w2, e2, tuple(int(x) for x in st)
+
+
+def optics_wspd(points, rho: float, cap: int = 1 << 22):
+    """The decomposition of ``optics_approx`` alone: -> (row_of_pos int64[n],
+    pairs int64[m][4] = (first A, count A, first B, count B) in tree positions)."""
+    p = _pts(points)
+    n, d = p.shape
+    row = np.zeros(n, np.int64)
+    pairs = np.zeros((cap, 4), np.int64)
+    m = ctypes.c_int64()
+    _check(_load().oracle_optics_wspd(_ptr(p), n, d, float(rho), _ptr(row), _ptr(pairs), cap, ctypes.byref(m)),
+           "oracle_optics_wspd")
+    if m.value > cap:
+        raise ValueError(f"{m.value} pairs exceed cap {cap}")
+    return row, pairs[:m.value].copy()

@@ -1,5 +1,6 @@
 /*
- * CPU checker for the Euclidean MST and the HDBSCAN* mutual-reachability MST.
+ * CPU checker for the Euclidean MST, the HDBSCAN* mutual-reachability MST and
+ * the approximate OPTICS MST.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
  * definition that the GPU library is compared against.  Only the tests, the
@@ -13,6 +14,10 @@
  *             neighbour counting p itself, the mutual reachability distance
  *             d_m(p,q) = max{cd(p), cd(q), d(p,q)}, and the MST of the
  *             complete graph weighted by d_m.
+ *   OPTICS-GanTaoApprox (paper Appendix)  the MST of the approximate base
+ *             graph built on a well-separated pair decomposition; its
+ *             readings (tree, separation, representatives, edge cases) are
+ *             stated at oracle_optics_approx below.
  *
  * Arithmetic and order (readings of a paper that fixes no precision):
  *   d2(p,q) = sum over k = 0..d-1, in that order, of (p_k - q_k)^2 in IEEE
@@ -477,5 +482,479 @@ int oracle_dendrogram(const int64_t *edges, const double *weights, int64_t n, in
 done:
     free(deg); free(adj); free(fill); free(dist); free(queue); free(par); free(top); free(cnt);
     free(heap); free(seen);
+    return rc;
+}
+
+/* ------------------------------------------------ approximate OPTICS */
+
+/*
+ * OPTICS-GanTaoApprox: the MST of Gan and Tao's approximate base graph, built
+ * on a well-separated pair decomposition (paper Appendix, "Parallel
+ * Approximate OPTICS").  Parameters minPts and rho >= 0; separation
+ * s = sqrt(8 / rho).
+ *
+ * The result depends on the spatial tree the decomposition runs on, so the
+ * tree is part of the definition here (paper Sec. 3.1.1: a spatial-median
+ * k-d tree with one point per leaf).  Readings, in the order they are used:
+ *
+ *  T1 (tree)  The spatial-median k-d tree of quantisation cells: every
+ *     point's coordinates are quantised inside the bounding box of all points
+ *     to b = min(31, floor(63 / d)) bits per dimension,
+ *         q_k = clamp(floor(((x_k - lo_k) / (hi_k - lo_k)) * (2^b - 1)), 0, 2^b - 1)
+ *     (q_k = 0 when hi_k = lo_k), and the bits are interleaved (bit b-1 of
+ *     every dimension first, dimension 0 first within a bit).  Points whose
+ *     codes are all equal form a group; a group of several points whose box
+ *     has some extent is quantised again inside its own box, giving a
+ *     further code word (single-point groups get 0), at most 6 words in all.
+ *     Points are ordered by their code words, then by input row.  A node is
+ *     a range of that order: it splits at the highest bit where the codes of
+ *     its first and last point differ (the next cell bisection that separates
+ *     its points), or, when all its codes are equal, at the highest bit where
+ *     its first and last positions differ.  Each such split halves the node's
+ *     cell along one dimension: the cell's spatial median.
+ *  T2 (boxes) A node's box is the tight box of its points; for d >= 4 each
+ *     bound is then rounded outward to binary32 (the box still holds every
+ *     point).
+ *  W1 (separation, Sec. 2.3) Nodes A and B are well separated when two balls
+ *     of the common radius r = max(rA, rB), centred at the box midpoints,
+ *     with rX half the box diagonal, are at least s r apart:
+ *         dist(cA, cB) - 2 r >= s r,  evaluated as  dc2 >= (s + 2)^2 * r2,
+ *     with dc2 = sum_k (cA_k - cB_k)^2, c_k = 0.5 * (lo_k + hi_k),
+ *     r2 = 0.25 * max(diag2(A), diag2(B)), diag2 = sum_k (hi_k - lo_k)^2,
+ *     and (s + 2)^2 formed as (s + 2) * (s + 2).
+ *  W2 (FindPair, Alg. 1) The decomposition starts from the two children of
+ *     every internal node.  A pair that is not well separated is replaced by
+ *     the two pairs (child, other) of the node with the larger diag2 (ties:
+ *     the node with more points, then A; a one-point node is never split).
+ *  R  (representatives) The paper draws the pair of representative points
+ *     at random; here the representative of a node is its first point in the
+ *     tree order, so the result is deterministic.
+ *  E  (base-graph edges of a pair, the four cases of the Appendix) with
+ *     c(X) = |X| >= minPts:
+ *         neither A nor B large: every point of A with every point of B;
+ *         A large, B not:        rep(A) with every point of B;
+ *         B large, A not:        every point of A with rep(B);
+ *         both large:            rep(A) with rep(B).
+ *     The edge weight is max{cd(u), cd(v), d(u, v) / (1 + rho)}, computed as
+ *         w2 = max(cd2(u), cd2(v), d2(u, v) / q),  q = (1 + rho) * (1 + rho).
+ *  M  (MST) As in the paper's implementation, each pair contributes the
+ *     K-lightest of its edges, K = (w2, d2, min id, max id); the output is
+ *     Kruskal's MST of these candidates under K (one candidate per pair
+ *     joins the two nodes, so the candidates span every point).
+ *
+ * Outputs: cd2[n]; the n-1 tree edges (min id, max id) sorted by K with w2
+ * and d2; stats[0] = well-separated pairs, stats[1] = point pairs whose
+ * weight was evaluated, stats[2] = pairs examined by the decomposition.
+ */
+#define AO_MAXW 6
+
+typedef struct {
+    int64_t first, count; /* range of tree positions */
+    int64_t left, right;  /* child node indices, -1 for a leaf */
+    double lo[7], hi[7];
+} ao_node_t;
+
+typedef struct {
+    const double *P;
+    int32_t d, L;
+    int64_t n;
+    uint64_t *w; /* code words, word-major: w[l * n + row] */
+} ao_sort_ctx_t;
+
+static ao_sort_ctx_t g_ao; /* qsort comparator context (one call at a time) */
+
+static int ao_bits(int32_t d) { return (63 / d) > 31 ? 31 : (63 / d); }
+
+static uint64_t ao_code(const double *x, const double *lo, const double *hi, int32_t d)
+{
+    int b = ao_bits(d);
+    double top = (double)((1ull << b) - 1);
+    uint64_t q[7];
+    for (int32_t k = 0; k < d; ++k) {
+        double r = hi[k] - lo[k];
+        double t = r > 0.0 ? (x[k] - lo[k]) / r : 0.0;
+        double f = floor(t * top);
+        f = f < 0.0 ? 0.0 : (f > top ? top : f);
+        q[k] = (uint64_t)f;
+    }
+    uint64_t c = 0;
+    for (int bit = b - 1; bit >= 0; --bit)
+        for (int32_t k = 0; k < d; ++k) c = (c << 1) | ((q[k] >> bit) & 1ull);
+    return c;
+}
+
+static int ao_row_cmp(const void *pa, const void *pb)
+{
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    for (int32_t l = 0; l < g_ao.L; ++l) {
+        uint64_t x = g_ao.w[(int64_t)l * g_ao.n + a], y = g_ao.w[(int64_t)l * g_ao.n + b];
+        if (x != y) return x < y ? -1 : 1;
+    }
+    return (a > b) - (a < b);
+}
+
+static int ao_clz64(uint64_t x) { return x ? __builtin_clzll(x) : 64; }
+static int ao_clz32(uint32_t x) { return x ? __builtin_clz(x) : 32; }
+
+/* common-prefix length of the codes at tree positions i and j (positions
+ * tell equal codes apart) */
+static int ao_plen(const uint64_t *w, int64_t n, int32_t L, const int64_t *row, int64_t i, int64_t j)
+{
+    for (int32_t l = 0; l < L; ++l) {
+        uint64_t a = w[(int64_t)l * n + row[i]], b = w[(int64_t)l * n + row[j]];
+        if (a != b) return 64 * l + ao_clz64(a ^ b);
+    }
+    return 64 * L + ao_clz32((uint32_t)(i ^ j));
+}
+
+static float ao_down(double x)
+{
+    float f = (float)x;
+    return ((double)f > x) ? nextafterf(f, -INFINITY) : f;
+}
+static float ao_up(double x)
+{
+    float f = (float)x;
+    return ((double)f < x) ? nextafterf(f, INFINITY) : f;
+}
+
+/* T1 + T2: the tree order row[0..n) and the nodes (node 0 is the root). */
+static int ao_tree(const double *P, int64_t n, int32_t d, int64_t *row, ao_node_t **nodes_out)
+{
+    uint64_t *w = (uint64_t *)calloc((size_t)AO_MAXW * (size_t)n, 8);
+    int64_t *gs = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    double *gb = (double *)malloc(sizeof(double) * 14 * (size_t)n);
+    ao_node_t *nd = (ao_node_t *)malloc(sizeof(ao_node_t) * (size_t)(2 * n));
+    int64_t *stk = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * n + 2));
+    if (!w || !gs || !gb || !nd || !stk) {
+        free(w); free(gs); free(gb); free(nd); free(stk);
+        return OR_ENOMEM;
+    }
+    double lo[7], hi[7];
+    for (int32_t k = 0; k < d; ++k) {
+        lo[k] = INFINITY;
+        hi[k] = -INFINITY;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t k = 0; k < d; ++k) {
+            double x = P[i * d + k];
+            lo[k] = x < lo[k] ? x : lo[k];
+            hi[k] = x > hi[k] ? x : hi[k];
+        }
+    for (int64_t i = 0; i < n; ++i) {
+        w[i] = ao_code(P + i * d, lo, hi, d);
+        row[i] = i;
+    }
+    int32_t L = 1;
+    g_ao.P = P;
+    g_ao.d = d;
+    g_ao.n = n;
+    g_ao.w = w;
+    g_ao.L = L;
+    qsort(row, (size_t)n, sizeof(int64_t), ao_row_cmp);
+    while (L < AO_MAXW && n > 1) {
+        /* groups of equal code words */
+        int64_t ng = 0;
+        int dup = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            int same = i > 0;
+            for (int32_t l = 0; l < L && same; ++l)
+                if (w[(int64_t)l * n + row[i]] != w[(int64_t)l * n + row[i - 1]]) same = 0;
+            if (!same) gs[ng++] = i;
+            else dup = 1;
+        }
+        gs[ng] = n;
+        if (!dup) break;
+        int refinable = 0;
+        for (int64_t g = 0; g < ng; ++g) {
+            double *b = gb + 14 * g;
+            for (int32_t k = 0; k < d; ++k) {
+                b[k] = INFINITY;
+                b[7 + k] = -INFINITY;
+            }
+            if (gs[g + 1] - gs[g] < 2) continue;
+            for (int64_t i = gs[g]; i < gs[g + 1]; ++i)
+                for (int32_t k = 0; k < d; ++k) {
+                    double x = P[row[i] * d + k];
+                    b[k] = x < b[k] ? x : b[k];
+                    b[7 + k] = x > b[7 + k] ? x : b[7 + k];
+                }
+            for (int32_t k = 0; k < d; ++k)
+                if (b[7 + k] > b[k]) refinable = 1;
+        }
+        if (!refinable) break;
+        for (int64_t g = 0; g < ng; ++g)
+            for (int64_t i = gs[g]; i < gs[g + 1]; ++i)
+                w[(int64_t)L * n + row[i]] =
+                    (gs[g + 1] - gs[g] > 1) ? ao_code(P + row[i] * d, gb + 14 * g, gb + 14 * g + 7, d) : 0;
+        ++L;
+        g_ao.L = L;
+        qsort(row, (size_t)n, sizeof(int64_t), ao_row_cmp);
+    }
+    /* radix tree over positions, top-down */
+    int64_t nn = 0, sp = 0;
+    nd[nn].first = 0;
+    nd[nn].count = n;
+    stk[sp++] = nn++;
+    while (sp) {
+        int64_t x = stk[--sp];
+        int64_t f = nd[x].first, c = nd[x].count;
+        for (int32_t k = 0; k < d; ++k) {
+            double a = INFINITY, b = -INFINITY;
+            for (int64_t i = f; i < f + c; ++i) {
+                double v = P[row[i] * d + k];
+                a = v < a ? v : a;
+                b = v > b ? v : b;
+            }
+            if (d >= 4) {
+                a = (double)ao_down(a);
+                b = (double)ao_up(b);
+            }
+            nd[x].lo[k] = a;
+            nd[x].hi[k] = b;
+        }
+        nd[x].left = nd[x].right = -1;
+        if (c == 1) continue;
+        int64_t l = f + c - 1;
+        int dl = ao_plen(w, n, L, row, f, l);
+        /* last position whose prefix with f is longer than dl */
+        int64_t a = f, b = l - 1;
+        while (a < b) {
+            int64_t m = a + (b - a + 1) / 2;
+            if (ao_plen(w, n, L, row, f, m) > dl) a = m;
+            else b = m - 1;
+        }
+        int64_t g = a;
+        nd[nn].first = f;
+        nd[nn].count = g - f + 1;
+        nd[x].left = nn;
+        stk[sp++] = nn++;
+        nd[nn].first = g + 1;
+        nd[nn].count = l - g;
+        nd[x].right = nn;
+        stk[sp++] = nn++;
+    }
+    free(w); free(gs); free(gb); free(stk);
+    *nodes_out = nd;
+    return OR_OK;
+}
+
+static double ao_diag2(const ao_node_t *A, int32_t d)
+{
+    double s = 0.0;
+    for (int32_t k = 0; k < d; ++k) {
+        double t = A->hi[k] - A->lo[k];
+        s = s + t * t;
+    }
+    return s;
+}
+
+/* W1 */
+static int ao_separated(const ao_node_t *A, const ao_node_t *B, int32_t d, double K, double dA, double dB)
+{
+    double dc2 = 0.0;
+    for (int32_t k = 0; k < d; ++k) {
+        double t = 0.5 * (A->lo[k] + A->hi[k]) - 0.5 * (B->lo[k] + B->hi[k]);
+        dc2 = dc2 + t * t;
+    }
+    double r2 = 0.25 * (dA > dB ? dA : dB);
+    return dc2 >= K * r2;
+}
+
+typedef struct {
+    key_t_ k;
+} ao_cand_t;
+
+static int ao_cand_cmp(const void *pa, const void *pb)
+{
+    const key_t_ *a = (const key_t_ *)pa, *b = (const key_t_ *)pb;
+    if (key_less(*a, *b)) return -1;
+    if (key_less(*b, *a)) return 1;
+    return 0;
+}
+
+static key_t_ ao_key(const double *P, int32_t d, const double *cd2, double q, int64_t u, int64_t v)
+{
+    key_t_ k;
+    double e2 = d2_of(P, d, u, v);
+    double c = cd2[u] > cd2[v] ? cd2[u] : cd2[v];
+    double a = e2 / q;
+    k.w2 = c > a ? c : a;
+    k.e2 = e2;
+    k.lo = u < v ? u : v;
+    k.hi = u < v ? v : u;
+    return k;
+}
+
+/* Walk the decomposition.  With pairs_out, every well-separated pair is
+ * written as (first A, count A, first B, count B) in tree positions (up to
+ * cap of them); with cand, each pair's candidate edge (E) is stored. */
+static int ao_walk(const double *P, int64_t n, int32_t d, const int64_t *row, const ao_node_t *nd, double rho,
+                   int32_t min_pts, const double *cd2, key_t_ **cand_out, int64_t *pairs_out, int64_t cap,
+                   int64_t *stats)
+{
+    double s = sqrt(8.0 / rho);
+    double K = (s + 2.0) * (s + 2.0);
+    double q = (1.0 + rho) * (1.0 + rho);
+    int64_t ccap = 1024, m = 0, evals = 0, visits = 0;
+    key_t_ *cand = cand_out ? (key_t_ *)malloc(sizeof(key_t_) * (size_t)ccap) : NULL;
+    int64_t scap = 1024, sp = 0;
+    int64_t *stk = (int64_t *)malloc(sizeof(int64_t) * 2 * (size_t)scap);
+    if ((cand_out && !cand) || !stk) {
+        free(cand);
+        free(stk);
+        return OR_ENOMEM;
+    }
+    /* W2: the children of every internal node */
+    for (int64_t x = 0; x < 2 * n - 1; ++x) {
+        if (nd[x].left < 0) continue;
+        if (sp == scap) {
+            scap *= 2;
+            int64_t *t = (int64_t *)realloc(stk, sizeof(int64_t) * 2 * (size_t)scap);
+            if (!t) { free(cand); free(stk); return OR_ENOMEM; }
+            stk = t;
+        }
+        stk[2 * sp] = nd[x].left;
+        stk[2 * sp + 1] = nd[x].right;
+        ++sp;
+    }
+    while (sp) {
+        --sp;
+        const ao_node_t *A = nd + stk[2 * sp], *B = nd + stk[2 * sp + 1];
+        int64_t ia = stk[2 * sp], ib = stk[2 * sp + 1];
+        ++visits;
+        double dA = ao_diag2(A, d), dB = ao_diag2(B, d);
+        if (ao_separated(A, B, d, K, dA, dB)) {
+            if (pairs_out && m < cap) {
+                pairs_out[4 * m] = A->first;
+                pairs_out[4 * m + 1] = A->count;
+                pairs_out[4 * m + 2] = B->first;
+                pairs_out[4 * m + 3] = B->count;
+            }
+            if (cand_out) {
+                /* E: the case's edge set, and its K-lightest edge */
+                int bigA = A->count >= min_pts, bigB = B->count >= min_pts;
+                int64_t a0 = A->first, a1 = bigA ? A->first + 1 : A->first + A->count;
+                int64_t b0 = B->first, b1 = bigB ? B->first + 1 : B->first + B->count;
+                key_t_ best = ao_key(P, d, cd2, q, row[a0], row[b0]);
+                for (int64_t i = a0; i < a1; ++i)
+                    for (int64_t j = b0; j < b1; ++j) {
+                        key_t_ k = ao_key(P, d, cd2, q, row[i], row[j]);
+                        if (key_less(k, best)) best = k;
+                    }
+                evals += (a1 - a0) * (b1 - b0);
+                if (m == ccap) {
+                    ccap *= 2;
+                    key_t_ *t = (key_t_ *)realloc(cand, sizeof(key_t_) * (size_t)ccap);
+                    if (!t) { free(cand); free(stk); return OR_ENOMEM; }
+                    cand = t;
+                }
+                cand[m] = best;
+            }
+            ++m;
+            continue;
+        }
+        int split_a = (B->count == 1) || (A->count > 1 && (dA > dB || (dA == dB && A->count >= B->count)));
+        const ao_node_t *X = split_a ? A : B;
+        int64_t oth = split_a ? ib : ia;
+        if (sp + 2 > scap) {
+            scap *= 2;
+            int64_t *t = (int64_t *)realloc(stk, sizeof(int64_t) * 2 * (size_t)scap);
+            if (!t) { free(cand); free(stk); return OR_ENOMEM; }
+            stk = t;
+        }
+        stk[2 * sp] = X->left;
+        stk[2 * sp + 1] = oth;
+        ++sp;
+        stk[2 * sp] = X->right;
+        stk[2 * sp + 1] = oth;
+        ++sp;
+    }
+    free(stk);
+    if (stats) {
+        stats[0] = m;
+        stats[1] = evals;
+        stats[2] = visits;
+    }
+    if (cand_out) *cand_out = cand;
+    return OR_OK;
+}
+
+static int ao_check(const double *P, int64_t n, int32_t d, double rho)
+{
+    if (check_points(P, n, d)) return OR_EINVAL;
+    if (d > 7 || !(rho > 0.0) || !isfinite(rho)) return OR_EINVAL;
+    return OR_OK;
+}
+
+int oracle_optics_approx(const double *P, int64_t n, int32_t d, int32_t min_pts, double rho, double *cd2,
+                         int64_t *edges, double *w2, double *e2, int64_t *stats)
+{
+    if (ao_check(P, n, d, rho) || min_pts < 1 || min_pts > n || !cd2) return OR_EINVAL;
+    int rc = oracle_core_dist2(P, n, d, min_pts, NULL, n, cd2);
+    if (rc) return rc;
+    if (stats) stats[0] = stats[1] = stats[2] = 0;
+    if (n == 1) return OR_OK;
+    int64_t *row = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *par = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!row || !par) {
+        free(row);
+        free(par);
+        return OR_ENOMEM;
+    }
+    ao_node_t *nd = NULL;
+    rc = ao_tree(P, n, d, row, &nd);
+    key_t_ *cand = NULL;
+    int64_t st[3] = {0, 0, 0};
+    if (!rc) rc = ao_walk(P, n, d, row, nd, rho, min_pts, cd2, &cand, NULL, 0, st);
+    free(nd);
+    free(row);
+    if (rc) {
+        free(par);
+        return rc;
+    }
+    /* M: Kruskal on the candidates in K order */
+    qsort(cand, (size_t)st[0], sizeof(key_t_), ao_cand_cmp);
+    for (int64_t i = 0; i < n; ++i) par[i] = i;
+    int64_t t = 0;
+    for (int64_t i = 0; i < st[0] && t < n - 1; ++i) {
+        int64_t a = uf_find(par, cand[i].lo), b = uf_find(par, cand[i].hi);
+        if (a == b) continue;
+        par[a] = b;
+        edges[2 * t] = cand[i].lo;
+        edges[2 * t + 1] = cand[i].hi;
+        w2[t] = cand[i].w2;
+        if (e2) e2[t] = cand[i].e2;
+        ++t;
+    }
+    free(cand);
+    free(par);
+    if (stats) {
+        stats[0] = st[0];
+        stats[1] = st[1];
+        stats[2] = st[2];
+    }
+    return t == n - 1 ? OR_OK : OR_EINVAL;
+}
+
+/* The decomposition alone (W1, W2 on the tree of T1, T2): the tree order
+ * (row_of_pos[i] = input row at tree position i) and up to cap pairs as
+ * (first A, count A, first B, count B); returns the number of pairs in
+ * *npairs. */
+int oracle_optics_wspd(const double *P, int64_t n, int32_t d, double rho, int64_t *row_of_pos, int64_t *pairs,
+                       int64_t cap, int64_t *npairs)
+{
+    if (ao_check(P, n, d, rho) || !row_of_pos || !npairs) return OR_EINVAL;
+    *npairs = 0;
+    if (n == 1) {
+        row_of_pos[0] = 0;
+        return OR_OK;
+    }
+    ao_node_t *nd = NULL;
+    int rc = ao_tree(P, n, d, row_of_pos, &nd);
+    int64_t st[3] = {0, 0, 0};
+    if (!rc) rc = ao_walk(P, n, d, row_of_pos, nd, rho, 1, NULL, NULL, pairs, cap, st);
+    free(nd);
+    *npairs = st[0];
     return rc;
 }
