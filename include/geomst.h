@@ -88,6 +88,38 @@ int geomst_hdbscan_dev(const double* d_points, int64_t n, int32_t d, int32_t min
                        void* stream);
 
 /*
+ * Approximate OPTICS (Appendix, "Parallel Approximate OPTICS", after Gan and
+ * Tao): the MST of the approximate base graph on a well-separated pair
+ * decomposition with separation s = sqrt(8 / rho).  Each pair (A, B)
+ * contributes the lightest of its base-graph edges, chosen by the Appendix's
+ * four cases (a node is large when it holds at least min_pts points: small
+ * with small joins every point pair, large with small joins the large node's
+ * representative to every point of the other, large with large joins the two
+ * representatives), weighted max{cd(u), cd(v), d(u, v) / (1 + rho)}; the
+ * result is the MST of these candidates under K = (w^2, d^2, min, max).  A
+ * node's representative is its first point in the spatial tree's order (the
+ * paper draws it at random), so results are deterministic and repeatable.
+ * Feeding the tree to geomst_dendrogram gives the approximate OPTICS
+ * reachability plot.
+ *   min_pts    1 <= min_pts <= min(n, 64)
+ *   rho        approximation parameter, rho > 0 and finite (rho = 0.125 gives
+ *              s = 8); the decomposition grows about as s^d pairs per
+ *              point, so small rho in high d is costly
+ *   core_dist  [n] float64 out, cd of each input row (cd^2 in the _sq output)
+ *   edges      [n-1][2] int64 out, sorted by K
+ *   weights    [n-1] float64 out, w = sqrt(w^2) correctly rounded (w^2 in
+ *              the _sq output)
+ * Errors as for geomst_hdbscan, plus EINVAL for rho outside (0, 1e300) and
+ * ENOMEM when the decomposition exceeds 2^31 pairs.  The _dev variant takes
+ * device pointers and queues on `stream`; the plain one host pointers.
+ */
+int geomst_optics_approx_dev(const double* d_points, int64_t n, int32_t d, int32_t min_pts, double rho,
+                             double* d_core_dist, double* d_core_dist_sq, int64_t* d_edges, double* d_weights,
+                             double* d_weights_sq, void* stream);
+int geomst_optics_approx(const double* points, int64_t n, int32_t d, int32_t min_pts, double rho,
+                         double* core_dist, int64_t* edges, double* weights);
+
+/*
  * Ordered dendrogram and reachability plot of a weighted spanning tree
  * (Sec. 2.1, "dendrogram" and "reachability plot"; Sec. 4.1, the ordered
  * dendrogram of a start vertex; Sec. 4.2, the top-down heavy/light

@@ -1,0 +1,164 @@
+// Approximate OPTICS (paper Appendix, "Parallel Approximate OPTICS", after
+// Gan and Tao): the MST of an approximate base graph built on a
+// well-separated pair decomposition with separation s = sqrt(8 / rho).
+//
+// For every well-separated pair (A, B) the base graph holds, by the four
+// cases of the Appendix (a node X is "large" when |X| >= minPts):
+//   neither large   every point of A with every point of B;
+//   only A large    the representative of A with every point of B;
+//   only B large    every point of A with the representative of B;
+//   both large      the two representatives;
+// with weight max{cd(u), cd(v), d(u, v) / (1 + rho)}.  As in the paper's
+// implementation each pair contributes the lightest of its edges (under the
+// total order K = (w^2, d^2, min id, max id)), and the MST of these candidates
+// is the result.  The paper draws the representative points at random; here
+// a node's representative is its first point in tree order, so the result is
+// deterministic.
+//
+// The decomposition is the FindPair recursion of Alg. 1 from the children of
+// every internal node, one breadth-first level per launch, with the sphere
+// test of Sec. 2.3: A and B are separated when balls of the common radius
+// r = max(rA, rB) about the box midpoints (rX half the box diagonal) are at
+// least s r apart, i.e. |cA - cB| >= (s + 2) r, evaluated on squares.  There
+// is no beta threshold and no connectivity pruning here: every pair of the
+// decomposition yields its candidate, and one Kruskal pass follows.
+#pragma once
+#include "round_kernels.h"
+
+namespace geomst {
+
+struct ApproxArgs {
+    Counters* cnt;
+    double K;         // (s + 2)^2
+    double q;         // (1 + rho)^2
+    int min_pts;
+    PairRec* qout;    // next level (room for two children per input pair)
+    EdgeList c;       // candidates (room for one per input pair beyond the count)
+};
+
+template <int D>
+__device__ __forceinline__ double approx_diag2(const NodeRec<D>& A) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double t = (double)A.hi[k] - (double)A.lo[k];
+        s = s + t * t;
+    }
+    return s;
+}
+
+// Sec. 2.3 separation on the boxes' bounding balls (squares, no rounding of
+// a square root enters the decision).
+template <int D>
+__device__ __forceinline__ bool approx_separated(const NodeRec<D>& A, const NodeRec<D>& B, double K, double dA,
+                                                 double dB) {
+    double dc2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double t = 0.5 * ((double)A.lo[k] + (double)A.hi[k]) - 0.5 * ((double)B.lo[k] + (double)B.hi[k]);
+        dc2 = dc2 + t * t;
+    }
+    const double r2 = 0.25 * fmax(dA, dB);
+    return dc2 >= K * r2;
+}
+
+// Base-graph edge between sorted positions i and j.
+template <int D>
+__device__ __forceinline__ EKey approx_key(const TreeView& t, double q, u32 i, u32 j) {
+    double e2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double x = t.X[(size_t)i * D + k] - t.X[(size_t)j * D + k];
+        e2 = e2 + x * x;
+    }
+    EKey key;
+    key.w2 = fmax(fmax(t.cd2[i], t.cd2[j]), e2 / q);
+    key.e2 = e2;
+    const u32 oi = t.orig[i], oj = t.orig[j];
+    key.lo = oi < oj ? oi : oj;
+    key.hi = oi < oj ? oj : oi;
+    return key;
+}
+
+using ApproxAlloc = BlockAllocN<2, 16>;
+constexpr int kApproxBlock = 256;
+
+// One level of the decomposition: lane v takes pair qin[v].  A separated
+// pair writes its candidate edge (the case's lightest); any other pair is
+// replaced by the two pairs (child, other) of the node with the larger box
+// diagonal (ties: more points, then A; a one-point node is never split).
+template <int D>
+__global__ void __launch_bounds__(kApproxBlock) k_approx_level(TreeView t, ApproxArgs r, const PairRec* qin, u32 nq) {
+    __shared__ ApproxAlloc S;
+    __shared__ unsigned long long shs[kApproxBlock / kWave];
+    const NodeRec<D>* N = nodes_of<D>(t);
+    u32* ctr[2] = {&r.cnt->c[C_QN], &r.cnt->c[C_C]};
+    unsigned long long visits = 0, evals = 0, sep = 0;
+    const u32 stride = gridDim.x * kApproxBlock;
+    for (u32 v0 = blockIdx.x * kApproxBlock; v0 < nq; v0 += stride) {
+        const u32 v = v0 + threadIdx.x;
+        bool cand = false, split = false;
+        EdgeOut e;
+        PairRec c0, c1;
+        if (v < nq) {
+            const PairRec p = qin[v];
+            const NodeRec<D> A = N[p.a], B = N[p.b];
+            const double dA = approx_diag2<D>(A), dB = approx_diag2<D>(B);
+            ++visits;
+            if (approx_separated<D>(A, B, r.K, dA, dB)) {
+                const bool bigA = A.count >= r.min_pts, bigB = B.count >= r.min_pts;
+                const u32 a0 = (u32)A.first, a1 = bigA ? a0 + 1 : a0 + (u32)A.count;
+                const u32 b0 = (u32)B.first, b1 = bigB ? b0 + 1 : b0 + (u32)B.count;
+                EKey best = approx_key<D>(t, r.q, a0, b0);
+                u32 bi = a0, bj = b0;
+                for (u32 i = a0; i < a1; ++i)
+                    for (u32 j = b0; j < b1; ++j) {
+                        const EKey k = approx_key<D>(t, r.q, i, j);
+                        if (key_less(k, best)) {
+                            best = k;
+                            bi = i;
+                            bj = j;
+                        }
+                    }
+                evals += (unsigned long long)(a1 - a0) * (b1 - b0);
+                ++sep;
+                e.k = best;
+                e.i = bi;
+                e.j = bj;
+                cand = true;
+            } else {
+                const bool split_a =
+                    (B.count == 1) || (A.count > 1 && (dA > dB || (dA == dB && A.count >= B.count)));
+                const NodeRec<D>& X = split_a ? A : B;
+                const u32 oth = split_a ? p.b : p.a;
+                const int2 ch = node_kids(t.n, X.first, X.count, X.split);
+                c0.a = (u32)ch.x;
+                c0.b = oth;
+                c0.lb2 = 0.0;
+                c1.a = (u32)ch.y;
+                c1.b = oth;
+                c1.lb2 = 0.0;
+                split = true;
+            }
+        }
+        const u32 cnt[2] = {split ? 2u : 0u, cand ? 1u : 0u};
+        u32 off[2];
+        block_alloc(S, cnt, ctr, off);
+        // room for every append was made before the launch
+        if (split) {
+            r.qout[off[0]] = c0;
+            r.qout[off[0] + 1] = c1;
+        }
+        if (cand) put_edge(r.c, off[1], e);
+    }
+    visits = block_sum_u64(visits, shs);
+    evals = block_sum_u64(evals, shs);
+    sep = block_sum_u64(sep, shs);
+    if (threadIdx.x == 0 && visits) {
+        atomicAdd(&r.cnt->c64[C64_VISITS], visits);
+        atomicAdd(&r.cnt->c64[C64_EVALS], evals);
+        atomicAdd(&r.cnt->c64[C64_BCCP], sep);
+    }
+}
+
+}  // namespace geomst

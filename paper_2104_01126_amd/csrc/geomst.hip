@@ -27,6 +27,7 @@
 #include "tree_kernels.h"
 #include "round_kernels.h"
 #include "dendro_kernels.h"
+#include "approx_kernels.h"
 
 namespace geomst {
 namespace {
@@ -904,6 +905,147 @@ struct Solver {
         if (c.c[C_P] > D.P[po].cap) D.P[po].ensure(std::max<size_t>((size_t)c.c[C_P] * 5 / 4, D.P[po].cap * 2), 0, s);
     }
 
+    // Kruskal on m edges of L: sorted by K, then Boruvka steps on the ranks
+    // until no edge joins two components (Sec. 3.1.2); tree edges go to OUT.
+    void kruskal(const EdgeList& L, u32 m) {
+        u32* perm = sort_edges(D, L, m, n, hdb, s);
+        D.alive[0].ensure((size_t)m * 4);
+        D.alive[1].ensure((size_t)m * 4);
+        D.apos[0].ensure((size_t)m * 8);
+        D.apos[1].ensure((size_t)m * 8);
+        D.ru.ensure((size_t)m * 4);
+        D.rv.ensure((size_t)m * 4);
+        u32* nalive = aux_dev(D, kAuxNalive);
+        unsigned gk = std::min(blocks(m, kBlock), (unsigned)kGrid);
+        k_alive_init<<<gk, kBlock, 0, s>>>(perm, L, m, D.alive[0].as<u32>(), D.apos[0].as<u64>());
+        LAUNCHCHK();
+        k_set_u32<<<1, 1, 0, s>>>(nalive, m);
+        LAUNCHCHK();
+        int ac = 0;
+        while (true) {
+            for (int j = 0; j < kBoruvkaBatch; ++j) {
+                TIMED(GEOMST_K_KRUSKAL);
+                u32* na_in = nalive + ac;
+                u32* na_out = nalive + (ac ^ 1);
+                const u32 stamp = --bstamp;  // decreasing: this step's keys beat older ones
+                k_bor_pick<<<gk, kBlock, 0, s>>>(D.alive[ac].as<u32>(), D.apos[ac].as<u64>(), na_in, m,
+                                                D.uf.as<u32>(), D.best.as<u64>(), stamp, D.ru.as<u32>(),
+                                                D.rv.as<u32>(), na_out, D.cnt.as<Counters>());
+                LAUNCHCHK();
+                k_bor_hook<<<std::min(blocks(m, kHookTile), 256u), kHookBlock, 0, s>>>(
+                    D.alive[ac].as<u32>(), na_in, m, perm, L, D.uf.as<u32>(),
+                    D.best.as<u64>(), stamp, D.ru.as<u32>(), D.rv.as<u32>(), D.alive[ac ^ 1].as<u32>(),
+                    D.apos[ac ^ 1].as<u64>(), na_out, D.OUT.list(), (u32)D.OUT.cap, D.cnt.as<Counters>());
+                LAUNCHCHK();
+                ac ^= 1;
+            }
+            read_counters(D, s, kAuxNalive + 8);  // the counters and the alive count
+            if (aux_host(D, kAuxNalive)[ac] == 0) break;
+        }
+    }
+
+    // Approximate OPTICS (paper Appendix; see approx_kernels.h): the whole
+    // decomposition level by level, each separated pair's candidate edge,
+    // then one Kruskal pass over the candidates.  Room for a level's appends
+    // (two children and one candidate per input pair) is made before its
+    // launch, so no append can overflow.
+    void run_approx(const double* P, double rho, long long* edges, double* w, double* w2, double* cd,
+                    double* cd2out) {
+        using clk = std::chrono::steady_clock;
+        auto t0 = clk::now();
+        HIPCHK(hipMemsetAsync(D.cnt.p, 0, sizeof(Counters), s));
+        HIPCHK(hipMemsetAsync((char*)D.cnt.p + offsetof(Counters, m), 0xff, sizeof(u64) * 4, s));
+        build_tree(P);
+        read_counters(D, s);
+        if (D.hcnt->c[C_ERR] & 2u) {
+            g_err = "a coordinate is not finite or exceeds 2^500 in magnitude";
+            throw Fail{GEOMST_EDOM};
+        }
+        auto t1 = clk::now();
+        core_distances();
+        HIPCHK(hipStreamSynchronize(s));
+        auto t2 = clk::now();
+        D.uf.ensure((size_t)n * 4);
+        D.best.ensure((size_t)n * 8);
+        k_iota<<<blocks(n, 256), 256, 0, s>>>(D.uf.as<u32>(), n);
+        LAUNCHCHK();
+        HIPCHK(hipMemsetAsync(D.best.p, 0xff, (size_t)n * 8, s));
+        bstamp = 0xffffffffu;
+        D.OUT.ensure((size_t)n + 64, 0, s);
+
+        const double sep = std::sqrt(8.0 / rho);
+        ApproxArgs a;
+        a.cnt = D.cnt.as<Counters>();
+        a.K = (sep + 2.0) * (sep + 2.0);
+        a.q = (1.0 + rho) * (1.0 + rho);
+        a.min_pts = minpts;
+        int b = 0;
+        u64 nq = (u64)(n - 1), m = 0;
+        D.Q[0].ensure(nq * sizeof(PairRec), 0, s);
+        k_init_frontier<D_><<<blocks(n - 1, 256), 256, 0, s>>>(t, 1, nullptr, D.Q[0].as<PairRec>());
+        LAUNCHCHK();
+        int levels = 0;
+        while (nq) {
+            if (m + nq >= 0x80000000ull || 2 * nq >= 0x80000000ull) {
+                g_err = "the decomposition has more than 2^31 pairs (choose a larger rho)";
+                throw Fail{GEOMST_ENOMEM};
+            }
+            D.Q[b ^ 1].ensure((size_t)(2 * nq) * sizeof(PairRec), 0, s);
+            D.C.ensure((size_t)(m + nq), (size_t)m, s);
+            a.qout = D.Q[b ^ 1].as<PairRec>();
+            a.c = D.C.list();
+            HIPCHK(hipMemsetAsync(&D.cnt.as<Counters>()->c[C_QN], 0, 4, s));
+            {
+                TIMED(GEOMST_K_EXPAND);
+                k_approx_level<D_><<<std::min(blocks(nq, kApproxBlock), 4096u), kApproxBlock, 0, s>>>(
+                    t, a, D.Q[b].as<PairRec>(), (u32)nq);
+                LAUNCHCHK();
+            }
+            read_counters(D, s);
+            ++levels;
+            nq = D.hcnt->c[C_QN];
+            m = D.hcnt->c[C_C];
+            b ^= 1;
+        }
+        if (m) kruskal(D.C.list(), (u32)m);
+        read_counters(D, s);
+        check_errors(D);
+        if (D.hcnt->c[C_OUT] != target_edges) {
+            g_err = "wrong number of tree edges";
+            throw Fail{GEOMST_EINTERNAL};
+        }
+        auto t3 = clk::now();
+        EdgeList O = D.OUT.list();
+        u32* perm = sort_edges(D, O, target_edges, n, true, s);
+        {
+            TIMED(GEOMST_K_OUTPUT);
+            k_write_edges<<<blocks(target_edges, 256), 256, 0, s>>>(O, perm, target_edges, nullptr, nullptr, edges,
+                                                                    w, w2);
+            LAUNCHCHK();
+            if (cd || cd2out) {
+                k_write_cd<<<blocks(n, 256), 256, 0, s>>>(D.cd2.as<double>(), D.orig.as<u32>(), n, cd, cd2out);
+                LAUNCHCHK();
+            }
+        }
+        read_counters(D, s);
+        check_errors(D);
+        auto t4 = clk::now();
+        auto ms = [](clk::time_point x, clk::time_point y) {
+            return std::chrono::duration<double, std::milli>(y - x).count();
+        };
+        st.rounds = levels;
+        st.pair_visits = (int64_t)D.hcnt->c64[C64_VISITS];
+        st.bccp_evals = (int64_t)D.hcnt->c64[C64_EVALS];
+        st.bccp_evals_done = st.bccp_evals;
+        st.bccp_pairs = (int64_t)D.hcnt->c64[C64_BCCP];
+        st.committed_edges = (int64_t)m;
+        st.ms_tree = ms(t0, t1);
+        st.ms_core = ms(t1, t2);
+        st.ms_rounds = ms(t2, t3);
+        st.ms_final = ms(t3, t4);
+        D.prof->finish(st);
+    }
+
     void run(const double* P, long long* edges, double* w, double* w2, double* cd, double* cd2out) {
         using clk = std::chrono::steady_clock;
         auto t0 = clk::now();
@@ -1250,45 +1392,7 @@ struct Solver {
             // Kruskal on the committed edges
             u32 m = D.hcnt->c[C_C];
             committed += m;
-            if (m) {
-                EdgeList L = D.C.list();
-                u32* perm = sort_edges(D, L, m, n, hdb, s);
-                D.alive[0].ensure((size_t)m * 4);
-                D.alive[1].ensure((size_t)m * 4);
-                D.apos[0].ensure((size_t)m * 8);
-                D.apos[1].ensure((size_t)m * 8);
-                D.ru.ensure((size_t)m * 4);
-                D.rv.ensure((size_t)m * 4);
-                u32* nalive = aux_dev(D, kAuxNalive);
-                unsigned gk = std::min(blocks(m, kBlock), (unsigned)kGrid);
-                k_alive_init<<<gk, kBlock, 0, s>>>(perm, L, m, D.alive[0].as<u32>(), D.apos[0].as<u64>());
-                LAUNCHCHK();
-                k_set_u32<<<1, 1, 0, s>>>(nalive, m);
-                LAUNCHCHK();
-                int ac = 0;
-                while (true) {
-                    for (int j = 0; j < kBoruvkaBatch; ++j) {
-                        TIMED(GEOMST_K_KRUSKAL);
-                        u32* na_in = nalive + ac;
-                        u32* na_out = nalive + (ac ^ 1);
-                        const u32 stamp = --bstamp;  // decreasing: this step's keys beat older ones
-                        k_bor_pick<<<gk, kBlock, 0, s>>>(D.alive[ac].as<u32>(), D.apos[ac].as<u64>(), na_in, m,
-                                                        D.uf.as<u32>(), D.best.as<u64>(), stamp, D.ru.as<u32>(),
-                                                        D.rv.as<u32>(), na_out, D.cnt.as<Counters>());
-                        LAUNCHCHK();
-                        k_bor_hook<<<std::min(blocks(m, kHookTile), 256u), kHookBlock, 0, s>>>(
-                            D.alive[ac].as<u32>(), na_in, m, perm, L, D.uf.as<u32>(),
-                            D.best.as<u64>(), stamp, D.ru.as<u32>(), D.rv.as<u32>(), D.alive[ac ^ 1].as<u32>(),
-                            D.apos[ac ^ 1].as<u64>(), na_out, D.OUT.list(), (u32)D.OUT.cap, D.cnt.as<Counters>());
-                        LAUNCHCHK();
-                        ac ^= 1;
-                    }
-                    u32 left = 0;
-                    read_counters(D, s, kAuxNalive + 8);  // the counters and the alive count
-                    left = aux_host(D, kAuxNalive)[ac];
-                    if (left == 0) break;
-                }
-            }
+            if (m) kruskal(D.C.list(), m);
             // The counters read last (after the Kruskal steps, or after the
             // expansion when nothing was committed) are this round's final
             // values.  Refresh the node components unless this round merged
@@ -1441,7 +1545,7 @@ int validate(const void* pts, int64_t n, int32_t d, int32_t min_pts, const void*
 
 // Solve with device pointers on stream s (device context locked by caller).
 void solve_dev(Device& D, hipStream_t s, const double* P, int n, int d, int minpts, long long* edges, double* w,
-               double* w2, double* cd, double* cd2) {
+               double* w2, double* cd, double* cd2, double rho = 0.0) {
     g_cur_stream = s;
     memset(&g_stats, 0, sizeof(g_stats));
     g_stats.n = n;
@@ -1470,7 +1574,10 @@ void solve_dev(Device& D, hipStream_t s, const double* P, int n, int d, int minp
 #define CASE(K)                                                   \
     case K: {                                                     \
         Solver<K> sv(D, s, n, minpts, g_stats, opts);             \
-        sv.run(P, edges, w, w2, cd, cd2);                         \
+        if (rho > 0.0)                                            \
+            sv.run_approx(P, rho, edges, w, w2, cd, cd2);         \
+        else                                                      \
+            sv.run(P, edges, w, w2, cd, cd2);                     \
         break;                                                    \
     }
         CASE(1)
@@ -1660,7 +1767,7 @@ void solve_host_items(Device& D, const HostItem* it, int64_t count) {
 }
 
 int run_dev(const double* P, int64_t n, int32_t d, int32_t minpts, long long* edges, double* w, double* w2,
-            double* cd, double* cd2, void* stream) {
+            double* cd, double* cd2, void* stream, double rho = 0.0) {
     g_err.clear();
     int rc = validate(P, n, d, minpts, edges);
     if (rc) return rc;
@@ -1669,7 +1776,7 @@ int run_dev(const double* P, int64_t n, int32_t d, int32_t minpts, long long* ed
         Device& D = device_ctx(&dev);
         std::lock_guard<std::mutex> lk(D.mu);
         ensure_init(D);
-        solve_dev(D, (hipStream_t)stream, P, (int)n, d, minpts, edges, w, w2, cd, cd2);
+        solve_dev(D, (hipStream_t)stream, P, (int)n, d, minpts, edges, w, w2, cd, cd2, rho);
     } catch (const Fail& f) {
         return f.code;
     } catch (const std::bad_alloc&) {
@@ -1679,7 +1786,8 @@ int run_dev(const double* P, int64_t n, int32_t d, int32_t minpts, long long* ed
     return GEOMST_OK;
 }
 
-int run_host(const double* P, int64_t n, int32_t d, int32_t minpts, int64_t* edges, double* w, double* cd) {
+int run_host(const double* P, int64_t n, int32_t d, int32_t minpts, int64_t* edges, double* w, double* cd,
+             double rho = 0.0) {
     g_err.clear();
     int rc = validate(P, n, d, minpts, edges);
     if (rc) return rc;
@@ -1696,7 +1804,7 @@ int run_host(const double* P, int64_t n, int32_t d, int32_t minpts, int64_t* edg
         D.cdout.ensure((size_t)n * 8);
         HIPCHK(hipMemcpyAsync(D.pin.p, P, (size_t)n * d * 8, hipMemcpyHostToDevice, s));
         solve_dev(D, s, D.pin.as<double>(), (int)n, d, minpts, D.eout.as<long long>(), w ? D.wout.as<double>() : nullptr,
-                  nullptr, (minpts > 0 && cd) ? D.cdout.as<double>() : nullptr, nullptr);
+                  nullptr, (minpts > 0 && cd) ? D.cdout.as<double>() : nullptr, nullptr, rho);
         if (m) HIPCHK(hipMemcpyAsync(edges, D.eout.p, m * 16, hipMemcpyDeviceToHost, s));
         if (m && w) HIPCHK(hipMemcpyAsync(w, D.wout.p, m * 8, hipMemcpyDeviceToHost, s));
         if (minpts > 0 && cd) HIPCHK(hipMemcpyAsync(cd, D.cdout.p, (size_t)n * 8, hipMemcpyDeviceToHost, s));
@@ -2332,6 +2440,38 @@ int geomst_hdbscan_dev(const double* d_points, int64_t n, int32_t d, int32_t min
     }
     return run_dev(d_points, n, d, min_pts, (long long*)d_edges, d_weights, d_weights_sq, d_core_dist,
                    d_core_dist_sq, stream);
+}
+
+namespace {
+int check_approx(int32_t min_pts, double rho) {
+    if (min_pts < 1) {
+        g_err = "min_pts must be >= 1";
+        return GEOMST_EINVAL;
+    }
+    if (!(rho > 0.0) || !(rho < 1e300)) {
+        g_err = "rho must be positive and finite";
+        return GEOMST_EINVAL;
+    }
+    return GEOMST_OK;
+}
+}  // namespace
+
+int geomst_optics_approx_dev(const double* d_points, int64_t n, int32_t d, int32_t min_pts, double rho,
+                             double* d_core_dist, double* d_core_dist_sq, int64_t* d_edges, double* d_weights,
+                             double* d_weights_sq, void* stream) {
+    g_err.clear();
+    int rc = check_approx(min_pts, rho);
+    if (rc) return rc;
+    return run_dev(d_points, n, d, min_pts, (long long*)d_edges, d_weights, d_weights_sq, d_core_dist,
+                   d_core_dist_sq, stream, rho);
+}
+
+int geomst_optics_approx(const double* points, int64_t n, int32_t d, int32_t min_pts, double rho,
+                         double* core_dist, int64_t* edges, double* weights) {
+    g_err.clear();
+    int rc = check_approx(min_pts, rho);
+    if (rc) return rc;
+    return run_host(points, n, d, min_pts, edges, weights, core_dist, rho);
 }
 
 int geomst_batch_dev(const double* d_points, int32_t stride, const geomst_batch_item_t* items, int64_t count,

@@ -91,6 +91,10 @@ def load(path: str = LIB_PATH):
     lib.geomst_emst_dev.argtypes = [P, i64, i32, P, P, P, P]
     lib.geomst_hdbscan_dev.argtypes = [P, i64, i32, i32, P, P, P, P, P, P]
     lib.geomst_emst_dev_noalloc.argtypes = [P, i64, i32, P, P, P, P]
+    lib.geomst_optics_approx_dev.argtypes = [P, i64, i32, i32, dbl, P, P, P, P, P, P]
+    lib.geomst_optics_approx.argtypes = [P, i64, i32, i32, dbl, P, P, P]
+    lib.geomst_optics_approx_dev.restype = ctypes.c_int
+    lib.geomst_optics_approx.restype = ctypes.c_int
     lib.geomst_dendrogram_dev.argtypes = [P, P, i64, i64, P, P, P, P, P]
     lib.geomst_dendrogram.argtypes = [P, P, i64, i64, P, P, P, P]
     lib.geomst_load_tuning.argtypes = [ctypes.c_char_p]
@@ -288,6 +292,42 @@ def hdbscan(points, min_pts: int, want_sq: bool = False):
     w = np.zeros(m)
     _check(lib.geomst_hdbscan(p.ctypes.data, n, d, int(min_pts), cd.ctypes.data, e.ctypes.data,
                               w.ctypes.data))
+    return cd, e, w
+
+
+def optics_approx(points, min_pts: int, rho: float, want_sq: bool = False):
+    """Approximate OPTICS MST (Gan-Tao base graph on the WSPD, s = sqrt(8/rho))
+    -> (core_dist [n], edges [n-1,2], weights [n-1][, core_dist_sq, weights_sq]).
+    numpy in -> numpy out (host path); CUDA tensor in -> CUDA tensors out."""
+    lib = load()
+    if _is_cuda_tensor(points):
+        import torch
+        p = points.contiguous()
+        if p.dtype != torch.float64 or p.dim() != 2:
+            raise ValueError("points must be a float64 [n, d] tensor")
+        n, d = p.shape
+        m = max(n - 1, 0)
+        dev = p.device
+        cd = torch.empty(n, dtype=torch.float64, device=dev)
+        e = torch.empty((m, 2), dtype=torch.int64, device=dev)
+        w = torch.empty(m, dtype=torch.float64, device=dev)
+        cd2 = torch.empty(n, dtype=torch.float64, device=dev) if want_sq else None
+        w2 = torch.empty(m, dtype=torch.float64, device=dev) if want_sq else None
+        _check(lib.geomst_optics_approx_dev(p.data_ptr(), n, d, int(min_pts), float(rho), cd.data_ptr(),
+                                            cd2.data_ptr() if cd2 is not None else None, e.data_ptr(),
+                                            w.data_ptr(), w2.data_ptr() if w2 is not None else None,
+                                            _stream_ptr()))
+        return (cd, e, w, cd2, w2) if want_sq else (cd, e, w)
+    p = np.ascontiguousarray(points, dtype=np.float64)
+    if p.ndim != 2:
+        raise ValueError("points must be [n, d]")
+    n, d = p.shape
+    m = max(n - 1, 0)
+    cd = np.zeros(n)
+    e = np.zeros((m, 2), np.int64)
+    w = np.zeros(m)
+    _check(lib.geomst_optics_approx(p.ctypes.data, n, d, int(min_pts), float(rho), cd.ctypes.data,
+                                    e.ctypes.data, w.ctypes.data))
     return cd, e, w
 
 

@@ -20,6 +20,11 @@ Gaussian mixtures with log-uniform widths for the latter):
                    log-uniform in [0.5,20]) and 5% uniform noise, seed 2.
 * ``batch_4096``   4,096 EMST instances, n log-uniform in [100,50000], d in
                    {2,3}, half uniform, half 8-Gaussian mixtures, seed 3.
+* ``optics_500k``  approximate OPTICS, minPts=10, rho=0.125 (s = 8, the
+                   setting of the paper's approximate-OPTICS runs): 500,000
+                   points in 3-D drawn like ``hdbscan_2m`` (64 Gaussians,
+                   centres uniform in [0,1e4)^3, sigma log-uniform in
+                   [0.5,20], plus 5% uniform noise), seed 5.
 * ``serving_trace`` a Poisson request stream at 2,000 requests/s for 60 s
                    (seed 4): 70% EMST, 30% HDBSCAN* with minPts in {5,10,16},
                    n log-uniform in [1e3,1e6], d in {2..7}, half uniform and
@@ -66,6 +71,23 @@ def hdbscan_2m(n_total: int = 2_000_000) -> np.ndarray:
     reduced test sizes; the full workload is ``n_total=2_000_000``."""
     rng = np.random.default_rng(2)
     d, k = 5, 64
+    centres = rng.uniform(0.0, 1e4, (k, d))
+    sig = np.exp(rng.uniform(math.log(0.5), math.log(20.0), k))
+    nc = (n_total * 95) // 100
+    nn = n_total - nc
+    lab = rng.integers(0, k, nc)
+    x = centres[lab] + sig[lab][:, None] * rng.standard_normal((nc, d))
+    noise = rng.uniform(0.0, 1e4, (nn, d))
+    p = np.concatenate([x, noise], axis=0)
+    p = p[rng.permutation(n_total)]
+    return _c(p)
+
+
+def optics_500k(n_total: int = 500_000) -> np.ndarray:
+    """64-Gaussian mixture plus 5% uniform noise in [0,1e4)^3 (seed 5);
+    ``n_total`` scales the counts for reduced test sizes."""
+    rng = np.random.default_rng(5)
+    d, k = 3, 64
     centres = rng.uniform(0.0, 1e4, (k, d))
     sig = np.exp(rng.uniform(math.log(0.5), math.log(20.0), k))
     nc = (n_total * 95) // 100
