@@ -43,6 +43,9 @@ WORKLOADS = {
     "batch_4096": dict(desc="Batched: 4,096 independent EMST instances, n log-uniform in [100,50000], d in {2,3}, "
                             "half uniform in the unit cube, half 8-Gaussian mixtures (sigma in [0.01,0.1]), seed 3",
                        n=None, d=3, min_pts=0),
+    "optics_500k": dict(desc="Approximate OPTICS (Gan-Tao base graph, rho=0.125, s=8), minPts=10, 500,000 points in "
+                             "3-D: 95% from 64 Gaussians (centres uniform in [0,1e4)^3, sigma log-uniform [0.5,20]) "
+                             "+ 5% uniform noise, seed 5", n=500_000, d=3, min_pts=10),
     "serve_poisson": dict(desc="Serving: Poisson stream at 2,000 requests/s, 70% EMST / 30% HDBSCAN* (minPts in "
                                "{5,10,16}), n log-uniform in [1e3,1e6], d in {2..7}, half uniform, half 8-Gaussian "
                                "mixtures, seed 4; 200 GB admission budget",
@@ -65,6 +68,14 @@ def solve(G, x, min_pts):
     return G.emst(x)
 
 
+def node_record_bytes(d, hdb=False):
+    """Bytes of one tree node the expansion reads: the box (2d binary64 bounds
+    for d <= 3, 2d binary32 for d >= 4), first/count/split/component (16 B),
+    and the (min, max) core-distance range (16 B) for HDBSCAN*."""
+    box = 16 * d if d <= 3 else 8 * d
+    return box + 16 + (16 if hdb else 0)
+
+
 def unit_model(fam, st, d, hdb=False):
     """Algorithmic work of one kernel family over a solve: (amount, unit,
     bound).  Bytes are the data the method itself must move, flops the
@@ -76,9 +87,10 @@ def unit_model(fam, st, d, hdb=False):
     if fam == "bccp_large":
         return st.big_evals * (3 * d - 1 + (2 if hdb else 0)), "TFLOP/s", "alu"
     if fam == "expand":
-        # per examined node pair: its 16-byte record and the two nodes' box
-        # (2d doubles), radius, range and component (8+8+4 bytes) each
-        return st.pair_visits * (16 + 2 * (16 * d + 20)), "GB/s", "hbm"
+        # per examined node pair: its 16-byte record and the two nodes'
+        # records (box, range, split and component), plus their core-distance
+        # ranges for HDBSCAN*
+        return st.pair_visits * (16 + 2 * node_record_bytes(d, hdb)), "GB/s", "hbm"
     if fam == "sort":
         # per element and 8-bit pass: 12 bytes read, 12 bytes written
         return st.sort_elems * 24, "GB/s", "hbm"
@@ -428,6 +440,52 @@ def extra_plain(G, torch, np, name, steps, warmup, dendrogram=False, variants=Fa
     return rec
 
 
+def extra_optics(G, torch, np, steps):
+    """Approximate OPTICS (paper Appendix) on its own workload: the whole
+    decomposition at s = 8, each pair's case candidate, one Kruskal pass."""
+    from paper_2104_01126_amd import workloads as W
+    wl = WORKLOADS["optics_500k"]
+    log("optics_500k: generating")
+    pts = W.optics_500k()
+    n, d = pts.shape
+    mp, rho = wl["min_pts"], 0.125
+    x = torch.from_numpy(pts).to("cuda:0")
+    G.optics_approx(x, mp, rho)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        t = time.perf_counter()
+        G.optics_approx(x, mp, rho)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1000.0)
+    st = G.stats()
+    G.set_option("kernel_timing", 1)
+    G.optics_approx(x, mp, rho)
+    torch.cuda.synchronize()
+    stk = G.stats()
+    G.set_option("kernel_timing", 0)
+    fams = G.KERNEL_FAMILIES
+    kms = {fams[i]: round(float(stk.kernel_ms[i]), 4) for i in range(len(fams))}
+    log(f"optics_500k: median {median(ts):.2f} ms over {steps} solves")
+    rec = {"workload": wl["desc"], "n": n, "d": d, "min_pts": mp, "rho": rho,
+           "median_ms": round(median(ts), 3), "points_per_s": round(n / (median(ts) / 1000.0), 1),
+           "solves": steps, "kernel_ms_breakdown": kms,
+           "counts": {"wspd_pairs": st.bccp_pairs, "point_pairs_evaluated": st.bccp_evals,
+                      "pair_visits": st.pair_visits, "levels": st.rounds, "candidates": st.committed_edges}}
+    ems = kms.get("expand", 0.0)
+    if ems > 0:
+        # the decomposition kernel (k_approx_level): per examined pair its
+        # record and the two node records
+        by = st.pair_visits * (16 + 2 * node_record_bytes(d))
+        rec["roofline_decomposition"] = {"kernel": "k_approx_level", "bound": "hbm",
+                                         "achieved": round(by / (ems / 1000.0) / 1e9, 3), "peak": HBM_PEAK_GBS,
+                                         "unit": "GB/s", "frac": round(by / (ems / 1000.0) / 1e9 / HBM_PEAK_GBS, 5),
+                                         "pairs_per_s": round(st.pair_visits / (ems / 1000.0), 1)}
+    del x
+    torch.cuda.empty_cache()
+    return rec
+
+
 def extra_c1_variants(G, torch, np, x, n, steps):
     """c1 under plain beta doubling, and through the host-array API."""
     out = {}
@@ -761,6 +819,7 @@ def main():
         ex["c2"] = extra_plain(G, torch, np, "hdbscan_2m", 5, 2, dendrogram=True, variants=True)
         ex["c3"] = extra_batch(G, torch, np, 5)
         ex["c4"] = extra_serve(G, a.serve_seconds, a.serve_workers)
+        ex["optics_approx"] = extra_optics(G, torch, np, 5)
         if not a.no_cpu_baseline:
             ex["oracle_single_thread"] = oracle_single_thread()
         ex["oracle_full_size"] = oracle_full_size_record()

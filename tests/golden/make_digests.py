@@ -9,10 +9,12 @@ from the HIP library.
 Digested bytes (little-endian, C order):
   edges  int64 [n-1][2]   (min id, max id), sorted by K = (w2, d2, min, max)
   w2     float64 [n-1]    squared weights in the same order
-  cd2    float64 [n]      squared core distances (HDBSCAN* only)
+  cd2    float64 [n]      squared core distances (HDBSCAN* and approximate OPTICS)
+The approximate-OPTICS record also stores the decomposition's counts
+(well-separated pairs, evaluated point pairs, examined pairs).
 
 Usage (each workload writes its own JSON file beside this script):
-    python tests/golden/make_digests.py emst_small batch_4096 emst_1m hdbscan_2m
+    python tests/golden/make_digests.py emst_small batch_4096 emst_1m hdbscan_2m optics_500k
 """
 from __future__ import annotations
 
@@ -85,11 +87,21 @@ def batch_digest(name: str):
     _write(name, rec)
 
 
+def optics_digest(name: str, p: np.ndarray, min_pts: int, rho: float):
+    t0 = time.time()
+    cd2, e, w2, _, st = oracle.optics_approx(p, min_pts, rho)
+    rec = _meta(name, t0)
+    rec.update({"n": int(len(p)), "d": int(p.shape[1]), "min_pts": min_pts, "rho": rho, "edges": sha(e),
+                "w2": sha(w2), "cd2": sha(cd2), "wspd_pairs": st[0], "evals": st[1], "visits": st[2]})
+    _write(name, rec)
+
+
 JOBS = {
     "emst_small": lambda: emst_digest("emst_small", W.emst_small()),
     "emst_1m": lambda: emst_digest("emst_1m", W.emst_1m()),
     "hdbscan_2m": lambda: hdbscan_digest("hdbscan_2m", W.hdbscan_2m(), 10),
     "batch_4096": lambda: batch_digest("batch_4096"),
+    "optics_500k": lambda: optics_digest("optics_500k", W.optics_500k(), 10, 0.125),
 }
 
 

@@ -133,3 +133,39 @@ def test_errors(G):
         with pytest.raises(G.GeomstError) as ei:
             G.optics_approx(p, mp, rho)
         assert ei.value.code == G.EINVAL
+
+
+def test_full_size_digest(G):
+    """The 500,000-point workload, byte for byte against the checker's digest
+    (tests/golden/make_digests.py optics_500k), with the decomposition's
+    counts; diagnostics first, so that a missing digest still checks the
+    tree's weights and shape."""
+    import hashlib
+    import json
+    import os
+    p = W.optics_500k()
+    n = len(p)
+    say("optics_approx full size", n)
+    (cd, e, w, cd2, w2), st = run(G, p, 10, 0.125)
+    assert e.shape == (n - 1, 2) and (e[:, 0] < e[:, 1]).all()
+    # every weight is the approximate weight of its own edge (checker's
+    # core distances of a sample, its keys of a sample of edges)
+    rng = np.random.default_rng(5)
+    idx = rng.choice(n, 64, replace=False)
+    assert same(cd2[idx], oracle.core_dist2(p, 10, idx))
+    ks = rng.choice(n - 1, 2000, replace=False)
+    _, e2s = oracle.edge_keys(p, e[ks, 0], e[ks, 1])
+    q = (1.0 + 0.125) * (1.0 + 0.125)
+    assert same(w2[ks], np.maximum(np.maximum(cd2[e[ks, 0]], cd2[e[ks, 1]]), e2s / q))
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digest_optics_500k.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/digest_optics_500k.json has not been generated")
+    g = json.load(open(path))
+
+    def sha(a):
+        return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+    assert g["n"] == n and g["min_pts"] == 10 and g["rho"] == 0.125
+    assert (st.bccp_pairs, st.bccp_evals, st.pair_visits) == (g["wspd_pairs"], g["evals"], g["visits"])
+    assert sha(cd2) == g["cd2"], "core distances differ from the checker's"
+    assert sha(e) == g["edges"], "edge list differs from the checker's"
+    assert sha(w2) == g["w2"], "squared weights differ from the checker's"
