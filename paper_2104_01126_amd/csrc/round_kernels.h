@@ -278,23 +278,32 @@ __device__ __forceinline__ void block_alloc(BlockAllocN<L, B>& S, const u32 (&cn
         for (int k = 0; k < W; ++k) S.wsum[k][w] = inc[k];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        u64 r[W];
+    if (w == 0) {
+        // wave 0 turns the per-wave sums into exclusive prefixes (one lane
+        // per wave) and reserves every list's block total with one atomic per
+        // list, issued by lanes 0..L-1 together: the counters are distinct
+        // addresses, so the atomics go out as one instruction and their
+        // round trips overlap
+        const int nw = (int)(blockDim.x / kWave);
+        const int ln = lane_id();
+        u64 tot[W];
 #pragma unroll
-        for (int k = 0; k < W; ++k) r[k] = 0;
-        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                u64 x = S.wsum[k][i];
-                S.wsum[k][i] = r[k];
-                r[k] += x;
-            }
+        for (int k = 0; k < W; ++k) {
+            const u64 v = ln < nw ? S.wsum[k][ln] : 0ull;
+            const u64 incl = wave_incl_scan_u64(v);
+            tot[k] = __shfl(incl, kWave - 1);
+            if (ln < nw) S.wsum[k][ln] = incl - v;
         }
+        u32 c = 0;
+        u32* cp = nullptr;
 #pragma unroll
         for (int l = 0; l < L; ++l) {
-            u32 c = (u32)((r[l / P] >> (B * (l % P))) & M);
-            S.base[l] = (c && counters[l]) ? atomicAdd(counters[l], c) : 0u;
+            if (ln == l) {
+                c = (u32)((tot[l / P] >> (B * (l % P))) & M);
+                cp = counters[l];
+            }
         }
+        if (ln < L) S.base[ln] = (cp && c) ? atomicAdd(cp, c) : 0u;
     }
     __syncthreads();
     u64 e[W];
