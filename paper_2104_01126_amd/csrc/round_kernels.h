@@ -728,20 +728,48 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
     }
 }
 
+// End of a level kernel: the block's three minima and three counts in one
+// LDS round (one barrier), then wave 0 reduces over the waves and lanes 0..5
+// issue the six atomics together.
 template <int NT>
 __device__ __forceinline__ void level_flush(const RoundArgs& r, LevelAcc& acc) {
-    __shared__ double shm[NT / kWave];
-    __shared__ unsigned long long shs[NT / kWave];
-    block_atomic_min(acc.minf, &r.cnt->m[M_F], shm);
-    block_atomic_min(acc.minp, &r.cnt->m[M_P], shm);
-    block_atomic_min(acc.minfar, &r.cnt->m[M_FAR], shm);
-    unsigned long long v = block_sum_u64(acc.visits, shs);
-    unsigned long long ev = block_sum_u64(acc.evals, shs);
-    unsigned long long so = block_sum_u64(acc.solved, shs);
-    if (threadIdx.x == 0 && v) {
-        atomicAdd(&r.cnt->c64[C64_VISITS], v);
-        atomicAdd(&r.cnt->c64[C64_EVALS], ev);
-        atomicAdd(&r.cnt->c64[C64_BCCP], so);
+    constexpr int NW = NT / kWave;
+    __shared__ double shm[3][NW];
+    __shared__ unsigned long long shs[3][NW];
+    const double inf_ = __longlong_as_double(0x7ff0000000000000ll);
+    double mv[3] = {acc.minf, acc.minp, acc.minfar};
+    unsigned long long sv[3] = {acc.visits, acc.evals, acc.solved};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        mv[i] = wave_min_f64(mv[i]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sv[i] += __shfl_xor(sv[i], o);
+    }
+    const int w = threadIdx.x / kWave, ln = lane_id();
+    if (ln == 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            shm[i][w] = mv[i];
+            shs[i][w] = sv[i];
+        }
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            mv[i] = wave_min_f64(ln < NW ? shm[i][ln] : inf_);
+            sv[i] = ln < NW ? shs[i][ln] : 0ull;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) sv[i] += __shfl_xor(sv[i], o);
+        }
+        if (ln < 3) {
+            const double v = ln == 0 ? mv[0] : (ln == 1 ? mv[1] : mv[2]);
+            u64* dst = &r.cnt->m[ln == 0 ? M_F : (ln == 1 ? M_P : M_FAR)];
+            if (v < inf_) atomic_min_pos_f64(dst, v);
+        } else if (ln < 6 && sv[0]) {
+            const unsigned long long v = ln == 3 ? sv[0] : (ln == 4 ? sv[1] : sv[2]);
+            atomicAdd(&r.cnt->c64[ln == 3 ? C64_VISITS : (ln == 4 ? C64_EVALS : C64_BCCP)], v);
+        }
     }
 }
 
@@ -775,12 +803,18 @@ __global__ void __launch_bounds__(LevelShape<D>::block) __attribute__((amdgpu_wa
 k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const u32* slot_in, u32* slot_next,
         u32* slot_clear) {
     __shared__ BlockAlloc S;
+    __shared__ u32 pre[kRegions + 1];  // region prefix sums (in LDS: registers are the scarce resource here)
     if (blockIdx.x == 0 && threadIdx.x < kRegions) slot_clear[threadIdx.x * kRegionStride] = 0;
     // an overflowed previous level counts more pairs than it stored: read
     // only what the queue holds (the overflow flag makes the round restart)
     constexpr int NT = LevelShape<D>::block;
-    u32 pre[kRegions + 1];
-    region_prefix(slot_in, cap_in, pre);
+    if (threadIdx.x == 0) {
+        u32 p[kRegions + 1];
+        region_prefix(slot_in, cap_in, p);
+#pragma unroll
+        for (int i = 0; i <= kRegions; ++i) pre[i] = p[i];
+    }
+    __syncthreads();
     const u32 nq = pre[kRegions];
     const int x = (int)(blockIdx.x % kRegions);
     const u32 j = blockIdx.x / kRegions, g = gridDim.x / kRegions;
