@@ -161,4 +161,57 @@ __global__ void __launch_bounds__(kApproxBlock) k_approx_level(TreeView t, Appro
     }
 }
 
+// Filtered Kruskal over the candidates (as the exact path filters pairs by
+// rounds of growing weight): a threshold t splits the remaining candidates
+// into the light ones (w2 bit pattern below t), which go to Kruskal, and the
+// heavy ones, which are kept only while their ends lie in different
+// components.  Every light key precedes every heavy key in K, so taking the
+// light ones first and dropping heavy edges inside a component (cycle
+// property) gives the same tree as one Kruskal pass over all candidates.
+
+// Every step-th squared weight of the list (the sample the threshold is
+// taken from).
+__global__ void k_sample_w2(const double* w2, u64 m, u64 step, u32 ns, double* out) {
+    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ns) out[i] = w2[(u64)i * step < m ? (u64)i * step : m - 1];
+}
+
+constexpr int kPartBlock = 256;
+using PartAlloc = BlockAllocN<2, 16>;
+
+// Light candidates to `light` (counter c[C_QN]; room for cap_light of them:
+// the caller sees a larger count and takes another route); heavy ones whose
+// ends are still in different components to `heavy` (counter c[C_C]; room for
+// every input).
+__global__ void __launch_bounds__(kPartBlock) k_partition_cand(EdgeList in, u32 m, u64 tbits, EdgeList light,
+                                                               u32 cap_light, EdgeList heavy, u32* parent,
+                                                               Counters* cnt) {
+    __shared__ PartAlloc S;
+    u32* ctr[2] = {&cnt->c[C_QN], &cnt->c[C_C]};
+    const u32 stride = gridDim.x * kPartBlock;
+    for (u32 v0 = blockIdx.x * kPartBlock; v0 < m; v0 += stride) {
+        const u32 v = v0 + threadIdx.x;
+        bool lt = false, hv = false;
+        double w2 = 0.0, e2 = 0.0;
+        u64 ids = 0, pos = 0;
+        if (v < m) {
+            w2 = in.w2[v];
+            e2 = in.e2[v];
+            ids = in.ids[v];
+            pos = in.pos[v];
+            if ((u64)__double_as_longlong(w2) < tbits) {
+                lt = true;
+            } else {
+                const u32 a = uf_find(parent, (u32)(pos >> 32), cnt), b = uf_find(parent, (u32)pos, cnt);
+                hv = a != b;
+            }
+        }
+        const u32 c2[2] = {lt ? 1u : 0u, hv ? 1u : 0u};
+        u32 off[2];
+        block_alloc(S, c2, ctr, off);
+        if (lt && off[0] < cap_light) put_edge_raw(light, off[0], w2, e2, ids, pos);  // else: counted, not kept
+        if (hv) put_edge_raw(heavy, off[1], w2, e2, ids, pos);
+    }
+}
+
 }  // namespace geomst

@@ -944,6 +944,69 @@ struct Solver {
         }
     }
 
+    // Kruskal over the m approximate-OPTICS candidates in D.C, a light
+    // slice at a time (see k_partition_cand): each slice holds the lightest
+    // quarter of what remains (at least 3n candidates), below a threshold
+    // read off a strided sample of the remaining weights; the rest keeps
+    // only edges between components.
+    void kruskal_filtered(u32 m) {
+        EdgeBufs* R = &D.C;
+        EdgeBufs* H = &D.P[1];
+        EdgeBufs& Lt = D.P[0];
+        u64 mr = m;
+        const u64 slice_min = std::max<u64>((u64)3 * (u64)n, 1u << 16);
+        constexpr u32 kSample = 1u << 16;
+        D.minmax.ensure(kSample * 8);
+        std::vector<double> smp;
+        while (mr) {
+            read_counters(D, s);
+            if (D.hcnt->c[C_OUT] >= target_edges) break;
+            // a quarter of what remains (at least 3n): the filter then drops
+            // most of the rest, so a few slices do
+            const u64 slice = std::max<u64>(slice_min, mr / 4);
+            if (mr <= 2 * slice_min) {
+                kruskal(R->list(), (u32)mr);
+                break;
+            }
+            // threshold: the sample quantile at slice / mr
+            const u64 step = mr / kSample;
+            const u32 ns = (u32)std::min<u64>(kSample, mr / step);
+            k_sample_w2<<<blocks(ns, 256), 256, 0, s>>>(R->w2.as<double>(), mr, step, ns, D.minmax.as<double>());
+            LAUNCHCHK();
+            smp.resize(ns);
+            HIPCHK(hipMemcpyAsync(smp.data(), D.minmax.p, (size_t)ns * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const size_t q = std::min<size_t>(ns - 1, (size_t)((double)ns * (double)slice / (double)mr));
+            std::nth_element(smp.begin(), smp.begin() + q, smp.end());
+            u64 tbits;
+            memcpy(&tbits, &smp[q], 8);
+            ++tbits;  // light: w2 <= the quantile
+            const u64 cap_light = std::min<u64>(mr, slice + slice / 4 + mr / 64);
+            Lt.ensure((size_t)cap_light, 0, s);
+            H->ensure((size_t)mr, 0, s);
+            HIPCHK(hipMemsetAsync(&D.cnt.as<Counters>()->c[C_QN], 0, 4, s));
+            HIPCHK(hipMemsetAsync(&D.cnt.as<Counters>()->c[C_C], 0, 4, s));
+            {
+                TIMED(GEOMST_K_KRUSKAL);
+                k_partition_cand<<<std::min(blocks(mr, kPartBlock), 4096u), kPartBlock, 0, s>>>(
+                    R->list(), (u32)mr, tbits, Lt.list(), (u32)cap_light, H->list(), D.uf.as<u32>(),
+                    D.cnt.as<Counters>());
+                LAUNCHCHK();
+            }
+            read_counters(D, s);
+            const u32 nl = D.hcnt->c[C_QN], nh = D.hcnt->c[C_C];
+            if (nl > cap_light) {  // the sample misjudged the slice: all that remains at once
+                kruskal(R->list(), (u32)mr);
+                break;
+            }
+            if (g_trace) fprintf(stderr, "[geomst] filtered kruskal: %llu candidates, %u light, %u kept\n",
+                                 (unsigned long long)mr, nl, nh);
+            if (nl) kruskal(Lt.list(), nl);
+            std::swap(R, H);  // the kept heavy edges are the next round's input
+            mr = nh;
+        }
+    }
+
     // Approximate OPTICS (paper Appendix; see approx_kernels.h): the whole
     // decomposition level by level, each separated pair's candidate edge,
     // then one Kruskal pass over the candidates.  Room for a level's appends
@@ -1007,7 +1070,7 @@ struct Solver {
             m = D.hcnt->c[C_C];
             b ^= 1;
         }
-        if (m) kruskal(D.C.list(), (u32)m);
+        kruskal_filtered((u32)m);
         read_counters(D, s);
         check_errors(D);
         if (D.hcnt->c[C_OUT] != target_edges) {
