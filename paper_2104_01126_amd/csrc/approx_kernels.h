@@ -20,8 +20,9 @@
 // test of Sec. 2.3: A and B are separated when balls of the common radius
 // r = max(rA, rB) about the box midpoints (rX half the box diagonal) are at
 // least s r apart, i.e. |cA - cB| >= (s + 2) r, evaluated on squares.  There
-// is no beta threshold and no connectivity pruning here: every pair of the
-// decomposition yields its candidate, and one Kruskal pass follows.
+// is no beta threshold and no connectivity pruning in the decomposition:
+// every pair yields its candidate; a filtered Kruskal over the candidates
+// follows (below).
 #pragma once
 #include "round_kernels.h"
 
