@@ -639,7 +639,7 @@ def oracle_full_size_record():
     """Full-size checker runs behind the parity digests (tests/golden/): run
     on the build host, not on this machine; context for the GPU rates."""
     out = {}
-    for name in ("emst_small", "emst_1m", "hdbscan_2m", "batch_4096"):
+    for name in ("emst_small", "emst_1m", "hdbscan_2m", "batch_4096", "optics_500k"):
         path = os.path.join(ROOT, "tests", "golden", f"digest_{name}.json")
         if os.path.exists(path):
             g = json.load(open(path))
