@@ -412,9 +412,10 @@ int geomst_get_stats(geomst_stats_t* out);
  *                    merged at least n / this many components (and at least
  *                    every fourth round); default 1024.
  *   "small_level_switch", "small_level_max"  expansion levels with at most
- *                    the first many pairs run in one workgroup, which keeps
- *                    going while levels stay at most the second size
- *                    (defaults 2048 and 4096).
+ *                    eight times the first many pairs run in eight
+ *                    workgroups, one eighth each, and each workgroup keeps
+ *                    expanding its share while its levels stay at most the
+ *                    second size (defaults 2048 and 4096).
  * Options are process-wide; every solve reads them once when it starts
  * (under a lock), so a change never reaches a solve already running.
  * Returns GEOMST_EINVAL for an unknown name or a bad value.

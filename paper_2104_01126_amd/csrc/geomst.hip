@@ -50,8 +50,8 @@ double g_share_scale = 1.0;  // server workers: scale of the workspace share a b
 constexpr int kMaxKeyLevels = 6;  // Morton key words per point (see k_morton_level)
 constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
 u32 g_refresh_div = 1024;    // refresh node components once a round merged n / this many
-u32 g_small_switch = 2048;  // queues up to this size go to the one-workgroup level kernel
-u32 g_small_max = 4096;     // ... which keeps going while a level stays this small
+u32 g_small_switch = 2048;  // queues up to kRegions times this go to the per-region level kernel
+u32 g_small_max = 4096;     // ... whose workgroups keep going while their levels stay this small
 constexpr int kBoruvkaBatch = 4;  // Boruvka steps launched between host checks
 constexpr u32 kSparseDiv = 64;  // beta grows faster while the tree has fewer than n / this many edges
 const bool g_trace = getenv("GEOMST_TRACE") != nullptr;
@@ -1326,11 +1326,12 @@ struct Solver {
                     // ring[lv % 4] its count.
                     int lv = 0;
                     while (nq > 0) {
-                        if (nq <= o.small_switch) {
+                        if (nq <= (u32)kRegions * o.small_switch) {
                             {
                                 TIMED(GEOMST_K_EXPAND);
                                 RoundArgs r = args(beta2, fo, 0, po);
-                                k_level_small<D_><<<1, SmallBlock<D_>::value, 0, s>>>(
+                                HIPCHK(hipMemsetAsync(aux_dev(D, kAuxLstate), 0, 4, s));
+                                k_level_small<D_><<<kRegions, SmallBlock<D_>::value, 0, s>>>(
                                     t, r, hdb, D.Q[0].as<PairRec>(), (u32)(D.capQ[0] / kRegions), D.Q[1].as<PairRec>(),
                                     (u32)(D.capQ[1] / kRegions), lv & 1, ring, (u32)(lv % kQRing), o.small_max,
                                     aux_dev(D, kAuxLstate));
@@ -1344,7 +1345,7 @@ struct Solver {
                             }
                             nq = aux_host(D, kAuxLstate)[0];
                             lv = (int)aux_host(D, kAuxLstate)[1];
-                            D.qmax_seen = std::max<size_t>(D.qmax_seen, (size_t)kRegions * nq);  // all in region 0
+                            D.qmax_seen = std::max<size_t>(D.qmax_seen, (size_t)kRegions * nq);  // at most all in one region
                             continue;
                         }
                         TimedChain chain(*D.prof, s, GEOMST_K_EXPAND);

@@ -835,15 +835,19 @@ k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const 
     level_flush<NT>(r, acc);
 }
 
-// Many small levels in one workgroup: the level barrier is __syncthreads and
-// the next queue's counter lives in LDS, so a chain of thin levels costs no
-// kernel launches or host round trips.  Stops when the queue is empty or
-// grows beyond `small_max` (then the grid-wide level kernel takes over).
-// The first level reads the regions of ring slot `slot_in` of buffer b_in;
-// later levels keep the whole queue in region 0, ping-ponging between q[0]
-// and q[1] (cap0, cap1: region capacities).  On exit ring slot b holds the
-// remaining count in its region 0 for the buffer b it ends in (every other
-// ring counter is zeroed), and state = {remaining, b}.
+// Many small levels without grid-wide launches: kRegions workgroups, each
+// taking one eighth of the level's pairs and then expanding its own share
+// level by level in its own queue region (the level barrier is
+// __syncthreads and the next queue's counter lives in LDS), so the thin
+// levels at the end of a round cost no kernel launches or host round trips.
+// A workgroup stops when its queue empties or grows beyond `small_max`.
+// The first level reads the regions of ring slot `slot_in` of buffer b_in
+// laid end to end; later levels ping-pong between region x of q[0] and q[1]
+// (cap0, cap1: region capacities).  Every workgroup leaves its remaining
+// pairs in region x of buffer b_out = b_in ^ 1 (copying them there when it
+// stopped in the other buffer), writes region x's count of ring slot b_out
+// (and zero in the other slots), and adds it to state[0]; state[1] = b_out.
+// state[0] is zero at launch.
 // 1024 threads where the level step fits 128 registers without spilling
 // (d <= 4), else 768.
 template <int D>
@@ -855,28 +859,37 @@ template <int D>
 __global__ void __launch_bounds__(SmallBlock<D>::value) k_level_small(TreeView t, RoundArgs r, int hdb, PairRec* q0, u32 cap0,
                                                              PairRec* q1, u32 cap1, int b_in, u32* ring,
                                                              u32 slot_in, u32 small_max, u32* state) {
+    constexpr int NT = SmallBlock<D>::value;
     __shared__ BlockAlloc S;
     __shared__ u32 qn;
+    __shared__ u32 pre[kRegions + 1];
     const double inf_ = __longlong_as_double(0x7ff0000000000000ll);
     LevelAcc acc = {inf_, inf_, inf_, 0, 0, 0};
+    const int x = (int)blockIdx.x;
+    if (threadIdx.x == 0) {
+        u32 p[kRegions + 1];
+        region_prefix(ring + slot_in * kSlotWords, b_in ? cap1 : cap0, p);
+#pragma unroll
+        for (int i = 0; i <= kRegions; ++i) pre[i] = p[i];
+    }
+    __syncthreads();
+    const u32 ntot = pre[kRegions];
+    const u32 lo = (u32)((u64)ntot * x / kRegions), hi = (u32)((u64)ntot * (x + 1) / kRegions);
     int b = b_in;
-    u32 pre[kRegions + 1];
-    region_prefix(ring + slot_in * kSlotWords, b ? cap1 : cap0, pre);
-    u32 nq = pre[kRegions];
+    u32 nq = hi - lo;
     bool first = true;
     while (nq > 0 && nq <= small_max) {
         if (threadIdx.x == 0) qn = 0;
         __syncthreads();
         u32* ctr[kLists] = {&r.cnt->c[C_TINY], nullptr, &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR], &qn};
         const PairRec* qin = b ? q1 : q0;
-        PairRec* qout = b ? q0 : q1;
         const u32 capi = b ? cap1 : cap0, capo = b ? cap0 : cap1;
-        for (u32 b0 = 0; b0 < nq; b0 += SmallBlock<D>::value) {
+        PairRec* qout = (b ? q0 : q1) + (size_t)x * capo;
+        for (u32 b0 = 0; b0 < nq; b0 += NT) {
             const u32 v = b0 + threadIdx.x;
             const bool have = v < nq;
-            const u32 i = (have && first) ? region_index(pre, capi, v) : v;
             PairRec pr = {0u, 0u, 0.0};
-            if (have) pr = qin[i];
+            if (have) pr = qin[first ? region_index(pre, capi, lo + v) : (size_t)x * capi + v];
             level_step<D>(t, r, hdb, have, pr, qout, capo, ctr, S, acc);
         }
         __syncthreads();
@@ -890,11 +903,25 @@ __global__ void __launch_bounds__(SmallBlock<D>::value) k_level_small(TreeView t
         nq = nn;
         __syncthreads();
     }
-    level_flush<SmallBlock<D>::value>(r, acc);
-    if (threadIdx.x < kQRing * kRegions) ring[threadIdx.x * kRegionStride] = threadIdx.x == b * kRegions ? nq : 0u;
+    // leave the remaining pairs in region x of buffer b_out
+    const int b_out = b_in ^ 1;
+    const u32 cap_out = b_out ? cap1 : cap0;
+    PairRec* dst = (b_out ? q1 : q0) + (size_t)x * cap_out;
+    if (nq && (first || b != b_out)) {
+        const PairRec* src = b ? q1 : q0;
+        const u32 caps = b ? cap1 : cap0;
+        if (nq > cap_out) {
+            if (threadIdx.x == 0) flag_overflow_q(r.cnt);
+            nq = 0;
+        }
+        for (u32 v = threadIdx.x; v < nq; v += NT)
+            dst[v] = src[first ? region_index(pre, caps, lo + v) : (size_t)x * caps + v];
+    }
+    level_flush<NT>(r, acc);
+    if (threadIdx.x < kQRing) ring[threadIdx.x * kSlotWords + x * kRegionStride] = (int)threadIdx.x == b_out ? nq : 0u;
     if (threadIdx.x == 0) {
-        state[0] = nq;
-        state[1] = (u32)b;
+        if (nq) atomicAdd(&state[0], nq);
+        if (x == 0) state[1] = (u32)b_out;
     }
 }
 
