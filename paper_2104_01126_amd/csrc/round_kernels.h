@@ -836,18 +836,20 @@ k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const 
 }
 
 // Many small levels without grid-wide launches: kRegions workgroups, each
-// taking one eighth of the level's pairs and then expanding its own share
-// level by level in its own queue region (the level barrier is
-// __syncthreads and the next queue's counter lives in LDS), so the thin
-// levels at the end of a round cost no kernel launches or host round trips.
-// A workgroup stops when its queue empties or grows beyond `small_max`.
-// The first level reads the regions of ring slot `slot_in` of buffer b_in
-// laid end to end; later levels ping-pong between region x of q[0] and q[1]
-// (cap0, cap1: region capacities).  Every workgroup leaves its remaining
-// pairs in region x of buffer b_out = b_in ^ 1 (copying them there when it
-// stopped in the other buffer), writes region x's count of ring slot b_out
-// (and zero in the other slots), and adds it to state[0]; state[1] = b_out.
-// state[0] is zero at launch.
+// expanding the pairs of its own queue region x level by level (the level
+// barrier is __syncthreads and the next queue's counter lives in LDS), so the
+// thin levels at the end of a round cost no kernel launches or host round
+// trips.  A workgroup only ever reads and writes region x of the two
+// buffers, so workgroups need not run together.  It always takes its first
+// level, then keeps going while its levels stay at most `small_max` pairs.
+// The input is region x of ring slot `slot_in` of buffer b_in (every level
+// kernel appends to the region of its workgroup's XCD, and the frontier
+// split seeds regions by tree position); levels ping-pong between region x
+// of q[0] and q[1] (cap0, cap1: region capacities).  Every workgroup leaves
+// its remaining pairs in region x of buffer b_out = b_in ^ 1 (copying them
+// there when it stopped in the other buffer), writes region x's count of
+// ring slot b_out (and zero in the other slots), and adds it to state[0];
+// state[1] = b_out.  state[0] is zero at launch.
 // 1024 threads where the level step fits 128 registers without spilling
 // (d <= 4), else 768.
 template <int D>
@@ -862,23 +864,14 @@ __global__ void __launch_bounds__(SmallBlock<D>::value) k_level_small(TreeView t
     constexpr int NT = SmallBlock<D>::value;
     __shared__ BlockAlloc S;
     __shared__ u32 qn;
-    __shared__ u32 pre[kRegions + 1];
     const double inf_ = __longlong_as_double(0x7ff0000000000000ll);
     LevelAcc acc = {inf_, inf_, inf_, 0, 0, 0};
     const int x = (int)blockIdx.x;
-    if (threadIdx.x == 0) {
-        u32 p[kRegions + 1];
-        region_prefix(ring + slot_in * kSlotWords, b_in ? cap1 : cap0, p);
-#pragma unroll
-        for (int i = 0; i <= kRegions; ++i) pre[i] = p[i];
-    }
-    __syncthreads();
-    const u32 ntot = pre[kRegions];
-    const u32 lo = (u32)((u64)ntot * x / kRegions), hi = (u32)((u64)ntot * (x + 1) / kRegions);
     int b = b_in;
-    u32 nq = hi - lo;
+    // an overflowed previous level counts more pairs than it stored
+    u32 nq = min(ring[slot_in * kSlotWords + x * kRegionStride], b_in ? cap1 : cap0);
     bool first = true;
-    while (nq > 0 && nq <= small_max) {
+    while (nq > 0 && (first || nq <= small_max)) {
         if (threadIdx.x == 0) qn = 0;
         __syncthreads();
         u32* ctr[kLists] = {&r.cnt->c[C_TINY], nullptr, &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR], &qn};
@@ -889,7 +882,7 @@ __global__ void __launch_bounds__(SmallBlock<D>::value) k_level_small(TreeView t
             const u32 v = b0 + threadIdx.x;
             const bool have = v < nq;
             PairRec pr = {0u, 0u, 0.0};
-            if (have) pr = qin[first ? region_index(pre, capi, lo + v) : (size_t)x * capi + v];
+            if (have) pr = qin[(size_t)x * capi + v];
             level_step<D>(t, r, hdb, have, pr, qout, capo, ctr, S, acc);
         }
         __syncthreads();
@@ -907,15 +900,13 @@ __global__ void __launch_bounds__(SmallBlock<D>::value) k_level_small(TreeView t
     const int b_out = b_in ^ 1;
     const u32 cap_out = b_out ? cap1 : cap0;
     PairRec* dst = (b_out ? q1 : q0) + (size_t)x * cap_out;
-    if (nq && (first || b != b_out)) {
-        const PairRec* src = b ? q1 : q0;
-        const u32 caps = b ? cap1 : cap0;
+    if (nq && b != b_out) {
+        const PairRec* src = (b ? q1 : q0) + (size_t)x * (b ? cap1 : cap0);
         if (nq > cap_out) {
             if (threadIdx.x == 0) flag_overflow_q(r.cnt);
             nq = 0;
         }
-        for (u32 v = threadIdx.x; v < nq; v += NT)
-            dst[v] = src[first ? region_index(pre, caps, lo + v) : (size_t)x * caps + v];
+        for (u32 v = threadIdx.x; v < nq; v += NT) dst[v] = src[v];
     }
     level_flush<NT>(r, acc);
     if (threadIdx.x < kQRing) ring[threadIdx.x * kSlotWords + x * kRegionStride] = (int)threadIdx.x == b_out ? nq : 0u;
