@@ -47,9 +47,11 @@ extern "C" {
 #define GEOMST_EDOM (-2)     /* a coordinate is not finite or |x| > 2^500 */
 #define GEOMST_ENOMEM (-3)   /* device or host allocation failed */
 #define GEOMST_EDEVICE (-4)  /* a HIP runtime call failed */
-#define GEOMST_ETIMEDOUT (-5)/* geomst_wait: the request is not done yet */
-#define GEOMST_ENOENT (-6)   /* unknown or already released ticket */
+#define GEOMST_EBUSY (-5)    /* reserved for a bounded request queue; not returned by this version */
+#define GEOMST_ETIMEDOUT (-6)/* geomst_wait: the request is not done yet */
+#define GEOMST_ECANCELED (-7)/* geomst_wait: the request was withdrawn by geomst_cancel */
 #define GEOMST_EINTERNAL (-8)/* an internal consistency check failed */
+#define GEOMST_ENOENT (-9)   /* unknown or already released ticket; missing tuning file */
 
 /*
  * Euclidean MST of host-resident points (Sec. 2.1, EMST).
@@ -302,12 +304,15 @@ int geomst_submit(geomst_server_t* srv, geomst_instance_t* req, uint64_t* ticket
 /* Waits up to timeout_us microseconds (< 0: forever; 0: poll).  When the
  * request is done: fills info (may be NULL), releases the ticket and returns
  * the request's result code.  Otherwise returns ETIMEDOUT and keeps the
- * ticket.  ENOENT for an unknown ticket. */
+ * ticket.  ECANCELED (once) for a ticket withdrawn by geomst_cancel, also
+ * when the withdrawal happens during the wait; ENOENT for an unknown or
+ * already released ticket. */
 int geomst_wait(geomst_server_t* srv, uint64_t ticket, int64_t timeout_us, geomst_request_info_t* info);
 
 /* Withdraws a request and releases its ticket.  A queued request is removed
  * without running; one already in a batch is waited for (its outputs may have
- * been written).  Returns OK, or ENOENT for an unknown ticket. */
+ * been written).  A later (or concurrent) geomst_wait on the ticket returns
+ * ECANCELED.  Returns OK, or ENOENT for an unknown ticket. */
 int geomst_cancel(geomst_server_t* srv, uint64_t ticket);
 
 int geomst_server_stats(geomst_server_t* srv, geomst_server_stats_t* out);

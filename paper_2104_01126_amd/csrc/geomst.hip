@@ -14,6 +14,7 @@
 #include <deque>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <memory>
 #include <algorithm>
 #include <string>
@@ -2247,6 +2248,7 @@ struct Server {
     std::deque<Request*> lane[2];  // 0: small requests (batched), 1: large requests (one at a time)
     int64_t small_max = 0;         // requests with n <= this go to the small lane
     std::unordered_map<uint64_t, Request*> all;
+    std::unordered_set<uint64_t> withdrawn;  // cancelled tickets not yet reported by a wait
     std::vector<std::thread> workers;
     std::vector<std::unique_ptr<Device>> ws;
     uint64_t next_ticket = 1;
@@ -2726,6 +2728,10 @@ int geomst_wait(geomst_server_t* srv, uint64_t ticket, int64_t timeout_us, geoms
         return GEOMST_ETIMEDOUT;
     auto f = srv->all.find(ticket);
     if (f == srv->all.end()) {
+        if (srv->withdrawn.erase(ticket)) {
+            g_err = "the request was cancelled";
+            return GEOMST_ECANCELED;
+        }
         g_err = "unknown ticket";
         return GEOMST_ENOENT;
     }
@@ -2770,6 +2776,7 @@ int geomst_cancel(geomst_server_t* srv, uint64_t ticket) {
         srv->st.queued -= 1;
     }
     srv->all.erase(f);
+    srv->withdrawn.insert(ticket);
     lk.unlock();
     delete r;
     srv->cv_done.notify_all();

@@ -22,9 +22,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgeomst.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "geomst.h")
 
-OK, EINVAL, EDOM, ENOMEM, EDEVICE, ETIMEDOUT, ENOENT, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -8
-_NAMES = {EINVAL: "EINVAL", EDOM: "EDOM", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ETIMEDOUT: "ETIMEDOUT",
-          ENOENT: "ENOENT", EINTERNAL: "EINTERNAL"}
+OK, EINVAL, EDOM, ENOMEM, EDEVICE, EBUSY, ETIMEDOUT, ECANCELED, EINTERNAL, ENOENT = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+_NAMES = {EINVAL: "EINVAL", EDOM: "EDOM", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", EBUSY: "EBUSY",
+          ETIMEDOUT: "ETIMEDOUT", ECANCELED: "ECANCELED", EINTERNAL: "EINTERNAL", ENOENT: "ENOENT"}
 
 
 class GeomstError(RuntimeError):
@@ -234,7 +234,7 @@ def emst(points, want_sq: bool = False):
 
 def header_constant(name: str, header: str = HEADER) -> int:
     """Integer value of a #define in include/geomst.h."""
-    m = re.search(r"#define\s+" + re.escape(name) + r"\s+(-?\d+)", open(header).read())
+    m = re.search(r"#define\s+" + re.escape(name) + r"\s+\(?(-?\d+)\)?", open(header).read())
     if not m:
         raise KeyError(name)
     return int(m.group(1))

@@ -211,3 +211,14 @@ def test_tuning_cache_parsing(lib, tmp_path):
         assert "line 1" in G.last_error()
     assert lib.geomst_load_tuning(str(tmp_path / "missing.jsonl").encode()) == G.ENOENT
     assert lib.geomst_load_tuning(None) == G.OK
+
+
+def test_error_codes_match_header():
+    """The binding's status constants are the header's values."""
+    from paper_2104_01126_amd import geomst as G
+    for name in ("OK", "EINVAL", "EDOM", "ENOMEM", "EDEVICE", "EBUSY", "ETIMEDOUT", "ECANCELED", "EINTERNAL",
+                 "ENOENT"):
+        assert getattr(G, name) == G.header_constant("GEOMST_" + name), name
+    vals = [G.header_constant("GEOMST_" + n) for n in ("EINVAL", "EDOM", "ENOMEM", "EDEVICE", "EBUSY", "ETIMEDOUT",
+                                                       "ECANCELED", "EINTERNAL", "ENOENT")]
+    assert len(set(vals)) == len(vals) and all(v < 0 for v in vals)

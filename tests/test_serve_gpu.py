@@ -146,6 +146,9 @@ def test_cancel_timeout_and_errors(G):
         for t in cancelled:
             with pytest.raises(G.GeomstError) as ex:
                 S.wait(t)
+            assert ex.value.code == G.ECANCELED
+            with pytest.raises(G.GeomstError) as ex:
+                S.wait(t)  # reported once
             assert ex.value.code == G.ENOENT
         # poll: either done or not yet
         try:
