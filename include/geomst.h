@@ -66,7 +66,10 @@ int geomst_emst(const double* points, int64_t n, int32_t d, int64_t* edges, doub
 /*
  * HDBSCAN* core distances and mutual reachability MST of host-resident points
  * (Sec. 2.1, HDBSCAN*; Sec. 3.2.2).
- *   min_pts    1 <= min_pts <= min(n, 64)
+ *   min_pts    1 <= min_pts <= min(n, 64): the k-NN keeps each query's k
+ *              smallest distances in registers, and 64 covers the paper's
+ *              range (minPts 10 in its tables, up to 50 in its sweep); a
+ *              larger value returns EINVAL
  *   core_dist  [n] float64 out (host), cd of each input row; may be NULL
  *   edges      [n-1][2] int64 out (host), sorted by K = (w^2, d^2, min, max)
  *   weights    [n-1] float64 out (host), mutual reachability distances; may be NULL
