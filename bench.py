@@ -684,6 +684,13 @@ def main():
     if a.workload == "serve_poisson":
         G.load()
         return bench_serve(a, G)
+    if a.workload == "optics_500k":
+        G.load()
+        for _ in range(a.warmup):
+            G.optics_approx(torch.zeros((2, 3), dtype=torch.float64, device="cuda:0"), 1, 0.125)
+        rec = extra_optics(G, torch, np, a.steps)
+        print(json.dumps({"workload": "optics_500k", "n_gpus": 1, "steps": a.steps, **rec}), flush=True)
+        return
     wl = WORKLOADS[a.workload]
     log(f"workload {a.workload}: generating")
     pts = gen(a.workload)
