@@ -402,7 +402,8 @@ __global__ void k_init_frontier(TreeView t, int hdb, const u32* pinst, PairRec* 
     p.a = (u32)c.x;
     p.b = (u32)c.y;
     double2 z = make_double2(0.0, 0.0);
-    p.lb2 = pair_wlb2<D>(N[p.a], N[p.b], hdb, hdb ? t.cdr[p.a] : z, hdb ? t.cdr[p.b] : z);
+    const NodeRec<D> A = N[p.a], B = N[p.b];
+    p.lb2 = pair_wlb2<D>(A, B, hdb, hdb ? node_cd<D>(t, A, p.a) : z, hdb ? node_cd<D>(t, B, p.b) : z);
     if (pinst && pinst[N[p.a].first] != pinst[N[p.b].first]) p.lb2 = __longlong_as_double(0x7ff0000000000000ll);
     f[i] = p;
 }
@@ -623,7 +624,7 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
         const int ka = A.comp, kb = B.comp;
         if (!(ka >= 0 && ka == kb)) {
             double2 z = make_double2(0.0, 0.0);
-            double2 ca = hdb ? t.cdr[a] : z, cb = hdb ? t.cdr[b] : z;
+            double2 ca = hdb ? node_cd<D>(t, A, a) : z, cb = hdb ? node_cd<D>(t, B, b) : z;
             lb = pair_wlb2<D>(A, B, hdb, ca, cb);
             const double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
             if (lb > r.beta2 && !card_due<D>(t, r.beta_card, a, b)) {
@@ -652,7 +653,7 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
                 // others, park the far ones
                 const NodeRec<D> C0 = N[ch.x], C1 = N[ch.y];
                 int kc[2] = {C0.comp, C1.comp};
-                double2 c0 = hdb ? t.cdr[ch.x] : z, c1 = hdb ? t.cdr[ch.y] : z;
+                double2 c0 = hdb ? node_cd<D>(t, C0, (u32)ch.x) : z, c1 = hdb ? node_cd<D>(t, C1, (u32)ch.y) : z;
                 lbc[0] = pair_wlb2<D>(C0, O, hdb, c0, co);
                 lbc[1] = pair_wlb2<D>(C1, O, hdb, c1, co);
 #pragma unroll
@@ -940,7 +941,7 @@ __global__ void __launch_bounds__(kBlock) k_rho_level(TreeView t, int hdb, int m
         const NodeRec<D> A = N[p.a], B = N[p.b];
         const double cur = bitsd(__hip_atomic_load(rho, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         const bool conn = A.comp >= 0 && A.comp == B.comp;
-        const double2 ca = hdb ? t.cdr[p.a] : z, cb = hdb ? t.cdr[p.b] : z;
+        const double2 ca = hdb ? node_cd<D>(t, A, p.a) : z, cb = hdb ? node_cd<D>(t, B, p.b) : z;
         const double lb = pair_wlb2<D>(A, B, hdb, ca, cb);
         if (!conn && (u64)A.count + (u64)B.count > (u64)beta_card && lb < cur) {
             const double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
@@ -954,7 +955,7 @@ __global__ void __launch_bounds__(kBlock) k_rho_level(TreeView t, int hdb, int m
                 const double2 co = split_a ? cb : ca;
                 const int2 ch = node_kids(t.n, X.first, X.count, X.split);
                 const NodeRec<D> C0 = N[ch.x], C1 = N[ch.y];
-                const double2 k0 = hdb ? t.cdr[ch.x] : z, k1 = hdb ? t.cdr[ch.y] : z;
+                const double2 k0 = hdb ? node_cd<D>(t, C0, (u32)ch.x) : z, k1 = hdb ? node_cd<D>(t, C1, (u32)ch.y) : z;
                 c0.a = (u32)ch.x;
                 c0.b = oth;
                 c0.lb2 = pair_wlb2<D>(C0, O, hdb, k0, co);

@@ -29,21 +29,38 @@ namespace geomst {
 // and the record fits one 64-byte line (80 bytes for d = 7) instead of two;
 // every bound computed from it is then still a bound of the computed
 // point-to-point values, only looser by the rounding.
+//
+// Where the padded record has 8 spare bytes (d = 4, 5, 7) it also carries
+// the node's core-distance range (HDBSCAN*) in binary32, the minimum rounded
+// down and the maximum up, so that the decomposition reads a node's box and
+// core distances from one line; the exact binary64 ranges stay in their own
+// array for every other use.
 template <int D>
 struct NodeBox {
     using type = typename std::conditional<(D >= 4), float, double>::type;
-    static constexpr int bytes = 2 * D * (int)sizeof(type) + 16;
+    static constexpr bool cd_in = D == 4 || D == 5 || D == 7;
+    static constexpr int bytes = 2 * D * (int)sizeof(type) + 16 + (cd_in ? 8 : 0);
     static constexpr int align = bytes <= 32 ? 32 : bytes <= 64 ? 64 : 16;
 };
 
+template <bool C>
+struct NodeCd {};
+template <>
+struct NodeCd<true> {
+    float cdlo, cdhi;  // (min cd2, max cd2) of the node's points, rounded outward
+};
+
 template <int D>
-struct alignas(NodeBox<D>::align) NodeRec {
+struct alignas(NodeBox<D>::align) NodeRec : NodeCd<NodeBox<D>::cd_in> {
     typename NodeBox<D>::type lo[D];
     typename NodeBox<D>::type hi[D];
     int first, count;
     int split;  // radix-tree split position g of an internal node; -1 for a leaf
     int comp;   // component of all the node's points, or -1
 };
+static_assert(sizeof(NodeRec<3>) == 64 && sizeof(NodeRec<4>) == 64 && sizeof(NodeRec<5>) == 64 &&
+                  sizeof(NodeRec<6>) == 64 && sizeof(NodeRec<7>) == 80,
+              "one 64-byte line per record up to d = 6");
 
 // Binary32 bounds rounded outward (towards -inf for a lower bound, +inf for
 // an upper bound); the comparisons with the binary64 value are exact.
@@ -74,6 +91,26 @@ struct TreeView {
 template <int D>
 __device__ __forceinline__ const NodeRec<D>* nodes_of(const TreeView& t) {
     return (const NodeRec<D>*)t.nodes;
+}
+
+// Core-distance range (min cd2, max cd2) of node `id` whose record is X:
+// from the record where it carries one (a range that contains the exact
+// one), else from the exact array.
+template <int D>
+__device__ __forceinline__ double2 node_cd(const TreeView& t, const NodeRec<D>& X, u32 id) {
+    if constexpr (NodeBox<D>::cd_in) return make_double2((double)X.cdlo, (double)X.cdhi);
+    else return t.cdr[id];
+}
+
+// Stores a node's exact range and, where the record has room, its outward
+// binary32 copy.
+template <int D>
+__device__ __forceinline__ void put_cd(NodeRec<D>& V, double2* cdr, int v, double2 cd) {
+    cdr[v] = cd;
+    if constexpr (NodeBox<D>::cd_in) {
+        V.cdlo = round_down_f32(cd.x);
+        V.cdhi = round_up_f32(cd.y);
+    }
 }
 
 // Children of an internal node from its range [f, f+c) and split g: the left
@@ -437,7 +474,7 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
         L.split = -1;
         L.comp = -1;
     }
-    if (cd2) cdr[leaf] = make_double2(cd2[p], cd2[p]);
+    if (cd2) put_cd<D>(nodes[leaf], cdr, leaf, make_double2(cd2[p], cd2[p]));
     int child = leaf;
     int v = parent[leaf];
     while (v >= 0) {
@@ -481,7 +518,7 @@ __global__ void __launch_bounds__(kBoundsBlock) k_bounds_local(int n, const doub
             double2 cb = (ch.y >= n - 1) ? make_double2(cd2[ch.y - (n - 1)], cd2[ch.y - (n - 1)]) : scd[ch.y - base];
             cd = make_double2(fmin(ca.x, cb.x), fmax(ca.y, cb.y));
             scd[v - base] = cd;
-            cdr[v] = cd;
+            put_cd<D>(V, cdr, v, cd);
         }
         if (geometry) write_box<D>(V, lo, hi);
         child = v;
@@ -531,7 +568,7 @@ __global__ void __launch_bounds__(kBoundsTop) k_bounds_top(int n, const int* par
             if (hdb) {
                 const volatile double2* ca = cdr + ch.x;
                 const volatile double2* cb = cdr + ch.y;
-                cdr[v] = make_double2(fmin(ca->x, cb->x), fmax(ca->y, cb->y));
+                put_cd<D>(V, cdr, v, make_double2(fmin(ca->x, cb->x), fmax(ca->y, cb->y)));
             }
             c = v;
             v = parent[v];
