@@ -71,9 +71,11 @@ def solve(G, x, min_pts):
 def node_record_bytes(d, hdb=False):
     """Bytes of one tree node the expansion reads: the box (2d binary64 bounds
     for d <= 3, 2d binary32 for d >= 4), first/count/split/component (16 B),
-    and the (min, max) core-distance range (16 B) for HDBSCAN*."""
+    and for HDBSCAN* the (min, max) core-distance range: 8 B in the record
+    where it fits (d = 4, 5, 7), else 16 B from its own array."""
     box = 16 * d if d <= 3 else 8 * d
-    return box + 16 + (16 if hdb else 0)
+    cd = 0 if not hdb else (8 if d in (4, 5, 7) else 16)
+    return box + 16 + cd
 
 
 def unit_model(fam, st, d, hdb=False):
