@@ -215,4 +215,74 @@ __global__ void __launch_bounds__(kPartBlock) k_partition_cand(EdgeList in, u32 
     }
 }
 
+// Weight buckets of the candidates: bucket b holds the candidates whose w2
+// bit pattern is at least t[b-1] and below t[b] (t ascending; the last
+// bucket is open above).  Counted first, then scattered into one list laid
+// out bucket after bucket, so the filtered Kruskal moves every candidate
+// once.
+constexpr int kMaxBuckets = 8;
+struct Buckets {
+    u64 t[kMaxBuckets - 1];
+    int nt;  // thresholds in use; nt + 1 buckets
+};
+
+__device__ __forceinline__ int bucket_of(const Buckets& bk, double w2) {
+    const u64 x = (u64)__double_as_longlong(w2);
+    int b = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxBuckets - 1; ++i) b += (i < bk.nt && x >= bk.t[i]) ? 1 : 0;
+    return b;
+}
+
+__global__ void __launch_bounds__(kPartBlock) k_bucket_count(const double* w2, u32 m, Buckets bk, u32* counts) {
+    __shared__ u32 h[kMaxBuckets];
+    if (threadIdx.x < kMaxBuckets) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (u32 v = blockIdx.x * kPartBlock + threadIdx.x; v < m; v += gridDim.x * kPartBlock)
+        atomicAdd(&h[bucket_of(bk, w2[v])], 1u);
+    __syncthreads();
+    if (threadIdx.x <= (unsigned)bk.nt && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+}
+
+using BucketAlloc = BlockAllocN<kMaxBuckets, 16>;
+
+// Scatter: bucket b's candidates go to out[base[b] + k], k from cursor[b].
+__global__ void __launch_bounds__(kPartBlock) k_bucket_scatter(EdgeList in, u32 m, Buckets bk, EdgeList out,
+                                                               Buckets base, u32* cursor) {
+    __shared__ BucketAlloc S;
+    u32* ctr[kMaxBuckets];
+#pragma unroll
+    for (int i = 0; i < kMaxBuckets; ++i) ctr[i] = i <= bk.nt ? cursor + i : nullptr;
+    const u32 stride = gridDim.x * kPartBlock;
+    for (u32 v0 = blockIdx.x * kPartBlock; v0 < m; v0 += stride) {
+        const u32 v = v0 + threadIdx.x;
+        int b = -1;
+        double w2 = 0.0, e2 = 0.0;
+        u64 ids = 0, pos = 0;
+        if (v < m) {
+            w2 = in.w2[v];
+            e2 = in.e2[v];
+            ids = in.ids[v];
+            pos = in.pos[v];
+            b = bucket_of(bk, w2);
+        }
+        u32 c[kMaxBuckets];
+#pragma unroll
+        for (int i = 0; i < kMaxBuckets; ++i) c[i] = b == i ? 1u : 0u;
+        u32 off[kMaxBuckets];
+        block_alloc(S, c, ctr, off);
+        if (b >= 0) {
+            u32 o = 0;
+            u64 bs = 0;
+#pragma unroll
+            for (int i = 0; i < kMaxBuckets; ++i)
+                if (b == i) {
+                    o = off[i];
+                    bs = i == 0 ? 0ull : base.t[i - 1];
+                }
+            put_edge_raw(out, (u32)(bs + o), w2, e2, ids, pos);
+        }
+    }
+}
+
 }  // namespace geomst

@@ -945,66 +945,102 @@ struct Solver {
         }
     }
 
-    // Kruskal over the m approximate-OPTICS candidates in D.C, a light
-    // slice at a time (see k_partition_cand): each slice holds the lightest
-    // quarter of what remains (at least 3n candidates), below a threshold
-    // read off a strided sample of the remaining weights; the rest keeps
-    // only edges between components.
+    // Kruskal over the m approximate-OPTICS candidates in D.C by weight
+    // buckets: the candidates are scattered once into buckets cut at
+    // quantiles of a strided sample of their weights (the lightest ~3n
+    // candidates, then up to 1/16, 1/4, 1/2, 5/8, 3/4 and 7/8 of them, then
+    // the rest);
+    // bucket 0 goes to Kruskal as it is, every later bucket first drops the
+    // edges whose ends the lighter buckets have already joined (cycle
+    // property), and the buckets stop once the tree is complete.
     void kruskal_filtered(u32 m) {
-        EdgeBufs* R = &D.C;
-        EdgeBufs* H = &D.P[1];
-        EdgeBufs& Lt = D.P[0];
-        u64 mr = m;
         const u64 slice_min = std::max<u64>((u64)3 * (u64)n, 1u << 16);
+        if ((u64)m <= 2 * slice_min) {
+            kruskal(D.C.list(), m);
+            return;
+        }
         constexpr u32 kSample = 1u << 16;
         D.minmax.ensure(kSample * 8);
-        std::vector<double> smp;
-        while (mr) {
+        const u64 step = (u64)m / kSample;
+        const u32 ns = (u32)std::min<u64>(kSample, (u64)m / step);
+        k_sample_w2<<<blocks(ns, 256), 256, 0, s>>>(D.C.w2.as<double>(), m, step, ns, D.minmax.as<double>());
+        LAUNCHCHK();
+        std::vector<double> smp(ns);
+        HIPCHK(hipMemcpyAsync(smp.data(), D.minmax.p, (size_t)ns * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::sort(smp.begin(), smp.end());
+        const double fr[7] = {std::max((double)slice_min / (double)m, 1.0 / 128.0), 1.0 / 16.0, 0.25, 0.5, 0.625,
+                              0.75, 0.875};
+        Buckets bk{};
+        bk.nt = 0;
+        for (double f : fr) {
+            const size_t q = std::min<size_t>(ns - 1, (size_t)(f * (double)ns));
+            u64 tb;
+            memcpy(&tb, &smp[q], 8);
+            ++tb;  // bucket below: w2 <= the quantile
+            if (bk.nt == 0 || tb > bk.t[bk.nt - 1]) bk.t[bk.nt++] = tb;
+        }
+        const int nbk = bk.nt + 1;
+        u32* cnt = aux_dev(D, kAuxLstate);  // 2 words there, then room up to the alive counts
+        static_assert(kAuxNalive - kAuxLstate >= 2 * kMaxBuckets * 4, "bucket counters fit the state words");
+        u32* cur = cnt + kMaxBuckets;
+        HIPCHK(hipMemsetAsync(cnt, 0, 2 * kMaxBuckets * 4, s));
+        {
+            TIMED(GEOMST_K_KRUSKAL);
+            k_bucket_count<<<std::min(blocks(m, kPartBlock), 4096u), kPartBlock, 0, s>>>(D.C.w2.as<double>(), m, bk,
+                                                                                        cnt);
+            LAUNCHCHK();
+        }
+        read_counters(D, s, kAuxLstate + 2 * kMaxBuckets * 4);
+        u32 count[kMaxBuckets], off[kMaxBuckets];
+        Buckets base{};
+        base.nt = bk.nt;
+        u32 run = 0;
+        for (int b = 0; b < nbk; ++b) {
+            count[b] = aux_host(D, kAuxLstate)[b];
+            off[b] = run;
+            if (b) base.t[b - 1] = run;
+            run += count[b];
+        }
+        if (run != m) {
+            g_err = "candidate buckets lost entries";
+            throw Fail{GEOMST_EINTERNAL};
+        }
+        D.P[0].ensure((size_t)m, 0, s);
+        {
+            TIMED(GEOMST_K_KRUSKAL);
+            k_bucket_scatter<<<std::min(blocks(m, kPartBlock), 4096u), kPartBlock, 0, s>>>(D.C.list(), m, bk,
+                                                                                          D.P[0].list(), base, cur);
+            LAUNCHCHK();
+        }
+        u32 maxb = 0;
+        for (int b = 1; b < nbk; ++b) maxb = std::max(maxb, count[b]);
+        if (maxb) D.P[1].ensure((size_t)maxb, 0, s);
+        for (int b = 0; b < nbk; ++b) {
+            if (!count[b]) continue;
+            EdgeList L = D.P[0].list();
+            EdgeList seg{L.w2 + off[b], L.e2 + off[b], L.ids + off[b], L.pos + off[b]};
+            if (b == 0) {
+                kruskal(seg, count[b]);
+                continue;
+            }
             read_counters(D, s);
             if (D.hcnt->c[C_OUT] >= target_edges) break;
-            // a quarter of what remains (at least 3n): the filter then drops
-            // most of the rest, so a few slices do
-            const u64 slice = std::max<u64>(slice_min, mr / 4);
-            if (mr <= 2 * slice_min) {
-                kruskal(R->list(), (u32)mr);
-                break;
-            }
-            // threshold: the sample quantile at slice / mr
-            const u64 step = mr / kSample;
-            const u32 ns = (u32)std::min<u64>(kSample, mr / step);
-            k_sample_w2<<<blocks(ns, 256), 256, 0, s>>>(R->w2.as<double>(), mr, step, ns, D.minmax.as<double>());
-            LAUNCHCHK();
-            smp.resize(ns);
-            HIPCHK(hipMemcpyAsync(smp.data(), D.minmax.p, (size_t)ns * 8, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            const size_t q = std::min<size_t>(ns - 1, (size_t)((double)ns * (double)slice / (double)mr));
-            std::nth_element(smp.begin(), smp.begin() + q, smp.end());
-            u64 tbits;
-            memcpy(&tbits, &smp[q], 8);
-            ++tbits;  // light: w2 <= the quantile
-            const u64 cap_light = std::min<u64>(mr, slice + slice / 4 + mr / 64);
-            Lt.ensure((size_t)cap_light, 0, s);
-            H->ensure((size_t)mr, 0, s);
-            HIPCHK(hipMemsetAsync(&D.cnt.as<Counters>()->c[C_QN], 0, 4, s));
             HIPCHK(hipMemsetAsync(&D.cnt.as<Counters>()->c[C_C], 0, 4, s));
             {
                 TIMED(GEOMST_K_KRUSKAL);
-                k_partition_cand<<<std::min(blocks(mr, kPartBlock), 4096u), kPartBlock, 0, s>>>(
-                    R->list(), (u32)mr, tbits, Lt.list(), (u32)cap_light, H->list(), D.uf.as<u32>(),
-                    D.cnt.as<Counters>());
+                // tbits 0: every candidate takes the heavy test (ends in
+                // different components), none is light
+                k_partition_cand<<<std::min(blocks(count[b], kPartBlock), 4096u), kPartBlock, 0, s>>>(
+                    seg, count[b], 0ull, D.P[1].list(), 0u, D.P[1].list(), D.uf.as<u32>(), D.cnt.as<Counters>());
                 LAUNCHCHK();
             }
             read_counters(D, s);
-            const u32 nl = D.hcnt->c[C_QN], nh = D.hcnt->c[C_C];
-            if (nl > cap_light) {  // the sample misjudged the slice: all that remains at once
-                kruskal(R->list(), (u32)mr);
-                break;
-            }
-            if (g_trace) fprintf(stderr, "[geomst] filtered kruskal: %llu candidates, %u light, %u kept\n",
-                                 (unsigned long long)mr, nl, nh);
-            if (nl) kruskal(Lt.list(), nl);
-            std::swap(R, H);  // the kept heavy edges are the next round's input
-            mr = nh;
+            const u32 kept = D.hcnt->c[C_C];
+            if (g_trace)
+                fprintf(stderr, "[geomst] filtered kruskal: bucket %d of %d: %u candidates, %u kept\n", b, nbk,
+                        count[b], kept);
+            if (kept) kruskal(D.P[1].list(), kept);
         }
     }
 
