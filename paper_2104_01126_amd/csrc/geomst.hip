@@ -2351,12 +2351,21 @@ void run_batch(Server* S, Device& D, std::vector<Request*>& batch) {
             }
             for (size_t i = 0; i < grp.size(); ++i) {
                 // one request may use the whole budget less what the other
-                // workers hold now
-                size_t others = 0;
-                for (auto& w : S->ws)
-                    if (w.get() != &D) others += w->budget.held.load(std::memory_order_relaxed);
-                status[i] = solve(&it[i], 1, S->budget > others ? S->budget - others : 0);
-                err[i] = g_err;
+                // workers hold now; when that is not enough, this worker's
+                // workspace is released and the request waits (bounded) for
+                // the others to finish and release theirs
+                for (int attempt = 0;; ++attempt) {
+                    size_t others = 0;
+                    for (auto& w : S->ws)
+                        if (w.get() != &D) others += w->budget.held.load(std::memory_order_relaxed);
+                    status[i] = solve(&it[i], 1, S->budget > others ? S->budget - others : 0);
+                    err[i] = g_err;
+                    if (status[i] != GEOMST_ENOMEM || attempt == 20) break;
+                    if (D.own) (void)hipStreamSynchronize(D.own);
+                    D.~Device();
+                    new (&D) Device();
+                    std::this_thread::sleep_for(std::chrono::milliseconds(50));
+                }
             }
         }
         {
@@ -2426,7 +2435,17 @@ void worker_loop(Server* S, int wi) {
             S->st.max_batch_requests = std::max<int64_t>(S->st.max_batch_requests, (int64_t)batch.size());
             S->st.max_batch_points = std::max(S->st.max_batch_points, pts);
         }
-        if (!batch.empty()) run_batch(S, D, batch);
+        if (!batch.empty()) {
+            run_batch(S, D, batch);
+            // a workspace grown beyond the worker's share (a request solved
+            // alone after a batch outgrew it) is released, so that the other
+            // workers' fallbacks find the budget free again
+            if (D.budget.held.load(std::memory_order_relaxed) > S->cap_per_worker) {
+                if (D.own) (void)hipStreamSynchronize(D.own);
+                D.~Device();
+                new (&D) Device();
+            }
+        }
         std::lock_guard<std::mutex> lk(S->mu);
         S->st.reserved_bytes -= (int64_t)fp;
     }

@@ -148,7 +148,8 @@ __device__ __forceinline__ bool card_due(const TreeView& t, u32 beta_card, u32 a
 // single points is always separated.
 template <int D>
 __device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRec<D>& B, int mutual, double2 ca,
-                                               double2 cb, double s, double dA, double dB) {
+                                               double2 cb, double s, double dA, double dB, const TreeView& t, u32 ia,
+                                               u32 ib) {
     if (A.count == 1 && B.count == 1) return true;
     double L = box_lb2<D>(A, B);
     // sphere radii: half the box diagonals (single precision suffices, the
@@ -163,6 +164,13 @@ __device__ __forceinline__ bool well_separated(const NodeRec<D>& A, const NodeRe
     double need = ra + rb + s * fmax(ra, rb);
     bool geo = (fmax(dA, dB) < L) && (c2 >= need * need);
     if (geo || !mutual) return geo;
+    // the mutual test compares core distances with each other: it takes the
+    // exact ranges (a record's binary32 copy would make it stricter than
+    // needed and lose most of its pairs)
+    if constexpr (NodeBox<D>::cd_in) {
+        ca = t.cdr[ia];
+        cb = t.cdr[ib];
+    }
     double gap = fmax(sqrt(c2) - ra - rb, 0.0);
     double lhs_s = fmax(fmax(dA, dB), fmax(ca.y, cb.y));
     double rhs_s = fmax(gap * gap, fmax(ca.x, cb.x));
@@ -629,7 +637,7 @@ __device__ __forceinline__ void level_step(const TreeView& t, const RoundArgs& r
             const double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
             if (lb > r.beta2 && !card_due<D>(t, r.beta_card, a, b)) {
                 to_f = true;
-            } else if (well_separated<D>(A, B, hdb && r.mutual, ca, cb, r.sep, dA, dB)) {
+            } else if (well_separated<D>(A, B, hdb && r.mutual, ca, cb, r.sep, dA, dB, t, a, b)) {
                 u64 work = (u64)A.count * (u64)B.count;
                 if (work <= (u64)kTinyEvals) {
                     // solved by k_tiny_bccp after the level loop, away from
@@ -945,7 +953,7 @@ __global__ void __launch_bounds__(kBlock) k_rho_level(TreeView t, int hdb, int m
         const double lb = pair_wlb2<D>(A, B, hdb, ca, cb);
         if (!conn && (u64)A.count + (u64)B.count > (u64)beta_card && lb < cur) {
             const double dA = box_diag2<D>(A), dB = box_diag2<D>(B);
-            if (well_separated<D>(A, B, hdb && mutual, ca, cb, sep, dA, dB)) {
+            if (well_separated<D>(A, B, hdb && mutual, ca, cb, sep, dA, dB, t, p.a, p.b)) {
                 atomicMin((unsigned long long*)rho, (unsigned long long)dbits(lb));
             } else {
                 const bool split_a = (B.count == 1) || (A.count > 1 && (dA > dB || (dA == dB && A.count >= B.count)));
