@@ -246,10 +246,16 @@ def replay(G, trace, pts, server_kw, label, dump=None):
     lat = np.zeros(len(trace))
     qdepth = 0
     done_at = 0.0
+    failed = []
     for i in range(len(trace)):
         while tickets[i] is None:
             time.sleep(0.0005)
-        e, w, cd, info = S.wait(tickets[i])
+        try:
+            e, w, cd, info = S.wait(tickets[i])
+        except G.GeomstError as err:  # recorded, not fatal: the line must still be printed
+            failed.append({"i": trace[i].index, "n": trace[i].n, "d": trace[i].d, "code": err.code})
+            lat[i] = np.nan
+            continue
         lat[i] = lag[i] * 1000.0 + info["latency_ms"]
         if dump is not None:
             r = trace[i]
@@ -265,10 +271,13 @@ def replay(G, trace, pts, server_kw, label, dump=None):
     st = S.stats()
     S.close()
     span = done_at - trace[0].arrival_s
-    npts = sum(r.n for r in trace)
-    return {"solves_per_s": round(len(trace) / span, 2), "points_per_s": round(npts / span, 1),
-            "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
-            "mean_ms": round(float(lat.mean()), 2), "makespan_s": round(span, 3),
+    ok = ~np.isnan(lat)
+    npts = sum(r.n for r, good in zip(trace, ok) if good)
+    latok = lat[ok] if ok.any() else np.zeros(1)
+    return {"solves_per_s": round(int(ok.sum()) / span, 2), "points_per_s": round(npts / span, 1),
+            "p50_ms": round(float(np.percentile(latok, 50)), 2), "p99_ms": round(float(np.percentile(latok, 99)), 2),
+            "mean_ms": round(float(latok.mean()), 2), "makespan_s": round(span, 3),
+            "failed_requests": len(failed), "failures": failed[:8],
             "batches_incl_warmup": st["batches"], "max_batch_requests": st["max_batch_requests"],
             "peak_reserved_gb": round(st["peak_reserved_bytes"] / 1e9, 2), "max_queue_seen": qdepth,
             "enomem_batches": st["enomem_batches"], "workspace_gb": round(st["workspace_bytes"] / 1e9, 2)}

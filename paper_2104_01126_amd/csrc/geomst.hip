@@ -2289,8 +2289,16 @@ struct Server {
     std::vector<std::unique_ptr<Device>> ws;
     uint64_t next_ticket = 1;
     bool stop = false;
+    std::atomic<int> want_release{0};  // workers solving a request alone that needs the others' memory
     geomst_server_stats_t st{};
 };
+
+// Releases a worker's workspace (waits for its queued work first).
+void release_workspace(Device& D) {
+    if (D.own) (void)hipStreamSynchronize(D.own);
+    D.~Device();
+    new (&D) Device();
+}
 
 // Solves a taken batch as forests of equal dimension and kind (EMST or
 // HDBSCAN*), so that no instance pays for padded coordinates or for the
@@ -2342,30 +2350,52 @@ void run_batch(Server* S, Device& D, std::vector<Request*>& batch) {
             // The workspace outgrew the device (the admission estimate does
             // not cover the pair lists of high-dimensional inputs): release
             // it and solve the requests one at a time.
-            if (D.own) (void)hipStreamSynchronize(D.own);  // nothing of the failed solve may still run
-            D.~Device();
-            new (&D) Device();
+            release_workspace(D);  // nothing of the failed solve may still run
             {
                 std::lock_guard<std::mutex> lk(S->mu);
                 S->st.enomem_batches += 1;
             }
+            auto others_hold = [&] {
+                size_t o = 0;
+                for (auto& w : S->ws)
+                    if (w.get() != &D) o += w->budget.held.load(std::memory_order_relaxed);
+                return o;
+            };
             for (size_t i = 0; i < grp.size(); ++i) {
                 // one request may use the whole budget less what the other
-                // workers hold now; when that is not enough, this worker's
-                // workspace is released and the request waits (bounded) for
-                // the others to finish and release theirs
-                for (int attempt = 0;; ++attempt) {
-                    size_t others = 0;
-                    for (auto& w : S->ws)
-                        if (w.get() != &D) others += w->budget.held.load(std::memory_order_relaxed);
-                    status[i] = solve(&it[i], 1, S->budget > others ? S->budget - others : 0);
+                // workers hold now; when that is not enough it is solved
+                // alone in whatever device memory is free (the budget is a
+                // soft admission limit; such solves count in
+                // enomem_batches); if the device itself runs out, the other
+                // workers are asked to release their workspaces after their
+                // current batch (idle ones at once), this worker releases its
+                // own, and the request is solved again once they have (or
+                // after two minutes) with what is then free
+                size_t others = others_hold();
+                status[i] = solve(&it[i], 1, S->budget > others ? S->budget - others : 0);
+                err[i] = g_err;
+                if (status[i] == GEOMST_ENOMEM) {
+                    status[i] = solve(&it[i], 1, ~(size_t)0);
                     err[i] = g_err;
-                    if (status[i] != GEOMST_ENOMEM || attempt == 20) break;
-                    if (D.own) (void)hipStreamSynchronize(D.own);
-                    D.~Device();
-                    new (&D) Device();
-                    std::this_thread::sleep_for(std::chrono::milliseconds(50));
                 }
+                bool asked = false;
+                for (int attempt = 0; attempt < 8 && status[i] == GEOMST_ENOMEM; ++attempt) {
+                    if (asked && others == 0) break;
+                    if (!asked) {
+                        asked = true;
+                        S->want_release.fetch_add(1);
+                        std::lock_guard<std::mutex> lk(S->mu);
+                        S->cv_work.notify_all();
+                    }
+                    release_workspace(D);
+                    const auto t0 = Clock::now();
+                    while (others_hold() != 0 && Clock::now() - t0 < std::chrono::seconds(120))
+                        std::this_thread::sleep_for(std::chrono::milliseconds(20));
+                    others = others_hold();
+                    status[i] = solve(&it[i], 1, S->budget > others ? S->budget - others : ~(size_t)0);
+                    err[i] = g_err;
+                }
+                if (asked) S->want_release.fetch_sub(1);
             }
         }
         {
@@ -2404,8 +2434,18 @@ void worker_loop(Server* S, int wi) {
         size_t fp = 0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [&] { return S->stop || !S->lane[0].empty() || !S->lane[1].empty(); });
+            const auto release_asked = [&] {
+                return S->want_release.load() > 0 && D.budget.held.load(std::memory_order_relaxed) > 0;
+            };
+            S->cv_work.wait(lk, [&] {
+                return S->stop || !S->lane[0].empty() || !S->lane[1].empty() || release_asked();
+            });
             if (S->stop) break;
+            if (S->lane[0].empty() && S->lane[1].empty()) {  // woken only to let go of the workspace
+                lk.unlock();
+                release_workspace(D);
+                continue;
+            }
             int ln;
             if (S->lane[0].empty()) ln = 1;
             else if (S->lane[1].empty()) ln = 0;
@@ -2437,14 +2477,10 @@ void worker_loop(Server* S, int wi) {
         }
         if (!batch.empty()) {
             run_batch(S, D, batch);
-            // a workspace grown beyond the worker's share (a request solved
-            // alone after a batch outgrew it) is released, so that the other
-            // workers' fallbacks find the budget free again
-            if (D.budget.held.load(std::memory_order_relaxed) > S->cap_per_worker) {
-                if (D.own) (void)hipStreamSynchronize(D.own);
-                D.~Device();
-                new (&D) Device();
-            }
+            // another worker solving a request alone ran out of device
+            // memory: let go of this workspace (a grown workspace is
+            // otherwise kept: regrowing it costs list restarts)
+            if (S->want_release.load() > 0) release_workspace(D);
         }
         std::lock_guard<std::mutex> lk(S->mu);
         S->st.reserved_bytes -= (int64_t)fp;
