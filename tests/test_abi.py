@@ -63,6 +63,11 @@ def test_rejects_bad_arguments_without_device(lib):
     assert lib.geomst_hdbscan(p.ctypes.data, 4, 3, 65, cd.ctypes.data, e.ctypes.data, None) == G.EINVAL
     assert lib.geomst_emst_dev(None, 4, 3, None, None, None, None) == G.EINVAL
     assert lib.geomst_emst_dev_noalloc(None, 4, 3, None, None, None, None) == G.EINVAL
+    # approximate OPTICS: rho and minPts are checked before any device call
+    for mp, rho in ((0, 0.5), (65, 0.5), (3, 0.0), (3, -1.0), (3, float("nan")), (3, float("inf")), (5, 0.5)):
+        assert lib.geomst_optics_approx(p.ctypes.data, 4, 3, mp, rho, cd.ctypes.data, e.ctypes.data,
+                                        None) == G.EINVAL, (mp, rho)
+    assert lib.geomst_optics_approx_dev(None, 4, 3, 3, 0.5, None, None, None, None, None, None) == G.EINVAL
     o = np.zeros(4, np.int64)
     r = np.zeros(4)
     w = np.zeros(3)
