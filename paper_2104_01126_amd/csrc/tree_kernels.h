@@ -588,9 +588,26 @@ constexpr int kKnnSeed = 32;  // sorted neighbours on each side of a wave's quer
 // most two children.  A root-to-leaf path of the radix tree splits on a
 // distinct bit of (key words, position) at every node, so the depth is at
 // most 6 * 63 key bits + 26 position bits = 404 and 512 entries never
-// overflow (the check below stays as a guard).  LDS per wave: 2 KB stack +
-// (64 + 2 * 32) staged rows of 8d bytes.
+// overflow (the check below stays as a guard).  An entry is 8 bytes: the two
+// children of an internal node, or (~node, first position) of a node small
+// enough to scan, so that a pop needs no load of the node's own record
+// before the loads of what comes next.  LDS per wave: the seed window's
+// (64 + 2 * 32) rows of 8d bytes, whose bytes the walk then reuses for its
+// 4 KB stack and one scanned node's 32 rows.
 constexpr int kKnnStack = 512;
+
+template <int D>
+struct KnnLds {
+    static constexpr int seed = (kWave + 2 * kKnnSeed) * D;    // doubles
+    static constexpr int walk = kKnnLeaf * D + kKnnStack;      // doubles (one int2 each)
+    static constexpr int doubles = seed > walk ? seed : walk;
+};
+
+// The stack entry of node v (its record R already loaded).
+template <int D>
+__device__ __forceinline__ int2 knn_entry(int n, int v, const NodeRec<D>& R) {
+    return R.count <= kKnnLeaf ? make_int2(~v, R.first) : node_kids(n, R.first, R.count, R.split);
+}
 
 template <int KMAX>
 __device__ __forceinline__ void topk_insert(double (&top)[KMAX], double v) {
@@ -636,9 +653,10 @@ struct KnnWaves {
 template <int D, int KMAX>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KnnWaves<D, KMAX>::value))) k_knn(TreeView t, int kk_all, const u32* pinst, const int2* irange,
                                            const int* ik, double* cd2_out, u32* err) {
-    __shared__ int stack[kKnnStack];
     static_assert(kKnnLeaf <= kWave, "a leaf is staged one row per lane");
-    __shared__ double rows[(kWave + 2 * kKnnSeed) * D];  // staged candidate rows
+    __shared__ double lds[KnnLds<D>::doubles];
+    double* rows = lds;  // the seed window's rows, then one scanned node's
+    int2* stack = reinterpret_cast<int2*>(lds + kKnnLeaf * D);  // used after the seed scan
     const int n = t.n;
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
     int p = blockIdx.x * kWave + lane_id();
@@ -652,6 +670,16 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KnnWave
         hi_r = rg.x + rg.y;
         kk = ik[ins];
     }
+    // the positions inside every lane's instance (all of [0, n) outside a
+    // batch), in scalar registers
+    int lo_all = lo_r, hi_all = hi_r;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo_all = max(lo_all, __shfl_xor(lo_all, o));
+        hi_all = min(hi_all, __shfl_xor(hi_all, o));
+    }
+    lo_all = __builtin_amdgcn_readfirstlane(lo_all);
+    hi_all = __builtin_amdgcn_readfirstlane(hi_all);
     double q[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) q[k] = t.X[(size_t)pq * D + k];
@@ -686,52 +714,89 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KnnWave
             kth = top[KMAX - 1];
         }
     }
-    if (lane_id() == 0) stack[0] = 0;  // root (the single leaf when n == 1)
+    const NodeRec<D>* N = nodes_of<D>(t);
+    __syncthreads();  // the seed rows are read before the stack reuses them
+    if (lane_id() == 0) stack[0] = knn_entry<D>(n, 0, N[0]);  // root (the single leaf when n == 1)
     int sp = 1;
     __syncthreads();
     while (sp > 0) {
         --sp;
-        int v = stack[sp];
+        const int ex = __builtin_amdgcn_readfirstlane(stack[sp].x);
+        const int ey = __builtin_amdgcn_readfirstlane(stack[sp].y);
         __syncthreads();
-        const NodeRec<D>* N = nodes_of<D>(t);
-        double lb = point_box_lb2<D>(q, N[v].lo, N[v].hi);
-        int2 r = make_int2(N[v].first, N[v].count);
-        bool want = live && lb < kth && r.x < hi_r && r.x + r.y > lo_r;
-        if (!__any(want)) continue;
-        if (r.y <= kKnnLeaf) {
-            if (lane_id() < r.y)
+        if (ex < 0) {
+            // A node of at most kKnnLeaf points: its rows are loaded together
+            // with its record and staged before the bound is tested (a row
+            // past the node is loaded when it exists and never read).
+            const int v = ~ex, f = ey;
+            const int row = f + lane_id();
+            if (lane_id() < kKnnLeaf && row < n)
 #pragma unroll
-                for (int k = 0; k < D; ++k) rows[lane_id() * D + k] = t.X[(size_t)(r.x + lane_id()) * D + k];
+                for (int k = 0; k < D; ++k) rows[lane_id() * D + k] = t.X[(size_t)row * D + k];
+            const double lb = point_box_lb2<D>(q, N[v].lo, N[v].hi);
+            const int c = __builtin_amdgcn_readfirstlane(N[v].count);
+            const bool want = live && lb < kth && f < hi_r && f + c > lo_r;
+            if (!__any(want)) continue;
             __syncthreads();
-            for (int j = r.x; j < r.x + r.y; ++j) {
-                if (j >= pre_lo && j < pre_hi) continue;  // seeded already
-                double dd = sqdist<D>(q, rows + (j - r.x) * D);
-                if (dd < kth && j >= lo_r && j < hi_r) {
-                    topk_insert<KMAX>(top, dd);
-                    kth = top[KMAX - 1];
+            // A node outside the seed window and inside every lane's
+            // instance needs no per-row test beyond the distance itself.
+            const bool plain = (f >= win_hi || f + c <= win_lo) && f >= lo_all && f + c <= hi_all;
+            if (plain) {
+                int i = 0;
+                for (; i + 4 <= c; i += 4) {
+                    double dd[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) dd[u] = sqdist<D>(q, rows + (i + u) * D);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (dd[u] < kth) {
+                            topk_insert<KMAX>(top, dd[u]);
+                            kth = top[KMAX - 1];
+                        }
+                }
+                for (; i < c; ++i) {
+                    const double dd = sqdist<D>(q, rows + i * D);
+                    if (dd < kth) {
+                        topk_insert<KMAX>(top, dd);
+                        kth = top[KMAX - 1];
+                    }
+                }
+            } else {
+                for (int i = 0; i < c; ++i) {
+                    const int j = f + i;
+                    const double dd = sqdist<D>(q, rows + i * D);
+                    if (dd < kth && (j < pre_lo || j >= pre_hi) && j >= lo_r && j < hi_r) {  // not seeded, own instance
+                        topk_insert<KMAX>(top, dd);
+                        kth = top[KMAX - 1];
+                    }
                 }
             }
-            __syncthreads();  // the rows are read before the next leaf is staged
+            __syncthreads();  // the rows are read before the next node is staged
         } else {
+            // An internal node: the children's records are loaded at once.
+            // A child goes on the stack only if some lane may still want it
+            // (its range meets the lane's instance and its bound is below the
+            // lane's k-th distance): the k-th distances only shrink, so a
+            // child no lane wants now is never wanted later.  A child's box
+            // lies inside its parent's and the bound is monotone in the box,
+            // so a parent that no lane wants any more pushes nothing.  The
+            // child nearer to the queries of most lanes is visited first.
+            const NodeRec<D>& A = N[ex];
+            const NodeRec<D>& B = N[ey];
+            const double la = point_box_lb2<D>(q, A.lo, A.hi);
+            const double lb = point_box_lb2<D>(q, B.lo, B.hi);
+            const int af = A.first, ac = A.count, bf = B.first, bc = B.count;
+            const bool wa = __any(live && la < kth && af < hi_r && af + ac > lo_r);
+            const bool wb = __any(live && lb < kth && bf < hi_r && bf + bc > lo_r);
+            if (!wa && !wb) continue;
             if (sp + 2 > kKnnStack) {
                 if (lane_id() == 0) atomicOr(err, 4u);
                 continue;
             }
-            const int g = N[v].split;
-            int2 c = node_kids(n, r.x, r.y, g);
-            // A child goes on the stack only if some lane may still want it
-            // (its range [first, g] or [g + 1, last] meets the lane's
-            // instance and its bound is below the lane's k-th distance): the
-            // k-th distances only shrink, so a child no lane wants now is
-            // never wanted later, and skipping it saves a dependent load.
-            // The child nearer to lane 0's query is visited first.
-            double la = point_box_lb2<D>(q, N[c.x].lo, N[c.x].hi);
-            double lr = point_box_lb2<D>(q, N[c.y].lo, N[c.y].hi);
-            const bool wa = __any(live && la < kth && r.x < hi_r && g + 1 > lo_r);
-            const bool wb = __any(live && lr < kth && g + 1 < hi_r && r.x + r.y > lo_r);
-            bool leftfirst = __shfl(la <= lr ? 1 : 0, 0) != 0;
-            const int first = leftfirst ? c.y : c.x, second = leftfirst ? c.x : c.y;
-            const bool wfirst = leftfirst ? wb : wa, wsecond = leftfirst ? wa : wb;
+            const bool bfirst = __popcll(__ballot(la <= lb)) >= 32;  // b pushed first, popped second
+            const int2 ea = knn_entry<D>(n, ex, A), eb = knn_entry<D>(n, ey, B);
+            const int2 first = bfirst ? eb : ea, second = bfirst ? ea : eb;
+            const bool wfirst = bfirst ? wb : wa, wsecond = bfirst ? wa : wb;
             if (lane_id() == 0) {
                 if (wfirst) stack[sp] = first;
                 if (wsecond) stack[sp + (wfirst ? 1 : 0)] = second;
