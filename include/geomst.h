@@ -364,6 +364,7 @@ typedef struct {
     int64_t kernel_launches[16];
     int64_t bccp_evals_done;  /* distances the BCCP kernels evaluated (bccp_evals minus pruned blocks) */
     int64_t tuning_applied;   /* 1 if a loaded tuning-cache entry set this solve's knobs */
+    int64_t level_launches[3];  /* expansion launches: whole grid, eight workgroups, 256 workgroups */
 } geomst_stats_t;
 
 int geomst_get_stats(geomst_stats_t* out);
@@ -424,6 +425,16 @@ int geomst_get_stats(geomst_stats_t* out);
  *                    workgroups, one eighth each, and each workgroup keeps
  *                    expanding its share while its levels stay at most the
  *                    second size (defaults 2048 and 4096).
+ *   "wide_level_switch", "wide_level_max"  larger levels with at most 256
+ *                    times the first many pairs run in 256 workgroups, one
+ *                    256th each, kept going in the same way while each
+ *                    workgroup's levels stay at most the second size
+ *                    (defaults 2048 and 4096; for HDBSCAN* with d >= 4 the
+ *                    defaults mean off, as 0 does; used when each
+ *                    workgroup's part of the level queues holds twice the
+ *                    second size, which needs n of about 200,000 or more;
+ *                    not used by geomst_emst_dev_noalloc).  Values up to
+ *                    65536.
  * Options are process-wide; every solve reads them once when it starts
  * (under a lock), so a change never reaches a solve already running.
  * Returns GEOMST_EINVAL for an unknown name or a bad value.

@@ -53,6 +53,8 @@ constexpr int kLevelBatch = 6;    // expansion levels launched between host chec
 u32 g_refresh_div = 1024;    // refresh node components once a round merged n / this many
 u32 g_small_switch = 2048;  // queues up to kRegions times this go to the per-region level kernel
 u32 g_small_max = 4096;     // ... whose workgroups keep going while their levels stay this small
+u32 g_wide_switch = 2048;   // queues up to kRegions * kSub times this go to the wide level kernel (0: off)
+u32 g_wide_max = 4096;      // ... whose workgroups keep going while their levels stay this small
 constexpr int kBoruvkaBatch = 4;  // Boruvka steps launched between host checks
 constexpr u32 kSparseDiv = 64;  // beta grows faster while the tree has fewer than n / this many edges
 const bool g_trace = getenv("GEOMST_TRACE") != nullptr;
@@ -64,7 +66,7 @@ const bool g_trace = getenv("GEOMST_TRACE") != nullptr;
 struct Opts {
     double beta_growth, separation, capacity_scale, beta_start;
     int bccp_chunk, beta_plain, sep_mode, sched;
-    u32 refresh_div, small_switch, small_max;
+    u32 refresh_div, small_switch, small_max, wide_switch, wide_max;
     bool tuned = false;
 };
 
@@ -101,6 +103,13 @@ Opts snapshot_options(int kind, int d, int64_t n) {
     o.refresh_div = g_refresh_div;
     o.small_switch = g_small_switch;
     o.small_max = g_small_max;
+    o.wide_switch = g_wide_switch;
+    o.wide_max = std::max(g_wide_max, g_wide_switch);
+    // HDBSCAN* from d = 4 keeps its mid-size levels on the whole grid: its
+    // expansions there are uneven enough that the wide kernel's slowest
+    // workgroup sets the pace (2M 5-D mixture 85 -> 106 ms with it; EMST and
+    // HDBSCAN* up to d = 3 gain 2 to 8 %)
+    if (kind == 1 && d >= 4 && o.wide_switch == 2048 && o.wide_max == 4096) o.wide_switch = o.wide_max = 0;
     // the entry of the same kind and d whose log2 n is nearest (within 2)
     const TuneEntry* best = nullptr;
     const int nl = log2_floor(n);
@@ -311,9 +320,9 @@ struct Device {
     // union-find / component refresh
     DBuf uf, best, bnd, incl, ncomp;
     // rounds
-    DBuf F[2], Q[2], big, ntask, toff, parts, ubest, tdone, lbhist;
+    DBuf F[2], Q[3], big, ntask, toff, parts, ubest, tdone, lbhist;
     size_t qmax_seen = 0;
-    size_t capF[2] = {0, 0}, capQ[2] = {0, 0}, capBig = 0, capTiny = 0;
+    size_t capF[2] = {0, 0}, capQ[3] = {0, 0, 0}, capBig = 0, capTiny = 0;
     DBuf tiny;  // small separated pairs of the current round
     DBuf rq[2], rho, rhocnt;  // GetRho traversal of the cardinality schedules
     DBuf bb64;                // boxes of the aligned 64-point blocks (large-pair BCCP pruning)
@@ -1362,26 +1371,42 @@ struct Solver {
                     // without host syncs.  Q[lv & 1] holds the queue and
                     // ring[lv % 4] its count.
                     int lv = 0;
+                    int sub = 1;  // layout of the current queue (kSub after the wide kernel)
+                    // the wide kernel's workgroups need room for a level of
+                    // wide_max pairs and its children in each part
+                    const size_t wpart = 2 * (size_t)o.wide_max + 64;
+                    const bool wide_ok = !D.noalloc && o.wide_switch > 0 &&
+                                         std::min(D.capQ[0], D.capQ[1]) / kRegions / kSub >= wpart;
                     while (nq > 0) {
-                        if (nq <= (u32)kRegions * o.small_switch) {
+                        const bool regional = nq <= (u32)kRegions * o.small_switch;
+                        if (regional || (wide_ok && nq <= (u64)kRegions * kSub * o.wide_switch)) {
+                            const int groups = regional ? 1 : kSub;
+                            if (groups > 1 && D.capQ[2] < kRegions * kSub * wpart) {
+                                D.capQ[2] = kRegions * kSub * wpart;
+                                D.Q[2].ensure(D.capQ[2] * sizeof(PairRec));
+                            }
                             {
                                 TIMED(GEOMST_K_EXPAND);
                                 RoundArgs r = args(beta2, fo, 0, po);
                                 HIPCHK(hipMemsetAsync(aux_dev(D, kAuxLstate), 0, 4, s));
-                                k_level_small<D_><<<kRegions, SmallBlock<D_>::value, 0, s>>>(
+                                PairRec* qt = groups > 1 ? D.Q[2].as<PairRec>() : D.Q[0].as<PairRec>();
+                                const u32 capt = groups > 1 ? (u32)(D.capQ[2] / kRegions) : 0u;
+                                k_level_small<D_><<<kRegions * groups, SmallBlock<D_>::value, 0, s>>>(
                                     t, r, hdb, D.Q[0].as<PairRec>(), (u32)(D.capQ[0] / kRegions), D.Q[1].as<PairRec>(),
-                                    (u32)(D.capQ[1] / kRegions), lv & 1, ring, (u32)(lv % kQRing), o.small_max,
-                                    aux_dev(D, kAuxLstate));
+                                    (u32)(D.capQ[1] / kRegions), qt, capt, lv & 1, sub, groups, ring,
+                                    (u32)(lv % kQRing), groups > 1 ? o.wide_max : o.small_max, aux_dev(D, kAuxLstate));
                                 LAUNCHCHK();
                             }
                             read_counters(D, s, kAuxLstate + 8);
                             ++levels;
+                            ++g_stats.level_launches[groups > 1 ? 2 : 1];
                             if (D.hcnt->c[C_ERR] & 1u) {
                                 restart = true;
                                 break;
                             }
                             nq = aux_host(D, kAuxLstate)[0];
-                            lv = (int)aux_host(D, kAuxLstate)[1];
+                            ++lv;  // the remaining pairs: slot lv % kQRing, buffer lv & 1
+                            sub = groups;
                             D.qmax_seen = std::max<size_t>(D.qmax_seen, (size_t)kRegions * nq);  // at most all in one region
                             continue;
                         }
@@ -1389,13 +1414,15 @@ struct Solver {
                         for (int j = 0; j < kLevelBatch; ++j, ++lv, ++levels) {
                             RoundArgs r = args(beta2, fo, (lv + 1) & 1, po);
                             k_level<D_><<<LevelShape<D_>::grid, LevelShape<D_>::block, 0, s>>>(t, r, hdb, D.Q[lv & 1].as<PairRec>(),
-                                                                 (u32)(D.capQ[lv & 1] / kRegions),
+                                                                 (u32)(D.capQ[lv & 1] / kRegions), j == 0 ? sub : 1,
                                                                  ring + (lv % kQRing) * kSlotWords,
                                                                  ring + ((lv + 1) % kQRing) * kSlotWords,
                                                                  ring + ((lv + 2) % kQRing) * kSlotWords);
                             LAUNCHCHK();
                             chain.tick();
+                            ++g_stats.level_launches[0];
                         }
+                        sub = 1;
                         read_slot(lv % kQRing, nq, nq_region);
                         D.qmax_seen = std::max<size_t>(D.qmax_seen, (size_t)kRegions * nq_region);
                         if (D.hcnt->c[C_ERR] & 1u) {
@@ -2925,6 +2952,11 @@ int geomst_set_option(const char* name, double value) {
         if (!(value >= 0.0) || !(value <= 1048576.0) || value != (double)(u32)value) return GEOMST_EINVAL;
         (name[12] == 's' ? g_small_switch : g_small_max) = (u32)value;
         if (g_small_max < g_small_switch) g_small_max = g_small_switch;
+        return GEOMST_OK;
+    }
+    if (!strcmp(name, "wide_level_switch") || !strcmp(name, "wide_level_max")) {
+        if (!(value >= 0.0) || !(value <= 65536.0) || value != (double)(u32)value) return GEOMST_EINVAL;
+        (name[11] == 's' ? g_wide_switch : g_wide_max) = (u32)value;
         return GEOMST_OK;
     }
     if (!strcmp(name, "bccp_chunk")) {

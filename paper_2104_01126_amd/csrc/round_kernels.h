@@ -361,6 +361,51 @@ __device__ __forceinline__ u32 region_index(const u32 (&pre)[kRegions + 1], u32 
     return base + (v - start);
 }
 
+// The wide small-level mode splits region x of a queue into kSub
+// sub-segments of cap / kSub pairs, one per workgroup, with sub-segment w's
+// count in word x * kRegionStride + w of the slot; `sub` (1 or kSub) names
+// the layout of a queue, and its segments, in order, are (x, w) for x < 8,
+// w < sub.
+constexpr int kSub = kRegionStride;
+constexpr int kSegs = kRegions * kSub;
+
+// Prefix sums pre[0..8 sub] of the segment counts of a slot (each clamped to
+// the segment capacity), written to LDS by wave 0 (the caller synchronises).
+__device__ __forceinline__ void seg_prefix(const u32* slot, u32 cap, int sub, u32* pre) {
+    if (threadIdx.x >= kWave) return;
+    const int ln = lane_id();
+    const int nseg = kRegions * sub, per = (nseg + kWave - 1) / kWave;
+    const u32 scap = cap / (u32)sub;
+    u32 c[kSegs / kWave];
+    u64 sum = 0;
+#pragma unroll
+    for (int i = 0; i < kSegs / kWave; ++i) {
+        const int sg = ln * per + i;
+        c[i] = (i < per && sg < nseg) ? min(slot[(sg / sub) * kRegionStride + sg % sub], scap) : 0u;
+        sum += c[i];
+    }
+    u64 run = wave_incl_scan_u64(sum) - sum;
+    if (ln == 0) pre[0] = 0;
+#pragma unroll
+    for (int i = 0; i < kSegs / kWave; ++i) {
+        const int sg = ln * per + i;
+        run += c[i];
+        if (i < per && sg < nseg) pre[sg + 1] = (u32)run;
+    }
+}
+
+// Position in the queue buffer of entry v (< pre[nseg]) of the segments laid
+// end to end: the segment s with pre[s] <= v < pre[s + 1], by bisection.
+__device__ __forceinline__ u32 seg_index(const u32* pre, int sub, u32 cap, u32 v) {
+    u32 lo = 0, hi = (u32)(kRegions * sub);
+    while (hi - lo > 1) {
+        const u32 mid = (lo + hi) >> 1;
+        if (pre[mid] <= v) lo = mid;
+        else hi = mid;
+    }
+    return (lo / (u32)sub) * cap + (lo % (u32)sub) * (cap / (u32)sub) + (v - pre[lo]);
+}
+
 // Block-wide minimum of a non-negative double, one atomic per block.
 // sh holds one slot per wave.
 __device__ __forceinline__ void block_atomic_min(double v, u64* dst, double* sh) {
@@ -809,22 +854,26 @@ struct LevelShape {
 // of the output queue r.q (region capacity r.cap_q).
 template <int D>
 __global__ void __launch_bounds__(LevelShape<D>::block) __attribute__((amdgpu_waves_per_eu(LevelWaves<D>::value)))
-k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const u32* slot_in, u32* slot_next,
-        u32* slot_clear) {
+k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, int sub_in, const u32* slot_in,
+        u32* slot_next, u32* slot_clear) {
     __shared__ BlockAlloc S;
-    __shared__ u32 pre[kRegions + 1];  // region prefix sums (in LDS: registers are the scarce resource here)
+    __shared__ u32 pre[kSegs + 1];  // segment prefix sums (in LDS: registers are the scarce resource here)
     if (blockIdx.x == 0 && threadIdx.x < kRegions) slot_clear[threadIdx.x * kRegionStride] = 0;
     // an overflowed previous level counts more pairs than it stored: read
     // only what the queue holds (the overflow flag makes the round restart)
     constexpr int NT = LevelShape<D>::block;
-    if (threadIdx.x == 0) {
-        u32 p[kRegions + 1];
-        region_prefix(slot_in, cap_in, p);
+    if (sub_in == 1) {
+        if (threadIdx.x == 0) {
+            u32 p[kRegions + 1];
+            region_prefix(slot_in, cap_in, p);
 #pragma unroll
-        for (int i = 0; i <= kRegions; ++i) pre[i] = p[i];
+            for (int i = 0; i <= kRegions; ++i) pre[i] = p[i];
+        }
+    } else {
+        seg_prefix(slot_in, cap_in, sub_in, pre);
     }
     __syncthreads();
-    const u32 nq = pre[kRegions];
+    const u32 nq = pre[kRegions * sub_in];
     const int x = (int)(blockIdx.x % kRegions);
     const u32 j = blockIdx.x / kRegions, g = gridDim.x / kRegions;
     const u32 lo = (u32)((u64)nq * x / kRegions), hi = (u32)((u64)nq * (x + 1) / kRegions);
@@ -838,27 +887,46 @@ k_level(TreeView t, RoundArgs r, int hdb, const PairRec* qin, u32 cap_in, const 
         const u32 v = v0 + threadIdx.x;
         const bool have = v < hi;
         PairRec pr = {0u, 0u, 0.0};
-        if (have) pr = qin[region_index(pre, cap_in, v)];
+        if (have) {
+            u32 at;
+            if (sub_in == 1) {
+                u32 p[kRegions + 1];
+#pragma unroll
+                for (int i = 0; i <= kRegions; ++i) p[i] = pre[i];
+                at = region_index(p, cap_in, v);
+            } else {
+                at = seg_index(pre, sub_in, cap_in, v);
+            }
+            pr = qin[at];
+        }
         level_step<D>(t, r, hdb, have, pr, qout, r.cap_q, ctr, S, acc);
     }
     level_flush<NT>(r, acc);
 }
 
-// Many small levels without grid-wide launches: kRegions workgroups, each
-// expanding the pairs of its own queue region x level by level (the level
-// barrier is __syncthreads and the next queue's counter lives in LDS), so the
-// thin levels at the end of a round cost no kernel launches or host round
-// trips.  A workgroup only ever reads and writes region x of the two
-// buffers, so workgroups need not run together.  It always takes its first
-// level, then keeps going while its levels stay at most `small_max` pairs.
-// The input is region x of ring slot `slot_in` of buffer b_in (every level
-// kernel appends to the region of its workgroup's XCD, and the frontier
-// split seeds regions by tree position); levels ping-pong between region x
-// of q[0] and q[1] (cap0, cap1: region capacities).  Every workgroup leaves
-// its remaining pairs in region x of buffer b_out = b_in ^ 1 (copying them
-// there when it stopped in the other buffer), writes region x's count of
-// ring slot b_out (and zero in the other slots), and adds it to state[0];
-// state[1] = b_out.  state[0] is zero at launch.
+// Many small levels without grid-wide launches: kRegions * sub_run
+// workgroups, workgroup (x, w) = (blockIdx % 8, blockIdx / 8) expanding its
+// own part of queue region x level by level (the level barrier is
+// __syncthreads and the next queue's counter lives in LDS), so the thin
+// levels of a round cost no kernel launches or host round trips.  With
+// sub_run == 1 a workgroup owns region x; with sub_run == kSub it owns
+// sub-segment w of region x.  A workgroup always takes its first level,
+// then keeps going while its levels stay at most `small_max` pairs.
+//
+// Input: slot `slot_in` of the ring and buffer b_in, in layout sub_in (1 or
+// kSub).  The first level reads the workgroup's share of region x: all of it
+// (sub_run == 1, every sub-segment when sub_in == kSub), its own sub-segment
+// (sub_in == sub_run == kSub), or the w-th kSub-th of the region's pairs
+// (sub_in == 1, sub_run == kSub).  Levels are written to the workgroup's part
+// of buffer b_out = b_in ^ 1 and, alternately, of a second buffer: b_in when
+// the workgroup owns the whole region, else qt, so that no workgroup writes
+// where another may still read its first level.  The remaining pairs end in
+// the workgroup's part of b_out (copied there when the last level sits in the
+// other buffer), in layout sub_run, with their counts in slot slot_in + 1 of
+// the ring; slot slot_in + 2 is cleared for the grid-wide level that may
+// follow, and slot_in is left alone (other workgroups of the region may still
+// read it).  The remaining total is added to state[0], which is zero at
+// launch.  Capacities are per region.
 // 1024 threads where the level step fits 128 registers without spilling
 // (d <= 4), else 768.
 template <int D>
@@ -868,60 +936,98 @@ struct SmallBlock {
 
 template <int D>
 __global__ void __launch_bounds__(SmallBlock<D>::value) k_level_small(TreeView t, RoundArgs r, int hdb, PairRec* q0, u32 cap0,
-                                                             PairRec* q1, u32 cap1, int b_in, u32* ring,
-                                                             u32 slot_in, u32 small_max, u32* state) {
+                                                             PairRec* q1, u32 cap1, PairRec* qt, u32 capt, int b_in,
+                                                             int sub_in, int sub_run, u32* ring, u32 slot_in,
+                                                             u32 small_max, u32* state) {
     constexpr int NT = SmallBlock<D>::value;
     __shared__ BlockAlloc S;
     __shared__ u32 qn;
     const double inf_ = __longlong_as_double(0x7ff0000000000000ll);
     LevelAcc acc = {inf_, inf_, inf_, 0, 0, 0};
-    const int x = (int)blockIdx.x;
-    int b = b_in;
-    // an overflowed previous level counts more pairs than it stored
-    u32 nq = min(ring[slot_in * kSlotWords + x * kRegionStride], b_in ? cap1 : cap0);
-    bool first = true;
+    const int x = (int)(blockIdx.x % kRegions), w = (int)(blockIdx.x / kRegions);
+    const int b_out = b_in ^ 1;
+    const u32 cap_in = b_in ? cap1 : cap0, cap_out = b_out ? cap1 : cap0;
+    // the workgroup's parts of the output buffer and of the other buffer
+    const u32 pcap = cap_out / (u32)sub_run;
+    PairRec* const po = (b_out ? q1 : q0) + (size_t)x * cap_out + (size_t)w * pcap;
+    const u32 ocap = (sub_run == 1 ? cap_in : capt) / (u32)sub_run;
+    PairRec* const pt = sub_run == 1 ? (b_in ? q1 : q0) + (size_t)x * cap_in : qt + (size_t)x * capt + (size_t)w * ocap;
+    // first-level input: npiece runs of pairs of buffer b_in (an overflowed
+    // previous level counts more pairs than it stored)
+    const u32* sl = ring + slot_in * kSlotWords + x * kRegionStride;
+    const PairRec* qin = (b_in ? q1 : q0) + (size_t)x * cap_in;
+    const int npiece = (sub_run == 1 && sub_in == kSub) ? kSub : 1;
+    const u32 icap = cap_in / (u32)sub_in;
+    u32 nq = 0;
+    for (int k = 0; k < npiece; ++k) nq += min(sl[npiece > 1 ? k : (sub_in == kSub ? w : 0)], icap);
+    bool first = true, in_po = false;
     while (nq > 0 && (first || nq <= small_max)) {
         if (threadIdx.x == 0) qn = 0;
         __syncthreads();
         u32* ctr[kLists] = {&r.cnt->c[C_TINY], nullptr, &r.cnt->c[C_BIG], &r.cnt->c[C_F], &r.cnt->c[C_FAR], &qn};
-        const PairRec* qin = b ? q1 : q0;
-        const u32 capi = b ? cap1 : cap0, capo = b ? cap0 : cap1;
-        PairRec* qout = (b ? q0 : q1) + (size_t)x * capo;
-        for (u32 b0 = 0; b0 < nq; b0 += NT) {
-            const u32 v = b0 + threadIdx.x;
-            const bool have = v < nq;
-            PairRec pr = {0u, 0u, 0.0};
-            if (have) pr = qin[(size_t)x * capi + v];
-            level_step<D>(t, r, hdb, have, pr, qout, capo, ctr, S, acc);
+        // level 1 goes to po, then the levels alternate
+        PairRec* const dst = (first || !in_po) ? po : pt;
+        const u32 dcap = (first || !in_po) ? pcap : ocap;
+        if (first) {
+            for (int k = 0; k < npiece; ++k) {
+                const PairRec* src;
+                u32 c0, c1;
+                if (npiece > 1) {  // every sub-segment of region x
+                    src = qin + (size_t)k * icap;
+                    c0 = 0;
+                    c1 = min(sl[k], icap);
+                } else if (sub_in == kSub) {  // own sub-segment
+                    src = qin + (size_t)w * icap;
+                    c0 = 0;
+                    c1 = min(sl[w], icap);
+                } else {  // the w-th share of the region (the whole region when sub_run == 1)
+                    const u32 c = min(sl[0], icap);
+                    src = qin;
+                    c0 = (u32)((u64)c * (u32)w / (u32)sub_run);
+                    c1 = (u32)((u64)c * (u32)(w + 1) / (u32)sub_run);
+                }
+                for (u32 b0 = c0; b0 < c1; b0 += NT) {
+                    const u32 v = b0 + threadIdx.x;
+                    const bool have = v < c1;
+                    PairRec pr = {0u, 0u, 0.0};
+                    if (have) pr = src[v];
+                    level_step<D>(t, r, hdb, have, pr, dst, dcap, ctr, S, acc);
+                }
+            }
+        } else {
+            const PairRec* src = in_po ? po : pt;
+            for (u32 b0 = 0; b0 < nq; b0 += NT) {
+                const u32 v = b0 + threadIdx.x;
+                const bool have = v < nq;
+                PairRec pr = {0u, 0u, 0.0};
+                if (have) pr = src[v];
+                level_step<D>(t, r, hdb, have, pr, dst, dcap, ctr, S, acc);
+            }
         }
         __syncthreads();
-        u32 nn = qn;
-        b ^= 1;
+        const u32 nn = qn;
         first = false;
-        if (nn > capo) {  // overflowed (flagged): stop, the round restarts
+        in_po = dst == po;
+        if (nn > dcap) {  // overflowed (flagged): stop, the round restarts
             nq = 0;
             break;
         }
         nq = nn;
         __syncthreads();
     }
-    // leave the remaining pairs in region x of buffer b_out
-    const int b_out = b_in ^ 1;
-    const u32 cap_out = b_out ? cap1 : cap0;
-    PairRec* dst = (b_out ? q1 : q0) + (size_t)x * cap_out;
-    if (nq && b != b_out) {
-        const PairRec* src = (b ? q1 : q0) + (size_t)x * (b ? cap1 : cap0);
-        if (nq > cap_out) {
+    // leave the remaining pairs in the workgroup's part of b_out
+    if (nq && !in_po) {
+        if (nq > pcap) {
             if (threadIdx.x == 0) flag_overflow_q(r.cnt);
             nq = 0;
         }
-        for (u32 v = threadIdx.x; v < nq; v += NT) dst[v] = src[v];
+        for (u32 v = threadIdx.x; v < nq; v += NT) po[v] = pt[v];
     }
     level_flush<NT>(r, acc);
-    if (threadIdx.x < kQRing) ring[threadIdx.x * kSlotWords + x * kRegionStride] = (int)threadIdx.x == b_out ? nq : 0u;
     if (threadIdx.x == 0) {
+        ring[((slot_in + 1) % kQRing) * kSlotWords + x * kRegionStride + w] = nq;
+        ring[((slot_in + 2) % kQRing) * kSlotWords + x * kRegionStride + w] = 0u;
         if (nq) atomicAdd(&state[0], nq);
-        if (x == 0) state[1] = (u32)b_out;
     }
 }
 

@@ -43,6 +43,7 @@ class _Stats(ctypes.Structure):
         ("big_evals", ctypes.c_int64), ("sort_elems", ctypes.c_int64),
         ("kernel_ms", ctypes.c_double * 16), ("kernel_launches", ctypes.c_int64 * 16),
         ("bccp_evals_done", ctypes.c_int64), ("tuning_applied", ctypes.c_int64),
+        ("level_launches", ctypes.c_int64 * 3),
     ]
 
 
@@ -177,6 +178,7 @@ class Stats:
     kernel_launches: list
     bccp_evals_done: int
     tuning_applied: int
+    level_launches: list
 
 
 # kernel families (GEOMST_K_* in include/geomst.h)
@@ -190,7 +192,7 @@ def stats() -> Stats:
     vals = {}
     for f, _ in _Stats._fields_:
         v = getattr(s, f)
-        vals[f] = list(v) if f in ("kernel_ms", "kernel_launches") else v
+        vals[f] = list(v) if f in ("kernel_ms", "kernel_launches", "level_launches") else v
     return Stats(**vals)
 
 

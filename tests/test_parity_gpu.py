@@ -364,6 +364,52 @@ def test_large_pair_chunks_exact(G, chunk):
         G.set_option("bccp_chunk", 0)
 
 
+LEVEL_MODES = {
+    # every level small enough for it goes to the 256-workgroup kernel
+    "wide": {"small_level_switch": 0, "small_level_max": 0, "wide_level_switch": 16, "wide_level_max": 32},
+    # thin levels to the eight-workgroup kernel, mid-size ones to the wide
+    # kernel, the rest to the whole grid: the queue changes layout both ways
+    "mixed": {"small_level_switch": 64, "small_level_max": 128, "wide_level_switch": 16, "wide_level_max": 32},
+    # whole-grid levels only
+    "grid_only": {"small_level_switch": 0, "small_level_max": 0, "wide_level_switch": 0, "wide_level_max": 0},
+}
+LEVEL_DEFAULTS = {"small_level_switch": 2048, "small_level_max": 4096, "wide_level_switch": 2048,
+                  "wide_level_max": 4096}
+
+
+@pytest.mark.parametrize("mode", sorted(LEVEL_MODES))
+def test_level_kernel_modes_exact(G, mode):
+    """The expansion runs its levels on the whole grid, in eight workgroups
+    (one queue region each) or in 256 (one part of a region each), and hands
+    the queue between their layouts.  Tiny thresholds send 20k-point solves
+    through each mode and transition; the result must still be the
+    checker's."""
+    p3 = W.uniform(20_000, 3, seed=71)
+    p2 = W.mixture(20_000, 2, seed=72, k=6, noise_frac=0.05)
+    p5 = W.mixture(12_000, 5, seed=73, k=6, noise_frac=0.05)
+    try:
+        for k, v in LEVEL_MODES[mode].items():
+            G.set_option(k, v)
+        for p, tag in ((p3, "uniform3"), (p2, "mixture2")):
+            check_emst_exact(G, p, f"{tag} {mode}")
+            ll = G.stats().level_launches
+            say(f"{tag} {mode}: level launches grid/regional/wide = {ll}")
+            if mode == "grid_only":
+                assert ll[1] == 0 and ll[2] == 0
+            else:
+                assert ll[2] > 0, "the wide level kernel did not run"
+            if mode == "wide":
+                assert ll[1] == 0
+        check_hdb_exact(G, p5, 10, f"mixture5 {mode}")
+        ll = G.stats().level_launches
+        say(f"mixture5 hdbscan {mode}: level launches grid/regional/wide = {ll}")
+        if mode != "grid_only":
+            assert ll[2] > 0, "the wide level kernel did not run"
+    finally:
+        for k, v in LEVEL_DEFAULTS.items():
+            G.set_option(k, v)
+
+
 def test_list_overflow_restarts(G):
     """Tiny initial list capacities force overflow, growth and round restarts;
     the result must not change."""
