@@ -137,7 +137,7 @@ struct Fail {
 
 // The device counters block: the Counters record followed by the few words
 // the host reads back with it, so that one copy serves each host check.
-constexpr size_t kAuxLstate = (sizeof(Counters) + 63) / 64 * 64;   // one-workgroup level state (2 words)
+constexpr size_t kAuxLstate = (sizeof(Counters) + 63) / 64 * 64;   // pairs left by a small-level launch (1 word)
 constexpr size_t kAuxNalive = kAuxLstate + 64;                     // Boruvka alive counts (2 words)
 constexpr size_t kAuxRing = (kAuxNalive + 64 + 255) / 256 * 256;   // level-queue count ring
 constexpr size_t kCntBytes = kAuxRing + (size_t)kQRing * kSlotWords * 4;
@@ -448,8 +448,10 @@ int id_bits(int n) {
 // rank -> edge).  Each key word is gathered once and then sorted as (key,
 // index) pairs with sequential passes, least significant word first, over
 // only the bits below the highest bit where the word's min and max differ
-// (every key shares the bits above).  Fast path: sort by w2 alone and keep
-// that order when no two w2 are equal.
+// (every key shares the bits above).  Fast path: sort by the leading bits of
+// w2 alone (about log2 m + 8 of the bits that vary, in whole 8-bit passes)
+// and keep that order when no two such keys are equal, else order each run
+// of equal leading bits by (w2, d2, ids) in place.
 u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_t s, const u32* pinst = nullptr) {
     D.kid.ensure((size_t)m * 8);
     D.kw2.ensure((size_t)m * 8);
@@ -466,8 +468,10 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
     unsigned gg = std::min(blocks(m, kBlock), (unsigned)kGrid);
     u64* mm = D.minmax.as<u64>();
     u32* tieflag = D.minmax.as<u32>() + 8;
+    int sh = 0;  // the fast path's sort covers the w2 bits from sh up
     // one word: gather through the current permutation (in place), then sort
-    auto word = [&](const u32* perm, int kind, bool check_ties) -> bool {
+    // on its varying bits (only the leading `lead` of them when lead > 0)
+    auto word = [&](const u32* perm, int kind, bool check_ties, int lead) -> bool {
         k_sort_init<<<1, kWave, 0, s>>>(mm, tieflag);
         LAUNCHCHK();
         k_gather_word<<<gg, kBlock, 0, s>>>(L, perm, m, kind, B, pinst, ka, va, mm);
@@ -478,26 +482,28 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
         u64 diff = h[0] ^ h[1];
         int bits = 0;
         while (bits < 64 && (diff >> bits)) ++bits;
-        g_stats.sort_elems += (int64_t)m * ((bits + 7) / 8);
-        if (radix_sort_pairs(ka, va, kb, vb, m, bits, D.stemp.p, s)) {
+        const int lo = (lead > 0 && bits > lead) ? bits - lead : 0;
+        sh = lo;
+        g_stats.sort_elems += (int64_t)m * ((bits - lo + 7) / 8);
+        if (radix_sort_pairs(ka, va, kb, vb, m, bits, D.stemp.p, s, lo)) {
             std::swap(ka, kb);
             std::swap(va, vb);
         }
         LAUNCHCHK();
         if (!check_ties) return false;
-        k_flag_ties<<<gg, kBlock, 0, s>>>(ka, m, tieflag);
+        k_flag_ties<<<gg, kBlock, 0, s>>>(ka, m, tieflag, lo);
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(D.hpin, tieflag, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         return D.hpin[0] != 0;
     };
-    // after sorting by w2: order the runs of equal w2 by (d2, ids); false if
-    // a run is too long for that
+    // after sorting by the leading bits of w2: order the runs of equal
+    // leading bits by (w2, d2, ids); false if a run is too long for that
     auto fix_runs = [&]() -> bool {
         D.ke2.ensure((size_t)m * 8);  // tieflag[1] (long runs) was cleared with the w2 word
-        k_run_keys<<<gg, kBlock, 0, s>>>(L, ka, va, m, kb, D.ke2.as<u64>());
+        k_run_keys<<<gg, kBlock, 0, s>>>(L, ka, va, m, kb, D.ke2.as<u64>(), sh);
         LAUNCHCHK();
-        k_fix_runs<<<gg, kBlock, 0, s>>>(ka, va, kb, D.ke2.as<u64>(), m, vb, tieflag + 1);
+        k_fix_runs<<<gg, kBlock, 0, s>>>(ka, va, kb, D.ke2.as<u64>(), m, vb, tieflag + 1, sh);
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(D.hpin, tieflag + 1, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -507,7 +513,7 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
     };
     // Batched output: the instance is the most significant word.
     auto finish = [&]() -> u32* {
-        if (pinst) word(va, 3, false);
+        if (pinst) word(va, 3, false, 0);
         return va;
     };
     // a short list: the whole order in one workgroup, no host round trip
@@ -516,13 +522,16 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
         LAUNCHCHK();
         return va;
     }
-    // fast path: order by w2; done when no two keys tie, or when every run of
-    // equal w2 is short enough to be ordered in place by (d2, ids); otherwise
-    // the full order, least significant word first
-    if (!word(nullptr, 2, true) || fix_runs()) return finish();
-    word(nullptr, 0, false);
-    if (hdb) word(va, 1, false);
-    word(va, 2, false);
+    // fast path: order by the leading bits of w2; done when no two keys tie
+    // there, or when every run of ties is short enough to be ordered in place
+    // by (w2, d2, ids); otherwise the full order, least significant word first
+    int lg = 0;
+    while (lg < 32 && (1u << lg) < m) ++lg;
+    const int lead = 8 * ((lg + 8 + 7) / 8);
+    if (!word(nullptr, 2, true, lead) || fix_runs()) return finish();
+    word(nullptr, 0, false, 0);
+    if (hdb) word(va, 1, false, 0);
+    word(va, 2, false, 0);
     return finish();
 }
 

@@ -1981,29 +1981,35 @@ __global__ void k_sort_init(u64* minmax, u32* flags) {
     }
 }
 
-// Flags whether two neighbours of a sorted key array are equal.
-__global__ void k_flag_ties(const u64* key, u32 m, u32* flag) {
+// Whether two keys are equal in their bits from sh up (the bits a sort on a
+// key's leading bits ordered).
+__device__ __forceinline__ bool same_lead(u64 a, u64 b, int sh) { return ((a ^ b) >> sh) == 0; }
+
+// Flags whether two neighbours of a sorted key array are equal in their bits
+// from sh up.
+__global__ void k_flag_ties(const u64* key, u32 m, u32* flag, int sh) {
     bool tie = false;
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x + 1; i < m; i += gridDim.x * blockDim.x)
-        tie |= key[i] == key[i - 1];
+        tie |= same_lead(key[i], key[i - 1], sh);
     if (__any(tie) && lane_id() == 0) atomicOr(flag, 1u);
 }
 
-// After a sort by w2 (keys `key`, permutation `val`): order every run of
-// equal w2 by (d2, ids), which completes the order K.  First the (d2, ids)
-// of every element that belongs to a run are gathered into sorted order
-// (te, ti), all elements in parallel; then every element of a run counts the
-// run's members that precede it in (d2, ids) and writes its edge to that
-// rank in `out` (elements outside runs are copied).  The members of a run sit
-// side by side, so the lanes of a run read the same words together.  A run
-// longer than kRunMax is flagged (the caller then sorts by every word).
+// After a sort by the bits of w2 from sh up (keys `key`, the whole w2 bits;
+// permutation `val`): order every run of keys equal in those bits by (w2,
+// d2, ids), which completes the order K.  First the (d2, ids) of every
+// element that belongs to a run are gathered into sorted order (te, ti), all
+// elements in parallel; then every element of a run counts the run's members
+// that precede it in (w2, d2, ids) and writes its edge to that rank in `out`
+// (elements outside runs are copied).  The members of a run sit side by
+// side, so the lanes of a run read the same words together.  A run longer
+// than kRunMax is flagged (the caller then sorts by every word).
 constexpr u32 kRunMax = 256;
 
 __global__ void __launch_bounds__(kBlock) k_run_keys(const EdgeList L, const u64* key, const u32* val, u32 m,
-                                                     u64* te, u64* ti) {
+                                                     u64* te, u64* ti, int sh) {
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         const u64 k = key[i];
-        if ((i > 0 && key[i - 1] == k) || (i + 1 < m && key[i + 1] == k)) {
+        if ((i > 0 && same_lead(key[i - 1], k, sh)) || (i + 1 < m && same_lead(key[i + 1], k, sh))) {
             const u32 v = val[i];
             te[i] = dbits(L.e2[v]);
             ti[i] = L.ids[v];
@@ -2012,27 +2018,27 @@ __global__ void __launch_bounds__(kBlock) k_run_keys(const EdgeList L, const u64
 }
 
 __global__ void __launch_bounds__(kBlock) k_fix_runs(const u64* key, const u32* val, const u64* te, const u64* ti,
-                                                     u32 m, u32* out, u32* longrun) {
+                                                     u32 m, u32* out, u32* longrun, int sh) {
     bool too_long = false;
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         const u64 k = key[i];
-        const bool left = i > 0 && key[i - 1] == k, right = i + 1 < m && key[i + 1] == k;
+        const bool left = i > 0 && same_lead(key[i - 1], k, sh), right = i + 1 < m && same_lead(key[i + 1], k, sh);
         if (!left && !right) {
             out[i] = val[i];
             continue;
         }
         u32 s = i, e = i + 1;
-        while (s > 0 && i - s < kRunMax && key[s - 1] == k) --s;
-        while (e < m && e - i < kRunMax && key[e] == k) ++e;
-        if (e - s > kRunMax || (s > 0 && key[s - 1] == k) || (e < m && key[e] == k)) {
+        while (s > 0 && i - s < kRunMax && same_lead(key[s - 1], k, sh)) --s;
+        while (e < m && e - i < kRunMax && same_lead(key[e], k, sh)) ++e;
+        if (e - s > kRunMax || (s > 0 && same_lead(key[s - 1], k, sh)) || (e < m && same_lead(key[e], k, sh))) {
             too_long = true;
             continue;
         }
         const u64 ve = te[i], vi = ti[i];
         u32 r = 0;
         for (u32 j = s; j < e; ++j) {
-            const u64 ue = te[j], uj = ti[j];
-            r += (ue < ve || (ue == ve && (uj < vi || (uj == vi && j < i)))) ? 1u : 0u;
+            const u64 uk = key[j], ue = te[j], uj = ti[j];
+            r += (uk < k || (uk == k && (ue < ve || (ue == ve && (uj < vi || (uj == vi && j < i)))))) ? 1u : 0u;
         }
         out[s + r] = val[i];
     }

@@ -253,15 +253,16 @@ void scan_inclusive_u32(const u32* in, u32* out, size_t count, void* temp, hipSt
 }
 
 int radix_sort_pairs(u64* key, u32* val, u64* key2, u32* val2, size_t count, int bits, void* temp,
-                     hipStream_t s) {
-    if (count <= 1 || bits <= 0) return 0;
+                     hipStream_t s, int lo_bit) {
+    bits = std::min(bits, 64);
+    if (count <= 1 || bits <= lo_bit) return 0;
     u32 nb = (u32)cdiv(count, kTile);
     u32* hist = (u32*)temp;
     u32* totals = hist + cdiv((size_t)nb * 256, 64) * 64;  // 256 digit totals
-    const int passes = (std::min(bits, 64) + 7) / 8;
+    const int passes = (bits - lo_bit + 7) / 8;
     int flip = 0;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
+        const int shift = lo_bit + 8 * p;
         u64* ki = flip ? key2 : key;
         u32* vi = flip ? val2 : val;
         u64* ko = flip ? key : key2;
