@@ -151,12 +151,29 @@ def equal_weight_blocks(blocks, side, seed):
     return p[rng.permutation(len(p))]
 
 
-@pytest.mark.parametrize("case", ["runs180", "runs60", "small_grid", "small_dups"])
+def near_tie_line(groups=100, per=200, seed=35):
+    """Points on a line whose gaps fall in `groups` tight groups (1 + j/64 plus
+    a multiple of 2^-30 below 2^-20): many distinct weights that share their
+    leading bits, spread over a wide range."""
+    rng = np.random.default_rng(seed)
+    j = np.repeat(np.arange(groups), per)
+    rng.shuffle(j)
+    gaps = 1.0 + j / 64.0 + rng.integers(0, 1000, size=j.size) * 2.0 ** -30
+    x = np.concatenate([[0.0], np.cumsum(gaps)])
+    return np.ascontiguousarray(np.stack([x, np.zeros_like(x)], 1))
+
+
+@pytest.mark.parametrize("case", ["runs180", "runs60", "small_grid", "small_dups", "near_ties"])
 def test_edge_sort_paths(G, case):
     """Equal-weight runs of every length class the edge sort treats apart:
     up to 64 and up to 256 members (ranked in place after the w2 pass), a
-    whole list of at most 2,048 edges (one-workgroup sort), and ties of both
-    kinds inside such short lists."""
+    whole list of at most 2,048 edges (one-workgroup sort), ties of both
+    kinds inside such short lists, and distinct weights equal in the leading
+    bits the fast pass sorts on (ordered in place by the whole weight)."""
+    if case == "near_ties":
+        p = near_tie_line()
+        check_emst_exact(G, p, case)
+        return
     if case == "runs180":
         p = equal_weight_blocks(12, 10, seed=31)      # runs of 180 equal w2
     elif case == "runs60":
