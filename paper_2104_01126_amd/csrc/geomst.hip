@@ -467,12 +467,12 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
     u32* vb = D.perm[1].as<u32>();
     unsigned gg = std::min(blocks(m, kBlock), (unsigned)kGrid);
     u64* mm = D.minmax.as<u64>();
-    u32* tieflag = D.minmax.as<u32>() + 8;
-    int sh = 0;  // the fast path's sort covers the w2 bits from sh up
+    u32* longrun = D.minmax.as<u32>() + 9;
+    int* lead_sh = (int*)(D.minmax.as<u32>() + 10);  // first w2 bit of the fast path's sort
     // one word: gather through the current permutation (in place), then sort
-    // on its varying bits (only the leading `lead` of them when lead > 0)
-    auto word = [&](const u32* perm, int kind, bool check_ties, int lead) -> bool {
-        k_sort_init<<<1, kWave, 0, s>>>(mm, tieflag);
+    // on the bits that vary
+    auto word = [&](const u32* perm, int kind) {
+        k_sort_init<<<1, kWave, 0, s>>>(mm, longrun - 1);
         LAUNCHCHK();
         k_gather_word<<<gg, kBlock, 0, s>>>(L, perm, m, kind, B, pinst, ka, va, mm);
         LAUNCHCHK();
@@ -482,38 +482,16 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
         u64 diff = h[0] ^ h[1];
         int bits = 0;
         while (bits < 64 && (diff >> bits)) ++bits;
-        const int lo = (lead > 0 && bits > lead) ? bits - lead : 0;
-        sh = lo;
-        g_stats.sort_elems += (int64_t)m * ((bits - lo + 7) / 8);
-        if (radix_sort_pairs(ka, va, kb, vb, m, bits, D.stemp.p, s, lo)) {
+        g_stats.sort_elems += (int64_t)m * ((bits + 7) / 8);
+        if (radix_sort_pairs(ka, va, kb, vb, m, bits, D.stemp.p, s)) {
             std::swap(ka, kb);
             std::swap(va, vb);
         }
         LAUNCHCHK();
-        if (!check_ties) return false;
-        k_flag_ties<<<gg, kBlock, 0, s>>>(ka, m, tieflag, lo);
-        LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(D.hpin, tieflag, 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        return D.hpin[0] != 0;
-    };
-    // after sorting by the leading bits of w2: order the runs of equal
-    // leading bits by (w2, d2, ids); false if a run is too long for that
-    auto fix_runs = [&]() -> bool {
-        D.ke2.ensure((size_t)m * 8);  // tieflag[1] (long runs) was cleared with the w2 word
-        k_run_keys<<<gg, kBlock, 0, s>>>(L, ka, va, m, kb, D.ke2.as<u64>(), sh);
-        LAUNCHCHK();
-        k_fix_runs<<<gg, kBlock, 0, s>>>(ka, va, kb, D.ke2.as<u64>(), m, vb, tieflag + 1, sh);
-        LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(D.hpin, tieflag + 1, 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (D.hpin[0] != 0) return false;
-        std::swap(va, vb);
-        return true;
     };
     // Batched output: the instance is the most significant word.
     auto finish = [&]() -> u32* {
-        if (pinst) word(va, 3, false, 0);
+        if (pinst) word(va, 3);
         return va;
     };
     // a short list: the whole order in one workgroup, no host round trip
@@ -522,16 +500,40 @@ u32* sort_edges(Device& D, const EdgeList& L, u32 m, int n, bool hdb, hipStream_
         LAUNCHCHK();
         return va;
     }
-    // fast path: order by the leading bits of w2; done when no two keys tie
-    // there, or when every run of ties is short enough to be ordered in place
-    // by (w2, d2, ids); otherwise the full order, least significant word first
+    // Fast path, one host round trip: sort by the leading `lead` varying bits
+    // of w2 (the first of them found on the device), then order each run of
+    // keys equal in those bits by (w2, d2, ids) in place.  A run too long
+    // for that sends the list to the full order, least significant word
+    // first.
     int lg = 0;
     while (lg < 32 && (1u << lg) < m) ++lg;
     const int lead = 8 * ((lg + 8 + 7) / 8);
-    if (!word(nullptr, 2, true, lead) || fix_runs()) return finish();
-    word(nullptr, 0, false, 0);
-    if (hdb) word(va, 1, false, 0);
-    word(va, 2, false, 0);
+    k_sort_init<<<1, kWave, 0, s>>>(mm, longrun - 1);
+    LAUNCHCHK();
+    k_gather_word<<<gg, kBlock, 0, s>>>(L, nullptr, m, 2, B, pinst, ka, va, mm);
+    LAUNCHCHK();
+    k_sort_lead<<<1, kWave, 0, s>>>(mm, lead, lead_sh);
+    LAUNCHCHK();
+    g_stats.sort_elems += (int64_t)m * (lead / 8);
+    if (radix_sort_pairs(ka, va, kb, vb, m, lead, D.stemp.p, s, 0, lead_sh)) {
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    LAUNCHCHK();
+    D.ke2.ensure((size_t)m * 8);
+    k_run_keys<<<gg, kBlock, 0, s>>>(L, ka, va, m, kb, D.ke2.as<u64>(), lead_sh);
+    LAUNCHCHK();
+    k_fix_runs<<<gg, kBlock, 0, s>>>(ka, va, kb, D.ke2.as<u64>(), m, vb, longrun, lead_sh);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(D.hpin, longrun, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (D.hpin[0] == 0) {
+        std::swap(va, vb);
+        return finish();
+    }
+    word(nullptr, 0);
+    if (hdb) word(va, 1);
+    word(va, 2);
     return finish();
 }
 

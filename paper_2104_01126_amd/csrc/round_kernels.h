@@ -1971,7 +1971,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_word(const EdgeList L, const 
 }
 
 // Clears the per-word state of the edge sort: the key word's running min and
-// max, the tie flag and the long-run flag.
+// max and two flag words (flags[1] is the long-run flag).
 __global__ void k_sort_init(u64* minmax, u32* flags) {
     if (threadIdx.x == 0) {
         minmax[0] = ~0ull;
@@ -1985,18 +1985,19 @@ __global__ void k_sort_init(u64* minmax, u32* flags) {
 // key's leading bits ordered).
 __device__ __forceinline__ bool same_lead(u64 a, u64 b, int sh) { return ((a ^ b) >> sh) == 0; }
 
-// Flags whether two neighbours of a sorted key array are equal in their bits
-// from sh up.
-__global__ void k_flag_ties(const u64* key, u32 m, u32* flag, int sh) {
-    bool tie = false;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x + 1; i < m; i += gridDim.x * blockDim.x)
-        tie |= same_lead(key[i], key[i - 1], sh);
-    if (__any(tie) && lane_id() == 0) atomicOr(flag, 1u);
+// The first w2 bit of a sort on the leading `lead` bits that vary between the
+// recorded min and max (0 when fewer vary), for the sort's device-side shift.
+__global__ void k_sort_lead(const u64* minmax, int lead, int* sh) {
+    if (threadIdx.x == 0) {
+        const u64 diff = minmax[0] ^ minmax[1];
+        const int bits = diff ? 64 - __clzll((long long)diff) : 0;
+        *sh = bits > lead ? bits - lead : 0;
+    }
 }
 
-// After a sort by the bits of w2 from sh up (keys `key`, the whole w2 bits;
+// After a sort by the bits of w2 from *dsh up (keys `key`, the whole w2 bits;
 // permutation `val`): order every run of keys equal in those bits by (w2,
-// d2, ids), which completes the order K.  First the (d2, ids) of every
+// d2, ids), which completes the order K (with no such run, `out` is `val`).  First the (d2, ids) of every
 // element that belongs to a run are gathered into sorted order (te, ti), all
 // elements in parallel; then every element of a run counts the run's members
 // that precede it in (w2, d2, ids) and writes its edge to that rank in `out`
@@ -2006,7 +2007,8 @@ __global__ void k_flag_ties(const u64* key, u32 m, u32* flag, int sh) {
 constexpr u32 kRunMax = 256;
 
 __global__ void __launch_bounds__(kBlock) k_run_keys(const EdgeList L, const u64* key, const u32* val, u32 m,
-                                                     u64* te, u64* ti, int sh) {
+                                                     u64* te, u64* ti, const int* dsh) {
+    const int sh = *dsh;
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         const u64 k = key[i];
         if ((i > 0 && same_lead(key[i - 1], k, sh)) || (i + 1 < m && same_lead(key[i + 1], k, sh))) {
@@ -2018,7 +2020,8 @@ __global__ void __launch_bounds__(kBlock) k_run_keys(const EdgeList L, const u64
 }
 
 __global__ void __launch_bounds__(kBlock) k_fix_runs(const u64* key, const u32* val, const u64* te, const u64* ti,
-                                                     u32 m, u32* out, u32* longrun, int sh) {
+                                                     u32 m, u32* out, u32* longrun, const int* dsh) {
+    const int sh = *dsh;
     bool too_long = false;
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         const u64 k = key[i];

@@ -105,8 +105,10 @@ struct PairKeys {
 };
 // Per-tile digit counts into the digit-major table.
 template <class K>
-__global__ void __launch_bounds__(kThreads) k_radix_hist(K keys, size_t count, int shift, u32* hist, u32 nblocks) {
+__global__ void __launch_bounds__(kThreads) k_radix_hist(K keys, size_t count, int shift, const int* dshift, u32* hist,
+                                                         u32 nblocks) {
     __shared__ u32 h[256];
+    if (dshift) shift += *dshift;
     h[threadIdx.x] = 0;
     __syncthreads();
     size_t base = (size_t)blockIdx.x * kTile;
@@ -151,8 +153,9 @@ __global__ void __launch_bounds__(kThreads) k_radix_rowscan(u32* hist, u32 nbloc
 // consecutive slots of one digit's run: coalesced stores instead of one
 // scattered store per element.
 __global__ void __launch_bounds__(kThreads) k_radix_scatter_lds(const u64* ki, const u32* vi, u64* ko, u32* vo,
-                                                                size_t count, int shift, const u32* offs,
-                                                                u32 nblocks, const u32* totals) {
+                                                                size_t count, int shift, const int* dshift,
+                                                                const u32* offs, u32 nblocks, const u32* totals) {
+    if (dshift) shift += *dshift;
     __shared__ u64 sk[kTile];
     __shared__ u32 sv[kTile];
     __shared__ u32 lstart[256], gbase[256], run[256];
@@ -253,7 +256,7 @@ void scan_inclusive_u32(const u32* in, u32* out, size_t count, void* temp, hipSt
 }
 
 int radix_sort_pairs(u64* key, u32* val, u64* key2, u32* val2, size_t count, int bits, void* temp,
-                     hipStream_t s, int lo_bit) {
+                     hipStream_t s, int lo_bit, const int* dshift) {
     bits = std::min(bits, 64);
     if (count <= 1 || bits <= lo_bit) return 0;
     u32 nb = (u32)cdiv(count, kTile);
@@ -268,9 +271,9 @@ int radix_sort_pairs(u64* key, u32* val, u64* key2, u32* val2, size_t count, int
         u64* ko = flip ? key : key2;
         u32* vo = flip ? val : val2;
         PairKeys K{ki};
-        k_radix_hist<<<nb, kThreads, 0, s>>>(K, count, shift, hist, nb);
+        k_radix_hist<<<nb, kThreads, 0, s>>>(K, count, shift, dshift, hist, nb);
         k_radix_rowscan<<<256, kThreads, 0, s>>>(hist, nb, totals);
-        k_radix_scatter_lds<<<nb, kThreads, 0, s>>>(ki, vi, ko, vo, count, shift, hist, nb, totals);
+        k_radix_scatter_lds<<<nb, kThreads, 0, s>>>(ki, vi, ko, vo, count, shift, dshift, hist, nb, totals);
         flip ^= 1;
     }
     return flip;
