@@ -854,6 +854,7 @@ struct Solver {
         r.cap_c = (u32)D.C.cap;
         r.pout = D.P[po].list();
         r.cap_p = (u32)D.P[po].cap;
+        r.labels = D.ncomp.as<int>();
         return r;
     }
 

@@ -82,6 +82,7 @@ struct RoundArgs {
     u32 cap_c;
     EdgeList pout;
     u32 cap_p;
+    const int* labels;  // compact copy of the node records' component labels
 };
 
 constexpr int kTinyEvals = 16;   // pairs with at most this many point pairs are solved inline
@@ -119,11 +120,13 @@ __device__ __forceinline__ double pair_wlb2(const NodeRec<D>& A, const NodeRec<D
     return l;
 }
 
-template <int D>
-__device__ __forceinline__ bool connected(const TreeView& t, u32 a, u32 b) {
-    const NodeRec<D>* N = nodes_of<D>(t);
-    int ca = N[a].comp;
-    return ca >= 0 && ca == N[b].comp;
+// Whether nodes a and b lie in one component, from the compact copy of the
+// records' component labels (4 bytes per node, equal to the records' labels
+// after every refresh and negative, like theirs, before the first): for
+// kernels that need no other field of the records.
+__device__ __forceinline__ bool connected_lab(const int* labels, u32 a, u32 b) {
+    const int ca = labels[a];
+    return ca >= 0 && ca == labels[b];
 }
 
 // GFK schedule (Alg. 2): a pair of cardinality at most beta_card has its BCCP
@@ -600,7 +603,7 @@ __global__ void __launch_bounds__(kBlock) k_split_far(TreeView t, RoundArgs r, c
             const u32 i = b0 + k * kBlock + threadIdx.x;
             if (i < nfin) {
                 p[k] = fin[i];
-                const bool keep = p[k].lb2 < inf && !connected<D>(t, p[k].a, p[k].b);
+                const bool keep = p[k].lb2 < inf && !connected_lab(r.labels, p[k].a, p[k].b);
                 const bool due = keep && (p[k].lb2 <= r.beta2 || card_due<D>(t, r.beta_card, p[k].a, p[k].b));
                 const bool near = keep && !due && p[k].lb2 <= r.t_near;
                 const bool far = keep && !due && !near;
