@@ -316,7 +316,7 @@ struct Device {
     DBuf pin, eout, wout, cdout;
     // tree
     DBuf keysA, keysB, gflag, gincl, gid, gstart, gbox, hflag;
-    DBuf part, bbox, key, val, key2, val2, stemp, X, orig, cd2, nodes, npar, flags, cdr, btop, nrange;
+    DBuf part, bbox, key, val, key2, val2, stemp, X, xc, orig, cd2, nodes, npar, flags, cdr, btop, nrange;
     // union-find / component refresh
     DBuf uf, best, bnd, incl, ncomp;
     // rounds
@@ -680,6 +680,7 @@ struct Solver {
         t.cd2 = nullptr;
         t.nodes = nodes;
         t.cdr = nullptr;
+        t.XC = nullptr;
     }
 
     // Node boxes (and, with cd2, core-distance ranges): block-local phase,
@@ -722,6 +723,10 @@ struct Solver {
         else if (minpts <= 32) knn_k<32>();
         else knn_k<64>();
         t.cd2 = D.cd2.as<double>();
+        D.xc.ensure((size_t)n * (D_ + 1) * 8);
+        k_append_cd<D_><<<blocks(n, 256), 256, 0, s>>>(D.X.as<double>(), D.cd2.as<double>(), D.xc.as<double>(), n);
+        LAUNCHCHK();
+        t.XC = D.xc.as<double>();
         bounds(true);
         t.cdr = D.cdr.as<double2>();
     }

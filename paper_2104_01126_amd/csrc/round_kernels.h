@@ -193,29 +193,34 @@ struct EdgeOut {
 };
 
 // The weight and squared distance of point_edge alone (same operations).
+// (HDBSCAN* reads the rows with the core distance appended, XC.)
 template <int D>
 __device__ __forceinline__ void point_w2(const TreeView& t, int hdb, u32 i, u32 j, double& w2, double& e2) {
     e2 = 0.0;
+    if (hdb) {
+        const double* a = t.XC + (size_t)i * (D + 1);
+        const double* b = t.XC + (size_t)j * (D + 1);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            double x = a[k] - b[k];
+            e2 = e2 + x * x;
+        }
+        w2 = fmax(fmax(a[D], b[D]), e2);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         double x = t.X[(size_t)i * D + k] - t.X[(size_t)j * D + k];
         e2 = e2 + x * x;
     }
     w2 = e2;
-    if (hdb) w2 = fmax(fmax(t.cd2[i], t.cd2[j]), e2);
 }
 
 template <int D>
 __device__ __forceinline__ EdgeOut point_edge(const TreeView& t, int hdb, u32 i, u32 j) {
     EdgeOut o;
-    double e2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        double x = t.X[(size_t)i * D + k] - t.X[(size_t)j * D + k];
-        e2 = e2 + x * x;
-    }
-    double w2 = e2;
-    if (hdb) w2 = fmax(fmax(t.cd2[i], t.cd2[j]), e2);
+    double e2, w2;
+    point_w2<D>(t, hdb, i, j, w2, e2);
     u32 oi = t.orig[i], oj = t.orig[j];
     o.k.w2 = w2;
     o.k.e2 = e2;

@@ -84,6 +84,7 @@ struct TreeView {
     const double* cd2;  // sorted position -> squared core distance, or null (EMST)
     const void* nodes;  // NodeRec<D>[2n-1]
     const double2* cdr; // [2n-1] (min cd2, max cd2) of the node's points (HDBSCAN*)
+    const double* XC;   // HDBSCAN*: each sorted point followed by its cd2, row-major [n][D+1]
 };
 // Node ids: internal nodes 0..n-2 (0 is the root), the leaf of sorted
 // position p is node n-1+p.
@@ -574,6 +575,17 @@ __global__ void __launch_bounds__(kBoundsTop) k_bounds_top(int n, const int* par
             v = parent[v];
         }
     }
+}
+
+// Rows of X with each point's squared core distance appended (one line per
+// point for the point-pair kernels instead of two).
+template <int D>
+__global__ void k_append_cd(const double* X, const double* cd2, double* XC, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+#pragma unroll
+    for (int k = 0; k < D; ++k) XC[(size_t)p * (D + 1) + k] = X[(size_t)p * D + k];
+    XC[(size_t)p * (D + 1) + D] = cd2[p];
 }
 
 // ------------------------------------------------------------ core distances
