@@ -1337,7 +1337,7 @@ struct Solver {
                 gfk_card = sched == 2 ? beta_card : 0;
             }
             const bool epoch = beta2 > t_near;
-            if (epoch) t_near = beta2 * g2 * g2 * g2;  // the band covers about three rounds
+            if (epoch) t_near = beta2 * g2 * g2;  // the band covers about two rounds
             ffo = epoch ? (ffc ^ 1) : ffc;
             // per-round counters reset on the device (error flags raised by
             // the previous round's last kernels stay for the next read), and
