@@ -509,10 +509,10 @@ __global__ void __launch_bounds__(kBlock) k_min_positive_lb(const PairRec* f, u3
     block_atomic_min(v, &cnt->m[M_F], sh);
 }
 
-// Near-frontier split: queue the pairs whose lower bound is within beta
-// (each in the region of its first node), keep the rest in the near list.  A
-// pair's connectivity is checked when it is expanded, so this pass only
-// streams the records.
+// Near-frontier split: drop the pairs whose nodes already lie in one
+// component (from the compact label copy: two 4-byte reads), queue the
+// pairs whose lower bound is within beta (each in the region of its first
+// node), keep the rest in the near list.
 constexpr int kSplitLists = kRegions + 2;  // regions, near list, far list
 using SplitAlloc = BlockAllocN<kSplitLists, 12>;
 
@@ -551,15 +551,16 @@ __global__ void __launch_bounds__(kBlock) k_split_frontier(TreeView t, RoundArgs
             const u32 i = b0 + k * kBlock + threadIdx.x;
             if (i < nfin) {
                 p[k] = fin[i];
-                const bool d = p[k].lb2 <= r.beta2 || card_due<D>(t, r.beta_card, p[k].a, p[k].b);
+                const bool keep = !connected_lab(r.labels, p[k].a, p[k].b);
+                const bool d = keep && (p[k].lb2 <= r.beta2 || card_due<D>(t, r.beta_card, p[k].a, p[k].b));
                 due |= (u32)d << k;
-                wait |= (u32)!d << k;
+                wait |= (u32)(keep && !d) << k;
                 if (d) {
                     const int rg = node_region(p[k].a, t.n);
                     rgs |= (u32)rg << (3 * k);
 #pragma unroll
                     for (int x = 0; x < kRegions; ++x) cnt[x] += (rg == x);
-                } else {
+                } else if (keep) {
                     ++cnt[kRegions];
                     minf = fmin(minf, p[k].lb2);
                 }
