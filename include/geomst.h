@@ -419,7 +419,8 @@ int geomst_get_stats(geomst_stats_t* out);
  *                    [64, 65536]; 0 restores the default 2048.
  *   "refresh_divisor"  node components are refreshed after a round that
  *                    merged at least n / this many components (and at least
- *                    every fourth round); default 1024.
+ *                    every fourth round); default 1048576, about every round
+ *                    that merged anything.
  *   "small_level_switch", "small_level_max"  expansion levels with at most
  *                    eight times the first many pairs run in eight
  *                    workgroups, one eighth each, and each workgroup keeps

@@ -50,7 +50,11 @@ int g_beta_plain = 0;        // 1: the threshold grows by exactly g every round 
 double g_share_scale = 1.0;  // server workers: scale of the workspace share a batch may grow to (testing aid)
 constexpr int kMaxKeyLevels = 6;  // Morton key words per point (see k_morton_level)
 constexpr int kLevelBatch = 6;    // expansion levels launched between host checks
-u32 g_refresh_div = 1024;    // refresh node components once a round merged n / this many
+// refresh node components once a round merged n / this many (the default
+// means about every round that merged anything: the splits and the levels
+// drop connected pairs by these labels, so fresh ones pay for the refresh)
+constexpr u32 kRefreshDefault = 1048576;
+u32 g_refresh_div = kRefreshDefault;
 u32 g_small_switch = 2048;  // queues up to kRegions times this go to the per-region level kernel
 u32 g_small_max = 4096;     // ... whose workgroups keep going while their levels stay this small
 u32 g_wide_switch = 2048;   // queues up to kRegions * kSub times this go to the wide level kernel (0: off)
@@ -123,7 +127,7 @@ Opts snapshot_options(int kind, int d, int64_t n) {
             o.small_switch = best->small_switch;
             o.small_max = std::max(best->small_max, best->small_switch);
         }
-        if (best->refresh_div && o.refresh_div == 1024) o.refresh_div = best->refresh_div;
+        if (best->refresh_div && o.refresh_div == kRefreshDefault) o.refresh_div = best->refresh_div;
         if (best->beta_growth > 0.0 && o.beta_growth == 0.0) o.beta_growth = best->beta_growth;
         if (best->beta_start >= 0.0 && o.beta_start == 0.0) o.beta_start = best->beta_start;
         o.tuned = true;

@@ -38,7 +38,7 @@ from . import geomst as G
 from . import workloads as W
 
 DEFAULTS = {"bccp_chunk": 2048, "small_level_switch": 2048, "small_level_max": 4096, "beta_growth": 0.0,
-            "refresh_divisor": 1024}
+            "refresh_divisor": 1048576}
 
 # candidate values per knob (small-level thresholds move together)
 CANDIDATES = {
@@ -46,7 +46,7 @@ CANDIDATES = {
     "small_levels": [(1024, 2048), (2048, 4096), (4096, 8192), (8192, 16384)],
     "beta_growth_emst": [1.5, 2.0, 3.0, 4.0],
     "beta_growth_hdbscan": [1.25, 1.4142135623730951, 2.0],
-    "refresh_divisor": [256, 1024, 4096],
+    "refresh_divisor": [1024, 16384, 1048576],
 }
 
 
