@@ -379,9 +379,9 @@ int geomst_get_stats(geomst_stats_t* out);
  *                    pairs' positive lower bounds is reached (default 0:
  *                    the smallest positive bound).
  *   "beta_schedule"  0 = default: the threshold grows by g per round, by g^2
- *                    while the tree holds fewer than n/64 edges, and (EMST)
- *                    by g^4 after a round that found no edge before the
- *                    first one; 1 = plain: beta <- max(g * beta, smallest
+ *                    while the tree holds fewer than n/16 edges (EMST) or
+ *                    n/64 (HDBSCAN*), and (EMST) by g^4 after a round that
+ *                    found no edge before the first one; 1 = plain: beta <- max(g * beta, smallest
  *                    waiting bound) every round, starting at the smallest
  *                    positive pair bound (doubling for EMST).
  *   "server_share_scale"  (0,1]: a server worker's batch may grow its

@@ -60,7 +60,10 @@ u32 g_small_max = 4096;     // ... whose workgroups keep going while their level
 u32 g_wide_switch = 2048;   // queues up to kRegions * kSub times this go to the wide level kernel (0: off)
 u32 g_wide_max = 4096;      // ... whose workgroups keep going while their levels stay this small
 constexpr int kBoruvkaBatch = 4;  // Boruvka steps launched between host checks
-constexpr u32 kSparseDiv = 64;  // beta grows faster while the tree has fewer than n / this many edges
+// beta grows faster while the tree has fewer than n / this many edges
+// (HDBSCAN*, whose larger early rounds cost more, and EMST)
+constexpr u32 kSparseDivHdb = 64;
+constexpr u32 kSparseDivEmst = 16;
 const bool g_trace = getenv("GEOMST_TRACE") != nullptr;
 
 // Options of one solve: the process-wide values (geomst_set_option) read
@@ -1598,7 +1601,7 @@ struct Solver {
                 beta_card = beta_card >= 0x80000000u ? 0xffffffffu : beta_card * 2;
                 continue;
             }
-            const bool sparse = !o.beta_plain && (u64)nout * kSparseDiv < (u64)n;
+            const bool sparse = !o.beta_plain && (u64)nout * (hdb ? kSparseDivHdb : kSparseDivEmst) < (u64)n;
             const bool empty = !o.beta_plain && !hdb && nout == 0 && m == 0 && nP == 0 && nbig == 0;
             beta2 = std::max(beta2 * (empty ? g2 * g2 * g2 * g2 : sparse ? g2 * g2 : g2), nxt);
         }
